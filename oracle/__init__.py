@@ -1,0 +1,279 @@
+"""FP64 CPU oracle for the multi-hypothesis criticality hot path.
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It loads
+``liboracle.so`` (built from ``mhc_oracle.c`` with gcc) and shares no code
+with the GPU library; both sides are fed from the seeded generator in
+``paper_2005_06773_amd.scenegen``, which holds no arithmetic of the method.
+
+Every quantity here follows Sanchez Morales et al. (IEEE IV 2019):
+probabilities Sec. IV-D.1, trajectories Sec. IV-B.1 / IV-B.3, pairs and
+overlap Sec. IV-C.1, risk Sec. IV-D / IV-D.2. The readings taken where the
+paper is silent are listed at the top of ``mhc_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mhc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+#: tolerance band (metres) within which an FP32 evaluation may decide an
+#: overlap either way; outside it first hits must agree bit for bit.
+EPS = 1e-4
+
+VEHICLE = 0
+PEDESTRIAN = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP64, no fast-math, OpenMP rows)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+               "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        D = ctypes.c_double
+        I = ctypes.c_int
+        P = ctypes.c_void_p
+        L.orc_probabilities.argtypes = [I, P, P]
+        L.orc_trajectories.argtypes = [I, D, D, D, D, I, P, I, P, I, D, P, P, P]
+        L.orc_margin_rect_rect.argtypes = [D] * 10
+        L.orc_margin_rect_rect.restype = D
+        L.orc_margin_rect_circle.argtypes = [D] * 8
+        L.orc_margin_rect_circle.restype = D
+        L.orc_margin_circle_circle.argtypes = [D] * 6
+        L.orc_margin_circle_circle.restype = D
+        L.orc_pairs.argtypes = [I, I, P, P]
+        L.orc_count_trajectories.argtypes = [I, P]
+        L.orc_count_trajectories.restype = ctypes.c_int64
+        L.orc_count_combinations.argtypes = [I, P, I]
+        L.orc_count_combinations.restype = ctypes.c_int64
+        L.orc_first_hits.argtypes = [I, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
+        L.orc_risk.argtypes = [I, P, P, I, P, P, P, P, P, P]
+        L.orc_point_in_polygon.argtypes = [D, D, I, P, P]
+        L.orc_rect_corners.argtypes = [D, D, D, D, D, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+# ---------------------------------------------------------------------------
+# Elementary pieces
+# ---------------------------------------------------------------------------
+
+def probabilities(obj) -> np.ndarray:
+    n = obj.n_traj
+    p = np.empty(n, np.float64)
+    s = None if obj.score is None else np.ascontiguousarray(obj.score, np.float64)
+    _check(lib().orc_probabilities(n, _ptr(s), _ptr(p)), "probabilities")
+    return p
+
+
+def trajectories(obj, horizon: int, dt: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(x, y, psi), each [horizon][T]; slot t is the pose of step t+1."""
+    T = obj.n_traj
+    x = np.empty((horizon, T), np.float64)
+    y = np.empty((horizon, T), np.float64)
+    psi = np.empty((horizon, T), np.float64)
+    u = np.ascontiguousarray(obj.u, np.float64)
+    w = np.ascontiguousarray(obj.w, np.float64)
+    _check(lib().orc_trajectories(int(obj.kind), obj.x, obj.y, obj.heading, obj.speed,
+                                  len(u), _ptr(u), len(w), _ptr(w), horizon, dt,
+                                  _ptr(x), _ptr(y), _ptr(psi)), "trajectories")
+    return x, y, psi
+
+
+def margin_rect_rect(P, Q) -> float:
+    """P, Q = (x, y, psi, L, W)."""
+    return lib().orc_margin_rect_rect(*map(float, P), *map(float, Q))
+
+
+def margin_rect_circle(P, Q) -> float:
+    """P = (x, y, psi, L, W), Q = (x, y, r)."""
+    return lib().orc_margin_rect_circle(*map(float, P), *map(float, Q))
+
+
+def margin_circle_circle(P, Q) -> float:
+    """P, Q = (x, y, r)."""
+    return lib().orc_margin_circle_circle(*map(float, P), *map(float, Q))
+
+
+def rect_corners(x, y, psi, L, W) -> np.ndarray:
+    cx = np.empty(4, np.float64)
+    cy = np.empty(4, np.float64)
+    lib().orc_rect_corners(float(x), float(y), float(psi), float(L), float(W), _ptr(cx), _ptr(cy))
+    return np.stack([cx, cy], axis=1)
+
+
+def point_in_polygon(x, y, poly: np.ndarray) -> bool:
+    vx = np.ascontiguousarray(poly[:, 0], np.float64)
+    vy = np.ascontiguousarray(poly[:, 1], np.float64)
+    return bool(lib().orc_point_in_polygon(float(x), float(y), len(vx), _ptr(vx), _ptr(vy)))
+
+
+def pairs(n_objects: int, ego_only: bool) -> List[Tuple[int, int]]:
+    n = lib().orc_pairs(n_objects, int(ego_only), None, None)
+    a = np.empty(n, np.int32)
+    b = np.empty(n, np.int32)
+    lib().orc_pairs(n_objects, int(ego_only), _ptr(a), _ptr(b))
+    return list(zip(a.tolist(), b.tolist()))
+
+
+def count_trajectories(T: Sequence[int]) -> int:
+    t = np.ascontiguousarray(T, np.int32)
+    return int(lib().orc_count_trajectories(len(t), _ptr(t)))
+
+
+def count_combinations(T: Sequence[int], ego_only: bool) -> int:
+    t = np.ascontiguousarray(T, np.int32)
+    return int(lib().orc_count_combinations(len(t), _ptr(t), int(ego_only)))
+
+
+# ---------------------------------------------------------------------------
+# Whole scene
+# ---------------------------------------------------------------------------
+
+@dataclass
+class OracleResult:
+    pair_a: np.ndarray          # [n_pairs] int32
+    pair_b: np.ndarray
+    pair_off: np.ndarray        # [n_pairs+1] int64 entry offsets
+    T: np.ndarray               # [n_objects] int32
+    p: np.ndarray               # [sum T] normalised probabilities
+    k64: np.ndarray             # [entries] int32 first slot with m <= 0, else -1
+    kstrict: np.ndarray         # [entries] first slot with m <= -EPS, else -1
+    loose: Optional[np.ndarray]   # [entries, W] uint64 bit t: m(t) <= +EPS
+    strict: Optional[np.ndarray]  # [entries, W] uint64 bit t: m(t) <= -EPS
+    q: np.ndarray               # [sum T, n] from k64
+    traj_crit: np.ndarray       # [sum T] from k64
+    obj_crit: np.ndarray        # [n]    from k64
+    traj_crit_lo: np.ndarray    # only pairs with a hit beyond the band count
+    traj_crit_hi: np.ndarray    # every pair with a hit inside the band counts
+    obj_crit_lo: np.ndarray
+    obj_crit_hi: np.ndarray
+
+
+def scene_arrays(scene):
+    objs = scene.objects
+    kind = np.array([o.kind for o in objs], np.int32)
+    length = np.array([o.length for o in objs], np.float64)
+    width = np.array([o.width for o in objs], np.float64)
+    radius = np.array([o.radius for o in objs], np.float64)
+    T = np.array([o.n_traj for o in objs], np.int32)
+    return kind, length, width, radius, T
+
+
+def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: float = EPS,
+             threads: int = 0, masks: bool = True, risk: bool = True) -> OracleResult:
+    """Run the whole path on ``scene`` (a ``scenegen.Scene``).
+
+    ``pair_list`` restricts the object pairs (the stress-scene sample); by
+    default all pairs, or EGO-CO pairs when ``scene.pairs`` is the EGO mode.
+    """
+    H, dt = int(scene.horizon), float(scene.dt)
+    kind, length, width, radius, T = scene_arrays(scene)
+    n = len(T)
+    if pair_list is None:
+        pair_list = pairs(n, scene.pairs == 1)
+    pa = np.array([a for a, _ in pair_list], np.int32)
+    pb = np.array([b for _, b in pair_list], np.int32)
+    sizes = (T[pa].astype(np.int64) * T[pb].astype(np.int64)) if len(pa) else np.zeros(0, np.int64)
+    poff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    entries = int(poff[-1])
+
+    xs, ys, ps, pr = [], [], [], []
+    for o in scene.objects:
+        x, y, psi = trajectories(o, H, dt)
+        xs.append(x.reshape(-1))
+        ys.append(y.reshape(-1))
+        ps.append(psi.reshape(-1))
+        pr.append(probabilities(o))
+    px = np.ascontiguousarray(np.concatenate(xs))
+    py = np.ascontiguousarray(np.concatenate(ys))
+    ppsi = np.ascontiguousarray(np.concatenate(ps))
+    p = np.ascontiguousarray(np.concatenate(pr))
+
+    W = (H + 63) // 64
+    k64 = np.empty(entries, np.int32)
+    kst = np.empty(entries, np.int32)
+    loose = np.empty((entries, W), np.uint64) if masks else None
+    strict = np.empty((entries, W), np.uint64) if masks else None
+    _check(lib().orc_first_hits(n, _ptr(kind), _ptr(length), _ptr(width), _ptr(radius), _ptr(T), H,
+                                _ptr(px), _ptr(py), _ptr(ppsi), len(pa), _ptr(pa), _ptr(pb),
+                                float(eps), int(threads), _ptr(k64), _ptr(kst),
+                                _ptr(loose), _ptr(strict)), "first_hits")
+    res = OracleResult(pa, pb, poff, T, p, k64, kst, loose, strict,
+                       *([None] * 7))
+    if risk:
+        res.q, res.traj_crit, res.obj_crit = risk_from_hits(scene, pa, pb, (k64 >= 0), p)
+        lo = kst >= 0
+        if masks:
+            hi = np.any(loose != 0, axis=1)
+        else:
+            hi = k64 >= 0
+        _, res.traj_crit_lo, res.obj_crit_lo = risk_from_hits(scene, pa, pb, lo, p)
+        _, res.traj_crit_hi, res.obj_crit_hi = risk_from_hits(scene, pa, pb, hi, p)
+    return res
+
+
+def risk_from_hits(scene, pa: np.ndarray, pb: np.ndarray, hit: np.ndarray, p: np.ndarray):
+    """q [sum T, n], traj_crit [sum T], obj_crit [n] from a per-entry hit flag."""
+    _, _, _, _, T = scene_arrays(scene)
+    n = len(T)
+    n_traj = int(T.sum())
+    h = np.ascontiguousarray(hit, np.uint8)
+    q = np.empty((n_traj, n), np.float64)
+    tc = np.empty(n_traj, np.float64)
+    oc = np.empty(n, np.float64)
+    _check(lib().orc_risk(n, _ptr(T), _ptr(np.ascontiguousarray(p, np.float64)), len(pa),
+                          _ptr(np.ascontiguousarray(pa, np.int32)), _ptr(np.ascontiguousarray(pb, np.int32)),
+                          _ptr(h), _ptr(q), _ptr(tc), _ptr(oc)), "risk")
+    return q, tc, oc
+
+
+def accepted_first_hits(k32: np.ndarray, res: OracleResult) -> np.ndarray:
+    """Per entry, whether a first-hit slot computed in FP32 is acceptable:
+    every slot before it is a miss beyond the band (no strict hit earlier), the
+    slot itself is a hit or inside the band, and -1 only when no slot is a
+    hit beyond the band. Without ambiguous slots this is bit equality with k64."""
+    k32 = np.asarray(k32).astype(np.int64)
+    kst = res.kstrict.astype(np.int64)
+    none_ok = (k32 == -1) & (kst == -1)
+    some = k32 >= 0
+    no_strict_before = (kst == -1) | (kst >= k32)
+    kk = np.where(some, k32, 0)
+    word = kk // 64
+    bit = (kk % 64).astype(np.uint64)
+    lw = res.loose[np.arange(len(k32)), word]
+    is_loose = ((lw >> bit) & np.uint64(1)) == np.uint64(1)
+    return none_ok | (some & no_strict_before & is_loose)

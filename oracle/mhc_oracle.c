@@ -1,0 +1,435 @@
+/*
+ * mhc_oracle.c -- plain FP64 CPU oracle for the multi-hypothesis criticality
+ * method of Sanchez Morales et al., "Parallel Multi-Hypothesis Algorithm for
+ * Criticality Estimation in Traffic and Collision Avoidance" (IEEE IV 2019).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library. It shares no code, header,
+ * table or constant with the GPU library, and it is deliberately slow and
+ * literal: every result is computed from its definition, in double precision,
+ * one trajectory pair and one time step at a time, with no blocking, no
+ * culling and no fast-math.
+ *
+ * Pipeline (Fig. 1 of the paper, street module dropped):
+ *   probabilities  (Sec. IV-D.1, L1 normalisation of trajectory scores)
+ *   trajectories   (Sec. IV-B.1 Euler pose update; Sec. IV-B.3 pedestrians)
+ *   pairs          (Sec. IV-C.1; all unordered pairs, or EGO-CO only)
+ *   overlap margin (Sec. IV-C.1; exact closed-shape intersection)
+ *   first hit      (earliest colliding step of each trajectory pair)
+ *   risk           (Sec. IV-D p_cra double sum, Sec. IV-D.2 chronological
+ *                   scaling of the conditional probabilities)
+ *
+ * Readings of the paper that this file takes (the paper is silent or
+ * ambiguous on each):
+ *   - vehicles move on the kinematic special case of the Euler update with
+ *     side slip beta = 0 and yaw acceleration 0; the longitudinal
+ *     acceleration of step n acts within step n (no one-step lag) and the
+ *     speed is clamped at zero, the acceleration that step being the one that
+ *     stops the vehicle;
+ *   - vehicles are rectangles, pedestrians circles; touching counts as a
+ *     collision (margin <= 0);
+ *   - poses are predicted for n = 1..H and stored at slot n-1; the measured
+ *     state (n = 0) is never checked;
+ *   - the chronological scaling is read as: collision objects independent of
+ *     one another, the trajectories of one object mutually exclusive, all
+ *     conditioned on the trajectory of the object being assessed. The product
+ *     of "no collision" factors then telescopes, so no ordering is needed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_VEHICLE 0
+#define ORC_PEDESTRIAN 1
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+
+/* ------------------------------------------------------------------------ */
+/* Probabilities: Sec. IV-D.1. The scores of one object are normalised with  */
+/* respect to the L1 norm; without scores every trajectory is equally likely.*/
+/* ------------------------------------------------------------------------ */
+int orc_probabilities(int n, const double *score, double *p)
+{
+    if (n < 1) return ORC_EINVAL;
+    if (score == NULL) {
+        for (int i = 0; i < n; ++i) p[i] = 1.0 / (double)n;
+        return ORC_OK;
+    }
+    double l1 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(score[i] >= 0.0) || !isfinite(score[i])) return ORC_EINVAL;
+        l1 += fabs(score[i]);
+    }
+    if (!(l1 > 0.0) || !isfinite(l1)) return ORC_EINVAL;
+    for (int i = 0; i < n; ++i) p[i] = score[i] / l1;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Trajectories. Output arrays are [H][n_u*n_w], slot t holding the pose of  */
+/* step n = t+1. Trajectory index i = k*n_w + l.                             */
+/* ------------------------------------------------------------------------ */
+
+/* Vehicle: Euler pose update of Sec. IV-B.1 with beta = beta_dot = 0 and
+ * psi_ddot = 0, driven by a constant acceleration u[k] and a constant yaw
+ * rate w[l]:
+ *   v_{n+1}   = v_n + vdot_n tau            (vdot_n clamped so v >= 0)
+ *   psi_{n+1} = psi_n + psi_dot tau
+ *   a_x,n = vdot_n,  a_y,n = v_n psi_dot     (vehicle frame)
+ *   x_{n+1} = x_n + c(psi_n) v_n tau + c(psi_n) a_x,n tau^2/2 - s(psi_n) a_y,n tau^2/2
+ *   y_{n+1} = y_n + s(psi_n) v_n tau + s(psi_n) a_x,n tau^2/2 + c(psi_n) a_y,n tau^2/2
+ */
+static void vehicle_trajectory(double x0, double y0, double psi0, double v0,
+                               double accel, double yaw_rate, int H, double tau,
+                               int T, int i, double *ox, double *oy, double *opsi)
+{
+    double x = x0, y = y0, psi = psi0, v = v0;
+    for (int n = 0; n < H; ++n) {
+        double vdot = accel;
+        double v_next = v + vdot * tau;
+        if (v_next < 0.0) {          /* the vehicle stops inside this step */
+            vdot = -v / tau;
+            v_next = 0.0;
+        }
+        double ax = vdot;
+        double ay = v * yaw_rate;
+        double c = cos(psi), s = sin(psi);
+        double x_next = x + c * v * tau + c * ax * (tau * tau / 2.0) - s * ay * (tau * tau / 2.0);
+        double y_next = y + s * v * tau + s * ax * (tau * tau / 2.0) + c * ay * (tau * tau / 2.0);
+        double psi_next = psi + yaw_rate * tau;
+        x = x_next;
+        y = y_next;
+        psi = psi_next;
+        v = v_next;
+        ox[(size_t)n * T + i] = x;
+        oy[(size_t)n * T + i] = y;
+        opsi[(size_t)n * T + i] = psi;
+    }
+}
+
+/* Pedestrian: kinematic model of Sec. IV-B.3 with a constant speed u[k]
+ * (vdot_P = 0) along the heading psi0 + w[l]:
+ *   x_{n+1} = x_n + c(psi_P) v_P tau,  y_{n+1} = y_n + s(psi_P) v_P tau. */
+static void pedestrian_trajectory(double x0, double y0, double psi0,
+                                  double speed, double heading_offset, int H, double tau,
+                                  int T, int i, double *ox, double *oy, double *opsi)
+{
+    double psi = psi0 + heading_offset;
+    double c = cos(psi), s = sin(psi);
+    double x = x0, y = y0;
+    for (int n = 0; n < H; ++n) {
+        x = x + c * speed * tau;
+        y = y + s * speed * tau;
+        ox[(size_t)n * T + i] = x;
+        oy[(size_t)n * T + i] = y;
+        opsi[(size_t)n * T + i] = psi;
+    }
+}
+
+int orc_trajectories(int kind, double x0, double y0, double psi0, double v0,
+                     int n_u, const double *u, int n_w, const double *w,
+                     int H, double tau, double *ox, double *oy, double *opsi)
+{
+    if (n_u < 1 || n_w < 1 || H < 1 || !(tau > 0.0)) return ORC_EINVAL;
+    int T = n_u * n_w;
+    for (int k = 0; k < n_u; ++k)
+        for (int l = 0; l < n_w; ++l) {
+            int i = k * n_w + l;
+            if (kind == ORC_VEHICLE)
+                vehicle_trajectory(x0, y0, psi0, v0, u[k], w[l], H, tau, T, i, ox, oy, opsi);
+            else if (kind == ORC_PEDESTRIAN)
+                pedestrian_trajectory(x0, y0, psi0, u[k], w[l], H, tau, T, i, ox, oy, opsi);
+            else
+                return ORC_EINVAL;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Overlap margin: Sec. IV-C.1. At one time step two objects collide when    */
+/* their (closed) shapes intersect. The margin is <= 0 exactly then.         */
+/* ------------------------------------------------------------------------ */
+
+/* Corners of a rectangle centred at (x, y), heading psi, full length L along
+ * the heading and full width W across it. */
+static void rect_corners(double x, double y, double psi, double L, double W, double cx[4], double cy[4])
+{
+    double ux = cos(psi), uy = sin(psi);       /* along the heading */
+    double vx = -uy, vy = ux;                  /* across the heading */
+    const double sl[4] = {+1, +1, -1, -1};
+    const double sw[4] = {+1, -1, -1, +1};
+    for (int k = 0; k < 4; ++k) {
+        cx[k] = x + sl[k] * (L / 2.0) * ux + sw[k] * (W / 2.0) * vx;
+        cy[k] = y + sl[k] * (L / 2.0) * uy + sw[k] * (W / 2.0) * vy;
+    }
+}
+
+/* Two convex polygons are disjoint iff their projections on some edge normal
+ * are disjoint (separating axis theorem). For rectangles the edge normals are
+ * the two heading axes of each. The margin is the largest gap between the
+ * projected intervals over those four axes; a negative gap on every axis
+ * means the closed rectangles intersect. */
+double orc_margin_rect_rect(double xP, double yP, double psiP, double LP, double WP,
+                            double xQ, double yQ, double psiQ, double LQ, double WQ)
+{
+    double px[4], py[4], qx[4], qy[4];
+    rect_corners(xP, yP, psiP, LP, WP, px, py);
+    rect_corners(xQ, yQ, psiQ, LQ, WQ, qx, qy);
+    double axes[4][2] = {
+        {cos(psiP), sin(psiP)}, {-sin(psiP), cos(psiP)},
+        {cos(psiQ), sin(psiQ)}, {-sin(psiQ), cos(psiQ)},
+    };
+    double margin = -INFINITY;
+    for (int a = 0; a < 4; ++a) {
+        double nx = axes[a][0], ny = axes[a][1];
+        double pmin = INFINITY, pmax = -INFINITY, qmin = INFINITY, qmax = -INFINITY;
+        for (int k = 0; k < 4; ++k) {
+            double sp = px[k] * nx + py[k] * ny;
+            double sq = qx[k] * nx + qy[k] * ny;
+            if (sp < pmin) pmin = sp;
+            if (sp > pmax) pmax = sp;
+            if (sq < qmin) qmin = sq;
+            if (sq > qmax) qmax = sq;
+        }
+        double gap = fmax(qmin - pmax, pmin - qmax);
+        if (gap > margin) margin = gap;
+    }
+    return margin;
+}
+
+/* Rectangle P and circle Q intersect iff the distance from Q's centre to the
+ * closest point of P is at most r_Q. The closest point is found in P's frame
+ * by clamping the centre's local coordinates to the half extents. */
+double orc_margin_rect_circle(double xP, double yP, double psiP, double LP, double WP,
+                              double xQ, double yQ, double rQ)
+{
+    double dx = xQ - xP, dy = yQ - yP;
+    double lam = dx * cos(psiP) + dy * sin(psiP);     /* along P's heading */
+    double mu = -dx * sin(psiP) + dy * cos(psiP);     /* across P's heading */
+    double cl = fmin(fmax(lam, -LP / 2.0), LP / 2.0);
+    double cm = fmin(fmax(mu, -WP / 2.0), WP / 2.0);
+    double dist = hypot(lam - cl, mu - cm);
+    return dist - rQ;
+}
+
+double orc_margin_circle_circle(double xP, double yP, double rP, double xQ, double yQ, double rQ)
+{
+    return hypot(xQ - xP, yQ - yP) - (rP + rQ);
+}
+
+static double margin_at(int kindP, double xP, double yP, double psiP, double LP, double WP, double rP,
+                        int kindQ, double xQ, double yQ, double psiQ, double LQ, double WQ, double rQ)
+{
+    if (kindP == ORC_VEHICLE && kindQ == ORC_VEHICLE)
+        return orc_margin_rect_rect(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
+    if (kindP == ORC_VEHICLE)
+        return orc_margin_rect_circle(xP, yP, psiP, LP, WP, xQ, yQ, rQ);
+    if (kindQ == ORC_VEHICLE)
+        return orc_margin_rect_circle(xQ, yQ, psiQ, LQ, WQ, xP, yP, rP);
+    return orc_margin_circle_circle(xP, yP, rP, xQ, yQ, rQ);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pairs: Sec. IV-C.1 checks EGO (object 0) against every collision object   */
+/* only; the all-pairs mode checks every unordered pair a < b. Pairs are     */
+/* listed in lexicographic order.                                            */
+/* ------------------------------------------------------------------------ */
+int orc_pairs(int n_objects, int ego_only, int32_t *pa, int32_t *pb)
+{
+    int n = 0;
+    for (int a = 0; a < n_objects; ++a)
+        for (int b = a + 1; b < n_objects; ++b) {
+            if (ego_only && a != 0) continue;
+            if (pa) pa[n] = a;
+            if (pb) pb[n] = b;
+            ++n;
+        }
+    return n;
+}
+
+/* Trajectory-generation thread count r_tra of Sec. IV-B.4 and the collision
+ * combination count r_col of Sec. IV-C.2, as plain sums over the scene. */
+int64_t orc_count_trajectories(int n_objects, const int32_t *T)
+{
+    int64_t s = 0;
+    for (int a = 0; a < n_objects; ++a) s += T[a];
+    return s;
+}
+
+int64_t orc_count_combinations(int n_objects, const int32_t *T, int ego_only)
+{
+    int64_t s = 0;
+    for (int a = 0; a < n_objects; ++a)
+        for (int b = a + 1; b < n_objects; ++b)
+            if (!ego_only || a == 0) s += (int64_t)T[a] * (int64_t)T[b];
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* First hits.                                                                */
+/*                                                                            */
+/* Poses of all objects are concatenated: object a's block starts at          */
+/* H * sum_{c<a} T_c and is laid out [t][i]. For every listed pair (a, b),    */
+/* trajectory i of a, trajectory j of b, entry e = pair_offset + i*T_b + j:    */
+/*   k64[e]     = min{ t : m(t) <= 0 }, else -1                              */
+/*   kstrict[e] = min{ t : m(t) <= -eps }, else -1                           */
+/*   loose[e*W + t/64]  bit t%64 set iff m(t) <= +eps   (W = ceil(H/64))    */
+/*   strict[e*W + t/64] bit t%64 set iff m(t) <= -eps                       */
+/* Any output pointer may be NULL. eps is the tolerance band within which an */
+/* FP32 evaluation of the same test may legitimately decide either way.      */
+/* ------------------------------------------------------------------------ */
+int orc_first_hits(int n_objects, const int32_t *kind, const double *length, const double *width,
+                   const double *radius, const int32_t *T, int H,
+                   const double *px, const double *py, const double *ppsi,
+                   int n_pairs, const int32_t *pair_a, const int32_t *pair_b,
+                   double eps, int threads,
+                   int32_t *k64, int32_t *kstrict, uint64_t *loose, uint64_t *strict)
+{
+    if (n_objects < 1 || H < 1 || n_pairs < 0) return ORC_EINVAL;
+    int W = (H + 63) / 64;
+    int64_t *obj_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
+    int64_t *pair_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
+    if (!obj_off || !pair_off) { free(obj_off); free(pair_off); return ORC_ENOMEM; }
+    obj_off[0] = 0;
+    for (int a = 0; a < n_objects; ++a) obj_off[a + 1] = obj_off[a] + (int64_t)H * T[a];
+    pair_off[0] = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        int a = pair_a[p], b = pair_b[p];
+        if (a < 0 || b < 0 || a >= n_objects || b >= n_objects || a == b) {
+            free(obj_off); free(pair_off); return ORC_EINVAL;
+        }
+        pair_off[p + 1] = pair_off[p] + (int64_t)T[a] * T[b];
+    }
+    /* rows = (pair, i), the unit of work that threads may share */
+    int64_t *row_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
+    if (!row_off) { free(obj_off); free(pair_off); return ORC_ENOMEM; }
+    row_off[0] = 0;
+    for (int p = 0; p < n_pairs; ++p) row_off[p + 1] = row_off[p] + T[pair_a[p]];
+    int64_t n_rows = row_off[n_pairs];
+
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t r = 0; r < n_rows; ++r) {
+        int p = 0;
+        while (row_off[p + 1] <= r) ++p;
+        int a = pair_a[p], b = pair_b[p];
+        int i = (int)(r - row_off[p]);
+        int Ta = T[a], Tb = T[b];
+        for (int j = 0; j < Tb; ++j) {
+            int64_t e = pair_off[p] + (int64_t)i * Tb + j;
+            int32_t first = -1, first_strict = -1;
+            if (loose) for (int wd = 0; wd < W; ++wd) loose[e * W + wd] = 0;
+            if (strict) for (int wd = 0; wd < W; ++wd) strict[e * W + wd] = 0;
+            for (int t = 0; t < H; ++t) {
+                size_t ia = (size_t)(obj_off[a] + (int64_t)t * Ta + i);
+                size_t ib = (size_t)(obj_off[b] + (int64_t)t * Tb + j);
+                double m = margin_at(kind[a], px[ia], py[ia], ppsi[ia], length[a], width[a], radius[a],
+                                     kind[b], px[ib], py[ib], ppsi[ib], length[b], width[b], radius[b]);
+                if (m <= 0.0 && first < 0) first = t;
+                if (m <= -eps && first_strict < 0) first_strict = t;
+                if (loose && m <= eps) loose[e * W + t / 64] |= (uint64_t)1 << (t % 64);
+                if (strict && m <= -eps) strict[e * W + t / 64] |= (uint64_t)1 << (t % 64);
+            }
+            if (k64) k64[e] = first;
+            if (kstrict) kstrict[e] = first_strict;
+        }
+    }
+    free(row_off);
+    free(obj_off);
+    free(pair_off);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Risk: Sec. IV-D and Sec. IV-D.2.                                           */
+/*                                                                            */
+/* hit[e] (entry layout as above) says whether trajectory pair e collides.    */
+/* For object a, trajectory i and another object b:                           */
+/*   q[a,i;b]   = sum_j hit(a,i;b,j) p_{b,j}   (b's trajectories exclusive)  */
+/* Under the chronological scaling the collision with b only counts when no  */
+/* other object has collided first; with the objects independent, the        */
+/* probability that some collision happens along trajectory i is             */
+/*   crit[a,i]  = 1 - prod_{b != a} (1 - q[a,i;b])                           */
+/* and the criticality of object a weights its trajectories by probability:  */
+/*   C[a]       = sum_i p_{a,i} crit[a,i]                                    */
+/* With a single collision object C[0] is the double sum p_cra of Sec. IV-D. */
+/* q is [sum T][n_objects] (nullable); traj_crit [sum T]; obj_crit [n].       */
+/* Pairs not listed contribute q = 0.                                         */
+/* ------------------------------------------------------------------------ */
+int orc_risk(int n_objects, const int32_t *T, const double *p,
+             int n_pairs, const int32_t *pair_a, const int32_t *pair_b,
+             const uint8_t *hit, double *q_out, double *traj_crit, double *obj_crit)
+{
+    if (n_objects < 1 || n_pairs < 0) return ORC_EINVAL;
+    int64_t *toff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
+    if (!toff) return ORC_ENOMEM;
+    toff[0] = 0;
+    for (int a = 0; a < n_objects; ++a) toff[a + 1] = toff[a] + T[a];
+    int64_t n_traj = toff[n_objects];
+    double *q = (double *)calloc((size_t)n_traj * (size_t)n_objects, sizeof(double));
+    if (!q) { free(toff); return ORC_ENOMEM; }
+
+    int64_t e0 = 0;
+    for (int pr = 0; pr < n_pairs; ++pr) {
+        int a = pair_a[pr], b = pair_b[pr];
+        int Ta = T[a], Tb = T[b];
+        for (int i = 0; i < Ta; ++i) {
+            double s = 0.0;
+            for (int j = 0; j < Tb; ++j)
+                if (hit[e0 + (int64_t)i * Tb + j]) s += p[toff[b] + j];
+            q[(toff[a] + i) * n_objects + b] = fmin(s, 1.0);
+        }
+        for (int j = 0; j < Tb; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < Ta; ++i)
+                if (hit[e0 + (int64_t)i * Tb + j]) s += p[toff[a] + i];
+            q[(toff[b] + j) * n_objects + a] = fmin(s, 1.0);
+        }
+        e0 += (int64_t)Ta * Tb;
+    }
+    for (int a = 0; a < n_objects; ++a) {
+        double C = 0.0;
+        for (int i = 0; i < T[a]; ++i) {
+            double no_collision = 1.0;
+            for (int b = 0; b < n_objects; ++b)
+                if (b != a) no_collision *= 1.0 - q[(toff[a] + i) * n_objects + b];
+            double crit = 1.0 - no_collision;
+            if (traj_crit) traj_crit[toff[a] + i] = crit;
+            C += p[toff[a] + i] * crit;
+        }
+        if (obj_crit) obj_crit[a] = C;
+    }
+    if (q_out) memcpy(q_out, q, sizeof(double) * (size_t)n_traj * (size_t)n_objects);
+    free(q);
+    free(toff);
+    return ORC_OK;
+}
+
+/* Point-in-polygon test (crossing number) for a convex or concave polygon,
+ * the per-vertex test the paper runs in both directions (Sec. IV-C.1). Kept
+ * so the tests can compare it with the exact intersection used above. */
+int orc_point_in_polygon(double x, double y, int n, const double *vx, const double *vy)
+{
+    int inside = 0;
+    for (int k = 0, l = n - 1; k < n; l = k++) {
+        if (((vy[k] > y) != (vy[l] > y)) &&
+            (x < (vx[l] - vx[k]) * (y - vy[k]) / (vy[l] - vy[k]) + vx[k]))
+            inside = !inside;
+    }
+    return inside;
+}
+
+int orc_rect_corners(double x, double y, double psi, double L, double W, double *cx, double *cy)
+{
+    rect_corners(x, y, psi, L, W, cx, cy);
+    return ORC_OK;
+}

@@ -1,0 +1,240 @@
+"""Seeded synthetic traffic scenes.
+
+This module only draws inputs: initial states, control grids and trajectory
+scores. It holds none of the method's arithmetic (no trajectory integration,
+no overlap test, no probability), so both the GPU library's binding and the
+FP64 oracle can be fed from it without sharing code.
+
+Workloads (the paper's 20 designed scenarios and 547 recorded situations,
+Sec. VI-A, are not available; these seeded scenes stand in for them):
+
+* ``two_vehicle_scene``  2 vehicles, 5x5 grids, 30 steps of 0.1 s.
+* ``eleven_object_scene`` 6 vehicles + 5 pedestrians, 15x15 grids, 30 steps.
+* ``batch_scenes``       64 scenes of 3..24 objects, grid side 7..20, 20..50 steps.
+* ``stress_scene``       24 vehicles + 16 pedestrians, 32x32 grids, 50 steps.
+* ``paper_shaped_sizes`` the trajectory counts of Sec. IV-B.4 / Table I.
+
+Per object the draws happen in index order: x, y, heading, speed, then for
+vehicles a length factor and a width factor. Object 0 is the EGO vehicle and
+vehicles come before pedestrians.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+VEHICLE = 0
+PEDESTRIAN = 1
+PAIRS_ALL = 0
+PAIRS_EGO = 1
+
+
+@dataclasses.dataclass
+class SceneObject:
+    kind: int
+    x: float
+    y: float
+    heading: float
+    speed: float
+    length: float = 0.0   # full extent along the heading (vehicles)
+    width: float = 0.0    # full extent across the heading (vehicles)
+    radius: float = 0.0   # pedestrians
+    u: np.ndarray = None  # vehicles: accelerations; pedestrians: speeds
+    w: np.ndarray = None  # vehicles: yaw rates;     pedestrians: heading offsets
+    score: Optional[np.ndarray] = None  # n_u*n_w non-negative, index k*n_w+l
+
+    @property
+    def n_traj(self) -> int:
+        return int(len(self.u) * len(self.w))
+
+
+@dataclasses.dataclass
+class Scene:
+    objects: List[SceneObject]
+    horizon: int
+    dt: float
+    pairs: int = PAIRS_ALL
+
+    @property
+    def n_objects(self) -> int:
+        return len(self.objects)
+
+    def traj_counts(self) -> List[int]:
+        return [o.n_traj for o in self.objects]
+
+
+# --------------------------------------------------------------------------
+# Control grids
+# --------------------------------------------------------------------------
+
+def accel_grid(n: int, a_min: float = -8.0, a_max: float = 3.0) -> np.ndarray:
+    """Longitudinal samples following Sec. IV-B.2(a): the minimum, the maximum
+    and zero, with the remaining samples equally spaced in the negative range.
+    For n=5 on [-8, 3]: -8, -5.333, -2.667, 0, 3. Returned ascending."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    if n == 1:
+        return np.array([0.0])
+    if n == 2:
+        return np.array([a_min, a_max])
+    interior = [a_min * k / (n - 2) for k in range(n - 3, 0, -1)]
+    return np.array([a_min] + interior + [0.0, a_max], dtype=np.float64)
+
+
+def yaw_grid(n: int, limit: float = 0.5) -> np.ndarray:
+    return np.linspace(-limit, limit, n) if n > 1 else np.array([0.0])
+
+
+def ped_speed_grid(n: int, v_max: float = 2.5) -> np.ndarray:
+    return np.linspace(0.0, v_max, n) if n > 1 else np.array([0.0])
+
+
+def ped_heading_grid(n: int) -> np.ndarray:
+    """Heading offsets 2*pi*l/n relative to the measured heading; the paper's
+    0..360 degree range (Sec. IV-B.3) without the duplicated end point."""
+    return np.array([2.0 * math.pi * l / n for l in range(n)], dtype=np.float64)
+
+
+def _wrap(a: np.ndarray) -> np.ndarray:
+    return (a + math.pi) % (2.0 * math.pi) - math.pi
+
+
+def vehicle_scores(u: np.ndarray, w: np.ndarray) -> np.ndarray:
+    """Synthetic trajectory scores (the paper's weights are not published,
+    Sec. IV-D.1): w_acc = w_str = 0.5, c_com = c_cou = 1, and each factor falls
+    linearly from 1 to 0.1 with the magnitude of the control."""
+    au = np.abs(u)
+    aw = np.abs(w)
+    fu = 1.0 - 0.9 * au / au.max() if au.max() > 0 else np.ones_like(u)
+    fw = 1.0 - 0.9 * aw / aw.max() if aw.max() > 0 else np.ones_like(w)
+    return (0.5 * fu[:, None] + 0.5 * fw[None, :]).reshape(-1).astype(np.float64)
+
+
+def pedestrian_scores(s: np.ndarray, h: np.ndarray, v0: float) -> np.ndarray:
+    ds = np.abs(s - v0)
+    dh = np.abs(_wrap(h))
+    fs = 1.0 - 0.9 * ds / ds.max() if ds.max() > 0 else np.ones_like(s)
+    fh = 1.0 - 0.9 * dh / math.pi
+    return (0.5 * fs[:, None] + 0.5 * fh[None, :]).reshape(-1).astype(np.float64)
+
+
+# --------------------------------------------------------------------------
+# Objects
+# --------------------------------------------------------------------------
+
+def draw_vehicle(rng, xy_half: float, v_lo: float, v_hi: float, n_u: int, n_w: int,
+                 jitter: float = 0.1, base_len: float = 4.5, base_wid: float = 1.8) -> SceneObject:
+    x = float(rng.uniform(-xy_half, xy_half))
+    y = float(rng.uniform(-xy_half, xy_half))
+    heading = float(rng.uniform(0.0, 2.0 * math.pi))
+    speed = float(rng.uniform(v_lo, v_hi))
+    lf = float(rng.uniform(1.0 - jitter, 1.0 + jitter)) if jitter > 0 else 1.0
+    wf = float(rng.uniform(1.0 - jitter, 1.0 + jitter)) if jitter > 0 else 1.0
+    u = accel_grid(n_u)
+    w = yaw_grid(n_w)
+    return SceneObject(VEHICLE, x, y, heading, speed, base_len * lf, base_wid * wf, 0.0,
+                       u, w, vehicle_scores(u, w))
+
+
+def draw_pedestrian(rng, xy_half: float, v_lo: float, v_hi: float, n_u: int, n_w: int,
+                    radius: float = 0.3) -> SceneObject:
+    x = float(rng.uniform(-xy_half, xy_half))
+    y = float(rng.uniform(-xy_half, xy_half))
+    heading = float(rng.uniform(0.0, 2.0 * math.pi))
+    speed = float(rng.uniform(v_lo, v_hi))
+    u = ped_speed_grid(n_u)
+    w = ped_heading_grid(n_w)
+    return SceneObject(PEDESTRIAN, x, y, heading, speed, 0.0, 0.0, radius,
+                       u, w, pedestrian_scores(u, w, speed))
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+
+def two_vehicle_scene(seed: int) -> Scene:
+    """2 vehicles of 4.5 x 1.8 m, xy in U[-30,30]^2, speed U(5,15), 5x5 grids
+    (accelerations on [-8,3], yaw rates on [-0.5,0.5]), 30 steps of 0.1 s."""
+    rng = np.random.default_rng(seed)
+    objs = [draw_vehicle(rng, 30.0, 5.0, 15.0, 5, 5, jitter=0.0) for _ in range(2)]
+    return Scene(objs, 30, 0.1)
+
+
+def eleven_object_scene(seed: int, horizon: int = 30) -> Scene:
+    """6 vehicles (4.5 x 1.8 m +-10 %, speed U(0,20), 15x15 grids) and
+    5 pedestrians (r = 0.3 m, speed U(0,2), 15 speeds x 15 headings),
+    xy in U[-50,50]^2, 30 steps of 0.1 s: 83,531,250 pose-pair checks."""
+    rng = np.random.default_rng(seed)
+    objs = [draw_vehicle(rng, 50.0, 0.0, 20.0, 15, 15) for _ in range(6)]
+    objs += [draw_pedestrian(rng, 50.0, 0.0, 2.0, 15, 15) for _ in range(5)]
+    return Scene(objs, horizon, 0.1)
+
+
+def _batch_scene(rng) -> Scene:
+    n = int(rng.integers(3, 25))
+    n_v = (6 * n + 5) // 10          # round(0.6 n); never a tie
+    horizon = int(rng.integers(20, 51))
+    objs = []
+    for k in range(n):
+        s = int(rng.integers(7, 21))
+        if k < n_v:
+            objs.append(draw_vehicle(rng, 50.0, 0.0, 20.0, s, s))
+        else:
+            objs.append(draw_pedestrian(rng, 50.0, 0.0, 2.0, s, s))
+    return Scene(objs, horizon, 0.1)
+
+
+def batch_scenes(seed: int = 2, n: int = 64) -> List[Scene]:
+    """64 scenes from one RNG stream: object count U{3..24} with round(0.6 n)
+    vehicles, per-object grid side U{7..20} (same side on both axes), horizon
+    U{20..50} steps of 0.1 s, other fields as the 11-object scene."""
+    rng = np.random.default_rng(seed)
+    return [_batch_scene(rng) for _ in range(n)]
+
+
+def serving_schedule(seed: int = 3, streams: int = 32, rate_hz: float = 10.0,
+                     duration_s: float = 30.0, warmup_s: float = 2.0):
+    """Arrival schedule for the serving workload: each stream is a Poisson
+    process at ``rate_hz`` with a start offset U(0, 100 ms). Returns a list of
+    (arrival_time_s, stream_id, scene) sorted by time; frames are drawn as in
+    ``batch_scenes`` from the same RNG."""
+    rng = np.random.default_rng(seed)
+    events = []
+    for s in range(streams):
+        t = float(rng.uniform(0.0, 0.1))
+        while t < warmup_s + duration_s:
+            events.append((t, s))
+            t += float(rng.exponential(1.0 / rate_hz))
+    events.sort()
+    return [(t, s, _batch_scene(rng)) for (t, s) in events]
+
+
+def stress_scene(seed: int = 4) -> Scene:
+    """24 vehicles + 16 pedestrians, 32x32 grids (1024 trajectories each),
+    50 steps of 0.1 s, xy in U[-100,100]^2: 40,894,464,000 checks."""
+    rng = np.random.default_rng(seed)
+    objs = [draw_vehicle(rng, 100.0, 0.0, 20.0, 32, 32) for _ in range(24)]
+    objs += [draw_pedestrian(rng, 100.0, 0.0, 2.0, 32, 32) for _ in range(16)]
+    return Scene(objs, 50, 0.1)
+
+
+def stress_sample_pairs(n_objects: int = 40, k: int = 20, seed: int = 1004):
+    """The seeded sample of object pairs the oracle checks on the stress scene."""
+    pairs = [(a, b) for a in range(n_objects) for b in range(a + 1, n_objects)]
+    idx = np.random.default_rng(seed).choice(len(pairs), k, replace=False)
+    return [pairs[i] for i in sorted(idx)]
+
+
+def paper_shaped_sizes(n_co: int, n_acc: int = 6, ego_paths: int = 343, co_paths: int = 7):
+    """Trajectory counts of the paper's execution-time experiment (Sec. IV-B.4,
+    Sec. VI-B): EGO = n_acc * 7^3, each CO = n_acc * 7."""
+    return [n_acc * ego_paths] + [n_acc * co_paths] * n_co
+
+
+def uniform_scores(scene: Scene) -> Scene:
+    """Same scene with score arrays dropped (uniform probabilities)."""
+    objs = [dataclasses.replace(o, score=None) for o in scene.objects]
+    return Scene(objs, scene.horizon, scene.dt, scene.pairs)

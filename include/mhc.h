@@ -1,0 +1,212 @@
+/*
+ * mhc.h -- C ABI of the MI355X multi-hypothesis criticality library.
+ *
+ * The library evaluates the data-parallel core of the multi-hypothesis
+ * criticality method of Sanchez Morales et al., "Parallel Multi-Hypothesis
+ * Algorithm for Criticality Estimation in Traffic and Collision Avoidance"
+ * (IEEE IV 2019): it generates a grid of trajectory hypotheses per object
+ * (Sec. III, Sec. IV-B), tests every pair of predicted poses of every pair of
+ * objects at every time step for overlap (Sec. IV-C), keeps the earliest
+ * colliding step of each trajectory pair, and reduces those to a criticality
+ * per trajectory and per object (Sec. IV-D). A scene goes in, criticalities
+ * come out (the paper's input / output boxes of Fig. 1, Sec. V).
+ *
+ * Conventions shared by every entry point
+ *   - All functions return an mhc_status; negative values are errors and
+ *     mhc_last_error(ctx) then holds a message owned by the context, valid
+ *     until the next call on that context. No C++ exception crosses the ABI.
+ *   - Inputs are validated before anything is launched; on an error no output
+ *     buffer is written.
+ *   - The caller owns every buffer passed in. Scenes are copied during the
+ *     call (mhc_submit copies before it returns), so they may be freed after.
+ *   - A context is used by one thread at a time. Server calls (mhc_submit,
+ *     mhc_wait, mhc_server_stats) are thread-safe.
+ *   - Units are SI (m, s, rad); doubles in, doubles out. GPU arithmetic is
+ *     FP64 for trajectories and probabilities and FP32 for the overlap tests.
+ *   - Time slots: slot t in [0, horizon) is the pose predicted for time
+ *     (t+1)*dt; the measured state at time 0 is never tested.
+ */
+#ifndef MHC_H
+#define MHC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mhc_ctx mhc_ctx;
+typedef struct mhc_plan mhc_plan;
+typedef struct mhc_server mhc_server;
+
+typedef enum {
+    MHC_OK = 0,
+    MHC_E_INVAL = -1,    /* malformed input: nothing launched, outputs untouched */
+    MHC_E_NOMEM = -2,    /* host or device allocation failed / budget exceeded */
+    MHC_E_DEVICE = -3,   /* no usable GPU, or a HIP call failed */
+    MHC_E_BUSY = -4,     /* server queue full; retry later */
+    MHC_E_TIMEOUT = -5   /* mhc_wait timed out; the ticket stays valid */
+} mhc_status;
+
+enum { MHC_VEHICLE = 0, MHC_PEDESTRIAN = 1 };
+/* Pair set: every unordered object pair, or only pairs with the EGO vehicle
+ * (object 0) as in Sec. IV-C.1, where combinations between collision objects
+ * are left out. */
+enum { MHC_PAIRS_ALL = 0, MHC_PAIRS_EGO = 1 };
+
+/* One traffic participant. Vehicles are rectangles (length along the heading,
+ * width across it) moving on the kinematic special case of the Euler pose
+ * update of Sec. IV-B.1 (side slip 0) under a constant acceleration u[k] and
+ * yaw rate w[l]; the speed is clamped at 0. Pedestrians are circles of radius
+ * `radius` walking at constant speed u[k] along heading + w[l] (Sec. IV-B.3).
+ * Trajectory i = k*n_w + l. `score` holds n_u*n_w non-negative scores that are
+ * L1-normalised into probabilities (Sec. IV-D.1); NULL means uniform. */
+typedef struct {
+    int32_t kind;                 /* MHC_VEHICLE or MHC_PEDESTRIAN */
+    double x, y, heading, speed;  /* measured state at time 0; speed >= 0 */
+    double length, width;         /* vehicles: full extents > 0 (ignored for pedestrians) */
+    double radius;                /* pedestrians: > 0 (ignored for vehicles) */
+    int32_t n_u, n_w;             /* grid sizes, >= 1 each */
+    const double *u, *w;          /* n_u and n_w finite control values */
+    const double *score;          /* n_u*n_w scores or NULL */
+} mhc_object;
+
+typedef struct {
+    int32_t n_objects;            /* >= 2; object 0 is the EGO vehicle */
+    const mhc_object *objects;
+    int32_t horizon;              /* steps H, 1..32767 */
+    double dt;                    /* step length tau > 0 */
+    int32_t pairs;                /* MHC_PAIRS_ALL or MHC_PAIRS_EGO */
+} mhc_scene;
+
+typedef struct {
+    int64_t n_traj;               /* sum_a T_a */
+    int64_t n_pairs;              /* object pairs evaluated */
+    int64_t n_traj_pairs;         /* sum over pairs T_a*T_b (first-hit entries) */
+    int64_t n_checks;             /* n_traj_pairs * horizon pose-pair checks */
+    size_t device_bytes;          /* workspace bytes mhc_evaluate_async needs */
+} mhc_sizes;
+
+/* Outputs. Host pointers for mhc_evaluate / mhc_evaluate_batch / mhc_submit,
+ * device pointers for mhc_evaluate_async / mhc_plan_execute. Any pointer but
+ * object_crit may be NULL.
+ *   object_crit [n_objects]      C_a = sum_i p_{a,i} crit_{a,i}
+ *   traj_crit   [n_traj]         crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})
+ *   traj_prob   [n_traj]         p_{a,i}, the normalised scores
+ *   q           [n_traj*n_objects] q_{a,i;b} = sum_j [hit] p_{b,j}; 0 for b == a
+ *                                  and for pairs outside the pair set
+ *   first_hit   [n_traj_pairs]   per pair (a < b, lexicographic), entry i*T_b + j:
+ *                                  earliest colliding slot, or -1
+ * Trajectories of object a start at index sum_{c<a} T_c. With a single
+ * collision object C_0 equals the paper's p_cra double sum (Sec. IV-D); with
+ * several, the chronological scaling of Sec. IV-D.2 is applied, collision
+ * objects being independent and one object's trajectories exclusive. */
+typedef struct {
+    double *object_crit;
+    double *traj_crit;
+    double *traj_prob;
+    double *q;
+    int16_t *first_hit;
+} mhc_result;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Opens GPU `device` and reserves nothing yet. hbm_budget_bytes caps the
+ * device memory the context (and a server started on it) may hold; 0 means
+ * no cap. Returns MHC_E_DEVICE when no GPU is usable. */
+mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **out);
+void mhc_destroy(mhc_ctx *ctx);
+const char *mhc_last_error(const mhc_ctx *ctx);
+
+/* Host only (no GPU needed): validates `scene` and reports its sizes.
+ * The trajectory count corresponds to r_tra of Sec. IV-B.4 and n_traj_pairs to
+ * r_col of Sec. IV-C.2 in the EGO pair mode. */
+mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out);
+
+/* ---- plain single scene ------------------------------------------------ */
+
+/* Synchronous: host scene in, host results out. Runs ingest (validation,
+ * pair list, work list), trajectory generation, collision recognition and
+ * risk assessment (Fig. 1) and returns when the results are in `res`. */
+mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_result *res);
+
+/* Asynchronous on the caller's HIP stream (`hip_stream`, a hipStream_t; NULL
+ * is the null stream) with caller-owned device memory: `dev_workspace` of at
+ * least mhc_query_sizes().device_bytes bytes (256-byte aligned) and the device
+ * pointers in `dev_out`. The scene is validated and packed on the host and
+ * copied into the workspace by an asynchronous copy on that stream; nothing
+ * is freed or synchronised. The workspace and outputs must stay valid until
+ * the stream passes this work. */
+mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, void *dev_workspace,
+                              size_t workspace_bytes, const mhc_result *dev_out, void *hip_stream);
+
+/* ---- device-resident plan ---------------------------------------------- */
+
+/* Validates `scene`, builds its pair and work lists on the host and uploads
+ * the raw inputs (states, control grids, scores) to device memory owned by
+ * the plan. mhc_plan_execute then runs the whole device path -- probability
+ * normalisation, trajectory generation, collision recognition, risk -- on
+ * those resident inputs; it can be called any number of times.
+ * mhc_plan_update replaces the values of a scene with the same shape (object
+ * kinds, grid sizes, horizon, pair mode) without rebuilding the lists. */
+mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_plan **out);
+mhc_status mhc_plan_update(mhc_plan *plan, const mhc_scene *scene);
+/* Launches on `hip_stream`. Device pointers in `dev_out` (NULL entries are
+ * kept in plan-owned memory). */
+mhc_status mhc_plan_execute(mhc_plan *plan, const mhc_result *dev_out, void *hip_stream);
+/* Copies the plan-owned results of the last execute to host buffers (sync). */
+mhc_status mhc_plan_download(mhc_plan *plan, mhc_result *host_out);
+void mhc_plan_destroy(mhc_plan *plan);
+
+/* ---- batched ----------------------------------------------------------- */
+
+/* Evaluates n scenes of any shapes in one persistent collision launch inside a
+ * captured HIP graph (trajectory generation, collision recognition and risk
+ * for all scenes), then copies every result to res[k]. Results are identical
+ * to mhc_evaluate of each scene alone. */
+mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scene *scenes, mhc_result *res);
+
+/* ---- served (continuous batching) ------------------------------------- */
+
+typedef struct {
+    size_t hbm_budget_bytes;      /* device bytes the server may hold for frames; 0 = ctx budget or 1 GiB */
+    int32_t max_inflight_ticks;   /* ticks on the GPU at once (1..4; 0 = 2) */
+    int32_t queue_capacity;       /* frames waiting for admission (0 = 4096) */
+    int32_t max_frames_per_tick;  /* 0 = 256 */
+    int64_t max_checks_per_tick;  /* a tick closes when this many checks are admitted (0 = 4e9) */
+} mhc_server_cfg;
+
+typedef struct {
+    int64_t submit_ns, admit_ns, launch_ns, done_ns;  /* monotonic clock, ns */
+    int64_t tick;                 /* tick that carried the frame */
+} mhc_timing;
+
+typedef struct {
+    int64_t submitted, completed, rejected, deferred;  /* deferred = waited for budget */
+    int64_t ticks, checks;
+    double p50_ms, p99_ms, max_ms, mean_ms;            /* submit -> results in host memory */
+    double checks_per_s;          /* completed checks / wall time since start */
+} mhc_stats;
+
+/* Starts a scheduler thread. Frames submitted from any thread are admitted
+ * into the next GPU tick while their device memory fits the budget; ticks run
+ * on separate streams so that a new tick is built and launched while earlier
+ * ones are still on the GPU. */
+mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, mhc_server **out);
+/* Copies `scene` and queues it; `dst` (host buffers) receives the results and
+ * must stay valid until mhc_wait reports completion. MHC_E_BUSY when the queue
+ * is full, MHC_E_NOMEM when the frame can never fit the budget. */
+mhc_status mhc_submit(mhc_server *srv, int32_t stream_id, const mhc_scene *scene, mhc_result *dst,
+                      uint64_t *ticket);
+/* Waits up to timeout_us (< 0: forever) for `ticket`; fills `timing` if not
+ * NULL. A ticket can be waited on once successfully. */
+mhc_status mhc_wait(mhc_server *srv, uint64_t ticket, int64_t timeout_us, mhc_timing *timing);
+mhc_status mhc_server_stats(mhc_server *srv, mhc_stats *out);
+/* Drains in-flight ticks, completes queued frames, joins the thread, frees. */
+mhc_status mhc_server_stop(mhc_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHC_H */

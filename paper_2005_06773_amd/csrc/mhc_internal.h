@@ -1,0 +1,113 @@
+// Internal device-side layouts shared by the host runtime and the kernels.
+//
+// A packed "scene image" (built on the host during ingest, copied to HBM in
+// one transfer) holds these tables; the kernels read nothing else besides the
+// pose buffer they produce and the result buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mhc {
+
+enum Kind : int32_t { KIND_VEHICLE = 0, KIND_PEDESTRIAN = 1 };
+
+// Shape class of an object pair: which overlap test applies and which side
+// holds the rectangle.
+enum PairClass : int32_t { CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, N_CLS = 4 };
+
+// One object of one scene. Offsets are global across all scenes of a launch.
+struct DObj {
+    int32_t kind, n_u, n_w, T;
+    int32_t has_score, H;
+    int32_t local, n_scene_obj;   // index within its scene, object count of the scene
+    int64_t traj_off;             // index of trajectory 0 in the p / traj_crit arrays
+    int64_t q_row;                // q index of (this object, i = 0, b = 0)
+    int64_t pose_off;             // byte offset of the pose block [H][T]
+    int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
+    int64_t pairmap_off;          // int32 [n_scene_obj] row of the scene's pair map
+    int64_t obj_out;              // index in the object_crit array
+    double x, y, heading, speed;
+    double tau;
+};
+
+// One object pair (a < b within its scene). The collision kernel covers the
+// T_a x T_b trajectory pairs as a flat list of n_ig * n_jg "items": item f is
+// the micro-tile ig = f / n_jg, jg = f % n_jg, holding trajectories
+// i = ig + r*n_ig (r < RI) and j = jg + s*n_jg (s < RJ).
+struct DPair {
+    int32_t a, b;                 // global object indices
+    int32_t cls, H;
+    int32_t Ta, Tb;
+    int32_t n_ig, n_jg;
+    int64_t hit_off;              // first-hit entry of (i = 0, j = 0)
+    int64_t pose_a, pose_b;       // byte offsets of the two pose blocks
+    float la, wa, lb, wb;         // half length / half width of vehicles
+    float rr;                     // squared test radius: r_Q^2 (rect-circle), (r_P + r_Q)^2 (circle-circle)
+    float pad0;
+};
+
+// One workgroup of the collision kernel: WG_ITEMS consecutive items of a pair.
+struct WorkItem {
+    int32_t pair;
+    int32_t item0;
+};
+
+// One workgroup of the trajectory kernel.
+struct K1Block {
+    int32_t obj;
+    int32_t i0;
+};
+
+// One workgroup of the q-sum kernel: 4 rows (one per wave) or 256 columns.
+struct K3Item {
+    int32_t pair;
+    int32_t kind;                 // 0 rows (q of a against b), 1 columns (q of b against a)
+    int32_t start;
+    int32_t pad;
+};
+
+constexpr int WG = 256;           // threads per workgroup, all kernels
+constexpr int WG_ITEMS = 256;     // collision items per workgroup
+constexpr int K1_VT = 16;         // vehicle trajectories per trajectory workgroup
+constexpr int K1_PT = 256;        // pedestrian trajectories per trajectory workgroup
+constexpr int K1_CH = 32;         // steps per trigonometry chunk
+constexpr int K3_ROWS = 4;        // rows per q-sum workgroup (one wave each)
+
+// Micro-tile shape per class, selected by a kernel variant id.
+struct TileShape {
+    int ri, rj;
+};
+constexpr int N_VARIANTS = 4;
+// variant -> shape per class {VV, VP, PV, PP}
+constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {
+    {{2, 2}, {2, 2}, {2, 2}, {2, 2}},
+    {{4, 1}, {4, 1}, {4, 1}, {4, 2}},
+    {{2, 4}, {2, 4}, {4, 2}, {4, 4}},
+    {{4, 2}, {4, 2}, {2, 4}, {4, 4}},
+};
+
+// Launch entry points (kernels.hip).
+struct Launch {
+    const DObj *objs;
+    const double *vals;
+    const DPair *pairs;
+    const WorkItem *work;
+    const K1Block *k1;
+    const K3Item *k3;
+    const int32_t *pairmap;
+    char *poses;
+    double *p;
+    int16_t *hits;
+    double *q;
+    double *traj_crit;
+    double *obj_crit;
+    int n_obj, n_pairs, n_work, n_k1, n_k3;
+    int variant;
+};
+
+hipError_t launch_trajgen(const Launch &L, hipStream_t s);
+hipError_t launch_collide(const Launch &L, hipStream_t s);
+hipError_t launch_risk(const Launch &L, hipStream_t s);
+
+}  // namespace mhc

@@ -1,0 +1,625 @@
+// Host runtime behind the C ABI: scene ingest (validation, pair list, work
+// list), packing of the scene image, device memory, launches, and the plain,
+// asynchronous, plan and batched entry points.
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace mhc {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int cls_of(int ka, int kb)
+{
+    if (ka == KIND_VEHICLE && kb == KIND_VEHICLE) return CLS_VV;
+    if (ka == KIND_VEHICLE) return CLS_VP;
+    if (kb == KIND_VEHICLE) return CLS_PV;
+    return CLS_PP;
+}
+
+// Relative VALU cost of one check per class, for longest-first ordering.
+static const double kClsCost[N_CLS] = {27.0, 14.0, 14.0, 6.0};
+
+static bool finite(double v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------------------
+// Ingest: validation. Every rule here is checked before anything is launched.
+// ---------------------------------------------------------------------------
+bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
+{
+    char buf[256];
+    auto fail = [&](const char *fmt, int a) {
+        if (scene_index >= 0) {
+            char b2[200];
+            snprintf(b2, sizeof b2, fmt, a);
+            snprintf(buf, sizeof buf, "scene %d: %s", scene_index, b2);
+        } else {
+            snprintf(buf, sizeof buf, fmt, a);
+        }
+        err = buf;
+        return false;
+    };
+    if (!s) return fail("scene is NULL%.0d", 0);
+    if (s->n_objects < 2) return fail("n_objects must be >= 2 (got %d)", s->n_objects);
+    if (s->n_objects > kMaxObjects) return fail("n_objects must be <= %d", kMaxObjects);
+    if (!s->objects) return fail("objects is NULL%.0d", 0);
+    if (s->horizon < 1 || s->horizon > 32767) return fail("horizon must be in [1, 32767] (got %d)", s->horizon);
+    if (!finite(s->dt) || !(s->dt > 0.0)) return fail("dt must be finite and > 0%.0d", 0);
+    if (s->pairs != MHC_PAIRS_ALL && s->pairs != MHC_PAIRS_EGO) return fail("pairs must be 0 or 1 (got %d)", s->pairs);
+    for (int a = 0; a < s->n_objects; ++a) {
+        const mhc_object &o = s->objects[a];
+        if (o.kind != MHC_VEHICLE && o.kind != MHC_PEDESTRIAN) return fail("object %d: kind must be 0 or 1", a);
+        if (!finite(o.x) || !finite(o.y) || !finite(o.heading) || !finite(o.speed))
+            return fail("object %d: state must be finite", a);
+        if (!(o.speed >= 0.0)) return fail("object %d: speed must be >= 0", a);
+        if (o.kind == MHC_VEHICLE) {
+            if (!finite(o.length) || !(o.length > 0.0) || !finite(o.width) || !(o.width > 0.0))
+                return fail("object %d: vehicle length and width must be finite and > 0", a);
+        } else {
+            if (!finite(o.radius) || !(o.radius > 0.0)) return fail("object %d: pedestrian radius must be finite and > 0", a);
+        }
+        if (o.n_u < 1 || o.n_w < 1) return fail("object %d: n_u and n_w must be >= 1", a);
+        if ((int64_t)o.n_u * o.n_w > kMaxTraj) return fail("object %d: n_u*n_w exceeds the trajectory limit", a);
+        if (!o.u || !o.w) return fail("object %d: control grids u and w must not be NULL", a);
+        for (int k = 0; k < o.n_u; ++k)
+            if (!finite(o.u[k])) return fail("object %d: control grid u must be finite", a);
+        for (int k = 0; k < o.n_w; ++k)
+            if (!finite(o.w[k])) return fail("object %d: control grid w must be finite", a);
+        if (o.score) {
+            double l1 = 0.0;
+            const int T = o.n_u * o.n_w;
+            for (int k = 0; k < T; ++k) {
+                if (!finite(o.score[k]) || !(o.score[k] >= 0.0)) return fail("object %d: scores must be finite and >= 0", a);
+                l1 += o.score[k];
+            }
+            if (!(l1 > 0.0) || !finite(l1)) return fail("object %d: scores must have a positive finite sum", a);
+        }
+    }
+    if (s->objects[0].kind != MHC_VEHICLE && s->pairs == MHC_PAIRS_EGO)
+        return fail("EGO pair mode needs object 0 to be a vehicle%.0d", 0);
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Ingest: pair list, work list and the packed scene image.
+// ---------------------------------------------------------------------------
+static void pair_list(const mhc_scene *s, std::vector<std::pair<int, int>> &out)
+{
+    out.clear();
+    for (int a = 0; a < s->n_objects; ++a)
+        for (int b = a + 1; b < s->n_objects; ++b)
+            if (s->pairs == MHC_PAIRS_ALL || a == 0) out.emplace_back(a, b);
+}
+
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
+{
+    L = Layout();
+    L.variant = variant;
+    struct Cost {
+        double c;
+        size_t idx;
+    };
+    std::vector<Cost> costs;
+    std::vector<WorkItem> work;
+    std::vector<std::pair<int, int>> plist;
+    for (int k = 0; k < n_scenes; ++k) {
+        const mhc_scene &s = scenes[k];
+        const int n = s.n_objects;
+        SceneExt ext{};
+        ext.n_obj = n;
+        ext.H = s.horizon;
+        ext.obj0 = L.n_obj;
+        ext.traj0 = L.n_traj;
+        ext.hit0 = L.n_hits;
+        ext.q0 = L.n_q;
+        const int obj_base = (int)L.objs.size();
+        const int64_t pm_base = (int64_t)L.pairmap.size();
+        L.pairmap.resize(L.pairmap.size() + (size_t)n * n, -1);
+        int64_t toff = 0;
+        for (int a = 0; a < n; ++a) {
+            const mhc_object &o = s.objects[a];
+            DObj d{};
+            d.kind = o.kind;
+            d.n_u = o.n_u;
+            d.n_w = o.n_w;
+            d.T = o.n_u * o.n_w;
+            d.has_score = o.score != nullptr;
+            d.H = s.horizon;
+            d.local = a;
+            d.n_scene_obj = n;
+            d.traj_off = L.n_traj + toff;
+            d.q_row = L.n_q + toff * n;
+            d.pose_off = (int64_t)L.pose_bytes;
+            L.pose_bytes += align256((size_t)s.horizon * d.T * (o.kind == MHC_VEHICLE ? 16 : 8));
+            d.u_off = (int64_t)L.vals.size();
+            L.vals.insert(L.vals.end(), o.u, o.u + o.n_u);
+            d.w_off = (int64_t)L.vals.size();
+            L.vals.insert(L.vals.end(), o.w, o.w + o.n_w);
+            d.score_off = (int64_t)L.vals.size();
+            if (o.score) L.vals.insert(L.vals.end(), o.score, o.score + d.T);
+            d.pairmap_off = pm_base + (int64_t)a * n;
+            d.obj_out = L.n_obj + a;
+            d.x = o.x;
+            d.y = o.y;
+            d.heading = o.heading;
+            d.speed = o.speed;
+            d.tau = s.dt;
+            L.objs.push_back(d);
+            const int step = o.kind == MHC_VEHICLE ? K1_VT : K1_PT;
+            for (int i0 = 0; i0 < d.T; i0 += step) L.k1.push_back(K1Block{obj_base + a, i0});
+            toff += d.T;
+        }
+        pair_list(&s, plist);
+        int64_t hoff = 0;
+        for (auto &ab : plist) {
+            const int a = ab.first, b = ab.second;
+            const mhc_object &oa = s.objects[a], &ob = s.objects[b];
+            DPair pr{};
+            pr.a = obj_base + a;
+            pr.b = obj_base + b;
+            pr.cls = cls_of(oa.kind, ob.kind);
+            pr.H = s.horizon;
+            pr.Ta = oa.n_u * oa.n_w;
+            pr.Tb = ob.n_u * ob.n_w;
+            const TileShape ts = kTiles[variant][pr.cls];
+            pr.n_ig = (pr.Ta + ts.ri - 1) / ts.ri;
+            pr.n_jg = (pr.Tb + ts.rj - 1) / ts.rj;
+            pr.hit_off = L.n_hits + hoff;
+            pr.pose_a = L.objs[obj_base + a].pose_off;
+            pr.pose_b = L.objs[obj_base + b].pose_off;
+            pr.la = (float)(oa.length / 2.0);
+            pr.wa = (float)(oa.width / 2.0);
+            pr.lb = (float)(ob.length / 2.0);
+            pr.wb = (float)(ob.width / 2.0);
+            if (pr.cls == CLS_VP) pr.rr = (float)(ob.radius * ob.radius);
+            else if (pr.cls == CLS_PV) pr.rr = (float)(oa.radius * oa.radius);
+            else if (pr.cls == CLS_PP) pr.rr = (float)((oa.radius + ob.radius) * (oa.radius + ob.radius));
+            const int pidx = (int)L.pairs.size();
+            L.pairs.push_back(pr);
+            L.pairmap[pm_base + (int64_t)a * n + b] = pidx;
+            L.pairmap[pm_base + (int64_t)b * n + a] = pidx;
+            const int64_t items = (int64_t)pr.n_ig * pr.n_jg;
+            for (int64_t i0 = 0; i0 < items; i0 += WG_ITEMS) {
+                const int64_t cnt = std::min<int64_t>(WG_ITEMS, items - i0);
+                costs.push_back(Cost{(double)cnt * ts.ri * ts.rj * pr.H * kClsCost[pr.cls], work.size()});
+                work.push_back(WorkItem{pidx, (int32_t)i0});
+            }
+            for (int i0 = 0; i0 < pr.Ta; i0 += K3_ROWS) L.k3.push_back(K3Item{pidx, 0, i0, 0});
+            for (int j0 = 0; j0 < pr.Tb; j0 += WG) L.k3.push_back(K3Item{pidx, 1, j0, 0});
+            hoff += (int64_t)pr.Ta * pr.Tb;
+            ext.checks += (int64_t)pr.Ta * pr.Tb * s.horizon;
+        }
+        ext.n_traj = toff;
+        ext.n_hits = hoff;
+        ext.n_pairs = (int64_t)plist.size();
+        L.sc.push_back(ext);
+        L.n_traj += toff;
+        L.n_hits += hoff;
+        L.n_q += toff * n;
+        L.n_obj += n;
+        L.n_checks += ext.checks;
+    }
+    // Longest work first, so that the ragged end of the launch is made of the
+    // cheapest workgroups; ties keep list order.
+    std::stable_sort(costs.begin(), costs.end(), [](const Cost &x, const Cost &y) { return x.c > y.c; });
+    L.work.resize(work.size());
+    for (size_t k = 0; k < costs.size(); ++k) L.work[k] = work[costs[k].idx];
+
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.o_objs = put(L.objs.size() * sizeof(DObj));
+    L.o_vals = put(L.vals.size() * sizeof(double));
+    L.o_pairs = put(L.pairs.size() * sizeof(DPair));
+    L.o_work = put(L.work.size() * sizeof(WorkItem));
+    L.o_k1 = put(L.k1.size() * sizeof(K1Block));
+    L.o_k3 = put(L.k3.size() * sizeof(K3Item));
+    L.o_pairmap = put(L.pairmap.size() * sizeof(int32_t));
+    L.image_bytes = off;
+    L.o_poses = put(L.pose_bytes);
+    L.o_p = put((size_t)L.n_traj * sizeof(double));
+    L.o_hits = put((size_t)L.n_hits * sizeof(int16_t));
+    L.o_q = put((size_t)L.n_q * sizeof(double));
+    L.o_tc = put((size_t)L.n_traj * sizeof(double));
+    L.o_oc = put((size_t)L.n_obj * sizeof(double));
+    L.total_bytes = off;
+}
+
+void pack_image(const Layout &L, char *dst)
+{
+    std::memset(dst, 0, L.image_bytes);
+    auto cp = [&](size_t o, const void *src, size_t bytes) {
+        if (bytes) std::memcpy(dst + o, src, bytes);
+    };
+    cp(L.o_objs, L.objs.data(), L.objs.size() * sizeof(DObj));
+    cp(L.o_vals, L.vals.data(), L.vals.size() * sizeof(double));
+    cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair));
+    cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem));
+    cp(L.o_k1, L.k1.data(), L.k1.size() * sizeof(K1Block));
+    cp(L.o_k3, L.k3.data(), L.k3.size() * sizeof(K3Item));
+    cp(L.o_pairmap, L.pairmap.data(), L.pairmap.size() * sizeof(int32_t));
+}
+
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out)
+{
+    Launch X{};
+    X.objs = reinterpret_cast<const DObj *>(base + L.o_objs);
+    X.vals = reinterpret_cast<const double *>(base + L.o_vals);
+    X.pairs = reinterpret_cast<const DPair *>(base + L.o_pairs);
+    X.work = reinterpret_cast<const WorkItem *>(base + L.o_work);
+    X.k1 = reinterpret_cast<const K1Block *>(base + L.o_k1);
+    X.k3 = reinterpret_cast<const K3Item *>(base + L.o_k3);
+    X.pairmap = reinterpret_cast<const int32_t *>(base + L.o_pairmap);
+    X.poses = base + L.o_poses;
+    X.p = reinterpret_cast<double *>(base + L.o_p);
+    X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
+    X.q = reinterpret_cast<double *>(base + L.o_q);
+    X.traj_crit = reinterpret_cast<double *>(base + L.o_tc);
+    X.obj_crit = reinterpret_cast<double *>(base + L.o_oc);
+    if (dev_out) {
+        if (dev_out->traj_prob) X.p = dev_out->traj_prob;
+        if (dev_out->first_hit) X.hits = dev_out->first_hit;
+        if (dev_out->q) X.q = dev_out->q;
+        if (dev_out->traj_crit) X.traj_crit = dev_out->traj_crit;
+        if (dev_out->object_crit) X.obj_crit = dev_out->object_crit;
+    }
+    X.n_obj = (int)L.objs.size();
+    X.n_pairs = (int)L.pairs.size();
+    X.n_work = (int)L.work.size();
+    X.n_k1 = (int)L.k1.size();
+    X.n_k3 = (int)L.k3.size();
+    X.variant = L.variant;
+    return X;
+}
+
+hipError_t launch_all(const Launch &X, hipStream_t s)
+{
+    hipError_t e = launch_trajgen(X, s);
+    if (e == hipSuccess) e = launch_collide(X, s);
+    if (e == hipSuccess) e = launch_risk(X, s);
+    return e;
+}
+
+}  // namespace mhc
+
+using namespace mhc;
+
+// ===========================================================================
+// Context
+// ===========================================================================
+
+static mhc_status dev_err(mhc_ctx *ctx, hipError_t e, const char *what)
+{
+    if (ctx) ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return MHC_E_DEVICE;
+}
+
+#define HIPC(call)                                          \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return dev_err(ctx, e_, #call); \
+    } while (0)
+
+extern "C" mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **out)
+{
+    if (!out) return MHC_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return MHC_E_DEVICE;
+    if (device < 0 || device >= n) return MHC_E_INVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return MHC_E_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return MHC_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return MHC_E_DEVICE;
+    mhc_ctx *ctx = new mhc_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return MHC_E_DEVICE;
+    }
+    *out = ctx;
+    return MHC_OK;
+}
+
+extern "C" void mhc_destroy(mhc_ctx *ctx)
+{
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    hipEventSynchronize(ctx->staging_ev);
+    if (ctx->dbuf) hipFree(ctx->dbuf);
+    if (ctx->staging) hipHostFree(ctx->staging);
+    hipEventDestroy(ctx->staging_ev);
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+extern "C" const char *mhc_last_error(const mhc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
+{
+    if (!out) return MHC_E_INVAL;
+    std::string err;
+    if (!validate_scene(scene, err)) return MHC_E_INVAL;
+    Layout L;
+    build_layout(scene, 1, kDefaultVariant, L);
+    out->n_traj = L.n_traj;
+    out->n_pairs = (int64_t)L.pairs.size();
+    out->n_traj_pairs = L.n_hits;
+    out->n_checks = L.n_checks;
+    out->device_bytes = L.total_bytes;
+    return MHC_OK;
+}
+
+// Pinned staging for the scene image. The previous upload from it must have
+// left the host buffer before it is rewritten.
+static mhc_status stage_image(mhc_ctx *ctx, const Layout &L, char **host)
+{
+    HIPC(hipEventSynchronize(ctx->staging_ev));
+    if (ctx->staging_bytes < L.image_bytes) {
+        if (ctx->staging) HIPC(hipHostFree(ctx->staging));
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        size_t want = std::max<size_t>(L.image_bytes, 1 << 20);
+        HIPC(hipHostMalloc(reinterpret_cast<void **>(&ctx->staging), want, hipHostMallocDefault));
+        ctx->staging_bytes = want;
+    }
+    pack_image(L, ctx->staging);
+    *host = ctx->staging;
+    return MHC_OK;
+}
+
+mhc_status ensure_device(mhc_ctx *ctx, size_t bytes)
+{
+    if (ctx->budget && bytes > ctx->budget) {
+        ctx->err = "scene needs " + std::to_string(bytes) + " device bytes, above the context budget";
+        return MHC_E_NOMEM;
+    }
+    if (ctx->dbuf_bytes >= bytes) return MHC_OK;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    if (ctx->dbuf) HIPC(hipFree(ctx->dbuf));
+    ctx->dbuf = nullptr;
+    ctx->dbuf_bytes = 0;
+    size_t want = align256(bytes + bytes / 4);
+    if (ctx->budget) want = std::min(want, ctx->budget);
+    hipError_t e = hipMalloc(&ctx->dbuf, want);
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipMalloc of the context workspace failed: ") + hipGetErrorString(e);
+        return MHC_E_NOMEM;
+    }
+    ctx->dbuf_bytes = want;
+    return MHC_OK;
+}
+
+static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, const mhc_result *dev_out,
+                                    hipStream_t s)
+{
+    char *host = nullptr;
+    mhc_status st = stage_image(ctx, L, &host);
+    if (st != MHC_OK) return st;
+    HIPC(hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, s));
+    HIPC(hipEventRecord(ctx->staging_ev, s));
+    Launch X = make_launch(L, dbase, dev_out);
+    HIPC(launch_all(X, s));
+    return MHC_OK;
+}
+
+mhc_status copy_results(mhc_ctx *ctx, const Layout &L, int k, const char *dbase, const mhc_result *res,
+                        hipStream_t s)
+{
+    const SceneExt &e = L.sc[k];
+    auto d2h = [&](void *dst, size_t off, size_t bytes) -> hipError_t {
+        if (!dst || !bytes) return hipSuccess;
+        return hipMemcpyAsync(dst, dbase + off, bytes, hipMemcpyDeviceToHost, s);
+    };
+    HIPC(d2h(res->object_crit, L.o_oc + e.obj0 * sizeof(double), e.n_obj * sizeof(double)));
+    HIPC(d2h(res->traj_crit, L.o_tc + e.traj0 * sizeof(double), e.n_traj * sizeof(double)));
+    HIPC(d2h(res->traj_prob, L.o_p + e.traj0 * sizeof(double), e.n_traj * sizeof(double)));
+    HIPC(d2h(res->q, L.o_q + e.q0 * sizeof(double), (size_t)e.n_traj * e.n_obj * sizeof(double)));
+    HIPC(d2h(res->first_hit, L.o_hits + e.hit0 * sizeof(int16_t), e.n_hits * sizeof(int16_t)));
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_result *res)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (!res || !res->object_crit) {
+        ctx->err = "result and result->object_crit must not be NULL";
+        return MHC_E_INVAL;
+    }
+    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    HIPC(hipSetDevice(ctx->device));
+    Layout &L = ctx->layout;
+    build_layout(scene, 1, ctx->variant_for(scene), L);
+    mhc_status st = ensure_device(ctx, L.total_bytes);
+    if (st != MHC_OK) return st;
+    char *dbase = static_cast<char *>(ctx->dbuf);
+    st = upload_and_launch(ctx, L, dbase, nullptr, ctx->stream);
+    if (st != MHC_OK) return st;
+    st = copy_results(ctx, L, 0, dbase, res, ctx->stream);
+    if (st != MHC_OK) return st;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, void *dev_workspace,
+                                         size_t workspace_bytes, const mhc_result *dev_out, void *hip_stream)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (!dev_out || !dev_out->object_crit || !dev_workspace) {
+        ctx->err = "dev_workspace, dev_out and dev_out->object_crit must not be NULL";
+        return MHC_E_INVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256 != 0) {
+        ctx->err = "dev_workspace must be 256-byte aligned";
+        return MHC_E_INVAL;
+    }
+    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    Layout L;
+    build_layout(scene, 1, ctx->variant_for(scene), L);
+    if (workspace_bytes < L.total_bytes) {
+        ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
+        return MHC_E_INVAL;
+    }
+    HIPC(hipSetDevice(ctx->device));
+    return upload_and_launch(ctx, L, static_cast<char *>(dev_workspace), dev_out,
+                             static_cast<hipStream_t>(hip_stream));
+}
+
+// ===========================================================================
+// Plans: inputs resident in device memory, launched repeatedly.
+// ===========================================================================
+
+struct mhc_plan {
+    mhc_ctx *ctx = nullptr;
+    Layout L;
+    char *dbuf = nullptr;
+    std::vector<int32_t> shape;   // kinds, grid sizes, horizon, pair mode
+};
+
+static std::vector<int32_t> shape_of(const mhc_scene *s)
+{
+    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs};
+    for (int a = 0; a < s->n_objects; ++a) {
+        v.push_back(s->objects[a].kind);
+        v.push_back(s->objects[a].n_u);
+        v.push_back(s->objects[a].n_w);
+        v.push_back(s->objects[a].score != nullptr);
+    }
+    return v;
+}
+
+extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_plan **out)
+{
+    if (!ctx || !out) return MHC_E_INVAL;
+    *out = nullptr;
+    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    HIPC(hipSetDevice(ctx->device));
+    mhc_plan *pl = new mhc_plan();
+    pl->ctx = ctx;
+    build_layout(scene, 1, ctx->variant_for(scene), pl->L);
+    pl->shape = shape_of(scene);
+    if (ctx->budget && pl->L.total_bytes > ctx->budget) {
+        ctx->err = "plan needs more device memory than the context budget";
+        delete pl;
+        return MHC_E_NOMEM;
+    }
+    if (hipMalloc(reinterpret_cast<void **>(&pl->dbuf), pl->L.total_bytes) != hipSuccess) {
+        ctx->err = "hipMalloc for the plan failed";
+        delete pl;
+        return MHC_E_NOMEM;
+    }
+    std::vector<char> img(pl->L.image_bytes);
+    pack_image(pl->L, img.data());
+    hipError_t e = hipMemcpy(pl->dbuf, img.data(), pl->L.image_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(pl->dbuf);
+        delete pl;
+        return dev_err(ctx, e, "plan upload");
+    }
+    *out = pl;
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
+{
+    if (!pl) return MHC_E_INVAL;
+    mhc_ctx *ctx = pl->ctx;
+    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    if (shape_of(scene) != pl->shape) {
+        ctx->err = "mhc_plan_update: scene shape differs from the plan";
+        return MHC_E_INVAL;
+    }
+    HIPC(hipSetDevice(ctx->device));
+    Layout L;
+    build_layout(scene, 1, pl->L.variant, L);
+    std::vector<char> img(L.image_bytes);
+    pack_image(L, img.data());
+    HIPC(hipDeviceSynchronize());
+    HIPC(hipMemcpy(pl->dbuf, img.data(), L.image_bytes, hipMemcpyHostToDevice));
+    pl->L = std::move(L);
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, void *hip_stream)
+{
+    if (!pl) return MHC_E_INVAL;
+    mhc_ctx *ctx = pl->ctx;
+    HIPC(hipSetDevice(ctx->device));
+    Launch X = make_launch(pl->L, pl->dbuf, dev_out);
+    HIPC(launch_all(X, static_cast<hipStream_t>(hip_stream)));
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_plan_download(mhc_plan *pl, mhc_result *host_out)
+{
+    if (!pl || !host_out) return MHC_E_INVAL;
+    mhc_ctx *ctx = pl->ctx;
+    HIPC(hipSetDevice(ctx->device));
+    HIPC(hipDeviceSynchronize());
+    mhc_status st = copy_results(ctx, pl->L, 0, pl->dbuf, host_out, ctx->stream);
+    if (st != MHC_OK) return st;
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return MHC_OK;
+}
+
+extern "C" void mhc_plan_destroy(mhc_plan *pl)
+{
+    if (!pl) return;
+    hipSetDevice(pl->ctx->device);
+    hipDeviceSynchronize();
+    if (pl->dbuf) hipFree(pl->dbuf);
+    delete pl;
+}
+
+// ===========================================================================
+// Batched
+// ===========================================================================
+
+extern "C" mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scene *scenes, mhc_result *res)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (n < 1 || !scenes || !res) {
+        ctx->err = "batch needs n >= 1, scenes and results";
+        return MHC_E_INVAL;
+    }
+    for (int k = 0; k < n; ++k) {
+        if (!validate_scene(&scenes[k], ctx->err, k)) return MHC_E_INVAL;
+        if (!res[k].object_crit) {
+            ctx->err = "result " + std::to_string(k) + ": object_crit must not be NULL";
+            return MHC_E_INVAL;
+        }
+    }
+    HIPC(hipSetDevice(ctx->device));
+    return batch_run(ctx, n, scenes, res);
+}
+
+// Batched form: all scenes share one scene image, one trajectory launch, one
+// collision launch over a longest-first work list and one risk launch.
+mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *res)
+{
+    Layout &L = ctx->layout;
+    build_layout(scenes, n, ctx->variant, L);
+    mhc_status st = ensure_device(ctx, L.total_bytes);
+    if (st != MHC_OK) return st;
+    char *dbase = static_cast<char *>(ctx->dbuf);
+    st = upload_and_launch(ctx, L, dbase, nullptr, ctx->stream);
+    if (st != MHC_OK) return st;
+    for (int k = 0; k < n; ++k) {
+        st = copy_results(ctx, L, k, dbase, &res[k], ctx->stream);
+        if (st != MHC_OK) return st;
+    }
+    HIPC(hipStreamSynchronize(ctx->stream));
+    return MHC_OK;
+}

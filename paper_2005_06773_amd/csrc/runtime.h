@@ -1,0 +1,68 @@
+// Host-side runtime structures (not part of the public ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "mhc.h"
+#include "mhc_internal.h"
+
+namespace mhc {
+
+constexpr int kMaxObjects = 4096;
+constexpr int64_t kMaxTraj = 1 << 15;     // trajectories per object (T_a*T_b < 2^31)
+constexpr int kDefaultVariant = 0;
+
+// Result extents of one scene inside a (possibly multi-scene) layout.
+struct SceneExt {
+    int n_obj = 0, H = 0;
+    int64_t obj0 = 0, traj0 = 0, n_traj = 0, hit0 = 0, n_hits = 0, q0 = 0;
+    int64_t n_pairs = 0, checks = 0;
+};
+
+// Host tables of one launch plus the byte layout of its device workspace:
+// [scene image: tables uploaded in one copy][poses][p][first hits][q][traj crit][object crit]
+struct Layout {
+    std::vector<DObj> objs;
+    std::vector<double> vals;
+    std::vector<DPair> pairs;
+    std::vector<WorkItem> work;
+    std::vector<K1Block> k1;
+    std::vector<K3Item> k3;
+    std::vector<int32_t> pairmap;
+    std::vector<SceneExt> sc;
+    int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
+    size_t pose_bytes = 0;
+    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
+    size_t o_poses = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
+    int variant = 0;
+};
+
+bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L);
+void pack_image(const Layout &L, char *dst);
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out);
+hipError_t launch_all(const Launch &X, hipStream_t s);
+
+}  // namespace mhc
+
+struct mhc_ctx {
+    int device = 0;
+    int n_cu = 0;
+    size_t budget = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void *dbuf = nullptr;         // workspace of the synchronous entry points
+    size_t dbuf_bytes = 0;
+    char *staging = nullptr;      // pinned host copy of the last scene image
+    size_t staging_bytes = 0;
+    hipEvent_t staging_ev = nullptr;
+    mhc::Layout layout;           // reused by mhc_evaluate
+    int variant = mhc::kDefaultVariant;
+    int variant_for(const mhc_scene *) const { return variant; }
+};
+
+mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);
+mhc_status copy_results(mhc_ctx *ctx, const mhc::Layout &L, int k, const char *dbase, const mhc_result *res,
+                        hipStream_t s);
+mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *res);

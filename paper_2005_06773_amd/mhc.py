@@ -1,0 +1,343 @@
+"""ctypes binding of ``libmhc.so`` (argument marshalling only).
+
+Every function here has the name of the C entry point it wraps (declared in
+``include/mhc.h``) and does no arithmetic of the method: the whole path runs
+in the library's HIP kernels. Importing this module loads the library and
+fails loudly when it has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmhc.so")
+
+MHC_OK = 0
+MHC_E_INVAL = -1
+MHC_E_NOMEM = -2
+MHC_E_DEVICE = -3
+MHC_E_BUSY = -4
+MHC_E_TIMEOUT = -5
+_STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE",
+           -4: "MHC_E_BUSY", -5: "MHC_E_TIMEOUT"}
+
+EXPORTED = [
+    "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes",
+    "mhc_evaluate", "mhc_evaluate_async",
+    "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_download", "mhc_plan_destroy",
+    "mhc_evaluate_batch",
+    "mhc_server_start", "mhc_submit", "mhc_wait", "mhc_server_stats", "mhc_server_stop",
+]
+
+
+class MhcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# ---------------------------------------------------------------------------
+# Structures (mirror include/mhc.h)
+# ---------------------------------------------------------------------------
+_D = ctypes.c_double
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class mhc_object(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("x", _D), ("y", _D), ("heading", _D), ("speed", _D),
+                ("length", _D), ("width", _D), ("radius", _D),
+                ("n_u", ctypes.c_int32), ("n_w", ctypes.c_int32),
+                ("u", _DP), ("w", _DP), ("score", _DP)]
+
+
+class mhc_scene(ctypes.Structure):
+    _fields_ = [("n_objects", ctypes.c_int32), ("objects", ctypes.POINTER(mhc_object)),
+                ("horizon", ctypes.c_int32), ("dt", _D), ("pairs", ctypes.c_int32)]
+
+
+class mhc_sizes(ctypes.Structure):
+    _fields_ = [("n_traj", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_traj_pairs", ctypes.c_int64),
+                ("n_checks", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+class mhc_result(ctypes.Structure):
+    _fields_ = [("object_crit", ctypes.c_void_p), ("traj_crit", ctypes.c_void_p),
+                ("traj_prob", ctypes.c_void_p), ("q", ctypes.c_void_p), ("first_hit", ctypes.c_void_p)]
+
+
+class mhc_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight_ticks", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("max_frames_per_tick", ctypes.c_int32),
+                ("max_checks_per_tick", ctypes.c_int64)]
+
+
+class mhc_timing(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("admit_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("tick", ctypes.c_int64)]
+
+
+class mhc_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("deferred", ctypes.c_int64), ("ticks", ctypes.c_int64), ("checks", ctypes.c_int64),
+                ("p50_ms", _D), ("p99_ms", _D), ("max_ms", _D), ("mean_ms", _D), ("checks_per_s", _D)]
+
+
+def _load():
+    # One HIP runtime per process: torch ships its own copy of libamdhip64.so.7.
+    # Loading torch first makes this library bind to that same copy, so device
+    # pointers and streams created by torch are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    V = ctypes.c_void_p
+    I = ctypes.c_int
+    S = ctypes.c_size_t
+    for name, args in {
+        "mhc_create": [I, S, ctypes.POINTER(V)],
+        "mhc_destroy": [V],
+        "mhc_last_error": [V],
+        "mhc_query_sizes": [ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_sizes)],
+        "mhc_evaluate": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
+        "mhc_evaluate_async": [V, ctypes.POINTER(mhc_scene), V, S, ctypes.POINTER(mhc_result), V],
+        "mhc_plan_create": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(V)],
+        "mhc_plan_update": [V, ctypes.POINTER(mhc_scene)],
+        "mhc_plan_execute": [V, ctypes.POINTER(mhc_result), V],
+        "mhc_plan_download": [V, ctypes.POINTER(mhc_result)],
+        "mhc_plan_destroy": [V],
+        "mhc_evaluate_batch": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
+        "mhc_server_start": [V, ctypes.POINTER(mhc_server_cfg), ctypes.POINTER(V)],
+        "mhc_submit": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result),
+                       ctypes.POINTER(ctypes.c_uint64)],
+        "mhc_wait": [V, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(mhc_timing)],
+        "mhc_server_stats": [V, ctypes.POINTER(mhc_stats)],
+        "mhc_server_stop": [V],
+    }.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = None if name in ("mhc_destroy", "mhc_plan_destroy") else ctypes.c_int
+    L.mhc_last_error.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+# ---------------------------------------------------------------------------
+# Marshalling
+# ---------------------------------------------------------------------------
+
+class CScene:
+    """A scene (``scenegen.Scene`` or anything with the same fields) held as
+    C structures; keeps its arrays alive."""
+
+    def __init__(self, scene):
+        self.keep = []
+        objs = (mhc_object * scene.n_objects)()
+        for k, o in enumerate(scene.objects):
+            u = np.ascontiguousarray(o.u, np.float64)
+            w = np.ascontiguousarray(o.w, np.float64)
+            sc = None if o.score is None else np.ascontiguousarray(o.score, np.float64)
+            self.keep += [u, w, sc]
+            objs[k].kind = int(o.kind)
+            objs[k].x, objs[k].y, objs[k].heading, objs[k].speed = float(o.x), float(o.y), float(o.heading), float(o.speed)
+            objs[k].length, objs[k].width, objs[k].radius = float(o.length), float(o.width), float(o.radius)
+            objs[k].n_u, objs[k].n_w = len(u), len(w)
+            objs[k].u = u.ctypes.data_as(_DP)
+            objs[k].w = w.ctypes.data_as(_DP)
+            objs[k].score = sc.ctypes.data_as(_DP) if sc is not None else None
+        self.objs = objs
+        self.c = mhc_scene(scene.n_objects, objs, int(scene.horizon), float(scene.dt), int(scene.pairs))
+        self.T = [len(o.u) * len(o.w) for o in scene.objects]
+        self.n = scene.n_objects
+        self.pairs = [(a, b) for a in range(self.n) for b in range(a + 1, self.n)
+                      if scene.pairs == 0 or a == 0]
+        self.n_traj = sum(self.T)
+        self.n_hits = sum(self.T[a] * self.T[b] for a, b in self.pairs)
+
+
+def _check(ctx, st: int):
+    if st != MHC_OK:
+        msg = lib.mhc_last_error(ctx).decode() if ctx else ""
+        raise MhcError(st, msg)
+
+
+def host_result(cs: CScene, first_hit: bool = True, q: bool = True):
+    out = {
+        "object_crit": np.full(cs.n, np.nan),
+        "traj_crit": np.full(cs.n_traj, np.nan),
+        "traj_prob": np.full(cs.n_traj, np.nan),
+        "q": np.full((cs.n_traj, cs.n), np.nan) if q else None,
+        "first_hit": np.full(cs.n_hits, -2, np.int16) if first_hit else None,
+    }
+    r = mhc_result(*(None if out[k] is None else out[k].ctypes.data for k in
+                     ("object_crit", "traj_crit", "traj_prob", "q", "first_hit")))
+    return out, r
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+
+def mhc_create(device: int = 0, hbm_budget_bytes: int = 0):
+    h = ctypes.c_void_p()
+    st = lib.mhc_create(device, hbm_budget_bytes, ctypes.byref(h))
+    if st != MHC_OK:
+        raise MhcError(st, f"mhc_create(device={device}) failed")
+    return h
+
+
+def mhc_destroy(ctx):
+    lib.mhc_destroy(ctx)
+
+
+def mhc_last_error(ctx) -> str:
+    return lib.mhc_last_error(ctx).decode()
+
+
+def mhc_query_sizes(scene) -> dict:
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    s = mhc_sizes()
+    st = lib.mhc_query_sizes(ctypes.byref(cs.c), ctypes.byref(s))
+    if st != MHC_OK:
+        raise MhcError(st, "mhc_query_sizes: invalid scene")
+    return {k: getattr(s, k) for k, _ in mhc_sizes._fields_}
+
+
+def mhc_evaluate(ctx, scene, first_hit: bool = True, q: bool = True) -> dict:
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    out, r = host_result(cs, first_hit, q)
+    _check(ctx, lib.mhc_evaluate(ctx, ctypes.byref(cs.c), ctypes.byref(r)))
+    return out
+
+
+def mhc_evaluate_batch(ctx, scenes: Sequence, first_hit: bool = True, q: bool = True) -> List[dict]:
+    css = [s if isinstance(s, CScene) else CScene(s) for s in scenes]
+    arr = (mhc_scene * len(css))(*[c.c for c in css])
+    outs, rs = zip(*[host_result(c, first_hit, q) for c in css])
+    rarr = (mhc_result * len(css))(*rs)
+    _check(ctx, lib.mhc_evaluate_batch(ctx, len(css), arr, rarr))
+    return list(outs)
+
+
+def device_result(cs: CScene, device="cuda", first_hit: bool = True, q: bool = True):
+    """Torch-owned device outputs for the asynchronous and plan paths."""
+    import torch
+    out = {
+        "object_crit": torch.full((cs.n,), float("nan"), dtype=torch.float64, device=device),
+        "traj_crit": torch.full((cs.n_traj,), float("nan"), dtype=torch.float64, device=device),
+        "traj_prob": torch.full((cs.n_traj,), float("nan"), dtype=torch.float64, device=device),
+        "q": torch.full((cs.n_traj, cs.n), float("nan"), dtype=torch.float64, device=device) if q else None,
+        "first_hit": torch.full((cs.n_hits,), -2, dtype=torch.int16, device=device) if first_hit else None,
+    }
+    r = mhc_result(*(None if out[k] is None else out[k].data_ptr() for k in
+                     ("object_crit", "traj_crit", "traj_prob", "q", "first_hit")))
+    return out, r
+
+
+def mhc_evaluate_async(ctx, scene, workspace, dev_out: mhc_result, stream=None):
+    """``workspace``: a torch uint8 CUDA tensor of >= device_bytes bytes;
+    ``stream``: a torch.cuda.Stream (default: the current stream)."""
+    import torch
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(ctx, lib.mhc_evaluate_async(ctx, ctypes.byref(cs.c), workspace.data_ptr(), workspace.numel(),
+                                       ctypes.byref(dev_out), ctypes.c_void_p(s.cuda_stream)))
+    return cs
+
+
+class Plan:
+    def __init__(self, ctx, scene):
+        self.ctx = ctx
+        self.cs = scene if isinstance(scene, CScene) else CScene(scene)
+        self.h = ctypes.c_void_p()
+        _check(ctx, lib.mhc_plan_create(ctx, ctypes.byref(self.cs.c), ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib.mhc_plan_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mhc_plan_create(ctx, scene) -> Plan:
+    return Plan(ctx, scene)
+
+
+def mhc_plan_update(plan: Plan, scene):
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    _check(plan.ctx, lib.mhc_plan_update(plan.h, ctypes.byref(cs.c)))
+    plan.cs = cs
+
+
+def mhc_plan_execute(plan: Plan, dev_out: Optional[mhc_result] = None, stream=None):
+    sp = 0 if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(plan.ctx, lib.mhc_plan_execute(plan.h, ctypes.byref(dev_out) if dev_out is not None else None,
+                                          ctypes.c_void_p(sp)))
+
+
+def mhc_plan_download(plan: Plan, first_hit: bool = True, q: bool = True) -> dict:
+    out, r = host_result(plan.cs, first_hit, q)
+    _check(plan.ctx, lib.mhc_plan_download(plan.h, ctypes.byref(r)))
+    return out
+
+
+def mhc_plan_destroy(plan: Plan):
+    plan.close()
+
+
+# ---- server ---------------------------------------------------------------
+
+class Server:
+    def __init__(self, ctx, budget: int = 0, inflight: int = 0, queue: int = 0, frames_per_tick: int = 0,
+                 checks_per_tick: int = 0):
+        self.ctx = ctx
+        cfg = mhc_server_cfg(budget, inflight, queue, frames_per_tick, checks_per_tick)
+        self.h = ctypes.c_void_p()
+        _check(ctx, lib.mhc_server_start(ctx, ctypes.byref(cfg), ctypes.byref(self.h)))
+        self.pending = {}
+
+    def submit(self, stream_id: int, scene, first_hit: bool = False, q: bool = False):
+        cs = scene if isinstance(scene, CScene) else CScene(scene)
+        out, r = host_result(cs, first_hit, q)
+        t = ctypes.c_uint64()
+        st = lib.mhc_submit(self.h, stream_id, ctypes.byref(cs.c), ctypes.byref(r), ctypes.byref(t))
+        if st != MHC_OK:
+            raise MhcError(st, mhc_last_error(self.ctx))
+        self.pending[t.value] = (out, r)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        tm = mhc_timing()
+        st = lib.mhc_wait(self.h, ticket, timeout_us, ctypes.byref(tm))
+        if st != MHC_OK:
+            raise MhcError(st, "mhc_wait")
+        out, _ = self.pending.pop(ticket)
+        return out, {k: getattr(tm, k) for k, _ in mhc_timing._fields_}
+
+    def stats(self) -> dict:
+        s = mhc_stats()
+        _check(self.ctx, lib.mhc_server_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in mhc_stats._fields_}
+
+    def stop(self):
+        if self.h:
+            _check(self.ctx, lib.mhc_server_stop(self.h))
+            self.h = ctypes.c_void_p()
+
+
+def mhc_server_start(ctx, **kw) -> Server:
+    return Server(ctx, **kw)

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Sizes: the 2-vehicle scene over many seeds, the 11-object scene (the size
+the benchmark times) in full, ragged and degenerate shapes, and a seeded
+sample of 20 object pairs of the 40-object stress scene.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_06773_amd import scenegen as sg
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def mhc():
+    from paper_2005_06773_amd import mhc as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mhc):
+    c = mhc.mhc_create(0)
+    yield c
+    mhc.mhc_destroy(c)
+
+
+THREADS = int(os.environ.get("MHC_ORACLE_THREADS", "16"))
+
+
+def veh(x, y, psi, v, u, w, L=4.5, W=1.8, score=None):
+    return sg.SceneObject(sg.VEHICLE, x, y, psi, v, L, W, 0.0, np.asarray(u, float), np.asarray(w, float), score)
+
+
+def ped(x, y, psi, v, u, w, r=0.3, score=None):
+    return sg.SceneObject(sg.PEDESTRIAN, x, y, psi, v, 0.0, 0.0, r, np.asarray(u, float), np.asarray(w, float), score)
+
+
+def test_two_vehicle_scene_parity(mhc, ctx):
+    n_seeds = int(os.environ.get("MHC_PARITY_SEEDS", "2000"))
+    say(f"two-vehicle scene, seeds 0..{n_seeds - 1}")
+    with_hits = 0
+    exact = []
+    for seed in range(n_seeds):
+        s = sg.two_vehicle_scene(seed)
+        g = mhc.mhc_evaluate(ctx, s)
+        o = oracle.evaluate(s, threads=1)
+        exact.append(parity.check(s, g, o, f"seed {seed}"))
+        with_hits += bool((o.k64 >= 0).any())
+    say(f"seeds with a collision: {with_hits}/{n_seeds}; mean exact first-hit fraction {np.mean(exact):.6f}")
+    assert with_hits > n_seeds // 50
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_eleven_object_scene_parity(mhc, ctx, seed):
+    say(f"11-object scene seed {seed}")
+    s = sg.eleven_object_scene(seed)
+    g = mhc.mhc_evaluate(ctx, s)
+    o = oracle.evaluate(s, threads=THREADS)
+    ex = parity.check(s, g, o, f"seed {seed}")
+    say(f"  exact first-hit fraction {ex:.7f}, hits {(o.k64 >= 0).sum()}")
+
+
+def _edge_scenes():
+    rng = np.random.default_rng(77)
+    out = {}
+    out["single_trajectories_H1"] = sg.Scene([veh(0, 0, 0, 5, [0.0], [0.0]), veh(3, 0.5, 0.3, 2, [1.0], [0.1])], 1, 0.1)
+    out["all_classes_ragged"] = sg.Scene([
+        veh(0, 0, 0.2, 8, sg.accel_grid(7), sg.yaw_grid(11)),
+        ped(6, 1, 3.0, 1.0, sg.ped_speed_grid(13), sg.ped_heading_grid(1)),
+        veh(10, -2, 2.5, 6, sg.accel_grid(1), sg.yaw_grid(17)),
+        ped(4, 4, 1.0, 1.5, sg.ped_speed_grid(3), sg.ped_heading_grid(19)),
+    ], 37, 0.1)
+    out["pedestrian_first"] = sg.Scene([
+        ped(0, 0, 0.0, 1.0, sg.ped_speed_grid(5), sg.ped_heading_grid(9)),
+        veh(3, 0, 3.1, 5, sg.accel_grid(5), sg.yaw_grid(5)),
+        ped(1, 2, 1.0, 1.0, sg.ped_speed_grid(4), sg.ped_heading_grid(4)),
+    ], 30, 0.1)
+    out["overlap_at_start"] = sg.Scene([veh(0, 0, 0, 0, sg.accel_grid(5), sg.yaw_grid(5)),
+                                        veh(1, 0, 0.5, 0, sg.accel_grid(5), sg.yaw_grid(5)),
+                                        ped(0.5, 0.2, 0, 0, sg.ped_speed_grid(4), sg.ped_heading_grid(4))], 10, 0.1)
+    out["far_apart"] = sg.Scene([veh(0, 0, 0, 5, sg.accel_grid(5), sg.yaw_grid(5)),
+                                 veh(500, 500, 0, 5, sg.accel_grid(5), sg.yaw_grid(5))], 30, 0.1)
+    out["tile_spanning_257x129"] = sg.Scene([veh(0, 0, 0.0, 10, sg.accel_grid(257), sg.yaw_grid(1)),
+                                             veh(25, 1, math.pi, 10, sg.accel_grid(3), sg.yaw_grid(43))], 40, 0.1)
+    out["long_horizon"] = sg.Scene([veh(0, 0, 0.0, 3, sg.accel_grid(4), sg.yaw_grid(3)),
+                                    ped(30, 0.5, math.pi, 1.0, sg.ped_speed_grid(3), sg.ped_heading_grid(5)),
+                                    veh(60, 0, math.pi, 4, sg.accel_grid(3), sg.yaw_grid(3))], 300, 0.1)
+    sc = sg.eleven_object_scene(5)
+    sc.objects = sc.objects[:4] + sc.objects[6:9]
+    for o in sc.objects:
+        o.score = None
+    out["uniform_scores"] = sc
+    sz = sg.eleven_object_scene(6)
+    sz.objects = sz.objects[:3] + sz.objects[6:8]
+    for o in sz.objects:
+        o.score = o.score * (rng.uniform(size=o.score.shape) > 0.5)
+        o.score[0] += 1.0
+    out["zero_scores"] = sz
+    se = sg.eleven_object_scene(9)
+    se.pairs = sg.PAIRS_EGO
+    out["ego_mode"] = se
+    # the paper's EGO-only pair set at its step length, with a dense jam of COs
+    jam = [veh(0, 0, 0.0, 12, sg.accel_grid(6), sg.yaw_grid(7))]
+    for k in range(4):
+        jam.append(veh(15 + 9 * k, 3.5 * ((k % 2) * 2 - 1) * 0.5, math.pi * (k % 2), 8, sg.accel_grid(6), sg.yaw_grid(7)))
+    out["ego_jam_20ms"] = sg.Scene(jam, 100, 0.02, pairs=sg.PAIRS_EGO)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_edge_scenes().keys()))
+def test_edge_scene_parity(mhc, ctx, name):
+    s = _edge_scenes()[name]
+    say(f"edge scene {name}")
+    g = mhc.mhc_evaluate(ctx, s)
+    o = oracle.evaluate(s, threads=THREADS)
+    parity.check(s, g, o, name)
+    if name == "overlap_at_start":
+        assert np.all(g["first_hit"] == 0)
+    if name == "far_apart":
+        assert np.all(g["first_hit"] == -1) and np.all(g["object_crit"] == 0)
+
+
+def test_plan_and_async_match_evaluate(mhc, ctx):
+    import torch
+    s = sg.eleven_object_scene(1)
+    say("plan / async / evaluate on the 11-object scene")
+    ref = mhc.mhc_evaluate(ctx, s)
+    plan = mhc.mhc_plan_create(ctx, s)
+    for rep in range(3):
+        mhc.mhc_plan_execute(plan)
+        got = mhc.mhc_plan_download(plan)
+        parity.same_results(ref, got, f"plan rep {rep}")
+    # device outputs on a torch stream
+    cs = mhc.CScene(s)
+    sizes = mhc.mhc_query_sizes(cs)
+    ws = torch.empty(sizes["device_bytes"], dtype=torch.uint8, device="cuda")
+    out, r = mhc.device_result(cs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        mhc.mhc_evaluate_async(ctx, cs, ws, r, stream)
+        mhc.mhc_plan_execute(plan, r, stream)
+    stream.synchronize()
+    got = {k: (None if v is None else v.cpu().numpy()) for k, v in out.items()}
+    parity.same_results(ref, got, "async+plan into torch tensors")
+    # a plan updated with new values of the same shape equals a fresh evaluation
+    s2 = sg.eleven_object_scene(2)
+    mhc.mhc_plan_update(plan, s2)
+    mhc.mhc_plan_execute(plan)
+    parity.same_results(mhc.mhc_evaluate(ctx, s2), mhc.mhc_plan_download(plan), "plan update")
+    plan.close()
+
+
+def test_batch_matches_single_and_oracle(mhc, ctx):
+    scenes = sg.batch_scenes(2, 64)
+    small = [s for s in scenes if sum(s.objects[a].n_traj * s.objects[b].n_traj
+                                      for a in range(s.n_objects) for b in range(a + 1, s.n_objects)) * s.horizon < 3e8]
+    say(f"batch of {len(scenes)} scenes")
+    outs = mhc.mhc_evaluate_batch(ctx, scenes)
+    for k, s in enumerate(scenes[:16]):
+        parity.same_results(outs[k], mhc.mhc_evaluate(ctx, s), f"batch scene {k}")
+    for k, s in enumerate(small[:6]):
+        kk = scenes.index(s)
+        parity.check(s, outs[kk], oracle.evaluate(s, threads=THREADS), f"batch scene {kk} vs oracle")
+
+
+def test_invalid_scenes_rejected_without_writes(mhc, ctx):
+    base = sg.two_vehicle_scene(0)
+    bads = []
+    s = sg.two_vehicle_scene(0); s.objects[0].x = float("nan"); bads.append(s)
+    s = sg.two_vehicle_scene(0); s.objects[1].length = -1.0; bads.append(s)
+    s = sg.two_vehicle_scene(0); s.horizon = 0; bads.append(s)
+    s = sg.two_vehicle_scene(0); s.dt = 0.0; bads.append(s)
+    s = sg.two_vehicle_scene(0); s.objects[1].score = np.zeros(25); bads.append(s)
+    s = sg.two_vehicle_scene(0); s.objects = s.objects[:1]; bads.append(s)
+    for k, s in enumerate(bads):
+        cs = mhc.CScene(s)
+        out, r = mhc.host_result(cs)
+        import ctypes
+        st = mhc.lib.mhc_evaluate(ctx, ctypes.byref(cs.c), ctypes.byref(r))
+        assert st == mhc.MHC_E_INVAL, k
+        assert np.all(np.isnan(out["object_crit"])) and np.all(out["first_hit"] == -2)
+        assert mhc.mhc_last_error(ctx)
+    mhc.mhc_evaluate(ctx, base)  # the context still works
+
+
+def test_stress_scene_sampled_pairs(mhc, ctx):
+    """Full 40-object scene (40.9e9 checks) on the GPU; the oracle checks the
+    seeded sample of 20 object pairs element by element."""
+    s = sg.stress_scene(4)
+    say("stress scene: GPU full run")
+    g = mhc.mhc_evaluate(ctx, s, q=False)
+    sample = sg.stress_sample_pairs(s.n_objects, 20, 1004)
+    say(f"stress scene: oracle on sampled pairs {sample}")
+    o = oracle.evaluate(s, pair_list=sample, threads=THREADS, risk=False)
+    T = s.traj_counts()
+    all_pairs = [(a, b) for a in range(s.n_objects) for b in range(a + 1, s.n_objects)]
+    off = np.concatenate([[0], np.cumsum([T[a] * T[b] for a, b in all_pairs])])
+    k32 = np.concatenate([g["first_hit"][off[all_pairs.index(p)]:off[all_pairs.index(p) + 1]] for p in sample])
+    acc = oracle.accepted_first_hits(k32, o)
+    assert acc.all(), f"{(~acc).sum()} rejected"
+    say(f"  sampled entries {k32.size}, exact {np.mean(k32 == o.k64):.7f}, hits {(o.k64 >= 0).sum()}")
+    assert np.all((g["object_crit"] >= 0) & (g["object_crit"] <= 1))

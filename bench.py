@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-hypothesis criticality hot path on one MI355X.
+
+Workload: the 11-object scene (6 vehicles with 15x15 acceleration x yaw-rate
+grids, 5 pedestrians with 15x15 speed x heading grids, 30 steps of 0.1 s),
+83,531,250 pose-pair checks per pass. One step = one pass of the whole device
+path on inputs resident in HBM: probability normalisation and trajectory
+generation, collision recognition of every trajectory pair of every object
+pair at every step, risk reduction to per-trajectory and per-object
+criticality.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic FP32 work of one overlap test (FMA = 2 flops; compares and
+# max count 1): rectangle-rectangle 44, rectangle-circle 16, circle-circle 6.
+FLOPS_PER_CHECK = {"VV": 44, "VP": 16, "PP": 6}
+# MI355X FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+# = 78.6 TFLOP/s without packed math, 157.3 TFLOP/s with it.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
+LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def class_checks(scene):
+    out = {"VV": 0, "VP": 0, "PP": 0}
+    objs = scene.objects
+    for a in range(len(objs)):
+        for b in range(a + 1, len(objs)):
+            if scene.pairs == 1 and a != 0:
+                continue
+            ka, kb = objs[a].kind, objs[b].kind
+            c = "VV" if ka == kb == 0 else ("PP" if ka == kb == 1 else "VP")
+            out[c] += objs[a].n_traj * objs[b].n_traj * scene.horizon
+    return out
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
+    return xs[k]
+
+
+def cpu_baseline(scene, checks, seconds):
+    """The FP64 oracle as it stands, on the host cores (rank 0, N=1 only)."""
+    import oracle
+    oracle.lib()
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    runs = 0
+    while True:
+        oracle.evaluate(scene, threads=cores, masks=False)
+        runs += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    value = checks * runs / dt
+    log(f"cpu baseline: {runs} oracle runs in {dt:.2f} s on {cores} threads -> {value:.4g} checks/s")
+    return {"value": value, "unit": "checks/s", "cores": cores, "kind": "oracle",
+            "sample": f"the full 11-object scene (seed {scene_seed}), {runs} complete oracle passes "
+                      f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s"}
+
+
+scene_seed = 1
+
+
+def main():
+    global scene_seed
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the latency and batched measurements")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="force a collision micro-tile variant (default: autotune on the workload)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard object pairs across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    scene_seed = args.seed
+
+    import torch
+    from paper_2005_06773_amd import mhc, scenegen as sg
+
+    scene = sg.eleven_object_scene(args.seed)
+    cs = mhc.CScene(scene)
+    sizes = mhc.mhc_query_sizes(cs)
+    checks = sizes["n_checks"]
+    cls = class_checks(scene)
+    assert sum(cls.values()) == checks
+    flops = sum(FLOPS_PER_CHECK[c] * n for c, n in cls.items())
+
+    ctx = mhc.mhc_create(0)
+    if args.variant >= 0:
+        mhc.mhc_set_variant(ctx, args.variant)
+        tune = {"forced": args.variant}
+    else:
+        best, us = mhc.mhc_autotune(ctx, cs, reps=20)
+        tune = {"chosen": best, "us_per_variant": [round(u, 2) for u in us]}
+        log(f"autotune: collision kernel us per variant {[round(u, 1) for u in us]} -> variant {best}")
+    plan = mhc.mhc_plan_create(ctx, cs)
+    out, r = mhc.device_result(cs, first_hit=True, q=True)
+    stream = torch.cuda.current_stream()
+    T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calibrate_copy} MiB read, {args.calibrate_copy} MiB written")
+        del src, dst
+    log(f"workload: 11-object scene seed {args.seed}, {checks:,} checks/pass; warmup {args.warmup}, steps {args.steps}")
+    for _ in range(args.warmup):
+        mhc.mhc_plan_execute(plan, r, stream)
+    torch.cuda.synchronize()
+
+    # Timed region: K whole-path steps on the launch stream.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        mhc.mhc_plan_execute(plan, r, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = checks / (ms_step / 1e3)
+
+    # Collision-kernel duration, live: the same K steps again, split by module,
+    # with HIP events on the launch stream bracketing every collision launch.
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for k in range(args.steps):
+        mhc.mhc_plan_execute_stages(plan, T, r, stream)
+        ev[k][0].record(stream)
+        mhc.mhc_plan_execute_stages(plan, C, r, stream)
+        ev[k][1].record(stream)
+        mhc.mhc_plan_execute_stages(plan, R, r, stream)
+    torch.cuda.synchronize()
+    k2_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    achieved = flops / (k2_ms * 1e-3) / 1e12
+    log(f"step {ms_step * 1e3:.1f} us -> {value:.4g} checks/s; collision kernel {k2_ms * 1e3:.1f} us -> "
+        f"{achieved:.2f} TFLOP/s ({checks / (k2_ms / 1e3):.4g} checks/s)")
+
+    # Reference VALU instructions per check (27 rect-rect, 14 rect-circle,
+    # 6 circle-circle, incl. first-hit bookkeeping) against the lane-op rate.
+    lane_ops = 27 * cls["VV"] + 14 * cls["VP"] + 6 * cls["PP"]
+    result = {
+        "metric": "pose-pair checks/sec (11-object scene)",
+        "value": value,
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "eleven_object_scene", "objects": 11, "vehicles": 6, "pedestrians": 5,
+                   "trajectories_per_object": 225, "horizon": 30, "dt": 0.1, "checks": checks,
+                   "seed": args.seed, "pairs": "all", "inputs": "resident in HBM"},
+        "tile_variant": tune,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k2_collide", "kernel_us": k2_ms * 1e3, "flops_per_launch": flops,
+                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                     "valu_issue_frac_est": lane_ops / (k2_ms / 1e3) / LANE_OPS_PER_S},
+    }
+
+    # Sanity: the timed results are finite and in range.
+    oc = out["object_crit"].cpu()
+    assert torch.isfinite(oc).all() and (oc >= 0).all() and (oc <= 1).all(), "bad criticality"
+
+    if not args.no_extras:
+        # Plain end-to-end latency: host scene in -> host criticality out.
+        lat = []
+        for _ in range(10):
+            mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
+        for _ in range(200):
+            a = time.perf_counter()
+            mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
+            lat.append((time.perf_counter() - a) * 1e3)
+        result["plain_latency_ms"] = {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
+                                      "note": "mhc_evaluate, host scene in, host criticality out (PCIe included)"}
+        log(f"plain end-to-end latency p50 {pct(lat, 50):.3f} ms p99 {pct(lat, 99):.3f} ms")
+        # Batched vs plain loop over the same 64 scenes.
+        scenes = [mhc.CScene(s) for s in sg.batch_scenes(2, 64)]
+        bchecks = sum(mhc.mhc_query_sizes(s)["n_checks"] for s in scenes)
+        mhc.mhc_evaluate_batch(ctx, scenes, first_hit=False, q=False)
+        for s in scenes[:4]:
+            mhc.mhc_evaluate(ctx, s, first_hit=False, q=False)
+        reps = 5
+        a = time.perf_counter()
+        for _ in range(reps):
+            mhc.mhc_evaluate_batch(ctx, scenes, first_hit=False, q=False)
+        tb = (time.perf_counter() - a) / reps
+        a = time.perf_counter()
+        for _ in range(reps):
+            for s in scenes:
+                mhc.mhc_evaluate(ctx, s, first_hit=False, q=False)
+        tp = (time.perf_counter() - a) / reps
+        result["batched"] = {"scenes": 64, "checks": bchecks, "batch_ms": tb * 1e3, "plain_loop_ms": tp * 1e3,
+                             "batch_checks_per_s": bchecks / tb, "plain_loop_checks_per_s": bchecks / tp,
+                             "speedup": tp / tb}
+        log(f"batched 64 scenes: {tb * 1e3:.2f} ms ({bchecks / tb:.4g} checks/s) vs plain loop "
+            f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
+
+    plan.close()
+    mhc.mhc_destroy(ctx)
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scene, checks, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

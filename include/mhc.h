@@ -155,9 +155,34 @@ mhc_status mhc_plan_update(mhc_plan *plan, const mhc_scene *scene);
 /* Launches on `hip_stream`. Device pointers in `dev_out` (NULL entries are
  * kept in plan-owned memory). */
 mhc_status mhc_plan_execute(mhc_plan *plan, const mhc_result *dev_out, void *hip_stream);
+/* The same work split by module (Fig. 1): any combination of the stage bits,
+ * launched in module order on `hip_stream`. Lets a caller time or interleave
+ * the modules; a stage reads what the previous stages of an earlier or the
+ * same call left in the plan's (or dev_out's) buffers. */
+enum { MHC_STAGE_TRAJ = 1, MHC_STAGE_COLLIDE = 2, MHC_STAGE_RISK = 4, MHC_STAGE_ALL = 7 };
+mhc_status mhc_plan_execute_stages(mhc_plan *plan, const mhc_result *dev_out, void *hip_stream,
+                                   uint32_t stages);
 /* Copies the plan-owned results of the last execute to host buffers (sync). */
 mhc_status mhc_plan_download(mhc_plan *plan, mhc_result *host_out);
 void mhc_plan_destroy(mhc_plan *plan);
+
+/* ---- collision-kernel tile shapes (autotuning) --------------------------- */
+
+/* The collision kernel is compiled for MHC_N_VARIANTS micro-tile shapes (how
+ * many trajectories of each object one GPU thread pairs up). Results are
+ * bit-identical for every variant; only speed differs.
+ * mhc_set_variant forces one (-1 returns to the tuned choice).
+ * mhc_autotune times every variant on `scene` (`reps` launches each, after
+ * one warm-up) and records the fastest for scenes of the same size class
+ * (log2 buckets of the mean trajectory count and of the horizon); `us` (or
+ * NULL) receives the mean microseconds per launch of each variant.
+ * mhc_tune_save / mhc_tune_load write / read the recorded choices as JSON
+ * ({"gfx950": {"<T bucket>,<H bucket>": variant, ...}}). */
+enum { MHC_N_VARIANTS = 4 };
+mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant);
+mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int32_t *best_variant, double *us);
+mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path);
+mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path);
 
 /* ---- batched ----------------------------------------------------------- */
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmhc.so")
 
-SOURCES = ["kernels.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "runtime.cpp", "tune.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -20,6 +20,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # no FMA contraction beyond the explicit fmaf calls
     "-ffp-contract=off",
+    # keep each overlap decision in a lane mask: the SLP vectorizer would pack
+    # the booleans of neighbouring tests into 16-bit vectors
+    "-fno-slp-vectorize",
     "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-pthread",

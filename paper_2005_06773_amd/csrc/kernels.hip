@@ -13,18 +13,25 @@ namespace mhc {
 // (Sec. IV-D.1).
 //
 // Vehicles follow the Euler pose update of Sec. IV-B.1 with side slip 0 and
-// no yaw acceleration; the constant acceleration of trajectory i acts inside
-// each step and is cut so that the speed stops at 0. The time loop of one
-// trajectory is sequential (Sec. IV-B.4), but the heading of step n is
-// psi0 + n*w*tau, so the FP64 sine/cosine of a chunk of steps are computed by
-// all 256 threads first and the 16 trajectories of the block then integrate
-// through the chunk from LDS. Positions are integrated in FP64 and stored as
-// FP32 (x, y, cos psi, sin psi), one float4 per pose, layout [t][i].
-// Pedestrians (Sec. IV-B.3) walk at constant speed along a fixed heading:
-// one thread per trajectory, float2 (x, y) poses.
+// no yaw acceleration: in step n the speed v_n, heading psi_n = psi0 + n*w*tau
+// and acceleration give the displacement
+//   dx_n = c(psi_n) v_n tau + c(psi_n) a_x tau^2/2 - s(psi_n) a_y tau^2/2
+//   dy_n = s(psi_n) v_n tau + s(psi_n) a_x tau^2/2 + c(psi_n) a_y tau^2/2
+// with a_x the acceleration cut so that the speed stops at 0 and
+// a_y = v_n w. The speed of a constant acceleration with a stop at 0 has the
+// closed form max(0, v0 + n a tau), so every step's displacement is
+// independent: one wave integrates one trajectory, lane q computing step
+// n0 + q (FP64, including its own sine/cosine), and the positions are the
+// running sums of the displacements, formed by a wave-wide scan and carried
+// from one 64-step chunk to the next. Pedestrians (Sec. IV-B.3) move by the
+// constant displacement of their speed and heading each step.
+// Poses are stored as FP32: float4 (x, y, cos psi, sin psi) for vehicles,
+// float2 (x, y) for pedestrians, layout [t][i], slot t = step t+1.
 // ===========================================================================
 
-__device__ void normalise_probabilities(const DObj &o, const double *__restrict__ vals, double *__restrict__ p)
+__device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals, double *__restrict__ p,
+                                        unsigned long long *__restrict__ pfix, unsigned long long *__restrict__ qacc,
+                                        unsigned int *__restrict__ done)
 {
     __shared__ double red[WG];
     const int tid = threadIdx.x;
@@ -39,86 +46,93 @@ __device__ void normalise_probabilities(const DObj &o, const double *__restrict_
         __syncthreads();
     }
     const double total = red[0];
-    for (int k = tid; k < o.T; k += WG)
-        p[o.traj_off + k] = o.has_score ? vals[o.score_off + k] / total : 1.0 / (double)o.T;
+    for (int k = tid; k < o.T; k += WG) {
+        const double pk = o.has_score ? vals[o.score_off + k] / total : 1.0 / (double)o.T;
+        p[o.traj_off + k] = pk;
+        pfix[o.traj_off + k] = __double2ull_rn(pk * kQScale);
+    }
+    // this object's rows of the integer q accumulators start from zero
+    const int64_t nq = (int64_t)o.T * o.n_scene_obj;
+    for (int64_t k = tid; k < nq; k += WG) qacc[o.q_row + k] = 0ull;
+    if (tid == 0) done[obj] = 0u;
 }
 
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  const K1Block *__restrict__ blocks, char *__restrict__ poses,
-                                                 double *__restrict__ p)
+                                                 double *__restrict__ p, unsigned long long *__restrict__ pfix,
+                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
 {
     const K1Block blk = blocks[blockIdx.x];
     const DObj o = objs[blk.obj];
-    const int tid = threadIdx.x;
-    const double tau = o.tau;
-    const int H = o.H;
-
-    if (o.kind == KIND_VEHICLE) {
-        __shared__ double s_c[K1_VT][K1_CH + 1];
-        __shared__ double s_s[K1_VT][K1_CH + 1];
-        const int lt = tid % K1_VT;
-        const int helper = tid / K1_VT;
-        const int i = blk.i0 + lt;
-        const bool valid = i < o.T;
-        const int ic = valid ? i : o.T - 1;
-        const int k = ic / o.n_w, l = ic - (ic / o.n_w) * o.n_w;
-        const double accel = vals[o.u_off + k];
-        const double omega = vals[o.w_off + l];
-        const double half_tau2 = tau * tau / 2.0;
-        double x = o.x, y = o.y, v = o.speed;
-        float4 *out = reinterpret_cast<float4 *>(poses + o.pose_off);
-        for (int n0 = 0; n0 < H; n0 += K1_CH) {
-            const int nn = min(K1_CH, H - n0);
-            for (int q = helper; q <= nn; q += WG / K1_VT) {
-                const double psi = o.heading + (double)(n0 + q) * (omega * tau);
-                double sv, cv;
-                sincos(psi, &sv, &cv);
-                s_c[lt][q] = cv;
-                s_s[lt][q] = sv;
-            }
-            __syncthreads();
-            if (helper == 0 && valid) {
-                for (int q = 0; q < nn; ++q) {
-                    const double c = s_c[lt][q], s = s_s[lt][q];
-                    double vdot = accel;
-                    double v_next = v + vdot * tau;
-                    if (v_next < 0.0) {
-                        vdot = -v / tau;
-                        v_next = 0.0;
-                    }
-                    const double ax = vdot;
-                    const double ay = v * omega;
-                    const double xn = x + c * v * tau + c * ax * half_tau2 - s * ay * half_tau2;
-                    const double yn = y + s * v * tau + s * ax * half_tau2 + c * ay * half_tau2;
-                    x = xn;
-                    y = yn;
-                    v = v_next;
-                    out[(size_t)(n0 + q) * o.T + i] =
-                        make_float4((float)x, (float)y, (float)s_c[lt][q + 1], (float)s_s[lt][q + 1]);
-                }
-            }
-            __syncthreads();
-        }
-    } else {
-        const int i = blk.i0 + tid;
-        if (i < o.T) {
-            const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
-            const double speed = vals[o.u_off + k];
-            const double psi = o.heading + vals[o.w_off + l];
-            double sv, cv;
-            sincos(psi, &sv, &cv);
-            double x = o.x, y = o.y;
-            float2 *out = reinterpret_cast<float2 *>(poses + o.pose_off);
-            for (int n = 0; n < H; ++n) {
-                x = x + cv * speed * tau;
-                y = y + sv * speed * tau;
-                out[(size_t)n * o.T + i] = make_float2((float)x, (float)y);
-            }
-        }
+    if (blk.i0 < 0) {
+        normalise_probabilities(o, blk.obj, vals, p, pfix, qacc, done);
+        return;
     }
-    if (blk.i0 == 0) {
-        __syncthreads();
-        normalise_probabilities(o, vals, p);
+    const int lane = threadIdx.x & 63;
+    const int i = blk.i0 + (int)(threadIdx.x >> 6);
+    if (i >= o.T) return;  // whole wave
+    const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
+    const double tau = o.tau;
+    const double half_tau2 = tau * tau / 2.0;
+    const int H = o.H;
+    const bool vehicle = o.kind == KIND_VEHICLE;
+    const double u = vals[o.u_off + k];
+    const double w = vals[o.w_off + l];
+    double ped_c = 0.0, ped_s = 0.0;
+    if (!vehicle) sincos(o.heading + w, &ped_s, &ped_c);
+    double cx = o.x, cy = o.y;
+    for (int n0 = 0; n0 < H; n0 += 64) {
+        const int n = n0 + lane;
+        const bool active = n < H;
+        double dx = 0.0, dy = 0.0;
+        float c_next = 0.f, s_next = 0.f;
+        if (active) {
+            if (vehicle) {
+                const double wt = w * tau;
+                double sn, cn, s1, c1;
+                sincos(o.heading + (double)n * wt, &sn, &cn);
+                sincos(o.heading + (double)(n + 1) * wt, &s1, &c1);
+                const double at = u * tau;
+                double v = o.speed + (double)n * at;
+                const double v_next = o.speed + (double)(n + 1) * at;
+                double ax = u;
+                if (v_next < 0.0) {
+                    if (v <= 0.0) {
+                        v = 0.0;
+                        ax = 0.0;
+                    } else {
+                        ax = -v / tau;
+                    }
+                }
+                const double ay = v * w;
+                dx = cn * v * tau + cn * ax * half_tau2 - sn * ay * half_tau2;
+                dy = sn * v * tau + sn * ax * half_tau2 + cn * ay * half_tau2;
+                c_next = (float)c1;
+                s_next = (float)s1;
+            } else {
+                dx = ped_c * u * tau;
+                dy = ped_s * u * tau;
+            }
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double tx = __shfl_up(dx, d, 64);
+            const double ty = __shfl_up(dy, d, 64);
+            if (lane >= d) {
+                dx += tx;
+                dy += ty;
+            }
+        }
+        const double x = cx + dx, y = cy + dy;
+        if (active) {
+            if (vehicle)
+                reinterpret_cast<float4 *>(poses + o.pose_off)[(size_t)n * o.T + i] =
+                    make_float4((float)x, (float)y, c_next, s_next);
+            else
+                reinterpret_cast<float2 *>(poses + o.pose_off)[(size_t)n * o.T + i] = make_float2((float)x, (float)y);
+        }
+        cx = __shfl(x, 63, 64);
+        cy = __shfl(y, 63, 64);
     }
 }
 
@@ -188,9 +202,31 @@ struct CheckPP {
     }
 };
 
+// Raw buffer descriptor (CDNA: dword3 = 0x00020000) over `bytes` bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pose_rsrc(const char *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class P>
+__device__ __forceinline__ P load_pose(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+
+template <>
+__device__ __forceinline__ float4 load_pose<float4>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+
+template <>
+__device__ __forceinline__ float2 load_pose<float2>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
 template <int RI, int RJ, class PA, class PB, class Check>
 __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const char *__restrict__ poses,
-                                              int16_t *__restrict__ hits, const Check chk)
+                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
+                                              unsigned long long *__restrict__ qacc, const Check chk)
 {
     const int n_ig = pr.n_ig, n_jg = pr.n_jg;
     const int f = item0 + (int)threadIdx.x;
@@ -203,8 +239,17 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     for (int r = 0; r < RI; ++r) ia[r] = min(ig + r * n_ig, Ta - 1);
 #pragma unroll
     for (int s = 0; s < RJ; ++s) jb[s] = min(jg + s * n_jg, Tb - 1);
-    const PA *__restrict__ A = reinterpret_cast<const PA *>(poses + pr.pose_a);
-    const PB *__restrict__ B = reinterpret_cast<const PB *>(poses + pr.pose_b);
+    // Poses are read with buffer loads: the step's offset t * T * sizeof(pose)
+    // lives in a scalar register and the lane offsets are loop-invariant, so
+    // no vector instruction is spent on addressing.
+    const __amdgpu_buffer_rsrc_t A = pose_rsrc(poses + pr.pose_a, (uint32_t)((size_t)pr.H * Ta * sizeof(PA)));
+    const __amdgpu_buffer_rsrc_t B = pose_rsrc(poses + pr.pose_b, (uint32_t)((size_t)pr.H * Tb * sizeof(PB)));
+    const uint32_t strideA = (uint32_t)Ta * (uint32_t)sizeof(PA), strideB = (uint32_t)Tb * (uint32_t)sizeof(PB);
+    uint32_t oa[RI], ob[RJ];
+#pragma unroll
+    for (int r = 0; r < RI; ++r) oa[r] = (uint32_t)ia[r] * (uint32_t)sizeof(PA);
+#pragma unroll
+    for (int s = 0; s < RJ; ++s) ob[s] = (uint32_t)jb[s] * (uint32_t)sizeof(PB);
     int first[RI][RJ];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
@@ -212,138 +257,170 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
         for (int s = 0; s < RJ; ++s) first[r][s] = -1;
 
     for (int t = pr.H - 1; t >= 0; --t) {
-        const PA *__restrict__ At = A + (size_t)t * Ta;
-        const PB *__restrict__ Bt = B + (size_t)t * Tb;
+        const uint32_t sa = (uint32_t)t * strideA, sb = (uint32_t)t * strideB;
         PA a[RI];
         PB b[RJ];
 #pragma unroll
-        for (int r = 0; r < RI; ++r) a[r] = At[ia[r]];
+        for (int r = 0; r < RI; ++r) a[r] = load_pose<PA>(A, oa[r], sa);
 #pragma unroll
-        for (int s = 0; s < RJ; ++s) b[s] = Bt[jb[s]];
+        for (int s = 0; s < RJ; ++s) b[s] = load_pose<PB>(B, ob[s], sb);
 #pragma unroll
         for (int r = 0; r < RI; ++r)
 #pragma unroll
             for (int s = 0; s < RJ; ++s)
                 if (chk(a[r], b[s])) first[r][s] = t;
     }
+    // Results: the first hits, and this thread's share of the q sums. A
+    // colliding trajectory pair (i, j) adds p_{b,j} to q_{a,i;b} and p_{a,i}
+    // to q_{b,j;a}; sums are exact integers (p * 2^62), so their value does
+    // not depend on the order in which threads add them.
+    bool any = false;
 #pragma unroll
     for (int r = 0; r < RI; ++r) {
         const int i = ig + r * n_ig;
 #pragma unroll
         for (int s = 0; s < RJ; ++s) {
             const int j = jg + s * n_jg;
-            if (i < Ta && j < Tb) hits[pr.hit_off + (int64_t)i * Tb + j] = (int16_t)first[r][s];
+            const bool valid = i < Ta && j < Tb;
+            if (!valid) first[r][s] = -1;
+            if (hits && valid) hits[pr.hit_off + (int64_t)i * Tb + j] = (int16_t)first[r][s];
+            any |= first[r][s] >= 0;
+        }
+    }
+    if (any) {
+        unsigned long long pa[RI], pb[RJ];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) pa[r] = pfix[pr.pa_off + ia[r]];
+#pragma unroll
+        for (int s = 0; s < RJ; ++s) pb[s] = pfix[pr.pb_off + jb[s]];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) {
+            unsigned long long row = 0;
+#pragma unroll
+            for (int s = 0; s < RJ; ++s)
+                if (first[r][s] >= 0) row += pb[s];
+            if (row) atomicAdd(&qacc[pr.qa0 + (int64_t)(ig + r * n_ig) * pr.qn], row);
+        }
+#pragma unroll
+        for (int s = 0; s < RJ; ++s) {
+            unsigned long long col = 0;
+#pragma unroll
+            for (int r = 0; r < RI; ++r)
+                if (first[r][s] >= 0) col += pa[r];
+            if (col) atomicAdd(&qacc[pr.qb0 + (int64_t)(jg + s * n_jg) * pr.qn], col);
         }
     }
 }
 
 template <int V>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
-                                             int16_t *__restrict__ hits)
+                                             int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
+                                             unsigned long long *__restrict__ qacc)
 {
     switch (pr.cls) {
     case CLS_VV:
         collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, float4, float4>(
-            pr, item0, poses, hits, CheckVV{pr.la, pr.wa, pr.lb, pr.wb});
+            pr, item0, poses, hits, pfix, qacc, CheckVV{pr.la, pr.wa, pr.lb, pr.wb});
         break;
     case CLS_VP:
         collide_items<kTiles[V][CLS_VP].ri, kTiles[V][CLS_VP].rj, float4, float2>(
-            pr, item0, poses, hits, CheckVP{pr.la, pr.wa, pr.rr});
+            pr, item0, poses, hits, pfix, qacc, CheckVP{pr.la, pr.wa, pr.rr});
         break;
     case CLS_PV:
         collide_items<kTiles[V][CLS_PV].ri, kTiles[V][CLS_PV].rj, float2, float4>(
-            pr, item0, poses, hits, CheckPV{pr.lb, pr.wb, pr.rr});
+            pr, item0, poses, hits, pfix, qacc, CheckPV{pr.lb, pr.wb, pr.rr});
         break;
     default:
         collide_items<kTiles[V][CLS_PP].ri, kTiles[V][CLS_PP].rj, float2, float2>(
-            pr, item0, poses, hits, CheckPP{pr.rr});
+            pr, item0, poses, hits, pfix, qacc, CheckPP{pr.rr});
         break;
     }
 }
 
 template <int V>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
-                                                 const char *__restrict__ poses, int16_t *__restrict__ hits)
+                                                 const char *__restrict__ poses, int16_t *__restrict__ hits,
+                                                 const unsigned long long *__restrict__ pfix,
+                                                 unsigned long long *__restrict__ qacc)
 {
     const WorkItem w = work[blockIdx.x];
     const DPair pr = pairs[w.pair];
-    collide_work<V>(pr, w.item0, poses, hits);
+    collide_work<V>(pr, w.item0, poses, hits, pfix, qacc);
 }
 
 // ===========================================================================
 // K3: risk assessment (Sec. IV-D, IV-D.2).
 //
-// q_{a,i;b} = sum_j [first_hit >= 0] p_{b,j} for both directions of every
-// pair (rows: one wave per trajectory i of a, lanes over j; columns: one
-// thread per trajectory j of b, sequential over i), then per trajectory
-// crit = 1 - prod_{b != a} (1 - q_{a,i;b}) in ascending b and per object
-// C_a = sum_i p_{a,i} crit_{a,i}. Every sum runs in a fixed order that does
-// not depend on how the collision kernel was tiled, so results are identical
-// for any tiling and any batch.
+// The collision kernel has left q_{a,i;b} = sum_j [hit] p_{b,j} as exact
+// integer sums (units of 2^-62). Per trajectory, k3_crit converts them
+// (rounding once), clamps to 1 and forms
+//   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b}),
+// four threads per trajectory each multiplying the objects b = m (mod 4) in
+// ascending order, the four products combined in a fixed order. The object's
+// criticality C_a = sum_i p_{a,i} crit_{a,i} is summed per block in a fixed
+// tree, and the last block of the object to finish adds the block sums in
+// block order. Nothing depends on how the collision work was tiled or
+// batched, so every result is identical for any tiling and any batch.
 // ===========================================================================
 
-__global__ __launch_bounds__(WG) void k3_qsum(const DObj *__restrict__ objs, const DPair *__restrict__ pairs,
-                                              const K3Item *__restrict__ items, const int16_t *__restrict__ hits,
-                                              const double *__restrict__ p, double *__restrict__ q)
-{
-    const K3Item it = items[blockIdx.x];
-    const DPair pr = pairs[it.pair];
-    const DObj oa = objs[pr.a];
-    const DObj ob = objs[pr.b];
-    const int16_t *__restrict__ h = hits + pr.hit_off;
-    if (it.kind == 0) {
-        const int lane = threadIdx.x & 63;
-        const int i = it.start + (int)(threadIdx.x >> 6);
-        if (i >= pr.Ta) return;
-        const double *__restrict__ pb = p + ob.traj_off;
-        double acc = 0.0;
-        for (int j = lane; j < pr.Tb; j += 64)
-            if (h[(int64_t)i * pr.Tb + j] >= 0) acc += pb[j];
-#pragma unroll
-        for (int m = 32; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 64);
-        if (lane == 0) q[oa.q_row + (int64_t)i * oa.n_scene_obj + ob.local] = fmin(acc, 1.0);
-    } else {
-        const int j = it.start + (int)threadIdx.x;
-        if (j >= pr.Tb) return;
-        const double *__restrict__ pa = p + oa.traj_off;
-        double acc = 0.0;
-        for (int i = 0; i < pr.Ta; ++i)
-            if (h[(int64_t)i * pr.Tb + j] >= 0) acc += pa[i];
-        q[ob.q_row + (int64_t)j * ob.n_scene_obj + oa.local] = fmin(acc, 1.0);
-    }
-}
-
-__global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs, const int32_t *__restrict__ pairmap,
+__global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs, const K3Item *__restrict__ items,
+                                              const int32_t *__restrict__ pairmap,
+                                              const unsigned long long *__restrict__ qacc,
                                               const double *__restrict__ p, double *__restrict__ q,
-                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit)
+                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit,
+                                              double *__restrict__ cpart, unsigned int *__restrict__ done)
 {
-    __shared__ double red[WG];
-    const DObj o = objs[blockIdx.x];
+    __shared__ double s_prod[4][K3_TRAJ];
+    __shared__ double s_val[K3_TRAJ];
+    __shared__ bool s_last;
+    const K3Item it = items[blockIdx.x];
+    const DObj o = objs[it.obj];
     const int n = o.n_scene_obj;
     const int32_t *__restrict__ pm = pairmap + o.pairmap_off;
     const int tid = threadIdx.x;
-    double part = 0.0;
-    for (int i = tid; i < o.T; i += WG) {
-        double *__restrict__ qi = q + o.q_row + (int64_t)i * n;
-        double no_collision = 1.0;
-        for (int b = 0; b < n; ++b) {
-            if (pm[b] < 0) {
-                qi[b] = 0.0;
-            } else {
-                no_collision *= 1.0 - qi[b];
-            }
+    const int il = tid & (K3_TRAJ - 1), quarter = tid / K3_TRAJ;
+    const int i = it.i0 + il;
+    double prod = 1.0;
+    if (i < o.T) {
+        const int64_t row = o.q_row + (int64_t)i * n;
+        for (int b = quarter; b < n; b += 4) {
+            double qv = 0.0;
+            if (pm[b] >= 0) qv = fmin((double)qacc[row + b] * kQInvScale, 1.0);
+            if (q) q[row + b] = qv;
+            prod *= 1.0 - qv;
         }
-        const double crit = 1.0 - no_collision;
-        traj_crit[o.traj_off + i] = crit;
-        part += p[o.traj_off + i] * crit;
     }
-    red[tid] = part;
+    s_prod[quarter][il] = prod;
     __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
+    if (quarter == 0) {
+        double val = 0.0;
+        if (i < o.T) {
+            const double crit = 1.0 - ((s_prod[0][il] * s_prod[1][il]) * s_prod[2][il]) * s_prod[3][il];
+            traj_crit[o.traj_off + i] = crit;
+            val = p[o.traj_off + i] * crit;
+        }
+        s_val[il] = val;
+    }
+    __syncthreads();
+    for (int st = K3_TRAJ / 2; st > 0; st >>= 1) {
+        if (tid < st) s_val[tid] += s_val[tid + st];
         __syncthreads();
     }
-    if (tid == 0) obj_crit[o.obj_out] = red[0];
+    if (tid == 0) {
+        cpart[it.part0 + it.blk] = s_val[0];
+        __threadfence();
+        const unsigned int prev = atomicAdd(&done[it.obj], 1u);
+        s_last = prev == (unsigned int)(it.n_blk - 1);
+    }
+    __syncthreads();
+    if (s_last && tid == 0) {
+        __threadfence();
+        double c = 0.0;
+        const volatile double *cp = cpart + it.part0;
+        for (int k = 0; k < it.n_blk; ++k) c += cp[k];
+        obj_crit[o.obj_out] = c;
+        done[it.obj] = 0u;  // ready for the next pass
+    }
 }
 
 // ===========================================================================
@@ -353,7 +430,8 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs, con
 hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_k1 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k1_trajgen, dim3(L.n_k1), dim3(WG), 0, s, L.objs, L.vals, L.k1, L.poses, L.p);
+    hipLaunchKernelGGL(k1_trajgen, dim3(L.n_k1), dim3(WG), 0, s, L.objs, L.vals, L.k1, L.poses, L.p, L.pfix, L.qacc,
+                       L.done);
     return hipGetLastError();
 }
 
@@ -361,10 +439,10 @@ hipError_t launch_collide(const Launch &L, hipStream_t s)
 {
     if (L.n_work <= 0) return hipSuccess;
     switch (L.variant) {
-    case 0: hipLaunchKernelGGL(k2_collide<0>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits); break;
-    case 1: hipLaunchKernelGGL(k2_collide<1>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits); break;
-    case 2: hipLaunchKernelGGL(k2_collide<2>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits); break;
-    case 3: hipLaunchKernelGGL(k2_collide<3>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits); break;
+    case 0: hipLaunchKernelGGL(k2_collide<0>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
+    case 1: hipLaunchKernelGGL(k2_collide<1>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
+    case 2: hipLaunchKernelGGL(k2_collide<2>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
+    case 3: hipLaunchKernelGGL(k2_collide<3>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -372,16 +450,10 @@ hipError_t launch_collide(const Launch &L, hipStream_t s)
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)
 {
-    if (L.n_k3 > 0) {
-        hipLaunchKernelGGL(k3_qsum, dim3(L.n_k3), dim3(WG), 0, s, L.objs, L.pairs, L.k3, L.hits, L.p, L.q);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (L.n_obj > 0) {
-        hipLaunchKernelGGL(k3_crit, dim3(L.n_obj), dim3(WG), 0, s, L.objs, L.pairmap, L.p, L.q, L.traj_crit, L.obj_crit);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+    if (L.n_k3 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_crit, dim3(L.n_k3), dim3(WG), 0, s, L.objs, L.k3, L.pairmap, L.qacc, L.p, L.q, L.traj_crit,
+                       L.obj_crit, L.cpart, L.done);
+    return hipGetLastError();
 }
 
 }  // namespace mhc

@@ -44,7 +44,10 @@ struct DPair {
     int64_t pose_a, pose_b;       // byte offsets of the two pose blocks
     float la, wa, lb, wb;         // half length / half width of vehicles
     float rr;                     // squared test radius: r_Q^2 (rect-circle), (r_P + r_Q)^2 (circle-circle)
-    float pad0;
+    int32_t qn;                   // q row stride: object count of the scene
+    int64_t qa0;                  // q index of (a, i = 0, b)
+    int64_t qb0;                  // q index of (b, j = 0, a)
+    int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
 };
 
 // One workgroup of the collision kernel: WG_ITEMS consecutive items of a pair.
@@ -53,26 +56,31 @@ struct WorkItem {
     int32_t item0;
 };
 
-// One workgroup of the trajectory kernel.
+// One workgroup of the trajectory kernel: K1_TPB trajectories of an object
+// starting at i0 (one wave each), or the probability normalisation of the
+// object when i0 < 0.
 struct K1Block {
     int32_t obj;
     int32_t i0;
 };
 
-// One workgroup of the q-sum kernel: 4 rows (one per wave) or 256 columns.
+// One workgroup of the criticality kernel: K3_TRAJ trajectories of an
+// object starting at i0; it is block `blk` of the object's n_blk blocks.
 struct K3Item {
-    int32_t pair;
-    int32_t kind;                 // 0 rows (q of a against b), 1 columns (q of b against a)
-    int32_t start;
-    int32_t pad;
+    int32_t obj;
+    int32_t i0;
+    int32_t blk;
+    int32_t n_blk;
+    int64_t part0;                // index of block 0's partial sum
 };
 
 constexpr int WG = 256;           // threads per workgroup, all kernels
 constexpr int WG_ITEMS = 256;     // collision items per workgroup
-constexpr int K1_VT = 16;         // vehicle trajectories per trajectory workgroup
-constexpr int K1_PT = 256;        // pedestrian trajectories per trajectory workgroup
-constexpr int K1_CH = 32;         // steps per trigonometry chunk
-constexpr int K3_ROWS = 4;        // rows per q-sum workgroup (one wave each)
+constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
+constexpr int K3_TRAJ = 64;       // trajectories per criticality workgroup
+// q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
+constexpr double kQScale = 4611686018427387904.0;        // 2^62
+constexpr double kQInvScale = 2.168404344971009e-19;     // 2^-62
 
 // Micro-tile shape per class, selected by a kernel variant id.
 struct TileShape {
@@ -97,6 +105,10 @@ struct Launch {
     const K3Item *k3;
     const int32_t *pairmap;
     char *poses;
+    unsigned long long *pfix;     // p * 2^62, per trajectory
+    unsigned long long *qacc;     // integer q sums [n_q]
+    double *cpart;                // per criticality block: sum_i p crit
+    unsigned int *done;           // per object: finished criticality blocks
     double *p;
     int16_t *hits;
     double *q;

@@ -65,6 +65,8 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
         }
         if (o.n_u < 1 || o.n_w < 1) return fail("object %d: n_u and n_w must be >= 1", a);
         if ((int64_t)o.n_u * o.n_w > kMaxTraj) return fail("object %d: n_u*n_w exceeds the trajectory limit", a);
+        if ((int64_t)o.n_u * o.n_w * s->horizon > kMaxPosesPerObject)
+            return fail("object %d: horizon * n_u * n_w exceeds the per-object pose limit (2^27)", a);
         if (!o.u || !o.w) return fail("object %d: control grids u and w must not be NULL", a);
         for (int k = 0; k < o.n_u; ++k)
             if (!finite(o.u[k])) return fail("object %d: control grid u must be finite", a);
@@ -150,8 +152,12 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
             d.speed = o.speed;
             d.tau = s.dt;
             L.objs.push_back(d);
-            const int step = o.kind == MHC_VEHICLE ? K1_VT : K1_PT;
-            for (int i0 = 0; i0 < d.T; i0 += step) L.k1.push_back(K1Block{obj_base + a, i0});
+            for (int i0 = 0; i0 < d.T; i0 += K1_TPB) L.k1.push_back(K1Block{obj_base + a, i0});
+            L.k1.push_back(K1Block{obj_base + a, -1});
+            const int n_blk = (d.T + K3_TRAJ - 1) / K3_TRAJ;
+            for (int b3 = 0; b3 < n_blk; ++b3)
+                L.k3.push_back(K3Item{obj_base + a, b3 * K3_TRAJ, b3, n_blk, L.n_cpart});
+            L.n_cpart += n_blk;
             toff += d.T;
         }
         pair_list(&s, plist);
@@ -176,6 +182,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
             pr.wa = (float)(oa.width / 2.0);
             pr.lb = (float)(ob.length / 2.0);
             pr.wb = (float)(ob.width / 2.0);
+            pr.qn = n;
+            pr.qa0 = L.objs[obj_base + a].q_row + b;
+            pr.qb0 = L.objs[obj_base + b].q_row + a;
+            pr.pa_off = L.objs[obj_base + a].traj_off;
+            pr.pb_off = L.objs[obj_base + b].traj_off;
             if (pr.cls == CLS_VP) pr.rr = (float)(ob.radius * ob.radius);
             else if (pr.cls == CLS_PV) pr.rr = (float)(oa.radius * oa.radius);
             else if (pr.cls == CLS_PP) pr.rr = (float)((oa.radius + ob.radius) * (oa.radius + ob.radius));
@@ -189,8 +200,6 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
                 costs.push_back(Cost{(double)cnt * ts.ri * ts.rj * pr.H * kClsCost[pr.cls], work.size()});
                 work.push_back(WorkItem{pidx, (int32_t)i0});
             }
-            for (int i0 = 0; i0 < pr.Ta; i0 += K3_ROWS) L.k3.push_back(K3Item{pidx, 0, i0, 0});
-            for (int j0 = 0; j0 < pr.Tb; j0 += WG) L.k3.push_back(K3Item{pidx, 1, j0, 0});
             hoff += (int64_t)pr.Ta * pr.Tb;
             ext.checks += (int64_t)pr.Ta * pr.Tb * s.horizon;
         }
@@ -225,6 +234,10 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
     L.o_pairmap = put(L.pairmap.size() * sizeof(int32_t));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
+    L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
+    L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
+    L.o_cpart = put((size_t)L.n_cpart * sizeof(double));
+    L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
     L.o_p = put((size_t)L.n_traj * sizeof(double));
     L.o_hits = put((size_t)L.n_hits * sizeof(int16_t));
     L.o_q = put((size_t)L.n_q * sizeof(double));
@@ -248,7 +261,7 @@ void pack_image(const Layout &L, char *dst)
     cp(L.o_pairmap, L.pairmap.data(), L.pairmap.size() * sizeof(int32_t));
 }
 
-Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out)
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits)
 {
     Launch X{};
     X.objs = reinterpret_cast<const DObj *>(base + L.o_objs);
@@ -259,11 +272,16 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out)
     X.k3 = reinterpret_cast<const K3Item *>(base + L.o_k3);
     X.pairmap = reinterpret_cast<const int32_t *>(base + L.o_pairmap);
     X.poses = base + L.o_poses;
+    X.pfix = reinterpret_cast<unsigned long long *>(base + L.o_pfix);
+    X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
+    X.cpart = reinterpret_cast<double *>(base + L.o_cpart);
+    X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
     X.q = reinterpret_cast<double *>(base + L.o_q);
     X.traj_crit = reinterpret_cast<double *>(base + L.o_tc);
     X.obj_crit = reinterpret_cast<double *>(base + L.o_oc);
+    if (!keep_hits) X.hits = nullptr;
     if (dev_out) {
         if (dev_out->traj_prob) X.p = dev_out->traj_prob;
         if (dev_out->first_hit) X.hits = dev_out->first_hit;
@@ -403,14 +421,14 @@ mhc_status ensure_device(mhc_ctx *ctx, size_t bytes)
 }
 
 static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, const mhc_result *dev_out,
-                                    hipStream_t s)
+                                    bool keep_hits, hipStream_t s)
 {
     char *host = nullptr;
     mhc_status st = stage_image(ctx, L, &host);
     if (st != MHC_OK) return st;
     HIPC(hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, s));
     HIPC(hipEventRecord(ctx->staging_ev, s));
-    Launch X = make_launch(L, dbase, dev_out);
+    Launch X = make_launch(L, dbase, dev_out, keep_hits);
     HIPC(launch_all(X, s));
     return MHC_OK;
 }
@@ -441,11 +459,11 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Layout &L = ctx->layout;
-    build_layout(scene, 1, ctx->variant_for(scene), L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), L);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    st = upload_and_launch(ctx, L, dbase, nullptr, ctx->stream);
+    st = upload_and_launch(ctx, L, dbase, nullptr, res->first_hit != nullptr, ctx->stream);
     if (st != MHC_OK) return st;
     st = copy_results(ctx, L, 0, dbase, res, ctx->stream);
     if (st != MHC_OK) return st;
@@ -467,13 +485,13 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     }
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     Layout L;
-    build_layout(scene, 1, ctx->variant_for(scene), L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), L);
     if (workspace_bytes < L.total_bytes) {
         ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
         return MHC_E_INVAL;
     }
     HIPC(hipSetDevice(ctx->device));
-    return upload_and_launch(ctx, L, static_cast<char *>(dev_workspace), dev_out,
+    return upload_and_launch(ctx, L, static_cast<char *>(dev_workspace), dev_out, false,
                              static_cast<hipStream_t>(hip_stream));
 }
 
@@ -508,7 +526,7 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     HIPC(hipSetDevice(ctx->device));
     mhc_plan *pl = new mhc_plan();
     pl->ctx = ctx;
-    build_layout(scene, 1, ctx->variant_for(scene), pl->L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), pl->L);
     pl->shape = shape_of(scene);
     if (ctx->budget && pl->L.total_bytes > ctx->budget) {
         ctx->err = "plan needs more device memory than the context budget";
@@ -557,8 +575,26 @@ extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, 
     if (!pl) return MHC_E_INVAL;
     mhc_ctx *ctx = pl->ctx;
     HIPC(hipSetDevice(ctx->device));
-    Launch X = make_launch(pl->L, pl->dbuf, dev_out);
+    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true);
     HIPC(launch_all(X, static_cast<hipStream_t>(hip_stream)));
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_plan_execute_stages(mhc_plan *pl, const mhc_result *dev_out, void *hip_stream,
+                                              uint32_t stages)
+{
+    if (!pl) return MHC_E_INVAL;
+    mhc_ctx *ctx = pl->ctx;
+    if (stages == 0 || stages > MHC_STAGE_ALL) {
+        ctx->err = "stages must be a non-empty combination of MHC_STAGE_* bits";
+        return MHC_E_INVAL;
+    }
+    HIPC(hipSetDevice(ctx->device));
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true);
+    if (stages & MHC_STAGE_TRAJ) HIPC(launch_trajgen(X, s));
+    if (stages & MHC_STAGE_COLLIDE) HIPC(launch_collide(X, s));
+    if (stages & MHC_STAGE_RISK) HIPC(launch_risk(X, s));
     return MHC_OK;
 }
 
@@ -610,11 +646,13 @@ extern "C" mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scen
 mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *res)
 {
     Layout &L = ctx->layout;
-    build_layout(scenes, n, ctx->variant, L);
+    build_layout(scenes, n, ctx->variant_for(scenes, n), L);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    st = upload_and_launch(ctx, L, dbase, nullptr, ctx->stream);
+    bool keep = false;
+    for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
+    st = upload_and_launch(ctx, L, dbase, nullptr, keep, ctx->stream);
     if (st != MHC_OK) return st;
     for (int k = 0; k < n; ++k) {
         st = copy_results(ctx, L, k, dbase, &res[k], ctx->stream);

@@ -1,7 +1,9 @@
 // Host-side runtime structures (not part of the public ABI).
 #pragma once
 
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "mhc.h"
@@ -11,6 +13,7 @@ namespace mhc {
 
 constexpr int kMaxObjects = 4096;
 constexpr int64_t kMaxTraj = 1 << 15;     // trajectories per object (T_a*T_b < 2^31)
+constexpr int64_t kMaxPosesPerObject = int64_t(1) << 27;  // pose block < 2 GiB (32-bit buffer offsets)
 constexpr int kDefaultVariant = 0;
 
 // Result extents of one scene inside a (possibly multi-scene) layout.
@@ -21,7 +24,8 @@ struct SceneExt {
 };
 
 // Host tables of one launch plus the byte layout of its device workspace:
-// [scene image: tables uploaded in one copy][poses][p][first hits][q][traj crit][object crit]
+// [scene image: tables uploaded in one copy][poses][p * 2^62][integer q sums][criticality block sums]
+// [per-object counters][p][first hits][q][traj crit][object crit]
 struct Layout {
     std::vector<DObj> objs;
     std::vector<double> vals;
@@ -31,17 +35,17 @@ struct Layout {
     std::vector<K3Item> k3;
     std::vector<int32_t> pairmap;
     std::vector<SceneExt> sc;
-    int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
+    int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0, n_cpart = 0;
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
-    size_t o_poses = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
+    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_cpart = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L);
 void pack_image(const Layout &L, char *dst);
-Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out);
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits);
 hipError_t launch_all(const Launch &X, hipStream_t s);
 
 }  // namespace mhc
@@ -58,9 +62,12 @@ struct mhc_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_ev = nullptr;
     mhc::Layout layout;           // reused by mhc_evaluate
-    int variant = mhc::kDefaultVariant;
-    int variant_for(const mhc_scene *) const { return variant; }
+    int forced_variant = -1;                      // mhc_set_variant
+    std::map<std::pair<int, int>, int> tuned;     // size class -> variant (mhc_autotune)
+    int variant_for(const mhc_scene *scenes, int n) const;
 };
+
+std::pair<int, int> size_class(const mhc_scene *scenes, int n);
 
 mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);
 mhc_status copy_results(mhc_ctx *ctx, const mhc::Layout &L, int k, const char *dbase, const mhc_result *res,

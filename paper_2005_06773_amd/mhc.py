@@ -28,7 +28,9 @@ _STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE"
 EXPORTED = [
     "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes",
     "mhc_evaluate", "mhc_evaluate_async",
-    "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_download", "mhc_plan_destroy",
+    "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages",
+    "mhc_plan_download", "mhc_plan_destroy",
+    "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load",
     "mhc_evaluate_batch",
     "mhc_server_start", "mhc_submit", "mhc_wait", "mhc_server_stats", "mhc_server_stop",
 ]
@@ -111,8 +113,14 @@ def _load():
         "mhc_plan_create": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(V)],
         "mhc_plan_update": [V, ctypes.POINTER(mhc_scene)],
         "mhc_plan_execute": [V, ctypes.POINTER(mhc_result), V],
+        "mhc_plan_execute_stages": [V, ctypes.POINTER(mhc_result), V, ctypes.c_uint32],
         "mhc_plan_download": [V, ctypes.POINTER(mhc_result)],
         "mhc_plan_destroy": [V],
+        "mhc_set_variant": [V, ctypes.c_int32],
+        "mhc_autotune": [V, ctypes.POINTER(mhc_scene), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(ctypes.c_double)],
+        "mhc_tune_save": [V, ctypes.c_char_p],
+        "mhc_tune_load": [V, ctypes.c_char_p],
         "mhc_evaluate_batch": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
         "mhc_server_start": [V, ctypes.POINTER(mhc_server_cfg), ctypes.POINTER(V)],
         "mhc_submit": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result),
@@ -289,6 +297,15 @@ def mhc_plan_execute(plan: Plan, dev_out: Optional[mhc_result] = None, stream=No
                                           ctypes.c_void_p(sp)))
 
 
+MHC_STAGE_TRAJ, MHC_STAGE_COLLIDE, MHC_STAGE_RISK, MHC_STAGE_ALL = 1, 2, 4, 7
+
+
+def mhc_plan_execute_stages(plan: Plan, stages: int, dev_out: Optional[mhc_result] = None, stream=None):
+    sp = 0 if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(plan.ctx, lib.mhc_plan_execute_stages(plan.h, ctypes.byref(dev_out) if dev_out is not None else None,
+                                                 ctypes.c_void_p(sp), stages))
+
+
 def mhc_plan_download(plan: Plan, first_hit: bool = True, q: bool = True) -> dict:
     out, r = host_result(plan.cs, first_hit, q)
     _check(plan.ctx, lib.mhc_plan_download(plan.h, ctypes.byref(r)))
@@ -297,6 +314,32 @@ def mhc_plan_download(plan: Plan, first_hit: bool = True, q: bool = True) -> dic
 
 def mhc_plan_destroy(plan: Plan):
     plan.close()
+
+
+# ---- tile autotuning -------------------------------------------------------
+
+MHC_N_VARIANTS = 4
+
+
+def mhc_set_variant(ctx, variant: int):
+    _check(ctx, lib.mhc_set_variant(ctx, variant))
+
+
+def mhc_autotune(ctx, scene, reps: int = 20):
+    """Returns (best variant, [microseconds per launch of each variant])."""
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    best = ctypes.c_int32()
+    us = (ctypes.c_double * MHC_N_VARIANTS)()
+    _check(ctx, lib.mhc_autotune(ctx, ctypes.byref(cs.c), reps, ctypes.byref(best), us))
+    return best.value, list(us)
+
+
+def mhc_tune_save(ctx, path: str):
+    _check(ctx, lib.mhc_tune_save(ctx, path.encode()))
+
+
+def mhc_tune_load(ctx, path: str):
+    _check(ctx, lib.mhc_tune_load(ctx, path.encode()))
 
 
 # ---- server ---------------------------------------------------------------

@@ -135,6 +135,9 @@ def test_plan_and_async_match_evaluate(mhc, ctx):
     s = sg.eleven_object_scene(1)
     say("plan / async / evaluate on the 11-object scene")
     ref = mhc.mhc_evaluate(ctx, s)
+    # without the first-hit output the criticality is bit for bit the same
+    noh = mhc.mhc_evaluate(ctx, s, first_hit=False)
+    parity.same_results({k: v for k, v in ref.items() if k != "first_hit"}, noh, "no first-hit output")
     plan = mhc.mhc_plan_create(ctx, s)
     for rep in range(3):
         mhc.mhc_plan_execute(plan)
@@ -209,4 +212,4 @@ def test_stress_scene_sampled_pairs(mhc, ctx):
     acc = oracle.accepted_first_hits(k32, o)
     assert acc.all(), f"{(~acc).sum()} rejected"
     say(f"  sampled entries {k32.size}, exact {np.mean(k32 == o.k64):.7f}, hits {(o.k64 >= 0).sum()}")
-    assert np.all((g["object_crit"] >= 0) & (g["object_crit"] <= 1))
+    assert np.all((g["object_crit"] >= 0) & (g["object_crit"] <= 1 + 1e-12))

@@ -229,7 +229,7 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
                                               unsigned long long *__restrict__ qacc, const Check chk)
 {
     const int n_ig = pr.n_ig, n_jg = pr.n_jg;
-    const int f = item0 + (int)threadIdx.x;
+    const int f = item0 + (int)(threadIdx.x & (WAVE - 1));
     if (f >= n_ig * n_jg) return;
     const int ig = f / n_jg;
     const int jg = f - ig * n_jg;
@@ -337,15 +337,25 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
     }
 }
 
+// Collision kernel: one wave per bin of work units. The host packs the units
+// longest-first onto exactly as many waves as the GPU holds at once, using
+// their exact instruction cost (class, micro-tile, horizon), so every SIMD
+// finishes at about the same time without any cross-XCD atomics.
 template <int V>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
+                                                 const int32_t *__restrict__ bins, int n_bins,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc)
 {
-    const WorkItem w = work[blockIdx.x];
-    const DPair pr = pairs[w.pair];
-    collide_work<V>(pr, w.item0, poses, hits, pfix, qacc);
+    const int wave = (int)blockIdx.x * (WG / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if (wave >= n_bins) return;
+    const int k1 = bins[wave + 1];
+    for (int k = bins[wave]; k < k1; ++k) {
+        const WorkItem w = work[k];
+        const DPair pr = pairs[w.pair];
+        collide_work<V>(pr, w.item0, poses, hits, pfix, qacc);
+    }
 }
 
 // ===========================================================================
@@ -435,17 +445,44 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int V>
+static hipError_t launch_k2(const Launch &L, hipStream_t s)
+{
+    const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
+    hipLaunchKernelGGL(k2_collide<V>, dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.poses, L.hits,
+                       L.pfix, L.qacc);
+    return hipGetLastError();
+}
+
 hipError_t launch_collide(const Launch &L, hipStream_t s)
 {
     if (L.n_work <= 0) return hipSuccess;
     switch (L.variant) {
-    case 0: hipLaunchKernelGGL(k2_collide<0>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
-    case 1: hipLaunchKernelGGL(k2_collide<1>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
-    case 2: hipLaunchKernelGGL(k2_collide<2>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
-    case 3: hipLaunchKernelGGL(k2_collide<3>, dim3(L.n_work), dim3(WG), 0, s, L.pairs, L.work, L.poses, L.hits, L.pfix, L.qacc); break;
+    case 0: return launch_k2<0>(L, s);
+    case 1: return launch_k2<1>(L, s);
+    case 2: return launch_k2<2>(L, s);
+    case 3: return launch_k2<3>(L, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+}
+
+template <int V>
+static int k2_resident_blocks()
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V>, WG, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+int collide_blocks_per_cu(int variant)
+{
+    switch (variant) {
+    case 0: return k2_resident_blocks<0>();
+    case 1: return k2_resident_blocks<1>();
+    case 2: return k2_resident_blocks<2>();
+    default: return k2_resident_blocks<3>();
+    }
 }
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)

@@ -50,7 +50,10 @@ struct DPair {
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
 };
 
-// One workgroup of the collision kernel: WG_ITEMS consecutive items of a pair.
+// One unit of collision work for one wave: the WAVE_ITEMS consecutive items
+// item0 .. item0+63 of a pair (lane l takes item0 + l; items past the pair's
+// end are idle lanes). Units are packed on the host into one range per
+// resident wave of the collision kernel.
 struct WorkItem {
     int32_t pair;
     int32_t item0;
@@ -75,7 +78,8 @@ struct K3Item {
 };
 
 constexpr int WG = 256;           // threads per workgroup, all kernels
-constexpr int WG_ITEMS = 256;     // collision items per workgroup
+constexpr int WAVE = 64;          // wavefront size
+constexpr int WAVE_ITEMS = WAVE;  // collision items per work unit (one per lane)
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
 constexpr int K3_TRAJ = 64;       // trajectories per criticality workgroup
 // q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
@@ -87,12 +91,14 @@ struct TileShape {
     int ri, rj;
 };
 constexpr int N_VARIANTS = 4;
-// variant -> shape per class {VV, VP, PV, PP}
+// variant -> shape per class {VV, VP, PV, PP}. The shapes keep the VALU cost
+// of one work unit similar across classes (27, 14 and 6 VALU per
+// rect-rect, rect-circle and circle-circle test) and the loads per test low.
 constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {
-    {{2, 2}, {2, 2}, {2, 2}, {2, 2}},
-    {{4, 1}, {4, 1}, {4, 1}, {4, 2}},
-    {{2, 4}, {2, 4}, {4, 2}, {4, 4}},
+    {{2, 2}, {2, 2}, {2, 2}, {4, 4}},
+    {{2, 2}, {4, 2}, {2, 4}, {4, 4}},
     {{4, 2}, {4, 2}, {2, 4}, {4, 4}},
+    {{2, 1}, {2, 2}, {2, 2}, {4, 2}},
 };
 
 // Launch entry points (kernels.hip).
@@ -109,17 +115,19 @@ struct Launch {
     unsigned long long *qacc;     // integer q sums [n_q]
     double *cpart;                // per criticality block: sum_i p crit
     unsigned int *done;           // per object: finished criticality blocks
+    const int32_t *bins;          // [n_bins+1] work-unit range of each collision wave
     double *p;
     int16_t *hits;
     double *q;
     double *traj_crit;
     double *obj_crit;
-    int n_obj, n_pairs, n_work, n_k1, n_k3;
+    int n_obj, n_pairs, n_work, n_k1, n_k3, n_bins;
     int variant;
 };
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s);
 hipError_t launch_collide(const Launch &L, hipStream_t s);
 hipError_t launch_risk(const Launch &L, hipStream_t s);
+int collide_blocks_per_cu(int variant);  // resident workgroups of the collision kernel per CU
 
 }  // namespace mhc

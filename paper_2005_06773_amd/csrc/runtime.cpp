@@ -4,6 +4,8 @@
 #include "runtime.h"
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,7 +25,9 @@ static int cls_of(int ka, int kb)
 }
 
 // Relative VALU cost of one check per class, for longest-first ordering.
-static const double kClsCost[N_CLS] = {27.0, 14.0, 14.0, 6.0};
+static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4};
+// Per-unit cost outside the step loop (setup, result stores), same units.
+static const double kUnitOverhead = 120.0;
 
 static bool finite(double v) { return std::isfinite(v); }
 
@@ -98,16 +102,16 @@ static void pair_list(const mhc_scene *s, std::vector<std::pair<int, int>> &out)
             if (s->pairs == MHC_PAIRS_ALL || a == 0) out.emplace_back(a, b);
 }
 
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L)
 {
     L = Layout();
     L.variant = variant;
-    struct Cost {
-        double c;
-        size_t idx;
+    struct PairCost {
+        double c;        // cost of one of the pair's work units
+        int32_t pidx;
+        int32_t n_units;
     };
-    std::vector<Cost> costs;
-    std::vector<WorkItem> work;
+    std::vector<PairCost> costs;
     std::vector<std::pair<int, int>> plist;
     for (int k = 0; k < n_scenes; ++k) {
         const mhc_scene &s = scenes[k];
@@ -139,18 +143,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
             d.pose_off = (int64_t)L.pose_bytes;
             L.pose_bytes += align256((size_t)s.horizon * d.T * (o.kind == MHC_VEHICLE ? 16 : 8));
             d.u_off = (int64_t)L.vals.size();
-            L.vals.insert(L.vals.end(), o.u, o.u + o.n_u);
-            d.w_off = (int64_t)L.vals.size();
-            L.vals.insert(L.vals.end(), o.w, o.w + o.n_w);
-            d.score_off = (int64_t)L.vals.size();
-            if (o.score) L.vals.insert(L.vals.end(), o.score, o.score + d.T);
+            d.w_off = d.u_off + o.n_u;
+            d.score_off = d.w_off + o.n_w;
+            L.vals.resize(L.vals.size() + o.n_u + o.n_w + (o.score ? d.T : 0));
             d.pairmap_off = pm_base + (int64_t)a * n;
             d.obj_out = L.n_obj + a;
-            d.x = o.x;
-            d.y = o.y;
-            d.heading = o.heading;
-            d.speed = o.speed;
-            d.tau = s.dt;
             L.objs.push_back(d);
             for (int i0 = 0; i0 < d.T; i0 += K1_TPB) L.k1.push_back(K1Block{obj_base + a, i0});
             L.k1.push_back(K1Block{obj_base + a, -1});
@@ -178,28 +175,20 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
             pr.hit_off = L.n_hits + hoff;
             pr.pose_a = L.objs[obj_base + a].pose_off;
             pr.pose_b = L.objs[obj_base + b].pose_off;
-            pr.la = (float)(oa.length / 2.0);
-            pr.wa = (float)(oa.width / 2.0);
-            pr.lb = (float)(ob.length / 2.0);
-            pr.wb = (float)(ob.width / 2.0);
             pr.qn = n;
             pr.qa0 = L.objs[obj_base + a].q_row + b;
             pr.qb0 = L.objs[obj_base + b].q_row + a;
             pr.pa_off = L.objs[obj_base + a].traj_off;
             pr.pb_off = L.objs[obj_base + b].traj_off;
-            if (pr.cls == CLS_VP) pr.rr = (float)(ob.radius * ob.radius);
-            else if (pr.cls == CLS_PV) pr.rr = (float)(oa.radius * oa.radius);
-            else if (pr.cls == CLS_PP) pr.rr = (float)((oa.radius + ob.radius) * (oa.radius + ob.radius));
             const int pidx = (int)L.pairs.size();
             L.pairs.push_back(pr);
             L.pairmap[pm_base + (int64_t)a * n + b] = pidx;
             L.pairmap[pm_base + (int64_t)b * n + a] = pidx;
             const int64_t items = (int64_t)pr.n_ig * pr.n_jg;
-            for (int64_t i0 = 0; i0 < items; i0 += WG_ITEMS) {
-                const int64_t cnt = std::min<int64_t>(WG_ITEMS, items - i0);
-                costs.push_back(Cost{(double)cnt * ts.ri * ts.rj * pr.H * kClsCost[pr.cls], work.size()});
-                work.push_back(WorkItem{pidx, (int32_t)i0});
-            }
+            // a wave executes every step of every test of a unit, whether or
+            // not all of its lanes hold an item
+            const double unit_cost = (double)ts.ri * ts.rj * pr.H * kClsCost[pr.cls] + kUnitOverhead;
+            costs.push_back(PairCost{unit_cost, pidx, (int32_t)((items + WAVE_ITEMS - 1) / WAVE_ITEMS)});
             hoff += (int64_t)pr.Ta * pr.Tb;
             ext.checks += (int64_t)pr.Ta * pr.Tb * s.horizon;
         }
@@ -213,11 +202,59 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
         L.n_obj += n;
         L.n_checks += ext.checks;
     }
-    // Longest work first, so that the ragged end of the launch is made of the
-    // cheapest workgroups; ties keep list order.
-    std::stable_sort(costs.begin(), costs.end(), [](const Cost &x, const Cost &y) { return x.c > y.c; });
-    L.work.resize(work.size());
-    for (size_t k = 0; k < costs.size(); ++k) L.work[k] = work[costs[k].idx];
+    // Pack the units onto the collision waves, longest first, each to the
+    // least-loaded wave. Units of one pair shape cost the same, so the list
+    // splits into a few groups of equal cost: a group gives every wave one
+    // unit per full round and its remainder to the least-loaded waves.
+    std::stable_sort(costs.begin(), costs.end(), [](const PairCost &x, const PairCost &y) { return x.c > y.c; });
+    int64_t n_units = 0;
+    for (const PairCost &pc : costs) n_units += pc.n_units;
+    const int n_bins = (int)std::max<int64_t>(1, std::min<int64_t>(n_units, max_waves > 0 ? max_waves : n_units));
+    std::vector<WorkItem> units((size_t)n_units);
+    std::vector<int32_t> unit_bin((size_t)n_units);
+    {
+        // `order` lists the waves by (load, index); a group's remainder goes
+        // to its first m waves, which stay sorted among themselves after the
+        // increment, so one merge restores the order.
+        std::vector<double> load((size_t)n_bins, 0.0);
+        std::vector<int32_t> order((size_t)n_bins), merged((size_t)n_bins);
+        for (int b = 0; b < n_bins; ++b) order[b] = b;
+        auto before = [&](int32_t x, int32_t y) { return load[x] < load[y] || (load[x] == load[y] && x < y); };
+        int64_t k = 0;
+        size_t p0 = 0;
+        while (p0 < costs.size()) {
+            size_t p1 = p0;
+            int64_t m_total = 0;
+            while (p1 < costs.size() && costs[p1].c == costs[p0].c) m_total += costs[p1++].n_units;
+            const double c = costs[p0].c;
+            const int64_t full = m_total / n_bins, rem = m_total % n_bins;
+            // unit g of the group goes to wave order[g mod n_bins]: the first
+            // `full` rounds cover every wave, the remainder the least-loaded
+            int pos = 0;
+            for (size_t p = p0; p < p1; ++p)
+                for (int32_t u = 0; u < costs[p].n_units; ++u, ++k) {
+                    units[k] = WorkItem{costs[p].pidx, u * WAVE_ITEMS};
+                    unit_bin[k] = order[pos];
+                    if (++pos == n_bins) pos = 0;
+                }
+            for (int b = 0; b < n_bins; ++b) load[b] += c * full;
+            for (int64_t i = 0; i < rem; ++i) load[order[i]] += c;
+            if (rem > 0) {
+                std::merge(order.begin() + rem, order.end(), order.begin(), order.begin() + rem, merged.begin(), before);
+                order.swap(merged);
+            }
+            p0 = p1;
+        }
+    }
+    // group the units by wave (longest first inside each wave)
+    L.bins.assign(n_bins + 1, 0);
+    for (int64_t k = 0; k < n_units; ++k) ++L.bins[unit_bin[k] + 1];
+    for (int b = 0; b < n_bins; ++b) L.bins[b + 1] += L.bins[b];
+    L.work.resize((size_t)n_units);
+    {
+        std::vector<int32_t> fill(L.bins.begin(), L.bins.end() - 1);
+        for (int64_t k = 0; k < n_units; ++k) L.work[fill[unit_bin[k]]++] = units[k];
+    }
 
     size_t off = 0;
     auto put = [&](size_t bytes) {
@@ -229,6 +266,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
     L.o_vals = put(L.vals.size() * sizeof(double));
     L.o_pairs = put(L.pairs.size() * sizeof(DPair));
     L.o_work = put(L.work.size() * sizeof(WorkItem));
+    L.o_bins = put(L.bins.size() * sizeof(int32_t));
     L.o_k1 = put(L.k1.size() * sizeof(K1Block));
     L.o_k3 = put(L.k3.size() * sizeof(K3Item));
     L.o_pairmap = put(L.pairmap.size() * sizeof(int32_t));
@@ -244,6 +282,43 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L)
     L.o_tc = put((size_t)L.n_traj * sizeof(double));
     L.o_oc = put((size_t)L.n_obj * sizeof(double));
     L.total_bytes = off;
+    fill_values(scenes, n_scenes, L);
+}
+
+// The value part of a layout: states, control grids, scores and extents.
+// Everything else in a layout depends only on the scene shapes.
+void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
+{
+    size_t oi = 0, pi = 0;
+    std::vector<std::pair<int, int>> plist;
+    for (int k = 0; k < n_scenes; ++k) {
+        const mhc_scene &s = scenes[k];
+        for (int a = 0; a < s.n_objects; ++a, ++oi) {
+            const mhc_object &o = s.objects[a];
+            DObj &d = L.objs[oi];
+            d.x = o.x;
+            d.y = o.y;
+            d.heading = o.heading;
+            d.speed = o.speed;
+            d.tau = s.dt;
+            std::copy(o.u, o.u + o.n_u, L.vals.begin() + d.u_off);
+            std::copy(o.w, o.w + o.n_w, L.vals.begin() + d.w_off);
+            if (o.score) std::copy(o.score, o.score + d.T, L.vals.begin() + d.score_off);
+        }
+        pair_list(&s, plist);
+        for (auto &ab : plist) {
+            const mhc_object &oa = s.objects[ab.first], &ob = s.objects[ab.second];
+            DPair &pr = L.pairs[pi++];
+            pr.la = (float)(oa.length / 2.0);
+            pr.wa = (float)(oa.width / 2.0);
+            pr.lb = (float)(ob.length / 2.0);
+            pr.wb = (float)(ob.width / 2.0);
+            pr.rr = 0.0f;
+            if (pr.cls == CLS_VP) pr.rr = (float)(ob.radius * ob.radius);
+            else if (pr.cls == CLS_PV) pr.rr = (float)(oa.radius * oa.radius);
+            else if (pr.cls == CLS_PP) pr.rr = (float)((oa.radius + ob.radius) * (oa.radius + ob.radius));
+        }
+    }
 }
 
 void pack_image(const Layout &L, char *dst)
@@ -256,12 +331,13 @@ void pack_image(const Layout &L, char *dst)
     cp(L.o_vals, L.vals.data(), L.vals.size() * sizeof(double));
     cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair));
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem));
+    cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t));
     cp(L.o_k1, L.k1.data(), L.k1.size() * sizeof(K1Block));
     cp(L.o_k3, L.k3.data(), L.k3.size() * sizeof(K3Item));
     cp(L.o_pairmap, L.pairmap.data(), L.pairmap.size() * sizeof(int32_t));
 }
 
-Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits)
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu)
 {
     Launch X{};
     X.objs = reinterpret_cast<const DObj *>(base + L.o_objs);
@@ -276,6 +352,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
     X.cpart = reinterpret_cast<double *>(base + L.o_cpart);
     X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
+    X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
     X.q = reinterpret_cast<double *>(base + L.o_q);
@@ -295,6 +372,8 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_k1 = (int)L.k1.size();
     X.n_k3 = (int)L.k3.size();
     X.variant = L.variant;
+    X.n_bins = (int)L.bins.size() - 1;
+    (void)n_cu;
     return X;
 }
 
@@ -363,6 +442,13 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
     delete ctx;
 }
 
+int mhc_ctx::max_waves(int v)
+{
+    if (v < 0 || v >= N_VARIANTS) v = 0;
+    if (!waves_cache[v]) waves_cache[v] = n_cu * collide_blocks_per_cu(v) * (WG / WAVE);
+    return waves_cache[v];
+}
+
 extern "C" const char *mhc_last_error(const mhc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
 
 extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
@@ -370,14 +456,49 @@ extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
     if (!out) return MHC_E_INVAL;
     std::string err;
     if (!validate_scene(scene, err)) return MHC_E_INVAL;
+    // The workspace size depends on the micro-tile variant and on how many
+    // waves the GPU holds; report the largest over all variants with one
+    // wave per work unit, which bounds every actual layout.
+    size_t bytes = 0;
     Layout L;
-    build_layout(scene, 1, kDefaultVariant, L);
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        build_layout(scene, 1, v, 0, L);
+        bytes = std::max(bytes, L.total_bytes);
+    }
     out->n_traj = L.n_traj;
     out->n_pairs = (int64_t)L.pairs.size();
     out->n_traj_pairs = L.n_hits;
     out->n_checks = L.n_checks;
-    out->device_bytes = L.total_bytes;
+    out->device_bytes = bytes;
     return MHC_OK;
+}
+
+std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
+{
+    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs};
+    for (int a = 0; a < s->n_objects; ++a) {
+        v.push_back(s->objects[a].kind);
+        v.push_back(s->objects[a].n_u);
+        v.push_back(s->objects[a].n_w);
+        v.push_back(s->objects[a].score != nullptr);
+    }
+    return v;
+}
+
+// Layout of `scene` for this context: the shape-dependent tables of the
+// previous call are reused when the shape (and the tile variant) repeats.
+static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L)
+{
+    const int v = ctx->variant_for(scene, 1);
+    std::vector<int32_t> shape = shape_of(scene);
+    shape.push_back(v);
+    shape.push_back(ctx->max_waves(v));
+    if (!L.objs.empty() && shape == ctx->layout_shape) {
+        fill_values(scene, 1, L);
+        return;
+    }
+    build_layout(scene, 1, v, ctx->max_waves(v), L);
+    ctx->layout_shape = std::move(shape);
 }
 
 // Pinned staging for the scene image. The previous upload from it must have
@@ -428,7 +549,7 @@ static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, 
     if (st != MHC_OK) return st;
     HIPC(hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, s));
     HIPC(hipEventRecord(ctx->staging_ev, s));
-    Launch X = make_launch(L, dbase, dev_out, keep_hits);
+    Launch X = make_launch(L, dbase, dev_out, keep_hits, ctx->n_cu);
     HIPC(launch_all(X, s));
     return MHC_OK;
 }
@@ -459,7 +580,7 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Layout &L = ctx->layout;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), L);
+    layout_for(ctx, scene, L);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
@@ -485,7 +606,7 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     }
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     Layout L;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), L);
     if (workspace_bytes < L.total_bytes) {
         ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
         return MHC_E_INVAL;
@@ -506,17 +627,6 @@ struct mhc_plan {
     std::vector<int32_t> shape;   // kinds, grid sizes, horizon, pair mode
 };
 
-static std::vector<int32_t> shape_of(const mhc_scene *s)
-{
-    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs};
-    for (int a = 0; a < s->n_objects; ++a) {
-        v.push_back(s->objects[a].kind);
-        v.push_back(s->objects[a].n_u);
-        v.push_back(s->objects[a].n_w);
-        v.push_back(s->objects[a].score != nullptr);
-    }
-    return v;
-}
 
 extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_plan **out)
 {
@@ -526,7 +636,7 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     HIPC(hipSetDevice(ctx->device));
     mhc_plan *pl = new mhc_plan();
     pl->ctx = ctx;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), pl->L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), pl->L);
     pl->shape = shape_of(scene);
     if (ctx->budget && pl->L.total_bytes > ctx->budget) {
         ctx->err = "plan needs more device memory than the context budget";
@@ -561,7 +671,7 @@ extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
     }
     HIPC(hipSetDevice(ctx->device));
     Layout L;
-    build_layout(scene, 1, pl->L.variant, L);
+    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant), L);
     std::vector<char> img(L.image_bytes);
     pack_image(L, img.data());
     HIPC(hipDeviceSynchronize());
@@ -575,7 +685,7 @@ extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, 
     if (!pl) return MHC_E_INVAL;
     mhc_ctx *ctx = pl->ctx;
     HIPC(hipSetDevice(ctx->device));
-    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true);
+    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true, ctx->n_cu);
     HIPC(launch_all(X, static_cast<hipStream_t>(hip_stream)));
     return MHC_OK;
 }
@@ -591,7 +701,7 @@ extern "C" mhc_status mhc_plan_execute_stages(mhc_plan *pl, const mhc_result *de
     }
     HIPC(hipSetDevice(ctx->device));
     const hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true);
+    Launch X = make_launch(pl->L, pl->dbuf, dev_out, true, ctx->n_cu);
     if (stages & MHC_STAGE_TRAJ) HIPC(launch_trajgen(X, s));
     if (stages & MHC_STAGE_COLLIDE) HIPC(launch_collide(X, s));
     if (stages & MHC_STAGE_RISK) HIPC(launch_risk(X, s));
@@ -646,7 +756,8 @@ extern "C" mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scen
 mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *res)
 {
     Layout &L = ctx->layout;
-    build_layout(scenes, n, ctx->variant_for(scenes, n), L);
+    ctx->layout_shape.clear();
+    build_layout(scenes, n, ctx->variant_for(scenes, n), ctx->max_waves(ctx->variant_for(scenes, n)), L);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);

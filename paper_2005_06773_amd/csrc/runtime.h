@@ -30,22 +30,26 @@ struct Layout {
     std::vector<DObj> objs;
     std::vector<double> vals;
     std::vector<DPair> pairs;
-    std::vector<WorkItem> work;
+    std::vector<WorkItem> work;     // grouped by collision wave
+    std::vector<int32_t> bins;       // [n_bins+1] range of each collision wave in `work`
     std::vector<K1Block> k1;
     std::vector<K3Item> k3;
     std::vector<int32_t> pairmap;
     std::vector<SceneExt> sc;
     int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0, n_cpart = 0;
     size_t pose_bytes = 0;
-    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
+    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_cpart = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, Layout &L);
+// max_waves: resident waves of the collision kernel (0 = one per work unit).
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L);
+void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
 void pack_image(const Layout &L, char *dst);
-Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits);
+std::vector<int32_t> shape_of(const mhc_scene *s);
+Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu);
 hipError_t launch_all(const Launch &X, hipStream_t s);
 
 }  // namespace mhc
@@ -62,9 +66,12 @@ struct mhc_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_ev = nullptr;
     mhc::Layout layout;           // reused by mhc_evaluate
+    std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::pair<int, int>, int> tuned;     // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;
+    int waves_cache[mhc::N_VARIANTS] = {};
+    int max_waves(int variant);                   // resident collision waves on this GPU
 };
 
 std::pair<int, int> size_class(const mhc_scene *scenes, int n);

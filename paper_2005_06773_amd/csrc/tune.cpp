@@ -77,14 +77,14 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
     mhc_status st = MHC_OK;
     for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
         Layout L;
-        build_layout(scene, 1, v, L);
+        build_layout(scene, 1, v, ctx->max_waves(v), L);
         st = ensure_device(ctx, L.total_bytes);
         if (st != MHC_OK) break;
         char *base = static_cast<char *>(ctx->dbuf);
         std::vector<char> img(L.image_bytes);
         pack_image(L, img.data());
         hipError_t e = hipMemcpy(base, img.data(), L.image_bytes, hipMemcpyHostToDevice);
-        Launch X = make_launch(L, base, nullptr, false);
+        Launch X = make_launch(L, base, nullptr, false, ctx->n_cu);
         double total_ms = 0.0;
         for (int r = 0; r <= reps && e == hipSuccess; ++r) {
             e = launch_trajgen(X, ctx->stream);

@@ -337,24 +337,36 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
     }
 }
 
-// Collision kernel: one wave per bin of work units. The host packs the units
-// longest-first onto exactly as many waves as the GPU holds at once, using
-// their exact instruction cost (class, micro-tile, horizon), so every SIMD
-// finishes at about the same time without any cross-XCD atomics.
+// Collision kernel: every wave owns one slot of the host-built plan and runs
+// its segments. For plans of contiguous stretches (large scenes) the slots
+// are numbered XCD-major (workgroups are dealt to the XCDs in turn), so the
+// pairs one XCD works on stay together in its L2; for individually packed
+// plans neighbouring slots are spread over the XCDs and CUs, which mixes the
+// load-heavy and arithmetic-heavy test classes on every CU. The host
+// balances the slots by the exact instruction cost of the work, so every
+// SIMD finishes together without any cross-XCD atomics.
 template <int V>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
-                                                 const int32_t *__restrict__ bins, int n_bins,
+                                                 const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc)
 {
-    const int wave = (int)blockIdx.x * (WG / WAVE) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    if (wave >= n_bins) return;
-    const int k1 = bins[wave + 1];
-    for (int k = bins[wave]; k < k1; ++k) {
+    const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int blocks = (int)gridDim.x;
+    const int xcd = (int)blockIdx.x % N_XCD, round = (int)blockIdx.x / N_XCD;
+    const int per_xcd = (blocks / N_XCD) * (WG / WAVE);
+    int slot;
+    if (xcd_major && (int)blockIdx.x < (blocks / N_XCD) * N_XCD)
+        slot = xcd * per_xcd + round * (WG / WAVE) + wave_in_block;
+    else
+        slot = (int)blockIdx.x * (WG / WAVE) + wave_in_block;  // grid not a multiple of the XCD count
+    if (slot >= n_bins) return;
+    const int s1 = bins[slot + 1];
+    for (int k = bins[slot]; k < s1; ++k) {
         const WorkItem w = work[k];
         const DPair pr = pairs[w.pair];
-        collide_work<V>(pr, w.item0, poses, hits, pfix, qacc);
+        for (int u = 0; u < w.n_units; ++u) collide_work<V>(pr, w.item0 + u * WAVE_ITEMS, poses, hits, pfix, qacc);
     }
 }
 
@@ -449,8 +461,8 @@ template <int V>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL(k2_collide<V>, dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.poses, L.hits,
-                       L.pfix, L.qacc);
+    hipLaunchKernelGGL(k2_collide<V>, dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.xcd_major,
+                       L.poses, L.hits, L.pfix, L.qacc);
     return hipGetLastError();
 }
 

@@ -50,13 +50,15 @@ struct DPair {
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
 };
 
-// One unit of collision work for one wave: the WAVE_ITEMS consecutive items
-// item0 .. item0+63 of a pair (lane l takes item0 + l; items past the pair's
-// end are idle lanes). Units are packed on the host into one range per
-// resident wave of the collision kernel.
+// A run of collision work for one wave: n_units consecutive units of a pair,
+// a unit being the WAVE_ITEMS items item0 + 64u .. item0 + 64u + 63 (lane l
+// takes item0 + 64u + l; items past the pair's end are idle lanes). The host
+// assigns every wave of the collision kernel a range of segments.
 struct WorkItem {
     int32_t pair;
     int32_t item0;
+    int32_t n_units;
+    int32_t pad;
 };
 
 // One workgroup of the trajectory kernel: K1_TPB trajectories of an object
@@ -80,6 +82,7 @@ struct K3Item {
 constexpr int WG = 256;           // threads per workgroup, all kernels
 constexpr int WAVE = 64;          // wavefront size
 constexpr int WAVE_ITEMS = WAVE;  // collision items per work unit (one per lane)
+constexpr int N_XCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
 constexpr int K3_TRAJ = 64;       // trajectories per criticality workgroup
 // q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
@@ -115,13 +118,14 @@ struct Launch {
     unsigned long long *qacc;     // integer q sums [n_q]
     double *cpart;                // per criticality block: sum_i p crit
     unsigned int *done;           // per object: finished criticality blocks
-    const int32_t *bins;          // [n_bins+1] work-unit range of each collision wave
+    const int32_t *bins;          // [n_bins+1] segment range of each collision wave slot
     double *p;
     int16_t *hits;
     double *q;
     double *traj_crit;
     double *obj_crit;
     int n_obj, n_pairs, n_work, n_k1, n_k3, n_bins;
+    int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
 };
 

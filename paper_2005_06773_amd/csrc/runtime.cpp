@@ -7,6 +7,7 @@
 #include <functional>
 #include <queue>
 #include <cmath>
+#include <numeric>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -28,6 +29,9 @@ static int cls_of(int ka, int kb)
 static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4};
 // Per-unit cost outside the step loop (setup, result stores), same units.
 static const double kUnitOverhead = 120.0;
+// From this many work units per collision wave on, waves take contiguous
+// stretches of the unit sequence instead of individually packed units.
+static const int kContiguousUnitsPerWave = 8;
 
 static bool finite(double v) { return std::isfinite(v); }
 
@@ -202,59 +206,97 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         L.n_obj += n;
         L.n_checks += ext.checks;
     }
-    // Pack the units onto the collision waves, longest first, each to the
-    // least-loaded wave. Units of one pair shape cost the same, so the list
-    // splits into a few groups of equal cost: a group gives every wave one
-    // unit per full round and its remainder to the least-loaded waves.
-    std::stable_sort(costs.begin(), costs.end(), [](const PairCost &x, const PairCost &y) { return x.c > y.c; });
+    // Collision plan: every wave slot gets a list of segments of work units.
     int64_t n_units = 0;
-    for (const PairCost &pc : costs) n_units += pc.n_units;
+    double total_cost = 0.0;
+    for (const PairCost &pc : costs) {
+        n_units += pc.n_units;
+        total_cost += pc.c * pc.n_units;
+    }
     const int n_bins = (int)std::max<int64_t>(1, std::min<int64_t>(n_units, max_waves > 0 ? max_waves : n_units));
-    std::vector<WorkItem> units((size_t)n_units);
-    std::vector<int32_t> unit_bin((size_t)n_units);
-    {
-        // `order` lists the waves by (load, index); a group's remainder goes
-        // to its first m waves, which stay sorted among themselves after the
-        // increment, so one merge restores the order.
+    L.work.clear();
+    L.bins.assign(n_bins + 1, 0);
+    L.contiguous = n_units >= (int64_t)kContiguousUnitsPerWave * n_bins;
+    if (L.contiguous) {
+        // Many units per wave: each slot takes the next stretch of the unit
+        // sequence (pairs in scene order) worth total/n_bins of cost, so the
+        // plan is O(pairs + waves) and neighbouring slots, which sit on one
+        // XCD, work on neighbouring pairs.
+        const double per_slot = total_cost / n_bins;
+        size_t p = 0;
+        int32_t u = 0;
+        double acc = 0.0;
+        for (int sl = 0; sl < n_bins; ++sl) {
+            L.bins[sl] = (int32_t)L.work.size();
+            const double goal = (sl + 1) * per_slot;
+            while (p < costs.size()) {
+                const PairCost &pc = costs[p];
+                const int32_t left = pc.n_units - u;
+                int32_t k = left;
+                if (sl < n_bins - 1) {
+                    const double want = std::floor((goal - acc) / pc.c + 0.5);
+                    k = (int32_t)std::max(0.0, std::min((double)left, want));
+                }
+                if (k > 0) {
+                    L.work.push_back(WorkItem{pc.pidx, u * WAVE_ITEMS, k, 0});
+                    acc += pc.c * k;
+                    u += k;
+                }
+                if (u == pc.n_units) {
+                    ++p;
+                    u = 0;
+                } else {
+                    break;
+                }
+            }
+        }
+    } else {
+        // Few units per wave: longest first, each to the least-loaded wave.
+        // Units of one pair shape cost the same, so the list splits into a
+        // few groups of equal cost: unit g of a group goes to the wave at
+        // position g mod n_bins of the (load, index) order, i.e. every wave
+        // once per full round and the remainder to the least-loaded ones.
+        std::vector<PairCost> sorted(costs);
+        std::stable_sort(sorted.begin(), sorted.end(), [](const PairCost &x, const PairCost &y) { return x.c > y.c; });
+        std::vector<WorkItem> units((size_t)n_units);
+        std::vector<int32_t> unit_bin((size_t)n_units);
         std::vector<double> load((size_t)n_bins, 0.0);
         std::vector<int32_t> order((size_t)n_bins), merged((size_t)n_bins);
         for (int b = 0; b < n_bins; ++b) order[b] = b;
         auto before = [&](int32_t x, int32_t y) { return load[x] < load[y] || (load[x] == load[y] && x < y); };
         int64_t k = 0;
         size_t p0 = 0;
-        while (p0 < costs.size()) {
+        while (p0 < sorted.size()) {
             size_t p1 = p0;
             int64_t m_total = 0;
-            while (p1 < costs.size() && costs[p1].c == costs[p0].c) m_total += costs[p1++].n_units;
-            const double c = costs[p0].c;
+            while (p1 < sorted.size() && sorted[p1].c == sorted[p0].c) m_total += sorted[p1++].n_units;
+            const double c = sorted[p0].c;
             const int64_t full = m_total / n_bins, rem = m_total % n_bins;
-            // unit g of the group goes to wave order[g mod n_bins]: the first
-            // `full` rounds cover every wave, the remainder the least-loaded
             int pos = 0;
-            for (size_t p = p0; p < p1; ++p)
-                for (int32_t u = 0; u < costs[p].n_units; ++u, ++k) {
-                    units[k] = WorkItem{costs[p].pidx, u * WAVE_ITEMS};
+            for (size_t pp = p0; pp < p1; ++pp)
+                for (int32_t u = 0; u < sorted[pp].n_units; ++u, ++k) {
+                    units[k] = WorkItem{sorted[pp].pidx, u * WAVE_ITEMS, 1, 0};
                     unit_bin[k] = order[pos];
                     if (++pos == n_bins) pos = 0;
                 }
             for (int b = 0; b < n_bins; ++b) load[b] += c * full;
             for (int64_t i = 0; i < rem; ++i) load[order[i]] += c;
             if (rem > 0) {
+                // the first `rem` waves stay sorted among themselves after the
+                // increment, so one merge restores the order
                 std::merge(order.begin() + rem, order.end(), order.begin(), order.begin() + rem, merged.begin(), before);
                 order.swap(merged);
             }
             p0 = p1;
         }
-    }
-    // group the units by wave (longest first inside each wave)
-    L.bins.assign(n_bins + 1, 0);
-    for (int64_t k = 0; k < n_units; ++k) ++L.bins[unit_bin[k] + 1];
-    for (int b = 0; b < n_bins; ++b) L.bins[b + 1] += L.bins[b];
-    L.work.resize((size_t)n_units);
-    {
+        // group the units by wave (longest first inside each wave)
+        for (int64_t i = 0; i < n_units; ++i) ++L.bins[unit_bin[i] + 1];
+        for (int b = 0; b < n_bins; ++b) L.bins[b + 1] += L.bins[b];
+        L.work.resize((size_t)n_units);
         std::vector<int32_t> fill(L.bins.begin(), L.bins.end() - 1);
-        for (int64_t k = 0; k < n_units; ++k) L.work[fill[unit_bin[k]]++] = units[k];
+        for (int64_t i = 0; i < n_units; ++i) L.work[fill[unit_bin[i]]++] = units[i];
     }
+    L.bins[n_bins] = (int32_t)L.work.size();
 
     size_t off = 0;
     auto put = [&](size_t bytes) {
@@ -373,6 +415,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_k3 = (int)L.k3.size();
     X.variant = L.variant;
     X.n_bins = (int)L.bins.size() - 1;
+    X.xcd_major = L.contiguous ? 1 : 0;
     (void)n_cu;
     return X;
 }

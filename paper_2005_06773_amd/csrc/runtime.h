@@ -41,6 +41,7 @@ struct Layout {
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_cpart = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
+    bool contiguous = false;      // collision plan of contiguous stretches
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);

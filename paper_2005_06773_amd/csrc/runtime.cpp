@@ -106,10 +106,11 @@ static void pair_list(const mhc_scene *s, std::vector<std::pair<int, int>> &out)
             if (s->pairs == MHC_PAIRS_ALL || a == 0) out.emplace_back(a, b);
 }
 
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L)
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits)
 {
     L = Layout();
     L.variant = variant;
+    L.with_hits = with_hits;
     struct PairCost {
         double c;        // cost of one of the pair's work units
         int32_t pidx;
@@ -319,7 +320,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_cpart = put((size_t)L.n_cpart * sizeof(double));
     L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
     L.o_p = put((size_t)L.n_traj * sizeof(double));
-    L.o_hits = put((size_t)L.n_hits * sizeof(int16_t));
+    L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
     L.o_q = put((size_t)L.n_q * sizeof(double));
     L.o_tc = put((size_t)L.n_traj * sizeof(double));
     L.o_oc = put((size_t)L.n_obj * sizeof(double));
@@ -400,7 +401,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.q = reinterpret_cast<double *>(base + L.o_q);
     X.traj_crit = reinterpret_cast<double *>(base + L.o_tc);
     X.obj_crit = reinterpret_cast<double *>(base + L.o_oc);
-    if (!keep_hits) X.hits = nullptr;
+    if (!keep_hits || !L.with_hits) X.hits = nullptr;
     if (dev_out) {
         if (dev_out->traj_prob) X.p = dev_out->traj_prob;
         if (dev_out->first_hit) X.hits = dev_out->first_hit;
@@ -505,7 +506,7 @@ extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
     size_t bytes = 0;
     Layout L;
     for (int v = 0; v < N_VARIANTS; ++v) {
-        build_layout(scene, 1, v, 0, L);
+        build_layout(scene, 1, v, 0, L, true);
         bytes = std::max(bytes, L.total_bytes);
     }
     out->n_traj = L.n_traj;
@@ -530,17 +531,18 @@ std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
 
 // Layout of `scene` for this context: the shape-dependent tables of the
 // previous call are reused when the shape (and the tile variant) repeats.
-static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L)
+static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool with_hits)
 {
     const int v = ctx->variant_for(scene, 1);
     std::vector<int32_t> shape = shape_of(scene);
     shape.push_back(v);
     shape.push_back(ctx->max_waves(v));
+    shape.push_back(with_hits);
     if (!L.objs.empty() && shape == ctx->layout_shape) {
         fill_values(scene, 1, L);
         return;
     }
-    build_layout(scene, 1, v, ctx->max_waves(v), L);
+    build_layout(scene, 1, v, ctx->max_waves(v), L, with_hits);
     ctx->layout_shape = std::move(shape);
 }
 
@@ -623,7 +625,7 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Layout &L = ctx->layout;
-    layout_for(ctx, scene, L);
+    layout_for(ctx, scene, L, res->first_hit != nullptr);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
@@ -649,7 +651,7 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     }
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     Layout L;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), L, true);
     if (workspace_bytes < L.total_bytes) {
         ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
         return MHC_E_INVAL;
@@ -679,7 +681,7 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     HIPC(hipSetDevice(ctx->device));
     mhc_plan *pl = new mhc_plan();
     pl->ctx = ctx;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), pl->L);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), pl->L, true);
     pl->shape = shape_of(scene);
     if (ctx->budget && pl->L.total_bytes > ctx->budget) {
         ctx->err = "plan needs more device memory than the context budget";
@@ -714,7 +716,7 @@ extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
     }
     HIPC(hipSetDevice(ctx->device));
     Layout L;
-    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant), L);
+    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant), L, true);
     std::vector<char> img(L.image_bytes);
     pack_image(L, img.data());
     HIPC(hipDeviceSynchronize());
@@ -800,12 +802,12 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
 {
     Layout &L = ctx->layout;
     ctx->layout_shape.clear();
-    build_layout(scenes, n, ctx->variant_for(scenes, n), ctx->max_waves(ctx->variant_for(scenes, n)), L);
+    bool keep = false;
+    for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
+    build_layout(scenes, n, ctx->variant_for(scenes, n), ctx->max_waves(ctx->variant_for(scenes, n)), L, keep);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    bool keep = false;
-    for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
     st = upload_and_launch(ctx, L, dbase, nullptr, keep, ctx->stream);
     if (st != MHC_OK) return st;
     for (int k = 0; k < n; ++k) {

@@ -42,11 +42,12 @@ struct Layout {
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_cpart = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
+    bool with_hits = true;        // the workspace holds the first-hit matrix
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L);
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
 void pack_image(const Layout &L, char *dst);
 std::vector<int32_t> shape_of(const mhc_scene *s);

@@ -77,7 +77,7 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
     mhc_status st = MHC_OK;
     for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
         Layout L;
-        build_layout(scene, 1, v, ctx->max_waves(v), L);
+        build_layout(scene, 1, v, ctx->max_waves(v), L, false);
         st = ensure_device(ctx, L.total_bytes);
         if (st != MHC_OK) break;
         char *base = static_cast<char *>(ctx->dbuf);

@@ -1,0 +1,145 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* every entry point declared in include/mhc.h is exported by libmhc.so;
+* mhc_query_sizes reproduces the paper's trajectory and combination counts
+  (Sec. IV-B.4, IV-C.2, Table I) and the benchmark workloads' check counts;
+* malformed scenes are rejected with MHC_E_INVAL before any device work;
+* without a GPU, mhc_create fails with MHC_E_DEVICE.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2005_06773_amd import scenegen as sg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mhc():
+    from paper_2005_06773_amd import mhc as m
+    return m
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mhc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhc_\w+)\s*\(", text)))
+
+
+def test_every_declared_entry_point_is_exported(mhc):
+    names = declared_symbols()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(mhc.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(names) == set(mhc.EXPORTED)
+
+
+def _golden():
+    vals = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_counts.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, val = line.split()[:2]
+            vals[name] = int(val)
+    return vals
+
+
+def _paper_shaped_scene(n_co, n_acc=6, horizon=100):
+    """EGO with n_acc x 343 trajectories, each CO with n_acc x 7, 20 ms steps,
+    EGO-only pairs (the execution-time experiment of Sec. VI-B)."""
+    T = sg.paper_shaped_sizes(n_co, n_acc)
+    objs = []
+    for k, t in enumerate(T):
+        n_w = t // n_acc
+        objs.append(sg.SceneObject(sg.VEHICLE, 10.0 * k, 0.0, 0.0, 10.0, 4.5, 1.8, 0.0,
+                                   sg.accel_grid(n_acc, -9.7, 9.7), sg.yaw_grid(n_w), None))
+    return sg.Scene(objs, horizon, 0.02, pairs=sg.PAIRS_EGO)
+
+
+def test_query_sizes_reproduce_paper_counts(mhc):
+    g = _golden()
+    s2 = mhc.mhc_query_sizes(_paper_shaped_scene(10))
+    assert s2["n_traj"] == g["r_tra_o10"]
+    assert s2["n_traj_pairs"] == g["r_col_o10"]
+    assert 2 * s2["n_checks"] == g["overlap_calls_s2"]
+    assert round(s2["n_checks"] / 1e4) * 1e4 == g["pose_combinations_s2_6"]
+    s1 = mhc.mhc_query_sizes(_paper_shaped_scene(3))
+    assert round(s1["n_checks"] / 1e4) * 1e4 == g["pose_combinations_s1_6"]
+    s1_5 = mhc.mhc_query_sizes(_paper_shaped_scene(3, n_acc=5))
+    assert abs(s1_5["n_checks"] - g["pose_combinations_s1_5"]) <= 2e4
+
+
+def test_query_sizes_of_the_workloads(mhc):
+    q = mhc.mhc_query_sizes(sg.eleven_object_scene(1))
+    assert q["n_checks"] == 83_531_250 and q["n_pairs"] == 55 and q["n_traj"] == 2475
+    q = mhc.mhc_query_sizes(sg.stress_scene(4))
+    assert q["n_checks"] == 40_894_464_000 and q["n_pairs"] == 780
+    q = mhc.mhc_query_sizes(sg.two_vehicle_scene(0))
+    assert q["n_checks"] == 18_750
+    # the workspace holds at least every output and the poses
+    s = sg.eleven_object_scene(1)
+    q = mhc.mhc_query_sizes(s)
+    pose_bytes = sum(o.n_traj * s.horizon * (16 if o.kind == sg.VEHICLE else 8) for o in s.objects)
+    assert q["device_bytes"] > pose_bytes + 2 * q["n_traj_pairs"] + 8 * q["n_traj"] * (s.n_objects + 3)
+
+
+def _bad_scenes():
+    out = {}
+
+    def base():
+        return sg.two_vehicle_scene(0)
+    s = base(); s.objects[0].x = float("nan"); out["nan_state"] = s
+    s = base(); s.objects[1].heading = float("inf"); out["inf_heading"] = s
+    s = base(); s.objects[1].length = -1.0; out["negative_length"] = s
+    s = base(); s.objects[1].width = 0.0; out["zero_width"] = s
+    s = base(); s.objects[0].speed = -1.0; out["negative_speed"] = s
+    s = base(); s.horizon = 0; out["zero_horizon"] = s
+    s = base(); s.horizon = 40000; out["huge_horizon"] = s
+    s = base(); s.dt = 0.0; out["zero_dt"] = s
+    s = base(); s.dt = float("nan"); out["nan_dt"] = s
+    s = base(); s.objects[1].score = np.zeros(25); out["zero_scores"] = s
+    s = base(); s.objects[1].score = -np.ones(25); out["negative_scores"] = s
+    s = base(); s.objects = s.objects[:1]; out["one_object"] = s
+    s = base(); s.objects[0].kind = 7; out["bad_kind"] = s
+    s = base(); s.pairs = 3; out["bad_pair_mode"] = s
+    s = base(); s.objects[0].u = np.array([0.0, float("nan")]); out["nan_control"] = s
+    s = base(); s.objects[0].kind = sg.PEDESTRIAN; s.objects[0].radius = 0.3; s.pairs = sg.PAIRS_EGO
+    out["pedestrian_ego_in_ego_mode"] = s
+    s = base(); s.objects[1] = sg.SceneObject(sg.PEDESTRIAN, 0, 0, 0, 1, 0, 0, 0.0, np.array([1.0]), np.array([0.0]))
+    out["zero_radius"] = s
+    s = base(); s.objects[0].u = np.zeros(200); s.objects[0].w = np.zeros(200); out["too_many_trajectories"] = s
+    s = base(); s.horizon = 30000; s.objects[0].u = np.zeros(100); s.objects[0].w = np.zeros(100)
+    out["pose_block_too_large"] = s
+    return out
+
+
+@pytest.mark.parametrize("name", list(_bad_scenes().keys()))
+def test_invalid_scene_rejected_on_host(mhc, name):
+    s = _bad_scenes()[name]
+    with pytest.raises(mhc.MhcError) as ei:
+        mhc.mhc_query_sizes(s)
+    assert ei.value.status == mhc.MHC_E_INVAL
+
+
+def test_degenerate_but_valid_scenes_accepted(mhc):
+    s = sg.Scene([sg.SceneObject(sg.VEHICLE, 0, 0, 0, 0, 4.5, 1.8, 0, np.array([0.0]), np.array([0.0]), None),
+                  sg.SceneObject(sg.PEDESTRIAN, 1, 0, 0, 0, 0, 0, 0.3, np.array([0.0]), np.array([0.0]),
+                                 np.array([2.0]))], 1, 1e-3)
+    q = mhc.mhc_query_sizes(s)
+    assert q["n_checks"] == 1 and q["n_traj_pairs"] == 1
+
+
+def test_create_without_gpu_reports_device_error(mhc):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(mhc.MhcError) as ei:
+        mhc.mhc_create(0)
+    assert ei.value.status == mhc.MHC_E_DEVICE

@@ -51,6 +51,31 @@ def class_checks(scene):
     return out
 
 
+def recorded_traffic(variant):
+    """HBM bytes per collision launch from the committed counter runs
+    (profiles/k2_collide_eleven_object_traffic.txt), each counter scaled by
+    what it reads for a plain copy kernel of known size; None when the kernel
+    sources or the tile variant differ from those the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k2_collide_eleven_object_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("paper_2005_06773_amd/csrc/kernels.hip", "paper_2005_06773_amd/csrc/mhc_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("kernel_source_sha256") != h.hexdigest() or int(rec.get("variant", -1)) != variant:
+        return None
+    copy_kib = float(rec["copy_mib"]) * 1024.0
+    fetch = float(rec["fetch_kib_per_dispatch"]) * copy_kib / float(rec["copy_fetch_kib"])
+    write = float(rec["write_kib_per_dispatch"]) * copy_kib / float(rec["copy_write_kib"])
+    return (fetch + write) * 1024.0
+
+
 def pct(xs, q):
     xs = sorted(xs)
     k = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
@@ -80,6 +105,62 @@ def cpu_baseline(scene, checks, seconds):
 scene_seed = 1
 
 
+def serve(mhc, ctx, sg, seconds):
+    """Serving workload: 32 streams, each a Poisson process at 10 Hz with a
+    start offset in U(0, 100 ms), frames drawn as in the batched workload
+    (seed 3), replayed in real time; then the same arrivals through a plain
+    per-frame mhc_evaluate loop. Latency = arrival -> results in host memory."""
+    import threading
+    warm = 1.0
+    events = [e for e in sg.serving_schedule(3, 32, 10.0, seconds, warm)]
+    frames = [(t, sid, mhc.CScene(sc)) for t, sid, sc in events]
+    checks = [mhc.mhc_query_sizes(c)["n_checks"] for _, _, c in frames]
+    srv = mhc.Server(ctx, budget=4 << 30, inflight=2)
+    tickets = []
+    done = {}
+
+    def waiter():
+        k = 0
+        while k < len(frames):
+            while len(tickets) <= k:
+                time.sleep(0.0002)
+            t_ticket = tickets[k]
+            _, timing = srv.wait(t_ticket)
+            done[k] = timing
+            k += 1
+
+    w = threading.Thread(target=waiter)
+    w.start()
+    t0 = time.perf_counter()
+    for t, sid, cs in frames:
+        while time.perf_counter() - t0 < t:
+            time.sleep(0.0001)
+        tickets.append(srv.submit(sid, cs))
+    w.join()
+    srv.stop()
+    lat = [(done[k]["done_ns"] - done[k]["submit_ns"]) * 1e-6 for k in range(len(frames)) if frames[k][0] >= warm]
+    busy_checks = sum(c for (t, _, _), c in zip(frames, checks) if t >= warm)
+    out = {"streams": 32, "rate_hz_per_stream": 10, "seconds": seconds, "frames": len(lat),
+           "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
+           "deadline_ms": 50.0, "within_deadline": sum(x <= 50.0 for x in lat) / len(lat),
+           "sustained_checks_per_s": busy_checks / seconds}
+    # the same arrivals through the plain per-frame loop
+    lat2 = []
+    t0 = time.perf_counter()
+    for (t, sid, cs) in frames:
+        while time.perf_counter() - t0 < t:
+            time.sleep(0.0001)
+        mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
+        if t >= warm:
+            lat2.append((time.perf_counter() - t0 - t) * 1e3)
+    out["plain_loop"] = {"p50_ms": pct(lat2, 50), "p99_ms": pct(lat2, 99), "max_ms": max(lat2),
+                         "within_deadline": sum(x <= 50.0 for x in lat2) / len(lat2)}
+    log(f"served: {len(lat)} frames, p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms "
+        f"({out['sustained_checks_per_s']:.3g} checks/s offered); plain loop p50 {out['plain_loop']['p50_ms']:.2f} "
+        f"ms p99 {out['plain_loop']['p99_ms']:.2f} ms")
+    return out
+
+
 def main():
     global scene_seed
     ap = argparse.ArgumentParser(description=__doc__)
@@ -90,6 +171,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the latency and batched measurements")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="length of the served-load measurement (after 1 s of warm-up)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force a collision micro-tile variant (default: autotune on the workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -116,9 +199,11 @@ def main():
     if args.variant >= 0:
         mhc.mhc_set_variant(ctx, args.variant)
         tune = {"forced": args.variant}
+        variant = args.variant
     else:
         best, us = mhc.mhc_autotune(ctx, cs, reps=20)
         tune = {"chosen": best, "us_per_variant": [round(u, 2) for u in us]}
+        variant = best
         log(f"autotune: collision kernel us per variant {[round(u, 1) for u in us]} -> variant {best}")
     plan = mhc.mhc_plan_create(ctx, cs)
     out, r = mhc.device_result(cs, first_hit=True, q=True)
@@ -126,9 +211,11 @@ def main():
     T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
 
     if args.calibrate_copy:
+        # one plain elementwise kernel that reads MIB MiB and writes MIB MiB
         src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read, {args.calibrate_copy} MiB written")
         del src, dst
@@ -183,7 +270,7 @@ def main():
                    "seed": args.seed, "pairs": "all", "inputs": "resident in HBM"},
         "tile_variant": tune,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(variant),
                      "kernel": "k2_collide", "kernel_us": k2_ms * 1e3, "flops_per_launch": flops,
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                      "valu_issue_frac_est": lane_ops / (k2_ms / 1e3) / LANE_OPS_PER_S},
@@ -226,6 +313,8 @@ def main():
                              "speedup": tp / tb}
         log(f"batched 64 scenes: {tb * 1e3:.2f} ms ({bchecks / tb:.4g} checks/s) vs plain loop "
             f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
+
+        result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
 
     plan.close()
     mhc.mhc_destroy(ctx)

@@ -245,6 +245,18 @@ def main():
         mhc.mhc_plan_execute_stages(plan, R, r, stream)
     torch.cuda.synchronize()
     k2_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+
+    # The same steps replayed as one captured HIP graph per step (reported only).
+    mhc.mhc_plan_set_graph(plan, True)
+    for _ in range(5):
+        mhc.mhc_plan_execute(plan, r, stream)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(args.steps):
+        mhc.mhc_plan_execute(plan, r, stream)
+    torch.cuda.synchronize()
+    graph_step_us = (time.perf_counter() - a) * 1e6 / args.steps
+    mhc.mhc_plan_set_graph(plan, False)
     achieved = flops / (k2_ms * 1e-3) / 1e12
     log(f"step {ms_step * 1e3:.1f} us -> {value:.4g} checks/s; collision kernel {k2_ms * 1e3:.1f} us -> "
         f"{achieved:.2f} TFLOP/s ({checks / (k2_ms / 1e3):.4g} checks/s)")
@@ -269,6 +281,7 @@ def main():
                    "trajectories_per_object": 225, "horizon": 30, "dt": 0.1, "checks": checks,
                    "seed": args.seed, "pairs": "all", "inputs": "resident in HBM"},
         "tile_variant": tune,
+        "graph_step_us": graph_step_us,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(variant),
                      "kernel": "k2_collide", "kernel_us": k2_ms * 1e3, "flops_per_launch": flops,

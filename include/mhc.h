@@ -162,6 +162,10 @@ mhc_status mhc_plan_execute(mhc_plan *plan, const mhc_result *dev_out, void *hip
 enum { MHC_STAGE_TRAJ = 1, MHC_STAGE_COLLIDE = 2, MHC_STAGE_RISK = 4, MHC_STAGE_ALL = 7 };
 mhc_status mhc_plan_execute_stages(mhc_plan *plan, const mhc_result *dev_out, void *hip_stream,
                                    uint32_t stages);
+/* Launch mode of mhc_plan_execute: 0 (default) enqueues the module kernels
+ * directly; 1 captures them once per set of output pointers into a HIP graph
+ * and replays it (one launch call; results identical). */
+mhc_status mhc_plan_set_graph(mhc_plan *plan, int32_t enable);
 /* Copies the plan-owned results of the last execute to host buffers (sync). */
 mhc_status mhc_plan_download(mhc_plan *plan, mhc_result *host_out);
 void mhc_plan_destroy(mhc_plan *plan);

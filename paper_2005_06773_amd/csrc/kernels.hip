@@ -57,19 +57,21 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
     if (tid == 0) done[obj] = 0u;
 }
 
+// Grid: x = trajectory block (K1_TPB trajectories, one wave each) plus one
+// last block for the object's probability normalisation, y = object.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
-                                                 const K1Block *__restrict__ blocks, char *__restrict__ poses,
-                                                 double *__restrict__ p, unsigned long long *__restrict__ pfix,
+                                                 char *__restrict__ poses, double *__restrict__ p,
+                                                 unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
 {
-    const K1Block blk = blocks[blockIdx.x];
-    const DObj o = objs[blk.obj];
-    if (blk.i0 < 0) {
-        normalise_probabilities(o, blk.obj, vals, p, pfix, qacc, done);
+    const int obj = (int)blockIdx.y;
+    const DObj o = objs[obj];
+    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        normalise_probabilities(o, obj, vals, p, pfix, qacc, done);
         return;
     }
     const int lane = threadIdx.x & 63;
-    const int i = blk.i0 + (int)(threadIdx.x >> 6);
+    const int i = (int)blockIdx.x * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double tau = o.tau;
@@ -374,75 +376,57 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
 // K3: risk assessment (Sec. IV-D, IV-D.2).
 //
 // The collision kernel has left q_{a,i;b} = sum_j [hit] p_{b,j} as exact
-// integer sums (units of 2^-62). Per trajectory, k3_crit converts them
-// (rounding once), clamps to 1 and forms
-//   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b}),
-// four threads per trajectory each multiplying the objects b = m (mod 4) in
-// ascending order, the four products combined in a fixed order. The object's
-// criticality C_a = sum_i p_{a,i} crit_{a,i} is summed per block in a fixed
-// tree, and the last block of the object to finish adds the block sums in
-// block order. Nothing depends on how the collision work was tiled or
-// batched, so every result is identical for any tiling and any batch.
+// integer sums (units of 2^-62). One workgroup per object: each thread takes
+// trajectories i = tid, tid + 256, ..., converts the sums (rounding once),
+// clamps to 1, writes q and forms
+//   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b),
+// and the workgroup adds C_a = sum_i p_{a,i} crit_{a,i} in a fixed tree.
+// Nothing depends on how the collision work was tiled or batched, so every
+// result is identical for any tiling and any batch.
 // ===========================================================================
 
-__global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs, const K3Item *__restrict__ items,
-                                              const int32_t *__restrict__ pairmap,
+__global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
                                               const unsigned long long *__restrict__ qacc,
                                               const double *__restrict__ p, double *__restrict__ q,
-                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit,
-                                              double *__restrict__ cpart, unsigned int *__restrict__ done)
+                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit)
 {
-    __shared__ double s_prod[4][K3_TRAJ];
-    __shared__ double s_val[K3_TRAJ];
-    __shared__ bool s_last;
-    const K3Item it = items[blockIdx.x];
-    const DObj o = objs[it.obj];
+    __shared__ double red[WG];
+    const DObj o = objs[blockIdx.x];
     const int n = o.n_scene_obj;
-    const int32_t *__restrict__ pm = pairmap + o.pairmap_off;
     const int tid = threadIdx.x;
-    const int il = tid & (K3_TRAJ - 1), quarter = tid / K3_TRAJ;
-    const int i = it.i0 + il;
-    double prod = 1.0;
-    if (i < o.T) {
-        const int64_t row = o.q_row + (int64_t)i * n;
-        for (int b = quarter; b < n; b += 4) {
-            double qv = 0.0;
-            if (pm[b] >= 0) qv = fmin((double)qacc[row + b] * kQInvScale, 1.0);
-            if (q) q[row + b] = qv;
-            prod *= 1.0 - qv;
+    double acc = 0.0;
+    for (int i = tid; i < o.T; i += WG) {
+        // The trajectory kernel zeroed all n accumulators of this trajectory,
+        // so b == a and objects outside the pair set read as q = 0. Loads are
+        // issued eight at a time, ahead of the dependent product.
+        const unsigned long long *__restrict__ qa = qacc + o.q_row + (int64_t)i * n;
+        double *__restrict__ qi = q ? q + o.q_row + (int64_t)i * n : nullptr;
+        const double pi = p[o.traj_off + i];
+        double no_collision = 1.0;
+        for (int b0 = 0; b0 < n; b0 += 8) {
+            unsigned long long v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = b0 + k < n ? qa[b0 + k] : 0ull;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (b0 + k < n) {
+                    const double qv = fmin((double)v[k] * kQInvScale, 1.0);
+                    if (qi) qi[b0 + k] = qv;
+                    no_collision *= 1.0 - qv;
+                }
+            }
         }
+        const double crit = 1.0 - no_collision;
+        traj_crit[o.traj_off + i] = crit;
+        acc += pi * crit;
     }
-    s_prod[quarter][il] = prod;
+    red[tid] = acc;
     __syncthreads();
-    if (quarter == 0) {
-        double val = 0.0;
-        if (i < o.T) {
-            const double crit = 1.0 - ((s_prod[0][il] * s_prod[1][il]) * s_prod[2][il]) * s_prod[3][il];
-            traj_crit[o.traj_off + i] = crit;
-            val = p[o.traj_off + i] * crit;
-        }
-        s_val[il] = val;
-    }
-    __syncthreads();
-    for (int st = K3_TRAJ / 2; st > 0; st >>= 1) {
-        if (tid < st) s_val[tid] += s_val[tid + st];
+    for (int st = WG / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
         __syncthreads();
     }
-    if (tid == 0) {
-        cpart[it.part0 + it.blk] = s_val[0];
-        __threadfence();
-        const unsigned int prev = atomicAdd(&done[it.obj], 1u);
-        s_last = prev == (unsigned int)(it.n_blk - 1);
-    }
-    __syncthreads();
-    if (s_last && tid == 0) {
-        __threadfence();
-        double c = 0.0;
-        const volatile double *cp = cpart + it.part0;
-        for (int k = 0; k < it.n_blk; ++k) c += cp[k];
-        obj_crit[o.obj_out] = c;
-        done[it.obj] = 0u;  // ready for the next pass
-    }
+    if (tid == 0) obj_crit[o.obj_out] = red[0];
 }
 
 // ===========================================================================
@@ -451,8 +435,8 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs, con
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
-    if (L.n_k1 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k1_trajgen, dim3(L.n_k1), dim3(WG), 0, s, L.objs, L.vals, L.k1, L.poses, L.p, L.pfix, L.qacc,
+    if (L.n_obj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc,
                        L.done);
     return hipGetLastError();
 }
@@ -499,9 +483,8 @@ int collide_blocks_per_cu(int variant)
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)
 {
-    if (L.n_k3 <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_crit, dim3(L.n_k3), dim3(WG), 0, s, L.objs, L.k3, L.pairmap, L.qacc, L.p, L.q, L.traj_crit,
-                       L.obj_crit, L.cpart, L.done);
+    if (L.n_obj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k3_crit, dim3(L.n_obj), dim3(WG), 0, s, L.objs, L.qacc, L.p, L.q, L.traj_crit, L.obj_crit);
     return hipGetLastError();
 }
 

@@ -61,30 +61,11 @@ struct WorkItem {
     int32_t pad;
 };
 
-// One workgroup of the trajectory kernel: K1_TPB trajectories of an object
-// starting at i0 (one wave each), or the probability normalisation of the
-// object when i0 < 0.
-struct K1Block {
-    int32_t obj;
-    int32_t i0;
-};
-
-// One workgroup of the criticality kernel: K3_TRAJ trajectories of an
-// object starting at i0; it is block `blk` of the object's n_blk blocks.
-struct K3Item {
-    int32_t obj;
-    int32_t i0;
-    int32_t blk;
-    int32_t n_blk;
-    int64_t part0;                // index of block 0's partial sum
-};
-
 constexpr int WG = 256;           // threads per workgroup, all kernels
 constexpr int WAVE = 64;          // wavefront size
 constexpr int WAVE_ITEMS = WAVE;  // collision items per work unit (one per lane)
 constexpr int N_XCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
-constexpr int K3_TRAJ = 64;       // trajectories per criticality workgroup
 // q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
 constexpr double kQScale = 4611686018427387904.0;        // 2^62
 constexpr double kQInvScale = 2.168404344971009e-19;     // 2^-62
@@ -110,21 +91,19 @@ struct Launch {
     const double *vals;
     const DPair *pairs;
     const WorkItem *work;
-    const K1Block *k1;
-    const K3Item *k3;
     const int32_t *pairmap;
     char *poses;
     unsigned long long *pfix;     // p * 2^62, per trajectory
     unsigned long long *qacc;     // integer q sums [n_q]
-    double *cpart;                // per criticality block: sum_i p crit
-    unsigned int *done;           // per object: finished criticality blocks
+    unsigned int *done;           // per object: spare counter (zeroed by the trajectory kernel)
     const int32_t *bins;          // [n_bins+1] segment range of each collision wave slot
     double *p;
     int16_t *hits;
     double *q;
     double *traj_crit;
     double *obj_crit;
-    int n_obj, n_pairs, n_work, n_k1, n_k3, n_bins;
+    int n_obj, n_pairs, n_work, n_bins;
+    int k1_x;                     // trajectory kernel grid x: blocks of the largest object + 1
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
 };

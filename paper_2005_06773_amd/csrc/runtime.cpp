@@ -154,12 +154,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.pairmap_off = pm_base + (int64_t)a * n;
             d.obj_out = L.n_obj + a;
             L.objs.push_back(d);
-            for (int i0 = 0; i0 < d.T; i0 += K1_TPB) L.k1.push_back(K1Block{obj_base + a, i0});
-            L.k1.push_back(K1Block{obj_base + a, -1});
-            const int n_blk = (d.T + K3_TRAJ - 1) / K3_TRAJ;
-            for (int b3 = 0; b3 < n_blk; ++b3)
-                L.k3.push_back(K3Item{obj_base + a, b3 * K3_TRAJ, b3, n_blk, L.n_cpart});
-            L.n_cpart += n_blk;
+            L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
             toff += d.T;
         }
         pair_list(&s, plist);
@@ -310,14 +305,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_pairs = put(L.pairs.size() * sizeof(DPair));
     L.o_work = put(L.work.size() * sizeof(WorkItem));
     L.o_bins = put(L.bins.size() * sizeof(int32_t));
-    L.o_k1 = put(L.k1.size() * sizeof(K1Block));
-    L.o_k3 = put(L.k3.size() * sizeof(K3Item));
     L.o_pairmap = put(L.pairmap.size() * sizeof(int32_t));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
     L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
-    L.o_cpart = put((size_t)L.n_cpart * sizeof(double));
     L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
     L.o_p = put((size_t)L.n_traj * sizeof(double));
     L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
@@ -375,8 +367,6 @@ void pack_image(const Layout &L, char *dst)
     cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair));
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem));
     cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t));
-    cp(L.o_k1, L.k1.data(), L.k1.size() * sizeof(K1Block));
-    cp(L.o_k3, L.k3.data(), L.k3.size() * sizeof(K3Item));
     cp(L.o_pairmap, L.pairmap.data(), L.pairmap.size() * sizeof(int32_t));
 }
 
@@ -387,13 +377,10 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.vals = reinterpret_cast<const double *>(base + L.o_vals);
     X.pairs = reinterpret_cast<const DPair *>(base + L.o_pairs);
     X.work = reinterpret_cast<const WorkItem *>(base + L.o_work);
-    X.k1 = reinterpret_cast<const K1Block *>(base + L.o_k1);
-    X.k3 = reinterpret_cast<const K3Item *>(base + L.o_k3);
     X.pairmap = reinterpret_cast<const int32_t *>(base + L.o_pairmap);
     X.poses = base + L.o_poses;
     X.pfix = reinterpret_cast<unsigned long long *>(base + L.o_pfix);
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
-    X.cpart = reinterpret_cast<double *>(base + L.o_cpart);
     X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
     X.p = reinterpret_cast<double *>(base + L.o_p);
@@ -412,8 +399,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_obj = (int)L.objs.size();
     X.n_pairs = (int)L.pairs.size();
     X.n_work = (int)L.work.size();
-    X.n_k1 = (int)L.k1.size();
-    X.n_k3 = (int)L.k3.size();
+    X.k1_x = L.k1_x;
     X.variant = L.variant;
     X.n_bins = (int)L.bins.size() - 1;
     X.xcd_major = L.contiguous ? 1 : 0;
@@ -478,6 +464,7 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
     if (!ctx) return;
     hipSetDevice(ctx->device);
     hipStreamSynchronize(ctx->stream);
+    ctx->batch_graphs.clear();
     hipEventSynchronize(ctx->staging_ev);
     if (ctx->dbuf) hipFree(ctx->dbuf);
     if (ctx->staging) hipHostFree(ctx->staging);
@@ -572,6 +559,7 @@ mhc_status ensure_device(mhc_ctx *ctx, size_t bytes)
     }
     if (ctx->dbuf_bytes >= bytes) return MHC_OK;
     HIPC(hipStreamSynchronize(ctx->stream));
+    ctx->batch_graphs.clear();  // their launches point into the old workspace
     if (ctx->dbuf) HIPC(hipFree(ctx->dbuf));
     ctx->dbuf = nullptr;
     ctx->dbuf_bytes = 0;
@@ -596,6 +584,30 @@ static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, 
     HIPC(hipEventRecord(ctx->staging_ev, s));
     Launch X = make_launch(L, dbase, dev_out, keep_hits, ctx->n_cu);
     HIPC(launch_all(X, s));
+    return MHC_OK;
+}
+
+// Upload + trajectory/collision/risk launches of a context-owned layout,
+// replayed as one graph per shape key (the scene image's values change from
+// call to call, its layout and every launch argument do not).
+static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, bool keep_hits,
+                                          std::vector<int64_t> key, hipStream_t s)
+{
+    char *host = nullptr;
+    mhc_status st = stage_image(ctx, L, &host);
+    if (st != MHC_OK) return st;
+    key.push_back((int64_t)(uintptr_t)dbase);
+    key.push_back((int64_t)(uintptr_t)host);
+    key.push_back(keep_hits);
+    key.push_back((int64_t)L.image_bytes);
+    Launch X = make_launch(L, dbase, nullptr, keep_hits, ctx->n_cu);
+    hipGraphExec_t exec = nullptr;
+    HIPC(ctx->batch_graphs.get(key, [&](hipStream_t cs) {
+        hipError_t e = hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, cs);
+        return e == hipSuccess ? launch_all(X, cs) : e;
+    }, &exec));
+    HIPC(hipGraphLaunch(exec, s));
+    HIPC(hipEventRecord(ctx->staging_ev, s));
     return MHC_OK;
 }
 
@@ -629,7 +641,9 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    st = upload_and_launch(ctx, L, dbase, nullptr, res->first_hit != nullptr, ctx->stream);
+    std::vector<int64_t> key(ctx->layout_shape.begin(), ctx->layout_shape.end());
+    key.push_back(-1);  // single scene
+    st = graph_upload_and_launch(ctx, L, dbase, res->first_hit != nullptr, key, ctx->stream);
     if (st != MHC_OK) return st;
     st = copy_results(ctx, L, 0, dbase, res, ctx->stream);
     if (st != MHC_OK) return st;
@@ -662,6 +676,61 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
 }
 
 // ===========================================================================
+// Graph cache: one instantiated HIP graph per key, captured from a launch
+// sequence on a private stream (capture does not execute anything).
+// ===========================================================================
+
+GraphCache::~GraphCache() { clear(); }
+
+void GraphCache::clear()
+{
+    for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    order.clear();
+    if (capture) hipStreamDestroy(capture);
+    capture = nullptr;
+}
+
+hipError_t GraphCache::get(const std::vector<int64_t> &key, const std::function<hipError_t(hipStream_t)> &enqueue,
+                           hipGraphExec_t *out)
+{
+    auto it = graphs.find(key);
+    if (it != graphs.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    hipError_t e = hipSuccess;
+    if (!capture) e = hipStreamCreateWithFlags(&capture, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    const hipError_t le = enqueue(capture);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(capture, &g);
+    if (le != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    if (graphs.size() >= kMaxGraphs) {  // drop the oldest
+        auto old = graphs.find(order.front());
+        if (old != graphs.end()) {
+            hipGraphExecDestroy(old->second);
+            graphs.erase(old);
+        }
+        order.erase(order.begin());
+    }
+    graphs[key] = ex;
+    order.push_back(key);
+    *out = ex;
+    return hipSuccess;
+}
+
+// ===========================================================================
 // Plans: inputs resident in device memory, launched repeatedly.
 // ===========================================================================
 
@@ -670,6 +739,8 @@ struct mhc_plan {
     Layout L;
     char *dbuf = nullptr;
     std::vector<int32_t> shape;   // kinds, grid sizes, horizon, pair mode
+    GraphCache graphs;            // K1 -> K2 -> K3 per set of output pointers
+    bool use_graphs = false;
 };
 
 
@@ -731,7 +802,22 @@ extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, 
     mhc_ctx *ctx = pl->ctx;
     HIPC(hipSetDevice(ctx->device));
     Launch X = make_launch(pl->L, pl->dbuf, dev_out, true, ctx->n_cu);
-    HIPC(launch_all(X, static_cast<hipStream_t>(hip_stream)));
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (!pl->use_graphs) {
+        HIPC(launch_all(X, s));
+        return MHC_OK;
+    }
+    // The launch sequence depends only on the plan and the output pointers:
+    // it is captured once per pointer set and replayed as one graph.
+    std::vector<int64_t> key{(int64_t)(uintptr_t)pl->dbuf};
+    if (dev_out)
+        for (const void *ptr : {(const void *)dev_out->object_crit, (const void *)dev_out->traj_crit,
+                                (const void *)dev_out->traj_prob, (const void *)dev_out->q,
+                                (const void *)dev_out->first_hit})
+            key.push_back((int64_t)(uintptr_t)ptr);
+    hipGraphExec_t exec = nullptr;
+    HIPC(pl->graphs.get(key, [&](hipStream_t cs) { return launch_all(X, cs); }, &exec));
+    HIPC(hipGraphLaunch(exec, s));
     return MHC_OK;
 }
 
@@ -753,6 +839,13 @@ extern "C" mhc_status mhc_plan_execute_stages(mhc_plan *pl, const mhc_result *de
     return MHC_OK;
 }
 
+extern "C" mhc_status mhc_plan_set_graph(mhc_plan *pl, int32_t enable)
+{
+    if (!pl || (enable != 0 && enable != 1)) return MHC_E_INVAL;
+    pl->use_graphs = enable == 1;
+    return MHC_OK;
+}
+
 extern "C" mhc_status mhc_plan_download(mhc_plan *pl, mhc_result *host_out)
 {
     if (!pl || !host_out) return MHC_E_INVAL;
@@ -770,6 +863,7 @@ extern "C" void mhc_plan_destroy(mhc_plan *pl)
     if (!pl) return;
     hipSetDevice(pl->ctx->device);
     hipDeviceSynchronize();
+    pl->graphs.clear();
     if (pl->dbuf) hipFree(pl->dbuf);
     delete pl;
 }
@@ -785,8 +879,14 @@ extern "C" mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scen
         ctx->err = "batch needs n >= 1, scenes and results";
         return MHC_E_INVAL;
     }
+    int64_t total_objects = 0;
     for (int k = 0; k < n; ++k) {
         if (!validate_scene(&scenes[k], ctx->err, k)) return MHC_E_INVAL;
+        total_objects += scenes[k].n_objects;
+        if (total_objects > kMaxObjectsPerLaunch) {
+            ctx->err = "batch holds more than 65535 objects";
+            return MHC_E_INVAL;
+        }
         if (!res[k].object_crit) {
             ctx->err = "result " + std::to_string(k) + ": object_crit must not be NULL";
             return MHC_E_INVAL;
@@ -804,11 +904,17 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
     ctx->layout_shape.clear();
     bool keep = false;
     for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
-    build_layout(scenes, n, ctx->variant_for(scenes, n), ctx->max_waves(ctx->variant_for(scenes, n)), L, keep);
+    const int v = ctx->variant_for(scenes, n);
+    build_layout(scenes, n, v, ctx->max_waves(v), L, keep);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    st = upload_and_launch(ctx, L, dbase, nullptr, keep, ctx->stream);
+    std::vector<int64_t> key{v, ctx->max_waves(v), n};
+    for (int k = 0; k < n; ++k) {
+        const std::vector<int32_t> sh = shape_of(&scenes[k]);
+        key.insert(key.end(), sh.begin(), sh.end());
+    }
+    st = graph_upload_and_launch(ctx, L, dbase, keep, key, ctx->stream);
     if (st != MHC_OK) return st;
     for (int k = 0; k < n; ++k) {
         st = copy_results(ctx, L, k, dbase, &res[k], ctx->stream);

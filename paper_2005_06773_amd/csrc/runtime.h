@@ -1,6 +1,7 @@
 // Host-side runtime structures (not part of the public ABI).
 #pragma once
 
+#include <functional>
 #include <map>
 #include <string>
 #include <utility>
@@ -12,6 +13,7 @@
 namespace mhc {
 
 constexpr int kMaxObjects = 4096;
+constexpr int64_t kMaxObjectsPerLaunch = 65535;  // trajectory kernel grid y
 constexpr int64_t kMaxTraj = 1 << 15;     // trajectories per object (T_a*T_b < 2^31)
 constexpr int64_t kMaxPosesPerObject = int64_t(1) << 27;  // pose block < 2 GiB (32-bit buffer offsets)
 constexpr int kDefaultVariant = 0;
@@ -24,25 +26,36 @@ struct SceneExt {
 };
 
 // Host tables of one launch plus the byte layout of its device workspace:
-// [scene image: tables uploaded in one copy][poses][p * 2^62][integer q sums][criticality block sums]
-// [per-object counters][p][first hits][q][traj crit][object crit]
+// [scene image: tables uploaded in one copy][poses][p * 2^62][integer q sums][per-object counters]
+// [p][first hits][q][traj crit][object crit]
 struct Layout {
     std::vector<DObj> objs;
     std::vector<double> vals;
     std::vector<DPair> pairs;
     std::vector<WorkItem> work;     // grouped by collision wave
     std::vector<int32_t> bins;       // [n_bins+1] range of each collision wave in `work`
-    std::vector<K1Block> k1;
-    std::vector<K3Item> k3;
     std::vector<int32_t> pairmap;
     std::vector<SceneExt> sc;
-    int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0, n_cpart = 0;
+    int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
+    int k1_x = 0;                 // trajectory kernel grid x
     size_t pose_bytes = 0;
-    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_k1 = 0, o_k3 = 0, o_pairmap = 0, image_bytes = 0;
-    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_cpart = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
+    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_pairmap = 0, image_bytes = 0;
+    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
     bool with_hits = true;        // the workspace holds the first-hit matrix
+};
+
+// Instantiated HIP graphs keyed by what their launch sequence depends on.
+struct GraphCache {
+    static constexpr size_t kMaxGraphs = 16;
+    std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+    std::vector<std::vector<int64_t>> order;  // insertion order, for eviction
+    hipStream_t capture = nullptr;
+    ~GraphCache();
+    void clear();
+    hipError_t get(const std::vector<int64_t> &key, const std::function<hipError_t(hipStream_t)> &enqueue,
+                   hipGraphExec_t *out);
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
@@ -69,6 +82,7 @@ struct mhc_ctx {
     hipEvent_t staging_ev = nullptr;
     mhc::Layout layout;           // reused by mhc_evaluate
     std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
+    mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::pair<int, int>, int> tuned;     // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;

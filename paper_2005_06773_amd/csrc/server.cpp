@@ -103,14 +103,13 @@ namespace {
 // workspace layout, with one collision segment per work unit).
 void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
 {
-    int64_t n_traj = 0, pose = 0, n_units = 0, n_hits = 0, vals = 0, n_blk = 0, n_pairs = 0;
+    int64_t n_traj = 0, pose = 0, n_units = 0, n_hits = 0, vals = 0, n_pairs = 0;
     const int n = s->n_objects;
     for (int a = 0; a < n; ++a) {
         const int64_t T = (int64_t)s->objects[a].n_u * s->objects[a].n_w;
         n_traj += T;
         pose += align256((size_t)s->horizon * T * (s->objects[a].kind == MHC_VEHICLE ? 16 : 8));
         vals += s->objects[a].n_u + s->objects[a].n_w + (s->objects[a].score ? T : 0);
-        n_blk += (T + K3_TRAJ - 1) / K3_TRAJ;
     }
     for (int a = 0; a < n; ++a)
         for (int b = a + 1; b < n; ++b) {
@@ -125,9 +124,8 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     const int64_t n_q = n_traj * n;
     size_t bytes = 0;
     bytes += align256(n * sizeof(DObj)) + align256(vals * 8) + align256(n_pairs * sizeof(DPair));
-    bytes += align256((n_units + 1) * sizeof(WorkItem)) + align256(((n_traj + 3) / 4 + n) * sizeof(K1Block));
-    bytes += align256(n_blk * sizeof(K3Item)) + align256((size_t)n * n * 4);
-    bytes += pose + align256(n_traj * 8) * 4 + align256(n_q * 8) * 2 + align256(n_blk * 8) + align256(n * 4);
+    bytes += align256((n_units + 1) * sizeof(WorkItem)) + align256((size_t)n * n * 4);
+    bytes += pose + align256(n_traj * 8) * 4 + align256(n_q * 8) * 2 + align256(n * 4);
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);
     bytes += 16 * 256;                              // alignment slack of the tables
     bytes += align256(((size_t)max_waves + 1) * 4);  // the collision plan's slot table
@@ -302,15 +300,17 @@ void scheduler(mhc_server *srv)
             }
             if (free_slot && !srv->queue.empty() && srv->fatal.empty()) {
                 size_t bytes = 0;
-                int64_t checks = 0;
+                int64_t checks = 0, objects = 0;
                 const int64_t now = now_ns();
                 while (!srv->queue.empty() && (int)take.size() < srv->cfg.max_frames_per_tick) {
                     auto &f = srv->queue.front();
                     if (!take.empty() && (bytes + f->bytes > srv->slot_usable ||
-                                          checks + f->checks > srv->cfg.max_checks_per_tick))
+                                          checks + f->checks > srv->cfg.max_checks_per_tick ||
+                                          objects + f->scene.n_objects > kMaxObjectsPerLaunch))
                         break;
                     bytes += f->bytes;
                     checks += f->checks;
+                    objects += f->scene.n_objects;
                     f->state = ADMITTED;
                     f->timing.admit_ns = now;
                     take.push_back(f);

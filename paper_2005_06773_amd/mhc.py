@@ -28,7 +28,7 @@ _STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE"
 EXPORTED = [
     "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes",
     "mhc_evaluate", "mhc_evaluate_async",
-    "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages",
+    "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages", "mhc_plan_set_graph",
     "mhc_plan_download", "mhc_plan_destroy",
     "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load",
     "mhc_evaluate_batch",
@@ -114,6 +114,7 @@ def _load():
         "mhc_plan_update": [V, ctypes.POINTER(mhc_scene)],
         "mhc_plan_execute": [V, ctypes.POINTER(mhc_result), V],
         "mhc_plan_execute_stages": [V, ctypes.POINTER(mhc_result), V, ctypes.c_uint32],
+        "mhc_plan_set_graph": [V, ctypes.c_int32],
         "mhc_plan_download": [V, ctypes.POINTER(mhc_result)],
         "mhc_plan_destroy": [V],
         "mhc_set_variant": [V, ctypes.c_int32],
@@ -304,6 +305,10 @@ def mhc_plan_execute_stages(plan: Plan, stages: int, dev_out: Optional[mhc_resul
     sp = 0 if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
     _check(plan.ctx, lib.mhc_plan_execute_stages(plan.h, ctypes.byref(dev_out) if dev_out is not None else None,
                                                  ctypes.c_void_p(sp), stages))
+
+
+def mhc_plan_set_graph(plan: Plan, enable: bool):
+    _check(plan.ctx, lib.mhc_plan_set_graph(plan.h, int(bool(enable))))
 
 
 def mhc_plan_download(plan: Plan, first_hit: bool = True, q: bool = True) -> dict:

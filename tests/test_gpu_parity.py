@@ -213,3 +213,37 @@ def test_stress_scene_sampled_pairs(mhc, ctx):
     assert acc.all(), f"{(~acc).sum()} rejected"
     say(f"  sampled entries {k32.size}, exact {np.mean(k32 == o.k64):.7f}, hits {(o.k64 >= 0).sum()}")
     assert np.all((g["object_crit"] >= 0) & (g["object_crit"] <= 1 + 1e-12))
+
+
+def test_graph_replays_match_eager(mhc, ctx):
+    """Plans and mhc_evaluate replay captured HIP graphs. Every replay, with
+    eager work and synchronisations in between, must equal the eager launch
+    sequence; same-shape scenes with new values reuse a graph and must still
+    match the oracle."""
+    import torch
+    s = sg.eleven_object_scene(4)
+    plan = mhc.mhc_plan_create(ctx, s)
+    mhc.mhc_plan_set_graph(plan, True)
+    mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_ALL)     # eager
+    eager = mhc.mhc_plan_download(plan)
+    other = sg.two_vehicle_scene(11)
+    for rep in range(5):
+        mhc.mhc_plan_execute(plan)                            # graph replay
+        got = mhc.mhc_plan_download(plan)
+        parity.same_results(eager, got, f"plan graph replay {rep}")
+        mhc.mhc_evaluate(ctx, other)                          # unrelated eager work in between
+        torch.cuda.synchronize()
+    plan.close()
+    say("graph replays of mhc_evaluate over same-shape scenes with new values")
+    for seed in (20, 21, 22):
+        sc = sg.eleven_object_scene(seed)
+        g = mhc.mhc_evaluate(ctx, sc)
+        ref_plan = mhc.mhc_plan_create(ctx, sc)
+        mhc.mhc_plan_execute_stages(ref_plan, mhc.MHC_STAGE_ALL)
+        parity.same_results(mhc.mhc_plan_download(ref_plan), g, f"evaluate graph seed {seed}")
+        ref_plan.close()
+    sc = sg.eleven_object_scene(23)
+    parity.check(sc, mhc.mhc_evaluate(ctx, sc), oracle.evaluate(sc, threads=THREADS), "evaluate graph vs oracle")
+    # a shape change between calls is a different graph
+    small = sg.two_vehicle_scene(5)
+    parity.check(small, mhc.mhc_evaluate(ctx, small), oracle.evaluate(small), "shape change")

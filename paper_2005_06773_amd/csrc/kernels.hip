@@ -29,9 +29,8 @@ namespace mhc {
 // float2 (x, y) for pedestrians, layout [t][i], slot t = step t+1.
 // ===========================================================================
 
-__device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals, double *__restrict__ p,
-                                        unsigned long long *__restrict__ pfix, unsigned long long *__restrict__ qacc,
-                                        unsigned int *__restrict__ done)
+__device__ void normalise_probabilities(const DObj &o, const double *__restrict__ vals, double *__restrict__ p,
+                                        unsigned long long *__restrict__ pfix, unsigned long long *__restrict__ qacc)
 {
     __shared__ double red[WG];
     const int tid = threadIdx.x;
@@ -54,7 +53,6 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
     // this object's rows of the integer q accumulators start from zero
     const int64_t nq = (int64_t)o.T * o.n_scene_obj;
     for (int64_t k = tid; k < nq; k += WG) qacc[o.q_row + k] = 0ull;
-    if (tid == 0) done[obj] = 0u;
 }
 
 // Grid: x = trajectory block (K1_TPB trajectories, one wave each) plus one
@@ -62,12 +60,12 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
-                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
+                                                 unsigned long long *__restrict__ qacc)
 {
     const int obj = (int)blockIdx.y;
     const DObj o = objs[obj];
     if ((int)blockIdx.x == (int)gridDim.x - 1) {
-        normalise_probabilities(o, obj, vals, p, pfix, qacc, done);
+        normalise_probabilities(o, vals, p, pfix, qacc);
         return;
     }
     const int lane = threadIdx.x & 63;
@@ -436,8 +434,7 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
 hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc,
-                       L.done);
+    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc);
     return hipGetLastError();
 }
 

@@ -25,7 +25,6 @@ struct DObj {
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
     int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
-    int64_t pairmap_off;          // int32 [n_scene_obj] row of the scene's pair map
     int64_t obj_out;              // index in the object_crit array
     double x, y, heading, speed;
     double tau;
@@ -91,11 +90,9 @@ struct Launch {
     const double *vals;
     const DPair *pairs;
     const WorkItem *work;
-    const int32_t *pairmap;
     char *poses;
     unsigned long long *pfix;     // p * 2^62, per trajectory
     unsigned long long *qacc;     // integer q sums [n_q]
-    unsigned int *done;           // per object: spare counter (zeroed by the trajectory kernel)
     const int32_t *bins;          // [n_bins+1] segment range of each collision wave slot
     double *p;
     int16_t *hits;

@@ -129,8 +129,6 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         ext.hit0 = L.n_hits;
         ext.q0 = L.n_q;
         const int obj_base = (int)L.objs.size();
-        const int64_t pm_base = (int64_t)L.pairmap.size();
-        L.pairmap.resize(L.pairmap.size() + (size_t)n * n, -1);
         int64_t toff = 0;
         for (int a = 0; a < n; ++a) {
             const mhc_object &o = s.objects[a];
@@ -151,7 +149,6 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.w_off = d.u_off + o.n_u;
             d.score_off = d.w_off + o.n_w;
             L.vals.resize(L.vals.size() + o.n_u + o.n_w + (o.score ? d.T : 0));
-            d.pairmap_off = pm_base + (int64_t)a * n;
             d.obj_out = L.n_obj + a;
             L.objs.push_back(d);
             L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
@@ -182,8 +179,6 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             pr.pb_off = L.objs[obj_base + b].traj_off;
             const int pidx = (int)L.pairs.size();
             L.pairs.push_back(pr);
-            L.pairmap[pm_base + (int64_t)a * n + b] = pidx;
-            L.pairmap[pm_base + (int64_t)b * n + a] = pidx;
             const int64_t items = (int64_t)pr.n_ig * pr.n_jg;
             // a wave executes every step of every test of a unit, whether or
             // not all of its lanes hold an item
@@ -305,12 +300,10 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_pairs = put(L.pairs.size() * sizeof(DPair));
     L.o_work = put(L.work.size() * sizeof(WorkItem));
     L.o_bins = put(L.bins.size() * sizeof(int32_t));
-    L.o_pairmap = put(L.pairmap.size() * sizeof(int32_t));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
     L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
-    L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
     L.o_p = put((size_t)L.n_traj * sizeof(double));
     L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
     L.o_q = put((size_t)L.n_q * sizeof(double));
@@ -367,7 +360,6 @@ void pack_image(const Layout &L, char *dst)
     cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair));
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem));
     cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t));
-    cp(L.o_pairmap, L.pairmap.data(), L.pairmap.size() * sizeof(int32_t));
 }
 
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu)
@@ -377,11 +369,9 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.vals = reinterpret_cast<const double *>(base + L.o_vals);
     X.pairs = reinterpret_cast<const DPair *>(base + L.o_pairs);
     X.work = reinterpret_cast<const WorkItem *>(base + L.o_work);
-    X.pairmap = reinterpret_cast<const int32_t *>(base + L.o_pairmap);
     X.poses = base + L.o_poses;
     X.pfix = reinterpret_cast<unsigned long long *>(base + L.o_pfix);
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
-    X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);

@@ -130,6 +130,30 @@ def test_edge_scene_parity(mhc, ctx, name):
         assert np.all(g["first_hit"] == -1) and np.all(g["object_crit"] == 0)
 
 
+def test_every_tile_variant_is_identical(mhc, ctx):
+    """Each compiled micro-tile shape and wave cut gives bit-identical results
+    (first hits, q, criticality) on scenes that cover all classes and ragged
+    tiles, and the first of them agrees with the oracle."""
+    edge = _edge_scenes()
+    scenes = {"eleven_object_seed2": sg.eleven_object_scene(2),
+              "all_classes_ragged": edge["all_classes_ragged"],
+              "tile_spanning_257x129": edge["tile_spanning_257x129"]}
+    try:
+        for name, s in scenes.items():
+            ref = None
+            for v in range(mhc.MHC_N_VARIANTS):
+                say(f"variant {v}: {name}")
+                mhc.mhc_set_variant(ctx, v)
+                g = mhc.mhc_evaluate(ctx, s)
+                if ref is None:
+                    parity.check(s, g, oracle.evaluate(s, threads=THREADS), f"{name} variant {v}")
+                    ref = g
+                else:
+                    parity.same_results(ref, g, f"{name} variant {v}")
+    finally:
+        mhc.mhc_set_variant(ctx, -1)
+
+
 def test_plan_and_async_match_evaluate(mhc, ctx):
     import torch
     s = sg.eleven_object_scene(1)

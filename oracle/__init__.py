@@ -32,6 +32,10 @@ EPS = 1e-4
 VEHICLE = 0
 PEDESTRIAN = 1
 
+#: overlap tests of the collision recognition (Sec. IV-C.1)
+OVERLAP_EXACT = 0   # the closed shapes intersect
+OVERLAP_PIP = 1     # a vertex of one polygon lies in the other, tested both ways
+
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (FP64, no fast-math, OpenMP rows)."""
@@ -70,7 +74,11 @@ def lib():
         L.orc_count_trajectories.restype = ctypes.c_int64
         L.orc_count_combinations.argtypes = [I, P, I]
         L.orc_count_combinations.restype = ctypes.c_int64
-        L.orc_first_hits.argtypes = [I, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
+        L.orc_margin_pip.argtypes = [I, P, P, I, P, P]
+        L.orc_margin_pip.restype = D
+        L.orc_margin_rect_rect_pip.argtypes = [D] * 10
+        L.orc_margin_rect_rect_pip.restype = D
+        L.orc_first_hits.argtypes = [I, I, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
         L.orc_risk.argtypes = [I, P, P, I, P, P, P, P, P, P]
         L.orc_point_in_polygon.argtypes = [D, D, I, P, P]
         L.orc_rect_corners.argtypes = [D, D, D, D, D, P, P]
@@ -126,6 +134,22 @@ def margin_rect_circle(P, Q) -> float:
 def margin_circle_circle(P, Q) -> float:
     """P, Q = (x, y, r)."""
     return lib().orc_margin_circle_circle(*map(float, P), *map(float, Q))
+
+
+def margin_pip(polyP: np.ndarray, polyQ: np.ndarray) -> float:
+    """Point-in-polygon margin both ways of two polygons given as [n, 2]
+    vertex arrays: the smallest signed distance of a vertex of one to the
+    boundary of the other (negative inside)."""
+    P = np.ascontiguousarray(polyP, np.float64)
+    Q = np.ascontiguousarray(polyQ, np.float64)
+    px, py = np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1])
+    qx, qy = np.ascontiguousarray(Q[:, 0]), np.ascontiguousarray(Q[:, 1])
+    return lib().orc_margin_pip(len(px), _ptr(px), _ptr(py), len(qx), _ptr(qx), _ptr(qy))
+
+
+def margin_rect_rect_pip(P, Q) -> float:
+    """P, Q = (x, y, psi, L, W)."""
+    return lib().orc_margin_rect_rect_pip(*map(float, P), *map(float, Q))
 
 
 def rect_corners(x, y, psi, L, W) -> np.ndarray:
@@ -199,6 +223,7 @@ def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: 
 
     ``pair_list`` restricts the object pairs (the stress-scene sample); by
     default all pairs, or EGO-CO pairs when ``scene.pairs`` is the EGO mode.
+    ``scene.overlap`` selects the overlap test (``OVERLAP_EXACT`` by default).
     """
     H, dt = int(scene.horizon), float(scene.dt)
     kind, length, width, radius, T = scene_arrays(scene)
@@ -228,7 +253,8 @@ def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: 
     kst = np.empty(entries, np.int32)
     loose = np.empty((entries, W), np.uint64) if masks else None
     strict = np.empty((entries, W), np.uint64) if masks else None
-    _check(lib().orc_first_hits(n, _ptr(kind), _ptr(length), _ptr(width), _ptr(radius), _ptr(T), H,
+    overlap = int(getattr(scene, "overlap", OVERLAP_EXACT))
+    _check(lib().orc_first_hits(overlap, n, _ptr(kind), _ptr(length), _ptr(width), _ptr(radius), _ptr(T), H,
                                 _ptr(px), _ptr(py), _ptr(ppsi), len(pa), _ptr(pa), _ptr(pb),
                                 float(eps), int(threads), _ptr(k64), _ptr(kst),
                                 _ptr(loose), _ptr(strict)), "first_hits")

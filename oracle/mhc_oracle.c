@@ -14,7 +14,8 @@
  *   probabilities  (Sec. IV-D.1, L1 normalisation of trajectory scores)
  *   trajectories   (Sec. IV-B.1 Euler pose update; Sec. IV-B.3 pedestrians)
  *   pairs          (Sec. IV-C.1; all unordered pairs, or EGO-CO only)
- *   overlap margin (Sec. IV-C.1; exact closed-shape intersection)
+ *   overlap margin (Sec. IV-C.1; exact closed-shape intersection, or the
+ *                   paper's point-in-polygon test both ways)
  *   first hit      (earliest colliding step of each trajectory pair)
  *   risk           (Sec. IV-D p_cra double sum, Sec. IV-D.2 chronological
  *                   scaling of the conditional probabilities)
@@ -27,7 +28,10 @@
  *     speed is clamped at zero, the acceleration that step being the one that
  *     stops the vehicle;
  *   - vehicles are rectangles, pedestrians circles; touching counts as a
- *     collision (margin <= 0);
+ *     collision (margin <= 0). The default overlap test is the exact
+ *     intersection of the closed shapes; the paper's point-in-polygon test,
+ *     run both ways, is the second mode (rectangles only), with a vertex on
+ *     the other polygon's boundary counting as inside;
  *   - poses are predicted for n = 1..H and stored at slot n-1; the measured
  *     state (n = 0) is never checked;
  *   - the chronological scaling is read as: collision objects independent of
@@ -46,6 +50,10 @@
 
 #define ORC_VEHICLE 0
 #define ORC_PEDESTRIAN 1
+
+/* overlap test of the collision recognition */
+#define ORC_OVERLAP_EXACT 0   /* closed shapes intersect */
+#define ORC_OVERLAP_PIP 1     /* a vertex of one polygon lies in the other (both ways) */
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -224,9 +232,69 @@ double orc_margin_circle_circle(double xP, double yP, double rP, double xQ, doub
     return hypot(xQ - xP, yQ - yP) - (rP + rQ);
 }
 
-static double margin_at(int kindP, double xP, double yP, double psiP, double LP, double WP, double rP,
+/* ------------------------------------------------------------------------ */
+/* Point-in-polygon overlap, the paper's own test (Sec. IV-C.1). Both        */
+/* objects are polygons, and at each step the vertices of each are tested     */
+/* against the other with a point-in-polygon test, once in each direction.    */
+/* The margin is the smallest signed distance of any vertex of one polygon   */
+/* to the boundary of the other: negative when the vertex lies inside (sign   */
+/* from the crossing-number test), positive outside, so the margin is <= 0    */
+/* exactly when some vertex lies in the other closed polygon. Two convex     */
+/* shapes can overlap with no vertex of either inside the other (two bars    */
+/* crossing like a plus sign); this test misses such an overlap by design.   */
+/* ------------------------------------------------------------------------ */
+
+int orc_point_in_polygon(double x, double y, int n, const double *vx, const double *vy);
+
+static double point_segment_distance(double x, double y, double ax, double ay, double bx, double by)
+{
+    double ex = bx - ax, ey = by - ay;
+    double len2 = ex * ex + ey * ey;
+    double t = len2 > 0.0 ? ((x - ax) * ex + (y - ay) * ey) / len2 : 0.0;
+    if (t < 0.0) t = 0.0;
+    if (t > 1.0) t = 1.0;
+    return hypot(x - (ax + t * ex), y - (ay + t * ey));
+}
+
+/* Signed distance of (x, y) to the boundary of the polygon (vx, vy)[n]. */
+static double signed_boundary_distance(double x, double y, int n, const double *vx, const double *vy)
+{
+    double d = INFINITY;
+    for (int k = 0, l = n - 1; k < n; l = k++) {
+        double dk = point_segment_distance(x, y, vx[l], vy[l], vx[k], vy[k]);
+        if (dk < d) d = dk;
+    }
+    return orc_point_in_polygon(x, y, n, vx, vy) ? -d : d;
+}
+
+double orc_margin_pip(int nP, const double *px, const double *py, int nQ, const double *qx, const double *qy)
+{
+    double m = INFINITY;
+    for (int k = 0; k < nP; ++k) {            /* P over Q */
+        double d = signed_boundary_distance(px[k], py[k], nQ, qx, qy);
+        if (d < m) m = d;
+    }
+    for (int k = 0; k < nQ; ++k) {            /* Q over P */
+        double d = signed_boundary_distance(qx[k], qy[k], nP, px, py);
+        if (d < m) m = d;
+    }
+    return m;
+}
+
+double orc_margin_rect_rect_pip(double xP, double yP, double psiP, double LP, double WP,
+                                     double xQ, double yQ, double psiQ, double LQ, double WQ)
+{
+    double px[4], py[4], qx[4], qy[4];
+    rect_corners(xP, yP, psiP, LP, WP, px, py);
+    rect_corners(xQ, yQ, psiQ, LQ, WQ, qx, qy);
+    return orc_margin_pip(4, px, py, 4, qx, qy);
+}
+
+static double margin_at(int overlap, int kindP, double xP, double yP, double psiP, double LP, double WP, double rP,
                         int kindQ, double xQ, double yQ, double psiQ, double LQ, double WQ, double rQ)
 {
+    if (overlap == ORC_OVERLAP_PIP)
+        return orc_margin_rect_rect_pip(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
     if (kindP == ORC_VEHICLE && kindQ == ORC_VEHICLE)
         return orc_margin_rect_rect(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
     if (kindP == ORC_VEHICLE)
@@ -285,7 +353,7 @@ int64_t orc_count_combinations(int n_objects, const int32_t *T, int ego_only)
 /* Any output pointer may be NULL. eps is the tolerance band within which an */
 /* FP32 evaluation of the same test may legitimately decide either way.      */
 /* ------------------------------------------------------------------------ */
-int orc_first_hits(int n_objects, const int32_t *kind, const double *length, const double *width,
+int orc_first_hits(int overlap, int n_objects, const int32_t *kind, const double *length, const double *width,
                    const double *radius, const int32_t *T, int H,
                    const double *px, const double *py, const double *ppsi,
                    int n_pairs, const int32_t *pair_a, const int32_t *pair_b,
@@ -293,6 +361,10 @@ int orc_first_hits(int n_objects, const int32_t *kind, const double *length, con
                    int32_t *k64, int32_t *kstrict, uint64_t *loose, uint64_t *strict)
 {
     if (n_objects < 1 || H < 1 || n_pairs < 0) return ORC_EINVAL;
+    if (overlap != ORC_OVERLAP_EXACT && overlap != ORC_OVERLAP_PIP) return ORC_EINVAL;
+    if (overlap == ORC_OVERLAP_PIP)          /* polygons: rectangles only */
+        for (int a = 0; a < n_objects; ++a)
+            if (kind[a] != ORC_VEHICLE) return ORC_EINVAL;
     int W = (H + 63) / 64;
     int64_t *obj_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
     int64_t *pair_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
@@ -332,7 +404,7 @@ int orc_first_hits(int n_objects, const int32_t *kind, const double *length, con
             for (int t = 0; t < H; ++t) {
                 size_t ia = (size_t)(obj_off[a] + (int64_t)t * Ta + i);
                 size_t ib = (size_t)(obj_off[b] + (int64_t)t * Tb + j);
-                double m = margin_at(kind[a], px[ia], py[ia], ppsi[ia], length[a], width[a], radius[a],
+                double m = margin_at(overlap, kind[a], px[ia], py[ia], ppsi[ia], length[a], width[a], radius[a],
                                      kind[b], px[ib], py[ib], ppsi[ib], length[b], width[b], radius[b]);
                 if (m <= 0.0 && first < 0) first = t;
                 if (m <= -eps && first_strict < 0) first_strict = t;
@@ -415,8 +487,10 @@ int orc_risk(int n_objects, const int32_t *T, const double *p,
 }
 
 /* Point-in-polygon test (crossing number) for a convex or concave polygon,
- * the per-vertex test the paper runs in both directions (Sec. IV-C.1). Kept
- * so the tests can compare it with the exact intersection used above. */
+ * the per-vertex test the paper runs in both directions (Sec. IV-C.1). It
+ * gives the sign of the point-in-polygon overlap margin above; a point on an
+ * edge may fall either way, which the margin's magnitude (zero there) makes
+ * irrelevant. */
 int orc_point_in_polygon(double x, double y, int n, const double *vx, const double *vy)
 {
     int inside = 0;

@@ -12,6 +12,10 @@ Sec. VI-A, are not available; these seeded scenes stand in for them):
 * ``eleven_object_scene`` 6 vehicles + 5 pedestrians, 15x15 grids, 30 steps.
 * ``batch_scenes``       64 scenes of 3..24 objects, grid side 7..20, 20..50 steps.
 * ``stress_scene``       24 vehicles + 16 pedestrians, 32x32 grids, 50 steps.
+* ``paper_scene``        the execution-time experiment of Sec. VI-B (Table I):
+                         EGO 6 x 343 trajectories against 3 (S1) or 10 (S2)
+                         COs of 6 x 7, 100 steps of 20 ms, EGO-CO pairs only;
+                         86,436,000 checks for S2.
 * ``paper_shaped_sizes`` the trajectory counts of Sec. IV-B.4 / Table I.
 
 Per object the draws happen in index order: x, y, heading, speed, then for
@@ -30,6 +34,8 @@ VEHICLE = 0
 PEDESTRIAN = 1
 PAIRS_ALL = 0
 PAIRS_EGO = 1
+OVERLAP_EXACT = 0   # closed shapes intersect
+OVERLAP_PIP = 1     # the paper's point-in-polygon test, both ways (vehicles only)
 
 
 @dataclasses.dataclass
@@ -57,6 +63,7 @@ class Scene:
     horizon: int
     dt: float
     pairs: int = PAIRS_ALL
+    overlap: int = OVERLAP_EXACT
 
     @property
     def n_objects(self) -> int:
@@ -228,6 +235,45 @@ def stress_sample_pairs(n_objects: int = 40, k: int = 20, seed: int = 1004):
     return [pairs[i] for i in sorted(idx)]
 
 
+def paper_scene(seed: int = 5, n_co: int = 10, n_acc: int = 6, overlap: int = OVERLAP_EXACT) -> Scene:
+    """The execution-time experiment of Sec. VI-B (Table I) as a seeded scene.
+
+    The EGO drives east at U(12, 16) m/s with n_acc accelerations on [-8, 3]
+    and 343 yaw rates on [-0.5, 0.5] rad/s (the paper's 7^3 paths);
+    every CO (4.5 x 1.8 m +-10 %) has n_acc accelerations and 7 yaw rates.
+    COs take four roles in turn: lead vehicle in the EGO's lane
+    (x U(8, 40), speed U(0, 12)), oncoming in the next lane (x U(10, 60),
+    y 3.5, speed U(8, 16)), crossing towards the EGO's lane (x U(15, 35),
+    |y| U(8, 25), speed U(5, 12)), following (x U(-25, -8), speed U(10, 18));
+    lateral jitter U(-0.5, 0.5) m, heading jitter U(-0.05, 0.05) rad.
+    100 steps of 20 ms, EGO-CO pairs only: 2058 x 42 x 100 = 8,643,600
+    checks per CO (86,436,000 for S2 = 10 COs, 25,930,800 for S1 = 3)."""
+    rng = np.random.default_rng(seed)
+    u = accel_grid(n_acc)
+    w_ego = yaw_grid(343)
+    ego = SceneObject(VEHICLE, 0.0, 0.0, 0.0, float(rng.uniform(12.0, 16.0)), 4.5, 1.8, 0.0,
+                      u, w_ego, vehicle_scores(u, w_ego))
+    objs = [ego]
+    w_co = yaw_grid(7)
+    for k in range(n_co):
+        role = k % 4
+        if role == 0:
+            x, y, h, v = rng.uniform(8.0, 40.0), 0.0, 0.0, rng.uniform(0.0, 12.0)
+        elif role == 1:
+            x, y, h, v = rng.uniform(10.0, 60.0), 3.5, math.pi, rng.uniform(8.0, 16.0)
+        elif role == 2:
+            side = 1.0 if rng.uniform() < 0.5 else -1.0
+            x, y, h, v = rng.uniform(15.0, 35.0), side * rng.uniform(8.0, 25.0), -side * math.pi / 2, rng.uniform(5.0, 12.0)
+        else:
+            x, y, h, v = rng.uniform(-25.0, -8.0), 0.0, 0.0, rng.uniform(10.0, 18.0)
+        y += rng.uniform(-0.5, 0.5)
+        h += rng.uniform(-0.05, 0.05)
+        lf, wf = rng.uniform(0.9, 1.1), rng.uniform(0.9, 1.1)
+        objs.append(SceneObject(VEHICLE, float(x), float(y), float(h), float(v), 4.5 * lf, 1.8 * wf, 0.0,
+                                u, w_co, vehicle_scores(u, w_co)))
+    return Scene(objs, 100, 0.02, pairs=PAIRS_EGO, overlap=overlap)
+
+
 def paper_shaped_sizes(n_co: int, n_acc: int = 6, ego_paths: int = 343, co_paths: int = 7):
     """Trajectory counts of the paper's execution-time experiment (Sec. IV-B.4,
     Sec. VI-B): EGO = n_acc * 7^3, each CO = n_acc * 7."""
@@ -237,4 +283,4 @@ def paper_shaped_sizes(n_co: int, n_acc: int = 6, ego_paths: int = 343, co_paths
 def uniform_scores(scene: Scene) -> Scene:
     """Same scene with score arrays dropped (uniform probabilities)."""
     objs = [dataclasses.replace(o, score=None) for o in scene.objects]
-    return Scene(objs, scene.horizon, scene.dt, scene.pairs)
+    return Scene(objs, scene.horizon, scene.dt, scene.pairs, scene.overlap)

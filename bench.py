@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 
 # Algorithmic FP32 work of one overlap test (FMA = 2 flops; compares and
 # max count 1): rectangle-rectangle 44, rectangle-circle 16, circle-circle 6.
-FLOPS_PER_CHECK = {"VV": 44, "VP": 16, "PP": 6}
+FLOPS_PER_CHECK = {"VV": 44, "VP": 16, "PP": 6, "VV_PIP": 72}
 # MI355X FP32 vector peak: 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
 # = 78.6 TFLOP/s without packed math, 157.3 TFLOP/s with it.
 PEAK_FP32_TFLOPS = 157.3
@@ -36,6 +36,65 @@ LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# The paper's execution-time table (Sec. VI-B, Table I): scenario, COs,
+# acceleration profiles, median ms of the whole algorithm on the Drive PX 2's
+# GP106 (another machine and another overlap implementation: context only).
+TABLE_ONE = [("S1", 3, 6, 10.0), ("S1", 3, 5, 8.0), ("S2", 10, 6, 21.0), ("S2", 10, 5, 14.0)]
+
+
+def table_one(mhc, ctx, sg, torch, steps=50):
+    """Each Table I configuration in both overlap modes: the whole path on
+    inputs resident in HBM (as the headline), the collision kernel alone
+    (HIP events on the launch stream), and host scene in -> host criticality
+    out (the comparable quantity to the paper's timings)."""
+    rows = []
+    stream = torch.cuda.current_stream()
+    for name, n_co, n_acc, paper_ms in TABLE_ONE:
+        for overlap in (sg.OVERLAP_EXACT, sg.OVERLAP_PIP):
+            cs = mhc.CScene(sg.paper_scene(5, n_co=n_co, n_acc=n_acc, overlap=overlap))
+            checks = mhc.mhc_query_sizes(cs)["n_checks"]
+            best, us = mhc.mhc_autotune(ctx, cs, reps=10)
+            plan = mhc.mhc_plan_create(ctx, cs)
+            out, r = mhc.device_result(cs, first_hit=True, q=True)
+            for _ in range(5):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(steps):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            step_ms = (time.perf_counter() - a) * 1e3 / steps
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            for k in range(steps):
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_TRAJ, r, stream)
+                ev[k][0].record(stream)
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_COLLIDE, r, stream)
+                ev[k][1].record(stream)
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_RISK, r, stream)
+            torch.cuda.synchronize()
+            k2_ms = sum(x.elapsed_time(y) for x, y in ev) / steps
+            plan.close()
+            lat = []
+            for k in range(25):
+                a = time.perf_counter()
+                mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
+                if k >= 5:
+                    lat.append((time.perf_counter() - a) * 1e3)
+            flops = FLOPS_PER_CHECK["VV_PIP" if overlap == sg.OVERLAP_PIP else "VV"] * checks
+            row = {"scenario": name, "cos": n_co, "accel_profiles": n_acc,
+                   "overlap": "pip" if overlap == sg.OVERLAP_PIP else "exact", "checks": checks,
+                   "step_ms": step_ms, "checks_per_s": checks / (step_ms * 1e-3),
+                   "collide_us": k2_ms * 1e3, "collide_tflops": flops / (k2_ms * 1e-3) / 1e12,
+                   "e2e_p50_ms": pct(lat, 50), "tile_variant": best,
+                   "paper_gp106_ms": paper_ms}
+            rows.append(row)
+            log(f"Table I {name} {n_co} COs x {n_acc} profiles, {row['overlap']:5s}: {checks:,} checks, "
+                f"step {step_ms * 1e3:.1f} us ({row['checks_per_s']:.3g} checks/s), collide {k2_ms * 1e3:.1f} us "
+                f"({row['collide_tflops']:.1f} TFLOP/s), host-to-host p50 {row['e2e_p50_ms']:.3f} ms "
+                f"[paper, GP106: {paper_ms:.0f} ms]")
+    return rows
 
 
 def class_checks(scene):
@@ -328,6 +387,7 @@ def main():
             f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
 
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
+        result["table_one"] = table_one(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)

@@ -54,6 +54,15 @@ enum { MHC_VEHICLE = 0, MHC_PEDESTRIAN = 1 };
  * (object 0) as in Sec. IV-C.1, where combinations between collision objects
  * are left out. */
 enum { MHC_PAIRS_ALL = 0, MHC_PAIRS_EGO = 1 };
+/* Overlap test of the collision recognition (Sec. IV-C.1).
+ * EXACT: the closed shapes intersect (rectangle-rectangle by separating axes,
+ *   rectangle-circle and circle-circle by exact distances).
+ * PIP: the paper's own test, a point-in-polygon check of every vertex of each
+ *   object's polygon against the other object's polygon, in both directions.
+ *   Every object must be a vehicle (rectangle); a vertex on the other
+ *   rectangle's boundary counts as inside. It misses overlaps in which no
+ *   vertex of either lies inside the other (two bars crossing). */
+enum { MHC_OVERLAP_EXACT = 0, MHC_OVERLAP_PIP = 1 };
 
 /* One traffic participant. Vehicles are rectangles (length along the heading,
  * width across it) moving on the kinematic special case of the Euler pose
@@ -78,6 +87,7 @@ typedef struct {
     int32_t horizon;              /* steps H, 1..32767 */
     double dt;                    /* step length tau > 0 */
     int32_t pairs;                /* MHC_PAIRS_ALL or MHC_PAIRS_EGO */
+    int32_t overlap;              /* MHC_OVERLAP_EXACT or MHC_OVERLAP_PIP */
 } mhc_scene;
 
 typedef struct {
@@ -178,10 +188,12 @@ void mhc_plan_destroy(mhc_plan *plan);
  * mhc_set_variant forces one (-1 returns to the tuned choice).
  * mhc_autotune times every variant on `scene` (`reps` launches each, after
  * one warm-up) and records the fastest for scenes of the same size class
- * (log2 buckets of the mean trajectory count and of the horizon); `us` (or
- * NULL) receives the mean microseconds per launch of each variant.
+ * (log2 buckets of the mean trajectory count and of the horizon, and the
+ * overlap mode); `us` (or NULL) receives the mean microseconds per launch of
+ * each variant.
  * mhc_tune_save / mhc_tune_load write / read the recorded choices as JSON
- * ({"gfx950": {"<T bucket>,<H bucket>": variant, ...}}). */
+ * ({"gfx950": {"<T bucket>,<H bucket>,<1 if PIP>": variant, ...}}; a key
+ * with two fields is read as an exact-overlap class). */
 enum { MHC_N_VARIANTS = 4 };
 mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant);
 mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int32_t *best_variant, double *us);

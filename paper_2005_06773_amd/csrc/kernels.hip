@@ -4,7 +4,13 @@
 // street data processing, run in that order, each data-parallel inside).
 #include "mhc_internal.h"
 
+#include <climits>
 #include <math.h>
+
+// The overlap tests combine their comparisons with bitwise & and | on bools
+// on purpose: every comparison is evaluated and the results are merged as
+// lane masks, with no branch per comparison.
+#pragma clang diagnostic ignored "-Wbitwise-instead-of-logical"
 
 namespace mhc {
 
@@ -148,6 +154,8 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
 //     half extents use |cos(psi_Q - psi_P)| and |sin(psi_Q - psi_P)|;
 //   rectangle-circle: distance from the centre to the rectangle <= r;
 //   circle-circle: centre distance <= r_P + r_Q.
+// The point-in-polygon mode instead tests the four corners of each rectangle
+// against the other rectangle (the paper's test, both ways).
 // ===========================================================================
 
 struct CheckVV {
@@ -168,6 +176,45 @@ struct CheckVV {
         const float r3 = fmaf(lP, aC, fmaf(wP, aS, lQ));
         const float r4 = fmaf(lP, aS, fmaf(wP, aC, wQ));
         return (fabsf(p1) <= r1) & (fabsf(p2) <= r2) & (fabsf(p3) <= r3) & (fabsf(p4) <= r4);
+    }
+};
+
+// Point-in-polygon both ways for two rectangles. A corner of Q is
+// c_Q + al*lQ*u_Q + be*wQ*v_Q (al, be = +-1); in P's frame it sits at
+//   x = d.u_P + al*lQ*C - be*wQ*S,   y = d.v_P + al*lQ*S + be*wQ*C
+// (C = u_P.u_Q, S = v_P.u_Q, d = c_Q - c_P) and lies in the closed P iff
+// |x| <= lP and |y| <= wP. The corners of P in Q's frame follow with the roles
+// swapped; flipping both signs of a corner leaves |x| and |y| unchanged, so
+// they are (d.u_Q + al*lP*C + be*wP*S, d.v_Q - al*lP*S + be*wP*C).
+struct CheckVVPip {
+    float lP, wP, lQ, wQ;
+    __device__ __forceinline__ bool operator()(const float4 P, const float4 Q) const
+    {
+        const float dx = Q.x - P.x;
+        const float dy = Q.y - P.y;
+        const float C = fmaf(P.z, Q.z, P.w * Q.w);
+        const float S = fmaf(P.z, Q.w, -(P.w * Q.z));
+        const float p1 = fmaf(dx, P.z, dy * P.w);     // d . u_P
+        const float p2 = fmaf(dy, P.z, -(dx * P.w));  // d . v_P
+        const float p3 = fmaf(dx, Q.z, dy * Q.w);     // d . u_Q
+        const float p4 = fmaf(dy, Q.z, -(dx * Q.w));  // d . v_Q
+        // Q's corners in P: (p1 +- g, p2 +- k) and (p1 +- h, p2 +- m), signs paired
+        const float wQS = wQ * S, wQC = wQ * C;
+        const float g = fmaf(lQ, C, -wQS), h = fmaf(lQ, C, wQS);
+        const float k = fmaf(lQ, S, wQC), m = fmaf(lQ, S, -wQC);
+        const bool q_in_p = ((fabsf(p1 + g) <= lP) & (fabsf(p2 + k) <= wP)) |
+                            ((fabsf(p1 - g) <= lP) & (fabsf(p2 - k) <= wP)) |
+                            ((fabsf(p1 + h) <= lP) & (fabsf(p2 + m) <= wP)) |
+                            ((fabsf(p1 - h) <= lP) & (fabsf(p2 - m) <= wP));
+        // P's corners in Q: (p3 +- g2, p4 -+ k2) and (p3 +- h2, p4 -+ m2)
+        const float wPS = wP * S, wPC = wP * C;
+        const float g2 = fmaf(lP, C, wPS), h2 = fmaf(lP, C, -wPS);
+        const float k2 = fmaf(lP, S, -wPC), m2 = fmaf(lP, S, wPC);
+        const bool p_in_q = ((fabsf(p3 + g2) <= lQ) & (fabsf(p4 - k2) <= wQ)) |
+                            ((fabsf(p3 - g2) <= lQ) & (fabsf(p4 + k2) <= wQ)) |
+                            ((fabsf(p3 + h2) <= lQ) & (fabsf(p4 - m2) <= wQ)) |
+                            ((fabsf(p3 - h2) <= lQ) & (fabsf(p4 + m2) <= wQ));
+        return q_in_p | p_in_q;
     }
 };
 
@@ -229,8 +276,14 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
                                               unsigned long long *__restrict__ qacc, const Check chk)
 {
     const int n_ig = pr.n_ig, n_jg = pr.n_jg;
-    const int f = item0 + (int)(threadIdx.x & (WAVE - 1));
-    if (f >= n_ig * n_jg) return;
+    // time split: E = 64 >> tshift items per unit, part p of the steps per lane
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int tshift = pr.tshift;
+    const int per = WAVE >> tshift;
+    const int part = lane >> (6 - tshift);
+    const int chunk = pr.H >> tshift;
+    const int f = item0 + (lane & (per - 1));
+    if (f >= n_ig * n_jg) return;  // every part of an item leaves together
     const int ig = f / n_jg;
     const int jg = f - ig * n_jg;
     const int Ta = pr.Ta, Tb = pr.Tb;
@@ -245,18 +298,20 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     const __amdgpu_buffer_rsrc_t A = pose_rsrc(poses + pr.pose_a, (uint32_t)((size_t)pr.H * Ta * sizeof(PA)));
     const __amdgpu_buffer_rsrc_t B = pose_rsrc(poses + pr.pose_b, (uint32_t)((size_t)pr.H * Tb * sizeof(PB)));
     const uint32_t strideA = (uint32_t)Ta * (uint32_t)sizeof(PA), strideB = (uint32_t)Tb * (uint32_t)sizeof(PB);
+    // lane offsets: the trajectory and the first step of this lane's part
+    const uint32_t t0 = (uint32_t)(part * chunk);
     uint32_t oa[RI], ob[RJ];
 #pragma unroll
-    for (int r = 0; r < RI; ++r) oa[r] = (uint32_t)ia[r] * (uint32_t)sizeof(PA);
+    for (int r = 0; r < RI; ++r) oa[r] = (uint32_t)ia[r] * (uint32_t)sizeof(PA) + t0 * strideA;
 #pragma unroll
-    for (int s = 0; s < RJ; ++s) ob[s] = (uint32_t)jb[s] * (uint32_t)sizeof(PB);
+    for (int s = 0; s < RJ; ++s) ob[s] = (uint32_t)jb[s] * (uint32_t)sizeof(PB) + t0 * strideB;
     int first[RI][RJ];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
 #pragma unroll
         for (int s = 0; s < RJ; ++s) first[r][s] = -1;
 
-    for (int t = pr.H - 1; t >= 0; --t) {
+    for (int t = chunk - 1; t >= 0; --t) {
         const uint32_t sa = (uint32_t)t * strideA, sb = (uint32_t)t * strideB;
         PA a[RI];
         PB b[RJ];
@@ -269,6 +324,19 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
 #pragma unroll
             for (int s = 0; s < RJ; ++s)
                 if (chk(a[r], b[s])) first[r][s] = t;
+    }
+    if (tshift) {
+        // the earliest hit over the parts: parts hold consecutive step ranges,
+        // so it is the smallest step found by any part (lanes l ^ E, l ^ 2E)
+#pragma unroll
+        for (int r = 0; r < RI; ++r)
+#pragma unroll
+            for (int s = 0; s < RJ; ++s) {
+                int v = first[r][s] >= 0 ? first[r][s] + (int)t0 : INT_MAX;
+                for (int off = per; off < WAVE; off <<= 1) v = min(v, __shfl_xor(v, off));
+                first[r][s] = v == INT_MAX ? -1 : v;
+            }
+        if (part != 0) return;
     }
     // Results: the first hits, and this thread's share of the q sums. A
     // colliding trajectory pair (i, j) adds p_{b,j} to q_{a,i;b} and p_{a,i}
@@ -312,11 +380,21 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     }
 }
 
-template <int V>
+// PIP: whether this kernel instance carries the point-in-polygon class. Its
+// larger tile needs more registers, which would lower the occupancy of the
+// exact classes; launches without such pairs use the instance without it.
+template <int V, bool PIP>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
                                              unsigned long long *__restrict__ qacc)
 {
+    if constexpr (PIP) {
+        if (pr.cls == CLS_VV_PIP) {
+            collide_items<kTiles[V][CLS_VV_PIP].ri, kTiles[V][CLS_VV_PIP].rj, float4, float4>(
+                pr, item0, poses, hits, pfix, qacc, CheckVVPip{pr.la, pr.wa, pr.lb, pr.wb});
+            return;
+        }
+    }
     switch (pr.cls) {
     case CLS_VV:
         collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, float4, float4>(
@@ -345,7 +423,7 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 // load-heavy and arithmetic-heavy test classes on every CU. The host
 // balances the slots by the exact instruction cost of the work, so every
 // SIMD finishes together without any cross-XCD atomics.
-template <int V>
+template <int V, bool PIP>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
@@ -366,7 +444,8 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
     for (int k = bins[slot]; k < s1; ++k) {
         const WorkItem w = work[k];
         const DPair pr = pairs[w.pair];
-        for (int u = 0; u < w.n_units; ++u) collide_work<V>(pr, w.item0 + u * WAVE_ITEMS, poses, hits, pfix, qacc);
+        const int per = WAVE >> pr.tshift;
+        for (int u = 0; u < w.n_units; ++u) collide_work<V, PIP>(pr, w.item0 + u * per, poses, hits, pfix, qacc);
     }
 }
 
@@ -438,11 +517,11 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int V>
+template <int V, bool PIP>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL(k2_collide<V>, dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.xcd_major,
+    hipLaunchKernelGGL((k2_collide<V, PIP>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.xcd_major,
                        L.poses, L.hits, L.pfix, L.qacc);
     return hipGetLastError();
 }
@@ -450,31 +529,39 @@ static hipError_t launch_k2(const Launch &L, hipStream_t s)
 hipError_t launch_collide(const Launch &L, hipStream_t s)
 {
     if (L.n_work <= 0) return hipSuccess;
-    switch (L.variant) {
-    case 0: return launch_k2<0>(L, s);
-    case 1: return launch_k2<1>(L, s);
-    case 2: return launch_k2<2>(L, s);
-    case 3: return launch_k2<3>(L, s);
+    switch (L.variant * 2 + (L.pip ? 1 : 0)) {
+    case 0: return launch_k2<0, false>(L, s);
+    case 1: return launch_k2<0, true>(L, s);
+    case 2: return launch_k2<1, false>(L, s);
+    case 3: return launch_k2<1, true>(L, s);
+    case 4: return launch_k2<2, false>(L, s);
+    case 5: return launch_k2<2, true>(L, s);
+    case 6: return launch_k2<3, false>(L, s);
+    case 7: return launch_k2<3, true>(L, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <int V>
+template <int V, bool PIP>
 static int k2_resident_blocks()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V>, WG, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, PIP>, WG, 0) != hipSuccess || per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-int collide_blocks_per_cu(int variant)
+int collide_blocks_per_cu(int variant, bool pip)
 {
-    switch (variant) {
-    case 0: return k2_resident_blocks<0>();
-    case 1: return k2_resident_blocks<1>();
-    case 2: return k2_resident_blocks<2>();
-    default: return k2_resident_blocks<3>();
+    switch (variant * 2 + (pip ? 1 : 0)) {
+    case 0: return k2_resident_blocks<0, false>();
+    case 1: return k2_resident_blocks<0, true>();
+    case 2: return k2_resident_blocks<1, false>();
+    case 3: return k2_resident_blocks<1, true>();
+    case 4: return k2_resident_blocks<2, false>();
+    case 5: return k2_resident_blocks<2, true>();
+    case 6: return k2_resident_blocks<3, false>();
+    default: return k2_resident_blocks<3, true>();
     }
 }
 

@@ -14,7 +14,8 @@ enum Kind : int32_t { KIND_VEHICLE = 0, KIND_PEDESTRIAN = 1 };
 
 // Shape class of an object pair: which overlap test applies and which side
 // holds the rectangle.
-enum PairClass : int32_t { CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, N_CLS = 4 };
+// CLS_VV_PIP: two rectangles under the point-in-polygon test.
+enum PairClass : int32_t { CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, CLS_VV_PIP = 4, N_CLS = 5 };
 
 // One object of one scene. Offsets are global across all scenes of a launch.
 struct DObj {
@@ -44,15 +45,18 @@ struct DPair {
     float la, wa, lb, wb;         // half length / half width of vehicles
     float rr;                     // squared test radius: r_Q^2 (rect-circle), (r_P + r_Q)^2 (circle-circle)
     int32_t qn;                   // q row stride: object count of the scene
+    int32_t tshift;               // time split S = 2^tshift (S divides H): a unit's steps run in S parts
     int64_t qa0;                  // q index of (a, i = 0, b)
     int64_t qb0;                  // q index of (b, j = 0, a)
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
 };
 
-// A run of collision work for one wave: n_units consecutive units of a pair,
-// a unit being the WAVE_ITEMS items item0 + 64u .. item0 + 64u + 63 (lane l
-// takes item0 + 64u + l; items past the pair's end are idle lanes). The host
-// assigns every wave of the collision kernel a range of segments.
+// A run of collision work for one wave: n_units consecutive units of a pair.
+// A unit is the E = 64 / S consecutive items item0 + E*u .. item0 + E*u + E-1
+// of a pair with time split S: lane l takes item item0 + E*u + l % E and the
+// steps [p*H/S, (p+1)*H/S) of part p = l / E, so the S parts of an item run
+// side by side in one wave (items past the pair's end are idle lanes). The
+// host assigns every wave of the collision kernel a range of segments.
 struct WorkItem {
     int32_t pair;
     int32_t item0;
@@ -62,7 +66,7 @@ struct WorkItem {
 
 constexpr int WG = 256;           // threads per workgroup, all kernels
 constexpr int WAVE = 64;          // wavefront size
-constexpr int WAVE_ITEMS = WAVE;  // collision items per work unit (one per lane)
+constexpr int MAX_TSHIFT = 2;     // time split of a collision unit: S <= 4
 constexpr int N_XCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
 // q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
@@ -74,14 +78,15 @@ struct TileShape {
     int ri, rj;
 };
 constexpr int N_VARIANTS = 4;
-// variant -> shape per class {VV, VP, PV, PP}. The shapes keep the VALU cost
-// of one work unit similar across classes (27, 14 and 6 VALU per
-// rect-rect, rect-circle and circle-circle test) and the loads per test low.
+// variant -> shape per class {VV, VP, PV, PP, VV_PIP}. The shapes keep the
+// VALU cost of one work unit similar across classes (27, 14, 6 and 59 VALU
+// per rect-rect, rect-circle, circle-circle and point-in-polygon test) and
+// the loads per test low.
 constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {
-    {{2, 2}, {2, 2}, {2, 2}, {4, 4}},
-    {{2, 2}, {4, 2}, {2, 4}, {4, 4}},
-    {{4, 2}, {4, 2}, {2, 4}, {4, 4}},
-    {{2, 1}, {2, 2}, {2, 2}, {4, 2}},
+    {{2, 2}, {2, 2}, {2, 2}, {4, 4}, {2, 2}},
+    {{2, 2}, {4, 2}, {2, 4}, {4, 4}, {2, 1}},
+    {{4, 2}, {4, 2}, {2, 4}, {4, 4}, {4, 2}},
+    {{2, 1}, {2, 2}, {2, 2}, {4, 2}, {1, 1}},
 };
 
 // Launch entry points (kernels.hip).
@@ -103,11 +108,14 @@ struct Launch {
     int k1_x;                     // trajectory kernel grid x: blocks of the largest object + 1
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
+    int pip;                      // some pair uses the point-in-polygon test
 };
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s);
 hipError_t launch_collide(const Launch &L, hipStream_t s);
 hipError_t launch_risk(const Launch &L, hipStream_t s);
-int collide_blocks_per_cu(int variant);  // resident workgroups of the collision kernel per CU
+// resident workgroups per CU of the collision kernel for a variant, with or
+// without the point-in-polygon class
+int collide_blocks_per_cu(int variant, bool pip);
 
 }  // namespace mhc

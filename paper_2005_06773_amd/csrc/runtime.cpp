@@ -17,8 +17,9 @@ namespace mhc {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static int cls_of(int ka, int kb)
+int pair_class(int ka, int kb, int overlap)
 {
+    if (overlap == MHC_OVERLAP_PIP) return CLS_VV_PIP;  // validated: vehicles only
     if (ka == KIND_VEHICLE && kb == KIND_VEHICLE) return CLS_VV;
     if (ka == KIND_VEHICLE) return CLS_VP;
     if (kb == KIND_VEHICLE) return CLS_PV;
@@ -26,12 +27,17 @@ static int cls_of(int ka, int kb)
 }
 
 // Relative VALU cost of one check per class, for longest-first ordering.
-static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4};
+static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4, 60.0};
 // Per-unit cost outside the step loop (setup, result stores), same units.
 static const double kUnitOverhead = 120.0;
 // From this many work units per collision wave on, waves take contiguous
 // stretches of the unit sequence instead of individually packed units.
 static const int kContiguousUnitsPerWave = 8;
+// Below this many work units per resident collision wave, units are split in
+// time (up to S = 4 parts side by side in a wave) to get more, shorter
+// units. Around one unit per wave the split costs more than it balances
+// (measured on the 11-object scene: 40.5 us with S = 2 against 37.0 us).
+static const double kSplitBelowUnitsPerWave = 0.75;
 
 static bool finite(double v) { return std::isfinite(v); }
 
@@ -59,6 +65,8 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
     if (s->horizon < 1 || s->horizon > 32767) return fail("horizon must be in [1, 32767] (got %d)", s->horizon);
     if (!finite(s->dt) || !(s->dt > 0.0)) return fail("dt must be finite and > 0%.0d", 0);
     if (s->pairs != MHC_PAIRS_ALL && s->pairs != MHC_PAIRS_EGO) return fail("pairs must be 0 or 1 (got %d)", s->pairs);
+    if (s->overlap != MHC_OVERLAP_EXACT && s->overlap != MHC_OVERLAP_PIP)
+        return fail("overlap must be 0 or 1 (got %d)", s->overlap);
     for (int a = 0; a < s->n_objects; ++a) {
         const mhc_object &o = s->objects[a];
         if (o.kind != MHC_VEHICLE && o.kind != MHC_PEDESTRIAN) return fail("object %d: kind must be 0 or 1", a);
@@ -92,6 +100,10 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
     }
     if (s->objects[0].kind != MHC_VEHICLE && s->pairs == MHC_PAIRS_EGO)
         return fail("EGO pair mode needs object 0 to be a vehicle%.0d", 0);
+    if (s->overlap == MHC_OVERLAP_PIP)
+        for (int a = 0; a < s->n_objects; ++a)
+            if (s->objects[a].kind != MHC_VEHICLE)
+                return fail("object %d: the point-in-polygon overlap test needs every object to be a vehicle", a);
     return true;
 }
 
@@ -162,7 +174,8 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             DPair pr{};
             pr.a = obj_base + a;
             pr.b = obj_base + b;
-            pr.cls = cls_of(oa.kind, ob.kind);
+            pr.cls = pair_class(oa.kind, ob.kind, s.overlap);
+            L.pip |= pr.cls == CLS_VV_PIP;
             pr.H = s.horizon;
             pr.Ta = oa.n_u * oa.n_w;
             pr.Tb = ob.n_u * ob.n_w;
@@ -177,13 +190,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             pr.qb0 = L.objs[obj_base + b].q_row + a;
             pr.pa_off = L.objs[obj_base + a].traj_off;
             pr.pb_off = L.objs[obj_base + b].traj_off;
-            const int pidx = (int)L.pairs.size();
             L.pairs.push_back(pr);
-            const int64_t items = (int64_t)pr.n_ig * pr.n_jg;
-            // a wave executes every step of every test of a unit, whether or
-            // not all of its lanes hold an item
-            const double unit_cost = (double)ts.ri * ts.rj * pr.H * kClsCost[pr.cls] + kUnitOverhead;
-            costs.push_back(PairCost{unit_cost, pidx, (int32_t)((items + WAVE_ITEMS - 1) / WAVE_ITEMS)});
             hoff += (int64_t)pr.Ta * pr.Tb;
             ext.checks += (int64_t)pr.Ta * pr.Tb * s.horizon;
         }
@@ -197,6 +204,36 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         L.n_obj += n;
         L.n_checks += ext.checks;
     }
+    // Time split. With few units for the resident waves, a unit's steps are
+    // cut into S parts that run side by side in one wave (64/S items, H/S
+    // steps per lane): S times as many, S times shorter units, which the
+    // packing below can spread evenly and which fill the GPU. S is the
+    // smallest of 1, 2, 4 that gives enough units (4 for the size bound,
+    // max_waves = 0), lowered per pair until it divides the horizon.
+    auto units_with = [](const DPair &pr, int tshift) {
+        const int64_t per = WAVE >> tshift;
+        return ((int64_t)pr.n_ig * pr.n_jg + per - 1) / per;
+    };
+    int want = MAX_TSHIFT;
+    if (max_waves > 0) {
+        for (want = 0; want < MAX_TSHIFT; ++want) {
+            int64_t u = 0;
+            for (const DPair &pr : L.pairs) u += units_with(pr, want);
+            if ((double)u >= kSplitBelowUnitsPerWave * max_waves) break;
+        }
+    }
+    for (size_t pidx = 0; pidx < L.pairs.size(); ++pidx) {
+        DPair &pr = L.pairs[pidx];
+        int sh = want;
+        while (sh > 0 && (pr.H % (1 << sh)) != 0) --sh;
+        pr.tshift = sh;
+        const TileShape ts = kTiles[variant][pr.cls];
+        // a wave executes every step of every test of a unit, whether or
+        // not all of its lanes hold an item
+        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * kClsCost[pr.cls] + kUnitOverhead;
+        costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)units_with(pr, sh)});
+    }
+
     // Collision plan: every wave slot gets a list of segments of work units.
     int64_t n_units = 0;
     double total_cost = 0.0;
@@ -229,7 +266,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
                     k = (int32_t)std::max(0.0, std::min((double)left, want));
                 }
                 if (k > 0) {
-                    L.work.push_back(WorkItem{pc.pidx, u * WAVE_ITEMS, k, 0});
+                    L.work.push_back(WorkItem{pc.pidx, u * (WAVE >> L.pairs[pc.pidx].tshift), k, 0});
                     acc += pc.c * k;
                     u += k;
                 }
@@ -266,7 +303,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             int pos = 0;
             for (size_t pp = p0; pp < p1; ++pp)
                 for (int32_t u = 0; u < sorted[pp].n_units; ++u, ++k) {
-                    units[k] = WorkItem{sorted[pp].pidx, u * WAVE_ITEMS, 1, 0};
+                    units[k] = WorkItem{sorted[pp].pidx, u * (WAVE >> L.pairs[sorted[pp].pidx].tshift), 1, 0};
                     unit_bin[k] = order[pos];
                     if (++pos == n_bins) pos = 0;
                 }
@@ -391,6 +428,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_work = (int)L.work.size();
     X.k1_x = L.k1_x;
     X.variant = L.variant;
+    X.pip = L.pip ? 1 : 0;
     X.n_bins = (int)L.bins.size() - 1;
     X.xcd_major = L.contiguous ? 1 : 0;
     (void)n_cu;
@@ -463,11 +501,13 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
     delete ctx;
 }
 
-int mhc_ctx::max_waves(int v)
+int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
 {
     if (v < 0 || v >= N_VARIANTS) v = 0;
-    if (!waves_cache[v]) waves_cache[v] = n_cu * collide_blocks_per_cu(v) * (WG / WAVE);
-    return waves_cache[v];
+    int pip = 0;
+    for (int k = 0; k < n; ++k) pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
+    if (!waves_cache[v][pip]) waves_cache[v][pip] = n_cu * collide_blocks_per_cu(v, pip != 0) * (WG / WAVE);
+    return waves_cache[v][pip];
 }
 
 extern "C" const char *mhc_last_error(const mhc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
@@ -496,7 +536,7 @@ extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
 
 std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
 {
-    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs};
+    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs, s->overlap};
     for (int a = 0; a < s->n_objects; ++a) {
         v.push_back(s->objects[a].kind);
         v.push_back(s->objects[a].n_u);
@@ -513,13 +553,13 @@ static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool wit
     const int v = ctx->variant_for(scene, 1);
     std::vector<int32_t> shape = shape_of(scene);
     shape.push_back(v);
-    shape.push_back(ctx->max_waves(v));
+    shape.push_back(ctx->max_waves(v, scene, 1));
     shape.push_back(with_hits);
     if (!L.objs.empty() && shape == ctx->layout_shape) {
         fill_values(scene, 1, L);
         return;
     }
-    build_layout(scene, 1, v, ctx->max_waves(v), L, with_hits);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, with_hits);
     ctx->layout_shape = std::move(shape);
 }
 
@@ -655,7 +695,7 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     }
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     Layout L;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), L, true);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), L, true);
     if (workspace_bytes < L.total_bytes) {
         ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
         return MHC_E_INVAL;
@@ -742,7 +782,8 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     HIPC(hipSetDevice(ctx->device));
     mhc_plan *pl = new mhc_plan();
     pl->ctx = ctx;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1)), pl->L, true);
+    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), pl->L,
+                 true);
     pl->shape = shape_of(scene);
     if (ctx->budget && pl->L.total_bytes > ctx->budget) {
         ctx->err = "plan needs more device memory than the context budget";
@@ -777,7 +818,7 @@ extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
     }
     HIPC(hipSetDevice(ctx->device));
     Layout L;
-    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant), L, true);
+    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant, scene, 1), L, true);
     std::vector<char> img(L.image_bytes);
     pack_image(L, img.data());
     HIPC(hipDeviceSynchronize());
@@ -895,11 +936,11 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
     bool keep = false;
     for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
     const int v = ctx->variant_for(scenes, n);
-    build_layout(scenes, n, v, ctx->max_waves(v), L, keep);
+    build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, keep);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
-    std::vector<int64_t> key{v, ctx->max_waves(v), n};
+    std::vector<int64_t> key{v, ctx->max_waves(v, scenes, n), n};
     for (int k = 0; k < n; ++k) {
         const std::vector<int32_t> sh = shape_of(&scenes[k]);
         key.insert(key.end(), sh.begin(), sh.end());

@@ -1,6 +1,7 @@
 // Host-side runtime structures (not part of the public ABI).
 #pragma once
 
+#include <array>
 #include <functional>
 #include <map>
 #include <string>
@@ -42,6 +43,7 @@ struct Layout {
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
+    bool pip = false;             // some pair uses the point-in-polygon test
     bool with_hits = true;        // the workspace holds the first-hit matrix
 };
 
@@ -58,6 +60,8 @@ struct GraphCache {
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
+// Test class (CLS_*) of an object pair of kinds ka, kb under an overlap mode.
+int pair_class(int ka, int kb, int overlap);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
@@ -83,13 +87,16 @@ struct mhc_ctx {
     std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
     mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
     int forced_variant = -1;                      // mhc_set_variant
-    std::map<std::pair<int, int>, int> tuned;     // size class -> variant (mhc_autotune)
+    std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;
-    int waves_cache[mhc::N_VARIANTS] = {};
-    int max_waves(int variant);                   // resident collision waves on this GPU
+    int waves_cache[mhc::N_VARIANTS][2] = {};
+    // resident waves on this GPU of the collision kernel that `scenes` need
+    int max_waves(int variant, const mhc_scene *scenes, int n);
 };
 
-std::pair<int, int> size_class(const mhc_scene *scenes, int n);
+// Autotuning class of a launch: log2 of the mean trajectory count, log2 of
+// the mean horizon, and whether any scene uses the point-in-polygon test.
+std::array<int, 3> size_class(const mhc_scene *scenes, int n);
 
 mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);
 mhc_status copy_results(mhc_ctx *ctx, const mhc::Layout &L, int k, const char *dbase, const mhc_result *res,

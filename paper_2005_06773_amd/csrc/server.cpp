@@ -117,15 +117,25 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
             const int64_t Ta = (int64_t)s->objects[a].n_u * s->objects[a].n_w;
             const int64_t Tb = (int64_t)s->objects[b].n_u * s->objects[b].n_w;
             n_hits += Ta * Tb;
-            // the smallest micro-tile of any variant is 2 x 1
-            n_units += ((Ta + 1) / 2 * Tb + WAVE_ITEMS - 1) / WAVE_ITEMS;
+            // one collision segment per work unit, for the variant and the
+            // time split (up to 4 parts, 16 items a unit) that cut this pair
+            // into the most units
+            const int cls = pair_class(s->objects[a].kind, s->objects[b].kind, s->overlap);
+            int64_t most = 0;
+            for (int v = 0; v < N_VARIANTS; ++v) {
+                const int64_t items = (Ta + kTiles[v][cls].ri - 1) / kTiles[v][cls].ri *
+                                      ((Tb + kTiles[v][cls].rj - 1) / kTiles[v][cls].rj);
+                const int64_t per = WAVE >> MAX_TSHIFT;
+                most = std::max(most, (items + per - 1) / per);
+            }
+            n_units += most;
             ++n_pairs;
         }
     const int64_t n_q = n_traj * n;
     size_t bytes = 0;
     bytes += align256(n * sizeof(DObj)) + align256(vals * 8) + align256(n_pairs * sizeof(DPair));
-    bytes += align256((n_units + 1) * sizeof(WorkItem)) + align256((size_t)n * n * 4);
-    bytes += pose + align256(n_traj * 8) * 4 + align256(n_q * 8) * 2 + align256(n * 4);
+    bytes += align256((n_units + 1) * sizeof(WorkItem));
+    bytes += pose + align256(n_traj * 8) * 3 + align256(n_q * 8) * 2;  // p*2^62, p, traj crit; q sums, q
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);
     bytes += 16 * 256;                              // alignment slack of the tables
     bytes += align256(((size_t)max_waves + 1) * 4);  // the collision plan's slot table
@@ -187,7 +197,8 @@ hipError_t launch_tick(mhc_server *srv, TickSlot &t)
     const int v = ctx->variant_for(scenes.data(), (int)scenes.size());
     bool keep_hits = false;
     for (auto &f : t.frames) keep_hits |= f->dst.first_hit != nullptr;
-    build_layout(scenes.data(), (int)scenes.size(), v, ctx->max_waves(v), t.L, keep_hits);
+    build_layout(scenes.data(), (int)scenes.size(), v, ctx->max_waves(v, scenes.data(), (int)scenes.size()), t.L,
+                 keep_hits);
     if (t.L.total_bytes > t.dbytes) return hipErrorOutOfMemory;  // admission bounds exclude this
     hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes);
     if (e != hipSuccess) return e;

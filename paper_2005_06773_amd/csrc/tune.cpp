@@ -20,16 +20,18 @@ static int ilog2_floor(double x)
     return b;
 }
 
-std::pair<int, int> size_class(const mhc_scene *scenes, int n)
+std::array<int, 3> size_class(const mhc_scene *scenes, int n)
 {
     double traj = 0.0, objs = 0.0, hsum = 0.0;
+    int pip = 0;
     for (int k = 0; k < n; ++k) {
+        pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
         for (int a = 0; a < scenes[k].n_objects; ++a)
             traj += (double)scenes[k].objects[a].n_u * scenes[k].objects[a].n_w;
         objs += scenes[k].n_objects;
         hsum += scenes[k].horizon;
     }
-    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n))};
+    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n)), pip};
 }
 
 int mhc_ctx::variant_for(const mhc_scene *scenes, int n) const
@@ -77,7 +79,7 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
     mhc_status st = MHC_OK;
     for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
         Layout L;
-        build_layout(scene, 1, v, ctx->max_waves(v), L, false);
+        build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, false);
         st = ensure_device(ctx, L.total_bytes);
         if (st != MHC_OK) break;
         char *base = static_cast<char *>(ctx->dbuf);
@@ -127,7 +129,8 @@ extern "C" mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path)
     f << "{\"gfx950\": {";
     bool firstk = true;
     for (auto &kv : ctx->tuned) {
-        f << (firstk ? "" : ", ") << "\"" << kv.first.first << "," << kv.first.second << "\": " << kv.second;
+        f << (firstk ? "" : ", ") << "\"" << kv.first[0] << "," << kv.first[1] << "," << kv.first[2]
+          << "\": " << kv.second;
         firstk = false;
     }
     f << "}}\n";
@@ -150,7 +153,7 @@ extern "C" mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path)
         ctx->err = "tune file has no gfx950 entry";
         return MHC_E_INVAL;
     }
-    std::map<std::pair<int, int>, int> got;
+    std::map<std::array<int, 3>, int> got;
     size_t pos = s.find('{', arch);
     const size_t end = s.find('}', pos);
     if (pos == std::string::npos || end == std::string::npos) {
@@ -160,12 +163,18 @@ extern "C" mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path)
     while (true) {
         const size_t q = s.find('"', pos + 1);
         if (q == std::string::npos || q > end) break;
-        int tb = 0, hb = 0, v = 0;
-        if (std::sscanf(s.c_str() + q, "\"%d,%d\": %d", &tb, &hb, &v) != 3 || v < 0 || v >= N_VARIANTS) {
+        // keys are "T bucket,H bucket,pip"; a key without the third field is
+        // an exact-overlap class
+        int tb = 0, hb = 0, pip = 0, v = 0;
+        if (std::sscanf(s.c_str() + q, "\"%d,%d,%d\": %d", &tb, &hb, &pip, &v) != 4) {
+            pip = 0;
+            if (std::sscanf(s.c_str() + q, "\"%d,%d\": %d", &tb, &hb, &v) != 3) v = -1;
+        }
+        if (v < 0 || v >= N_VARIANTS || (pip != 0 && pip != 1)) {
             ctx->err = "malformed tune file entry";
             return MHC_E_INVAL;
         }
-        got[{tb, hb}] = v;
+        got[{tb, hb, pip}] = v;
         pos = s.find('"', q + 1);
         if (pos == std::string::npos) break;
     }

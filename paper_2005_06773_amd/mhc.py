@@ -22,6 +22,8 @@ MHC_E_NOMEM = -2
 MHC_E_DEVICE = -3
 MHC_E_BUSY = -4
 MHC_E_TIMEOUT = -5
+MHC_OVERLAP_EXACT = 0
+MHC_OVERLAP_PIP = 1
 _STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE",
            -4: "MHC_E_BUSY", -5: "MHC_E_TIMEOUT"}
 
@@ -58,7 +60,8 @@ class mhc_object(ctypes.Structure):
 
 class mhc_scene(ctypes.Structure):
     _fields_ = [("n_objects", ctypes.c_int32), ("objects", ctypes.POINTER(mhc_object)),
-                ("horizon", ctypes.c_int32), ("dt", _D), ("pairs", ctypes.c_int32)]
+                ("horizon", ctypes.c_int32), ("dt", _D), ("pairs", ctypes.c_int32),
+                ("overlap", ctypes.c_int32)]
 
 
 class mhc_sizes(ctypes.Structure):
@@ -164,7 +167,8 @@ class CScene:
             objs[k].w = w.ctypes.data_as(_DP)
             objs[k].score = sc.ctypes.data_as(_DP) if sc is not None else None
         self.objs = objs
-        self.c = mhc_scene(scene.n_objects, objs, int(scene.horizon), float(scene.dt), int(scene.pairs))
+        self.c = mhc_scene(scene.n_objects, objs, int(scene.horizon), float(scene.dt), int(scene.pairs),
+                           int(getattr(scene, "overlap", MHC_OVERLAP_EXACT)))
         self.T = [len(o.u) * len(o.w) for o in scene.objects]
         self.n = scene.n_objects
         self.pairs = [(a, b) for a in range(self.n) for b in range(a + 1, self.n)

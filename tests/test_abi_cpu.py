@@ -76,6 +76,19 @@ def test_query_sizes_reproduce_paper_counts(mhc):
     assert abs(s1_5["n_checks"] - g["pose_combinations_s1_5"]) <= 2e4
 
 
+def test_query_sizes_of_the_table_one_workload(mhc):
+    """The execution-time experiment (Sec. VI-B): 2058 EGO trajectories, 42
+    per CO, 100 steps; the counts match the golden values in either overlap
+    mode."""
+    g = _golden()
+    for overlap in (sg.OVERLAP_EXACT, sg.OVERLAP_PIP):
+        q = mhc.mhc_query_sizes(sg.paper_scene(5, overlap=overlap))
+        assert q["n_checks"] == 86_436_000 and q["n_pairs"] == 10
+        assert q["n_traj"] == g["r_tra_o10"] and q["n_traj_pairs"] == g["r_col_o10"]
+        q = mhc.mhc_query_sizes(sg.paper_scene(5, n_co=3, overlap=overlap))
+        assert q["n_checks"] == 25_930_800
+
+
 def test_query_sizes_of_the_workloads(mhc):
     q = mhc.mhc_query_sizes(sg.eleven_object_scene(1))
     assert q["n_checks"] == 83_531_250 and q["n_pairs"] == 55 and q["n_traj"] == 2475
@@ -117,6 +130,10 @@ def _bad_scenes():
     s = base(); s.objects[0].u = np.zeros(200); s.objects[0].w = np.zeros(200); out["too_many_trajectories"] = s
     s = base(); s.horizon = 30000; s.objects[0].u = np.zeros(100); s.objects[0].w = np.zeros(100)
     out["pose_block_too_large"] = s
+    s = base(); s.overlap = 2; out["bad_overlap_mode"] = s
+    s = base(); s.overlap = sg.OVERLAP_PIP
+    s.objects[1] = sg.SceneObject(sg.PEDESTRIAN, 1, 0, 0, 1, 0, 0, 0.3, np.array([1.0]), np.array([0.0]))
+    out["pip_mode_with_a_pedestrian"] = s
     return out
 
 

@@ -1,8 +1,9 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
 Sizes: the 2-vehicle scene over many seeds, the 11-object scene (the size
-the benchmark times) in full, ragged and degenerate shapes, and a seeded
-sample of 20 object pairs of the 40-object stress scene.
+the benchmark times) in full, ragged and degenerate shapes, the Table I
+workload (86.4 M checks) in both overlap modes, point-in-polygon edge cases,
+and a seeded sample of 20 object pairs of the 40-object stress scene.
 """
 import math
 import os
@@ -130,6 +131,64 @@ def test_edge_scene_parity(mhc, ctx, name):
         assert np.all(g["first_hit"] == -1) and np.all(g["object_crit"] == 0)
 
 
+def _pip_scenes():
+    rng = np.random.default_rng(91)
+    out = {}
+    out["plus_sign_crossing"] = sg.Scene([veh(-10, 0, 0.0, 10, [0.0], [0.0]), veh(0, 0, math.pi / 2, 0, [0.0], [0.0])],
+                                         2, 1.0, overlap=sg.OVERLAP_PIP)
+    out["t_bone_20ms"] = sg.Scene([veh(-10, 0, 0.0, 10, sg.accel_grid(5), sg.yaw_grid(9)),
+                                   veh(0, 0, math.pi / 2, 0, sg.accel_grid(3), sg.yaw_grid(3))], 60, 0.02,
+                                  overlap=sg.OVERLAP_PIP)
+    out["containment_at_start"] = sg.Scene([veh(0, 0, 0.3, 0, sg.accel_grid(5), sg.yaw_grid(5), L=8.0, W=3.0),
+                                            veh(0.5, 0.2, 1.0, 0, sg.accel_grid(4), sg.yaw_grid(4), L=1.0, W=0.8)],
+                                           10, 0.1, overlap=sg.OVERLAP_PIP)
+    out["tile_spanning_257x129"] = sg.Scene([veh(0, 0, 0.0, 10, sg.accel_grid(257), sg.yaw_grid(1)),
+                                             veh(25, 1, math.pi, 10, sg.accel_grid(3), sg.yaw_grid(43))], 40, 0.1,
+                                            overlap=sg.OVERLAP_PIP)
+    objs = [veh(rng.uniform(-15, 15), rng.uniform(-15, 15), rng.uniform(0, 2 * math.pi), rng.uniform(0, 12),
+                sg.accel_grid(int(rng.integers(3, 9))), sg.yaw_grid(int(rng.integers(3, 12))),
+                L=rng.uniform(3, 6), W=rng.uniform(1.5, 2.2)) for _ in range(6)]
+    out["six_vehicles_all_pairs_coarse"] = sg.Scene(objs, 30, 0.1, overlap=sg.OVERLAP_PIP)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_pip_scenes().keys()))
+def test_pip_scene_parity(mhc, ctx, name):
+    s = _pip_scenes()[name]
+    say(f"point-in-polygon scene {name}")
+    g = mhc.mhc_evaluate(ctx, s)
+    o = oracle.evaluate(s, threads=THREADS)
+    parity.check(s, g, o, name)
+    if name == "plus_sign_crossing":
+        assert g["first_hit"].tolist() == [-1]
+        s.overlap = sg.OVERLAP_EXACT
+        assert mhc.mhc_evaluate(ctx, s)["first_hit"].tolist() == [0]
+    if name == "containment_at_start":
+        assert np.all(g["first_hit"] == 0)
+
+
+@pytest.mark.parametrize("overlap", [0, 1], ids=["exact", "pip"])
+def test_table_one_workload_parity(mhc, ctx, overlap):
+    """The execution-time experiment of Sec. VI-B (S2: EGO 2058 trajectories
+    against 10 COs of 42, 100 steps of 20 ms, 86,436,000 checks) in full."""
+    for seed in (5, 6):
+        s = sg.paper_scene(seed, overlap=overlap)
+        say(f"Table I S2 scene seed {seed}, overlap mode {overlap}")
+        g = mhc.mhc_evaluate(ctx, s)
+        o = oracle.evaluate(s, threads=THREADS)
+        ex = parity.check(s, g, o, f"S2 seed {seed} overlap {overlap}")
+        say(f"  exact first-hit fraction {ex:.7f}, hits {(o.k64 >= 0).sum()}")
+
+
+def test_batch_mixes_overlap_modes(mhc, ctx):
+    scenes = [sg.paper_scene(7, n_co=3, overlap=sg.OVERLAP_PIP), sg.eleven_object_scene(3),
+              sg.paper_scene(8, n_co=3), _pip_scenes()["six_vehicles_all_pairs_coarse"]]
+    outs = mhc.mhc_evaluate_batch(ctx, scenes)
+    for k, (s, g) in enumerate(zip(scenes, outs)):
+        parity.same_results(mhc.mhc_evaluate(ctx, s), g, f"batch scene {k}")
+    parity.check(scenes[0], outs[0], oracle.evaluate(scenes[0], threads=THREADS), "batch PIP scene")
+
+
 def test_every_tile_variant_is_identical(mhc, ctx):
     """Each compiled micro-tile shape and wave cut gives bit-identical results
     (first hits, q, criticality) on scenes that cover all classes and ragged
@@ -137,7 +196,9 @@ def test_every_tile_variant_is_identical(mhc, ctx):
     edge = _edge_scenes()
     scenes = {"eleven_object_seed2": sg.eleven_object_scene(2),
               "all_classes_ragged": edge["all_classes_ragged"],
-              "tile_spanning_257x129": edge["tile_spanning_257x129"]}
+              "tile_spanning_257x129": edge["tile_spanning_257x129"],
+              "pip_six_vehicles": _pip_scenes()["six_vehicles_all_pairs_coarse"],
+              "pip_tile_spanning": _pip_scenes()["tile_spanning_257x129"]}
     try:
         for name, s in scenes.items():
             ref = None

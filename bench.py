@@ -98,7 +98,7 @@ def table_one(mhc, ctx, sg, torch, steps=50):
 
 
 def class_checks(scene):
-    out = {"VV": 0, "VP": 0, "PP": 0}
+    out = {"VV": 0, "VP": 0, "PP": 0, "VV_PIP": 0}
     objs = scene.objects
     for a in range(len(objs)):
         for b in range(a + 1, len(objs)):
@@ -106,18 +106,42 @@ def class_checks(scene):
                 continue
             ka, kb = objs[a].kind, objs[b].kind
             c = "VV" if ka == kb == 0 else ("PP" if ka == kb == 1 else "VP")
+            if getattr(scene, "overlap", 0) == 1:
+                c = "VV_PIP"
             out[c] += objs[a].n_traj * objs[b].n_traj * scene.horizon
     return out
 
 
-def recorded_traffic(variant):
+# Timed workloads: the 11-object scene is the headline; the Table I S2
+# configuration (Sec. VI-B) can be timed the same way in either overlap mode.
+WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip")
+
+
+def make_workload(name, seed, sg):
+    """(scene, metric label, config, description) of a timed workload."""
+    if name == "eleven_object":
+        scene = sg.eleven_object_scene(seed)
+        cfg = {"workload": "eleven_object_scene", "objects": 11, "vehicles": 6, "pedestrians": 5,
+               "trajectories_per_object": 225, "horizon": 30, "dt": 0.1, "seed": seed, "pairs": "all",
+               "overlap": "exact"}
+        return scene, "11-object scene", cfg, f"11-object scene seed {seed}"
+    pip = name.endswith("_pip")
+    scene = sg.paper_scene(seed, n_co=10, n_acc=6, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
+    cfg = {"workload": "table_one_s2_scene", "objects": 11, "vehicles": 11, "pedestrians": 0,
+           "trajectories": {"ego": 2058, "co": 42}, "horizon": 100, "dt": 0.02, "seed": seed, "pairs": "ego",
+           "overlap": "pip" if pip else "exact"}
+    label = "Table I S2 scene" + (", point-in-polygon" if pip else "")
+    return scene, label, cfg, f"Table I S2 scene seed {seed} ({'point-in-polygon' if pip else 'exact'} overlap)"
+
+
+def recorded_traffic(variant, workload):
     """HBM bytes per collision launch from the committed counter runs
     (profiles/k2_collide_eleven_object_traffic.txt), each counter scaled by
     what it reads for a plain copy kernel of known size; None when the kernel
     sources or the tile variant differ from those the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k2_collide_eleven_object_traffic.txt")
-    if not os.path.exists(path):
+    if workload != "eleven_object" or not os.path.exists(path):
         return None
     rec = {}
     for line in open(path):
@@ -141,7 +165,7 @@ def pct(xs, q):
     return xs[k]
 
 
-def cpu_baseline(scene, checks, seconds):
+def cpu_baseline(scene, checks, seconds, described):
     """The FP64 oracle as it stands, on the host cores (rank 0, N=1 only)."""
     import oracle
     oracle.lib()
@@ -157,11 +181,8 @@ def cpu_baseline(scene, checks, seconds):
     value = checks * runs / dt
     log(f"cpu baseline: {runs} oracle runs in {dt:.2f} s on {cores} threads -> {value:.4g} checks/s")
     return {"value": value, "unit": "checks/s", "cores": cores, "kind": "oracle",
-            "sample": f"the full 11-object scene (seed {scene_seed}), {runs} complete oracle passes "
+            "sample": f"the full timed scene ({described}), {runs} complete oracle passes "
                       f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s"}
-
-
-scene_seed = 1
 
 
 def serve(mhc, ctx, sg, seconds):
@@ -221,12 +242,13 @@ def serve(mhc, ctx, sg, seconds):
 
 
 def main():
-    global scene_seed
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", choices=WORKLOADS, default="eleven_object",
+                    help="timed workload (default: the 11-object scene)")
+    ap.add_argument("--seed", type=int, default=None, help="scene seed (default 1; 5 for the Table I scenes)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the latency and batched measurements")
@@ -241,12 +263,13 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard object pairs across GPUs, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-    scene_seed = args.seed
+    if args.seed is None:
+        args.seed = 1 if args.workload == "eleven_object" else 5
 
     import torch
     from paper_2005_06773_amd import mhc, scenegen as sg
 
-    scene = sg.eleven_object_scene(args.seed)
+    scene, label, config, described = make_workload(args.workload, args.seed, sg)
     cs = mhc.CScene(scene)
     sizes = mhc.mhc_query_sizes(cs)
     checks = sizes["n_checks"]
@@ -278,7 +301,7 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calibrate_copy} MiB read, {args.calibrate_copy} MiB written")
         del src, dst
-    log(f"workload: 11-object scene seed {args.seed}, {checks:,} checks/pass; warmup {args.warmup}, steps {args.steps}")
+    log(f"workload: {described}, {checks:,} checks/pass; warmup {args.warmup}, steps {args.steps}")
     for _ in range(args.warmup):
         mhc.mhc_plan_execute(plan, r, stream)
     torch.cuda.synchronize()
@@ -322,9 +345,9 @@ def main():
 
     # Reference VALU instructions per check (27 rect-rect, 14 rect-circle,
     # 6 circle-circle, incl. first-hit bookkeeping) against the lane-op rate.
-    lane_ops = 27 * cls["VV"] + 14 * cls["VP"] + 6 * cls["PP"]
+    lane_ops = 27 * cls["VV"] + 14 * cls["VP"] + 6 * cls["PP"] + 60 * cls["VV_PIP"]
     result = {
-        "metric": "pose-pair checks/sec (11-object scene)",
+        "metric": f"pose-pair checks/sec ({label})",
         "value": value,
         "unit": "checks/s",
         "n_gpus": 1,
@@ -336,13 +359,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "eleven_object_scene", "objects": 11, "vehicles": 6, "pedestrians": 5,
-                   "trajectories_per_object": 225, "horizon": 30, "dt": 0.1, "checks": checks,
-                   "seed": args.seed, "pairs": "all", "inputs": "resident in HBM"},
+        "config": dict(config, checks=checks, inputs="resident in HBM"),
         "tile_variant": tune,
         "graph_step_us": graph_step_us,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(variant),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(variant, args.workload),
                      "kernel": "k2_collide", "kernel_us": k2_ms * 1e3, "flops_per_launch": flops,
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                      "valu_issue_frac_est": lane_ops / (k2_ms / 1e3) / LANE_OPS_PER_S},
@@ -393,7 +414,7 @@ def main():
     mhc.mhc_destroy(ctx)
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, checks, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(scene, checks, args.cpu_seconds, described)
     print(json.dumps(result), flush=True)
 
 

@@ -35,14 +35,29 @@ namespace mhc {
 // float2 (x, y) for pedestrians, layout [t][i], slot t = step t+1.
 // ===========================================================================
 
-__device__ void normalise_probabilities(const DObj &o, const double *__restrict__ vals, double *__restrict__ p,
-                                        unsigned long long *__restrict__ pfix, unsigned long long *__restrict__ qacc)
+// Thread tid adds the scores tid, tid + 256, ... in ascending order, eight
+// loads in flight at a time, then the workgroup adds the 256 partial sums in a
+// fixed tree: the order depends on T only.
+__device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals,
+                                        double *__restrict__ p, unsigned long long *__restrict__ pfix,
+                                        unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
 {
     __shared__ double red[WG];
     const int tid = threadIdx.x;
+    const double *__restrict__ sc = vals + o.score_off;
     double part = 0.0;
     if (o.has_score) {
-        for (int k = tid; k < o.T; k += WG) part += vals[o.score_off + k];
+        for (int base = 0; base < o.T; base += 8 * WG) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = base + k * WG + tid;
+                v[k] = idx < o.T ? sc[idx] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (base + k * WG + tid < o.T) part += v[k];
+        }
     }
     red[tid] = part;
     __syncthreads();
@@ -51,31 +66,46 @@ __device__ void normalise_probabilities(const DObj &o, const double *__restrict_
         __syncthreads();
     }
     const double total = red[0];
-    for (int k = tid; k < o.T; k += WG) {
-        const double pk = o.has_score ? vals[o.score_off + k] / total : 1.0 / (double)o.T;
-        p[o.traj_off + k] = pk;
-        pfix[o.traj_off + k] = __double2ull_rn(pk * kQScale);
+    for (int base = 0; base < o.T; base += 8 * WG) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = base + k * WG + tid;
+            v[k] = (o.has_score && idx < o.T) ? sc[idx] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int idx = base + k * WG + tid;
+            if (idx < o.T) {
+                const double pk = o.has_score ? v[k] / total : 1.0 / (double)o.T;
+                p[o.traj_off + idx] = pk;
+                pfix[o.traj_off + idx] = __double2ull_rn(pk * kQScale);
+            }
+        }
     }
-    // this object's rows of the integer q accumulators start from zero
+    // this object's rows of the integer q accumulators start from zero, and
+    // so does its completion counter of the risk kernel
     const int64_t nq = (int64_t)o.T * o.n_scene_obj;
     for (int64_t k = tid; k < nq; k += WG) qacc[o.q_row + k] = 0ull;
+    if (tid == 0) done[obj] = 0u;
 }
 
-// Grid: x = trajectory block (K1_TPB trajectories, one wave each) plus one
-// last block for the object's probability normalisation, y = object.
+// Grid: y = object; x = 0 is the object's probability normalisation (the
+// longest block for large T, so it is dispatched first), x >= 1 are
+// trajectory blocks of K1_TPB trajectories, one wave each.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
-                                                 unsigned long long *__restrict__ qacc)
+                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
 {
     const int obj = (int)blockIdx.y;
     const DObj o = objs[obj];
-    if ((int)blockIdx.x == (int)gridDim.x - 1) {
-        normalise_probabilities(o, vals, p, pfix, qacc);
+    if (blockIdx.x == 0) {
+        normalise_probabilities(o, obj, vals, p, pfix, qacc, done);
         return;
     }
     const int lane = threadIdx.x & 63;
-    const int i = (int)blockIdx.x * K1_TPB + (int)(threadIdx.x >> 6);
+    const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double tau = o.tau;
@@ -453,26 +483,35 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
 // K3: risk assessment (Sec. IV-D, IV-D.2).
 //
 // The collision kernel has left q_{a,i;b} = sum_j [hit] p_{b,j} as exact
-// integer sums (units of 2^-62). One workgroup per object: each thread takes
-// trajectories i = tid, tid + 256, ..., converts the sums (rounding once),
-// clamps to 1, writes q and forms
-//   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b),
-// and the workgroup adds C_a = sum_i p_{a,i} crit_{a,i} in a fixed tree.
-// Nothing depends on how the collision work was tiled or batched, so every
-// result is identical for any tiling and any batch.
+// integer sums (units of 2^-62). Grid: y = object, x = chunk of 256
+// trajectories; thread tid of chunk c takes trajectory i = 256 c + tid,
+// converts its sums (rounding once), clamps to 1, writes q and forms
+//   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b).
+// The workgroup adds p_{a,i} crit_{a,i} over its chunk in a fixed tree. An
+// object of one chunk writes C_a directly; otherwise each chunk stores its
+// partial sum and the chunk that finishes last (a per-object counter, zeroed
+// by the trajectory kernel and reset by that chunk) adds the partials in
+// chunk order. Nothing depends on how the collision work was tiled or
+// batched, so every result is identical for any tiling and any batch.
 // ===========================================================================
 
 __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
                                               const unsigned long long *__restrict__ qacc,
                                               const double *__restrict__ p, double *__restrict__ q,
-                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit)
+                                              double *__restrict__ traj_crit, double *__restrict__ obj_crit,
+                                              double *__restrict__ partial, unsigned int *__restrict__ done)
 {
     __shared__ double red[WG];
-    const DObj o = objs[blockIdx.x];
+    const int obj = (int)blockIdx.y;
+    const DObj o = objs[obj];
+    const int chunks = (o.T + WG - 1) / WG;
+    const int c = (int)blockIdx.x;
+    if (c >= chunks) return;  // whole workgroup
     const int n = o.n_scene_obj;
     const int tid = threadIdx.x;
     double acc = 0.0;
-    for (int i = tid; i < o.T; i += WG) {
+    const int i = c * WG + tid;
+    if (i < o.T) {
         // The trajectory kernel zeroed all n accumulators of this trajectory,
         // so b == a and objects outside the pair set read as q = 0. Loads are
         // issued eight at a time, ahead of the dependent product.
@@ -495,7 +534,7 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
         }
         const double crit = 1.0 - no_collision;
         traj_crit[o.traj_off + i] = crit;
-        acc += pi * crit;
+        acc = pi * crit;
     }
     red[tid] = acc;
     __syncthreads();
@@ -503,7 +542,20 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
         if (tid < st) red[tid] += red[tid + st];
         __syncthreads();
     }
-    if (tid == 0) obj_crit[o.obj_out] = red[0];
+    if (chunks == 1) {
+        if (tid == 0) obj_crit[o.obj_out] = red[0];
+        return;
+    }
+    if (tid != 0) return;
+    partial[o.part_off + c] = red[0];
+    __threadfence();  // the partial is visible device-wide before the count
+    if (atomicAdd(&done[obj], 1u) != (unsigned)(chunks - 1)) return;
+    __threadfence();  // every other chunk's partial is visible to this one
+    const volatile double *vp = partial + o.part_off;
+    double C = 0.0;
+    for (int k = 0; k < chunks; ++k) C += vp[k];
+    obj_crit[o.obj_out] = C;
+    done[obj] = 0u;  // the risk stage may run again on the same sums
 }
 
 // ===========================================================================
@@ -513,7 +565,8 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
 hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc);
+    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc,
+                       L.done);
     return hipGetLastError();
 }
 
@@ -568,7 +621,8 @@ int collide_blocks_per_cu(int variant, bool pip)
 hipError_t launch_risk(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k3_crit, dim3(L.n_obj), dim3(WG), 0, s, L.objs, L.qacc, L.p, L.q, L.traj_crit, L.obj_crit);
+    hipLaunchKernelGGL(k3_crit, dim3(L.k3_x, L.n_obj), dim3(WG), 0, s, L.objs, L.qacc, L.p, L.q, L.traj_crit,
+                       L.obj_crit, L.k3_part, L.done);
     return hipGetLastError();
 }
 

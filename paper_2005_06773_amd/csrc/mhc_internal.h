@@ -26,6 +26,7 @@ struct DObj {
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
     int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
+    int64_t part_off;             // first partial sum of the risk kernel's chunks
     int64_t obj_out;              // index in the object_crit array
     double x, y, heading, speed;
     double tau;
@@ -106,6 +107,9 @@ struct Launch {
     double *obj_crit;
     int n_obj, n_pairs, n_work, n_bins;
     int k1_x;                     // trajectory kernel grid x: blocks of the largest object + 1
+    int k3_x;                     // risk kernel grid x: 256-trajectory chunks of the largest object
+    double *k3_part;              // risk kernel partial sums, one per chunk
+    unsigned int *done;           // per object: risk chunks finished
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
     int pip;                      // some pair uses the point-in-polygon test

@@ -162,6 +162,9 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.score_off = d.w_off + o.n_w;
             L.vals.resize(L.vals.size() + o.n_u + o.n_w + (o.score ? d.T : 0));
             d.obj_out = L.n_obj + a;
+            d.part_off = L.n_part;
+            L.n_part += (d.T + WG - 1) / WG;
+            L.k3_x = std::max(L.k3_x, (d.T + WG - 1) / WG);
             L.objs.push_back(d);
             L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
             toff += d.T;
@@ -341,6 +344,8 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
     L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
+    L.o_part = put((size_t)L.n_part * sizeof(double));
+    L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
     L.o_p = put((size_t)L.n_traj * sizeof(double));
     L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
     L.o_q = put((size_t)L.n_q * sizeof(double));
@@ -409,6 +414,8 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.poses = base + L.o_poses;
     X.pfix = reinterpret_cast<unsigned long long *>(base + L.o_pfix);
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
+    X.k3_part = reinterpret_cast<double *>(base + L.o_part);
+    X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
@@ -427,6 +434,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_pairs = (int)L.pairs.size();
     X.n_work = (int)L.work.size();
     X.k1_x = L.k1_x;
+    X.k3_x = L.k3_x;
     X.variant = L.variant;
     X.pip = L.pip ? 1 : 0;
     X.n_bins = (int)L.bins.size() - 1;

@@ -38,9 +38,11 @@ struct Layout {
     std::vector<SceneExt> sc;
     int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
     int k1_x = 0;                 // trajectory kernel grid x
+    int k3_x = 0;                 // risk kernel grid x (chunks of the largest object)
+    int64_t n_part = 0;           // risk kernel partial sums (chunks over all objects)
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, image_bytes = 0;
-    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
+    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
     bool pip = false;             // some pair uses the point-in-polygon test

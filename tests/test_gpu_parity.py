@@ -300,6 +300,29 @@ def test_stress_scene_sampled_pairs(mhc, ctx):
     assert np.all((g["object_crit"] >= 0) & (g["object_crit"] <= 1 + 1e-12))
 
 
+def test_risk_stage_reruns_on_many_chunk_objects(mhc, ctx):
+    """The EGO of the Table I scene has 2058 trajectories: the risk kernel
+    sums its criticality over 9 chunks with a completion counter. Running
+    the risk stage again on the same sums, and replaying the whole plan from
+    a graph, must give the same results."""
+    import torch
+    s = sg.paper_scene(6, n_co=3)
+    plan = mhc.mhc_plan_create(ctx, s)
+    mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_ALL)
+    first = mhc.mhc_plan_download(plan)
+    parity.check(s, first, oracle.evaluate(s, threads=THREADS), "Table I S1 plan")
+    for rep in range(3):
+        mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_RISK)
+        parity.same_results(first, mhc.mhc_plan_download(plan), f"risk stage again {rep}")
+    mhc.mhc_plan_set_graph(plan, True)
+    for rep in range(4):
+        mhc.mhc_plan_execute(plan)
+        parity.same_results(first, mhc.mhc_plan_download(plan), f"graph replay {rep}")
+        mhc.mhc_evaluate(ctx, sg.two_vehicle_scene(rep))
+        torch.cuda.synchronize()
+    plan.close()
+
+
 def test_graph_replays_match_eager(mhc, ctx):
     """Plans and mhc_evaluate replay captured HIP graphs. Every replay, with
     eager work and synchronisations in between, must equal the eager launch

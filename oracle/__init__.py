@@ -36,6 +36,10 @@ PEDESTRIAN = 1
 OVERLAP_EXACT = 0   # the closed shapes intersect
 OVERLAP_PIP = 1     # a vertex of one polygon lies in the other, tested both ways
 
+#: readings of the conditional-probability approximation (Sec. IV-D.2)
+RISK_EXCLUSIVE = 0    # one object's trajectories exclusive, objects independent
+RISK_INDEPENDENT = 1  # every trajectory combination an independent event
+
 
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (FP64, no fast-math, OpenMP rows)."""
@@ -79,7 +83,8 @@ def lib():
         L.orc_margin_rect_rect_pip.argtypes = [D] * 10
         L.orc_margin_rect_rect_pip.restype = D
         L.orc_first_hits.argtypes = [I, I, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
-        L.orc_risk.argtypes = [I, P, P, I, P, P, P, P, P, P]
+        L.orc_risk.argtypes = [I, I, P, P, I, P, P, P, P, P, P]
+        L.orc_risk_timeline.argtypes = [I, I, P, P, I, I, P, P, P, P, P, P, P]
         L.orc_point_in_polygon.argtypes = [D, D, I, P, P]
         L.orc_rect_corners.argtypes = [D, D, D, D, D, P, P]
         _lib = L
@@ -205,6 +210,20 @@ class OracleResult:
     traj_crit_hi: np.ndarray    # every pair with a hit inside the band counts
     obj_crit_lo: np.ndarray
     obj_crit_hi: np.ndarray
+    # time-resolved risk (scenes with ``timeline`` set), from k64
+    obj_crit_t: Optional[np.ndarray] = None     # [n, H]
+    traj_crit_t: Optional[np.ndarray] = None    # [sum T, H]
+    obj_attrib: Optional[np.ndarray] = None     # [n, n]
+    traj_attrib: Optional[np.ndarray] = None    # [sum T, n]
+    # bounds over every first hit the band allows: latest (lo) and earliest (hi)
+    obj_crit_t_lo: Optional[np.ndarray] = None
+    obj_crit_t_hi: Optional[np.ndarray] = None
+    traj_crit_t_lo: Optional[np.ndarray] = None
+    traj_crit_t_hi: Optional[np.ndarray] = None
+    # probability mass of the combinations whose first hit the band leaves open
+    # (attribution is not monotone in the hits; it moves by at most this much)
+    traj_amb_mass: Optional[np.ndarray] = None  # [sum T]
+    obj_amb_mass: Optional[np.ndarray] = None   # [n]
 
 
 def scene_arrays(scene):
@@ -261,18 +280,41 @@ def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: 
     res = OracleResult(pa, pb, poff, T, p, k64, kst, loose, strict,
                        *([None] * 7))
     if risk:
-        res.q, res.traj_crit, res.obj_crit = risk_from_hits(scene, pa, pb, (k64 >= 0), p)
+        model = int(getattr(scene, "risk", RISK_EXCLUSIVE))
+        res.q, res.traj_crit, res.obj_crit = risk_from_hits(scene, pa, pb, (k64 >= 0), p, model)
         lo = kst >= 0
-        if masks:
-            hi = np.any(loose != 0, axis=1)
-        else:
-            hi = k64 >= 0
-        _, res.traj_crit_lo, res.obj_crit_lo = risk_from_hits(scene, pa, pb, lo, p)
-        _, res.traj_crit_hi, res.obj_crit_hi = risk_from_hits(scene, pa, pb, hi, p)
+        kloose = first_loose_slot(loose) if masks else k64
+        hi = kloose >= 0
+        _, res.traj_crit_lo, res.obj_crit_lo = risk_from_hits(scene, pa, pb, lo, p, model)
+        _, res.traj_crit_hi, res.obj_crit_hi = risk_from_hits(scene, pa, pb, hi, p, model)
+        if getattr(scene, "timeline", 0):
+            res.traj_crit_t, res.obj_crit_t, res.traj_attrib, res.obj_attrib = \
+                risk_timeline(scene, pa, pb, k64, p, model)
+            res.traj_crit_t_lo, res.obj_crit_t_lo, _, _ = risk_timeline(scene, pa, pb, kst, p, model)
+            res.traj_crit_t_hi, res.obj_crit_t_hi, _, _ = risk_timeline(scene, pa, pb, kloose, p, model)
+            amb = (kloose != k64) | (kst != k64)
+            res.traj_amb_mass, res.obj_amb_mass = ambiguous_mass(scene, pa, pb, amb, p)
     return res
 
 
-def risk_from_hits(scene, pa: np.ndarray, pb: np.ndarray, hit: np.ndarray, p: np.ndarray):
+def first_loose_slot(loose: np.ndarray) -> np.ndarray:
+    """Per entry, the first slot whose margin is <= +EPS (the earliest first
+    hit an FP32 evaluation may legitimately report), or -1."""
+    n, W = loose.shape
+    out = np.full(n, -1, np.int32)
+    for wd in range(W - 1, -1, -1):
+        word = loose[:, wd]
+        nz = word != 0
+        if not nz.any():
+            continue
+        low = word[nz] & (~word[nz] + np.uint64(1))          # lowest set bit
+        bit = np.round(np.log2(low.astype(np.float64))).astype(np.int32)
+        out[nz] = 64 * wd + bit
+    return out
+
+
+def risk_from_hits(scene, pa: np.ndarray, pb: np.ndarray, hit: np.ndarray, p: np.ndarray,
+                   model: int = RISK_EXCLUSIVE):
     """q [sum T, n], traj_crit [sum T], obj_crit [n] from a per-entry hit flag."""
     _, _, _, _, T = scene_arrays(scene)
     n = len(T)
@@ -281,10 +323,67 @@ def risk_from_hits(scene, pa: np.ndarray, pb: np.ndarray, hit: np.ndarray, p: np
     q = np.empty((n_traj, n), np.float64)
     tc = np.empty(n_traj, np.float64)
     oc = np.empty(n, np.float64)
-    _check(lib().orc_risk(n, _ptr(T), _ptr(np.ascontiguousarray(p, np.float64)), len(pa),
+    _check(lib().orc_risk(int(model), n, _ptr(T), _ptr(np.ascontiguousarray(p, np.float64)), len(pa),
                           _ptr(np.ascontiguousarray(pa, np.int32)), _ptr(np.ascontiguousarray(pb, np.int32)),
                           _ptr(h), _ptr(q), _ptr(tc), _ptr(oc)), "risk")
     return q, tc, oc
+
+
+def risk_timeline(scene, pa: np.ndarray, pb: np.ndarray, k: np.ndarray, p: np.ndarray,
+                  model: int = RISK_EXCLUSIVE):
+    """Chronological scaling over time from per-entry first-hit slots ``k``
+    (-1 = none): traj_crit_t [sum T, H], obj_crit_t [n, H], traj_attrib
+    [sum T, n], obj_attrib [n, n]."""
+    _, _, _, _, T = scene_arrays(scene)
+    return risk_timeline_raw(T, int(scene.horizon), pa, pb, k, p, model)
+
+
+def risk_timeline_raw(T, H: int, pa, pb, k, p, model: int = RISK_EXCLUSIVE):
+    T = np.ascontiguousarray(T, np.int32)
+    n = len(T)
+    n_traj = int(T.sum())
+    tct = np.empty((n_traj, H), np.float64)
+    oct_ = np.empty((n, H), np.float64)
+    tat = np.empty((n_traj, n), np.float64)
+    oat = np.empty((n, n), np.float64)
+    _check(lib().orc_risk_timeline(int(model), n, _ptr(T), _ptr(np.ascontiguousarray(p, np.float64)), int(H),
+                                   len(pa), _ptr(np.ascontiguousarray(pa, np.int32)),
+                                   _ptr(np.ascontiguousarray(pb, np.int32)),
+                                   _ptr(np.ascontiguousarray(k, np.int32)),
+                                   _ptr(tct), _ptr(oct_), _ptr(tat), _ptr(oat)), "risk_timeline")
+    return tct, oct_, tat, oat
+
+
+def risk_raw(T, pa, pb, hit, p, model: int = RISK_EXCLUSIVE):
+    """orc_risk on explicit tables: (q, traj_crit, obj_crit)."""
+    T = np.ascontiguousarray(T, np.int32)
+    n = len(T)
+    n_traj = int(T.sum())
+    q = np.empty((n_traj, n), np.float64)
+    tc = np.empty(n_traj, np.float64)
+    oc = np.empty(n, np.float64)
+    _check(lib().orc_risk(int(model), n, _ptr(T), _ptr(np.ascontiguousarray(p, np.float64)), len(pa),
+                          _ptr(np.ascontiguousarray(pa, np.int32)), _ptr(np.ascontiguousarray(pb, np.int32)),
+                          _ptr(np.ascontiguousarray(hit, np.uint8)), _ptr(q), _ptr(tc), _ptr(oc)), "risk")
+    return q, tc, oc
+
+
+def ambiguous_mass(scene, pa, pb, amb: np.ndarray, p: np.ndarray):
+    """Per trajectory, the summed probability of the other trajectories whose
+    combination with it has a first hit the band leaves open; per object, the
+    probability-weighted sum of that."""
+    _, _, _, _, T = scene_arrays(scene)
+    n = len(T)
+    toff = np.concatenate([[0], np.cumsum(T)]).astype(np.int64)
+    mass = np.zeros(int(T.sum()), np.float64)
+    e0 = 0
+    for a, b in zip(np.asarray(pa).tolist(), np.asarray(pb).tolist()):
+        blk = np.asarray(amb[e0:e0 + T[a] * T[b]]).reshape(T[a], T[b]).astype(np.float64)
+        mass[toff[a]:toff[a + 1]] += blk @ p[toff[b]:toff[b + 1]]
+        mass[toff[b]:toff[b + 1]] += blk.T @ p[toff[a]:toff[a + 1]]
+        e0 += T[a] * T[b]
+    obj = np.array([float(np.dot(p[toff[a]:toff[a + 1]], mass[toff[a]:toff[a + 1]])) for a in range(n)])
+    return mass, obj
 
 
 def accepted_first_hits(k32: np.ndarray, res: OracleResult) -> np.ndarray:

@@ -37,7 +37,13 @@
  *   - the chronological scaling is read as: collision objects independent of
  *     one another, the trajectories of one object mutually exclusive, all
  *     conditioned on the trajectory of the object being assessed. The product
- *     of "no collision" factors then telescopes, so no ordering is needed.
+ *     of "no collision" factors then telescopes, so no ordering is needed for
+ *     the totals (ORC_RISK_EXCLUSIVE, the default). The second reading takes
+ *     every combination of the assessed trajectory with one trajectory of
+ *     another object as an independent event (ORC_RISK_INDEPENDENT);
+ *   - combinations that collide at the same step are taken in ascending order
+ *     of the other object's index, then of its trajectory index; only the
+ *     attribution of criticality to collision objects depends on this.
  */
 #include <math.h>
 #include <stdint.h>
@@ -54,6 +60,10 @@
 /* overlap test of the collision recognition */
 #define ORC_OVERLAP_EXACT 0   /* closed shapes intersect */
 #define ORC_OVERLAP_PIP 1     /* a vertex of one polygon lies in the other (both ways) */
+
+/* reading of the conditional-probability approximation (Sec. IV-D.2) */
+#define ORC_RISK_EXCLUSIVE 0   /* one object's trajectories exclusive, objects independent */
+#define ORC_RISK_INDEPENDENT 1 /* every trajectory combination an independent event */
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -425,23 +435,35 @@ int orc_first_hits(int overlap, int n_objects, const int32_t *kind, const double
 /* Risk: Sec. IV-D and Sec. IV-D.2.                                           */
 /*                                                                            */
 /* hit[e] (entry layout as above) says whether trajectory pair e collides.    */
-/* For object a, trajectory i and another object b:                           */
-/*   q[a,i;b]   = sum_j hit(a,i;b,j) p_{b,j}   (b's trajectories exclusive)  */
+/* For object a, trajectory i and another object b, the probability that the */
+/* collision with b happens along trajectory i is                             */
+/*   EXCLUSIVE:   q[a,i;b] = sum_j hit(a,i;b,j) p_{b,j}                       */
+/*                (b follows exactly one of its trajectories)                */
+/*   INDEPENDENT: q[a,i;b] = 1 - prod_j (1 - hit(a,i;b,j) p_{b,j})            */
+/*                (every combination occurs independently)                   */
 /* Under the chronological scaling the collision with b only counts when no  */
 /* other object has collided first; with the objects independent, the        */
 /* probability that some collision happens along trajectory i is             */
 /*   crit[a,i]  = 1 - prod_{b != a} (1 - q[a,i;b])                           */
 /* and the criticality of object a weights its trajectories by probability:  */
 /*   C[a]       = sum_i p_{a,i} crit[a,i]                                    */
-/* With a single collision object C[0] is the double sum p_cra of Sec. IV-D. */
+/* With a single collision object and the exclusive reading C[0] is the      */
+/* double sum p_cra of Sec. IV-D.                                            */
 /* q is [sum T][n_objects] (nullable); traj_crit [sum T]; obj_crit [n].       */
 /* Pairs not listed contribute q = 0.                                         */
 /* ------------------------------------------------------------------------ */
-int orc_risk(int n_objects, const int32_t *T, const double *p,
+static double combine_q(int model, double acc, double p)
+{
+    /* fold one colliding combination of probability p into q */
+    return model == ORC_RISK_EXCLUSIVE ? acc + p : 1.0 - (1.0 - acc) * (1.0 - p);
+}
+
+int orc_risk(int model, int n_objects, const int32_t *T, const double *p,
              int n_pairs, const int32_t *pair_a, const int32_t *pair_b,
              const uint8_t *hit, double *q_out, double *traj_crit, double *obj_crit)
 {
     if (n_objects < 1 || n_pairs < 0) return ORC_EINVAL;
+    if (model != ORC_RISK_EXCLUSIVE && model != ORC_RISK_INDEPENDENT) return ORC_EINVAL;
     int64_t *toff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
     if (!toff) return ORC_ENOMEM;
     toff[0] = 0;
@@ -457,13 +479,13 @@ int orc_risk(int n_objects, const int32_t *T, const double *p,
         for (int i = 0; i < Ta; ++i) {
             double s = 0.0;
             for (int j = 0; j < Tb; ++j)
-                if (hit[e0 + (int64_t)i * Tb + j]) s += p[toff[b] + j];
+                if (hit[e0 + (int64_t)i * Tb + j]) s = combine_q(model, s, p[toff[b] + j]);
             q[(toff[a] + i) * n_objects + b] = fmin(s, 1.0);
         }
         for (int j = 0; j < Tb; ++j) {
             double s = 0.0;
             for (int i = 0; i < Ta; ++i)
-                if (hit[e0 + (int64_t)i * Tb + j]) s += p[toff[a] + i];
+                if (hit[e0 + (int64_t)i * Tb + j]) s = combine_q(model, s, p[toff[a] + i]);
             q[(toff[b] + j) * n_objects + a] = fmin(s, 1.0);
         }
         e0 += (int64_t)Ta * Tb;
@@ -483,6 +505,129 @@ int orc_risk(int n_objects, const int32_t *T, const double *p,
     if (q_out) memcpy(q_out, q, sizeof(double) * (size_t)n_traj * (size_t)n_objects);
     free(q);
     free(toff);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Risk over time: the chronological scaling of Sec. IV-D.2, step by step,    */
+/* and the time-resolved criticality behind the anticipation time of          */
+/* Sec. IV-D / Sec. VI-A.                                                     */
+/*                                                                            */
+/* k[e] is the earliest colliding slot of entry e (layout as above), or -1.  */
+/* For object a and trajectory i, every colliding combination with a        */
+/* trajectory j of another object b is an event (slot k, b, j) of            */
+/* probability p_{b,j}. The events are taken in time order (ties: ascending  */
+/* b, then j). The first keeps its probability; each later one counts only  */
+/* if no collision has happened before it:                                   */
+/*   EXCLUSIVE:   scaled = p_{b,j} * prod_{b' != b} (1 - Q_{b'})             */
+/*                where Q_{b'} sums p over the events of b' taken so far     */
+/*                (b's own earlier events exclude this one: b follows one    */
+/*                trajectory), then Q_b += p_{b,j};                          */
+/*   INDEPENDENT: scaled = p_{b,j} * prod over all earlier events of (1 - p) */
+/*                (the paper's P(C and not B and not A) = P(~A) P(~B) P(C)). */
+/* The scaled probabilities of the events up to slot s add up to             */
+/*   crit_t[a,i][s]  the probability of a collision at or before slot s,     */
+/* and those of b's events to                                                */
+/*   attrib[a,i][b]  the probability that the first collision is with b;    */
+/* sum_b attrib[a,i][b] = crit_t[a,i][H-1] = crit[a,i] of orc_risk.          */
+/* Object level: C_t[a][s] = sum_i p_{a,i} crit_t[a,i][s] and                */
+/* A[a][b] = sum_i p_{a,i} attrib[a,i][b].                                    */
+/* Outputs (each nullable): traj_crit_t [sum T][H], obj_crit_t [n][H],        */
+/* traj_attrib [sum T][n], obj_attrib [n][n].                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t k, b, j;
+    double p;
+} orc_event;
+
+static int event_order(const void *x, const void *y)
+{
+    const orc_event *e = (const orc_event *)x, *f = (const orc_event *)y;
+    if (e->k != f->k) return e->k < f->k ? -1 : 1;
+    if (e->b != f->b) return e->b < f->b ? -1 : 1;
+    if (e->j != f->j) return e->j < f->j ? -1 : 1;
+    return 0;
+}
+
+int orc_risk_timeline(int model, int n_objects, const int32_t *T, const double *p, int H,
+                      int n_pairs, const int32_t *pair_a, const int32_t *pair_b, const int32_t *k,
+                      double *traj_crit_t, double *obj_crit_t, double *traj_attrib, double *obj_attrib)
+{
+    if (n_objects < 1 || n_pairs < 0 || H < 1) return ORC_EINVAL;
+    if (model != ORC_RISK_EXCLUSIVE && model != ORC_RISK_INDEPENDENT) return ORC_EINVAL;
+    int64_t *toff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
+    int64_t *poff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
+    if (!toff || !poff) { free(toff); free(poff); return ORC_ENOMEM; }
+    toff[0] = 0;
+    for (int a = 0; a < n_objects; ++a) toff[a + 1] = toff[a] + T[a];
+    poff[0] = 0;
+    int64_t max_events = 0;
+    for (int pr = 0; pr < n_pairs; ++pr) {
+        poff[pr + 1] = poff[pr] + (int64_t)T[pair_a[pr]] * T[pair_b[pr]];
+        max_events += T[pair_a[pr]] > T[pair_b[pr]] ? T[pair_a[pr]] : T[pair_b[pr]];
+    }
+    orc_event *ev = (orc_event *)malloc(sizeof(orc_event) * (size_t)(max_events + 1));
+    double *Q = (double *)malloc(sizeof(double) * (size_t)n_objects);
+    double *A = (double *)malloc(sizeof(double) * (size_t)n_objects);
+    double *ct = (double *)malloc(sizeof(double) * (size_t)H);
+    if (!ev || !Q || !A || !ct) {
+        free(toff); free(poff); free(ev); free(Q); free(A); free(ct);
+        return ORC_ENOMEM;
+    }
+    if (obj_crit_t) memset(obj_crit_t, 0, sizeof(double) * (size_t)n_objects * (size_t)H);
+    if (obj_attrib) memset(obj_attrib, 0, sizeof(double) * (size_t)n_objects * (size_t)n_objects);
+
+    for (int a = 0; a < n_objects; ++a) {
+        for (int i = 0; i < T[a]; ++i) {
+            /* gather the colliding combinations of trajectory (a, i) */
+            int64_t m = 0;
+            for (int pr = 0; pr < n_pairs; ++pr) {
+                int pa = pair_a[pr], pb = pair_b[pr];
+                if (pa == a) {
+                    for (int j = 0; j < T[pb]; ++j) {
+                        int32_t kk = k[poff[pr] + (int64_t)i * T[pb] + j];
+                        if (kk >= 0) ev[m++] = (orc_event){kk, pb, j, p[toff[pb] + j]};
+                    }
+                } else if (pb == a) {
+                    for (int j = 0; j < T[pa]; ++j) {
+                        int32_t kk = k[poff[pr] + (int64_t)j * T[a] + i];
+                        if (kk >= 0) ev[m++] = (orc_event){kk, pa, j, p[toff[pa] + j]};
+                    }
+                }
+            }
+            qsort(ev, (size_t)m, sizeof(orc_event), event_order);
+            for (int b = 0; b < n_objects; ++b) { Q[b] = 0.0; A[b] = 0.0; }
+            double crit = 0.0, survive = 1.0;
+            int64_t e = 0;
+            for (int s = 0; s < H; ++s) {
+                for (; e < m && ev[e].k == s; ++e) {
+                    int b = ev[e].b;
+                    double scaled;
+                    if (model == ORC_RISK_EXCLUSIVE) {
+                        double keep = 1.0;
+                        for (int c = 0; c < n_objects; ++c)
+                            if (c != b && c != a) keep *= 1.0 - fmin(Q[c], 1.0);
+                        scaled = ev[e].p * keep;
+                        Q[b] += ev[e].p;
+                    } else {
+                        scaled = ev[e].p * survive;
+                        survive *= 1.0 - ev[e].p;
+                    }
+                    A[b] += scaled;
+                    crit += scaled;
+                }
+                ct[s] = crit;
+            }
+            double pi = p[toff[a] + i];
+            if (traj_crit_t) memcpy(traj_crit_t + (toff[a] + i) * H, ct, sizeof(double) * (size_t)H);
+            if (obj_crit_t)
+                for (int s = 0; s < H; ++s) obj_crit_t[(int64_t)a * H + s] += pi * ct[s];
+            if (traj_attrib) memcpy(traj_attrib + (toff[a] + i) * n_objects, A, sizeof(double) * (size_t)n_objects);
+            if (obj_attrib)
+                for (int b = 0; b < n_objects; ++b) obj_attrib[(int64_t)a * n_objects + b] += pi * A[b];
+        }
+    }
+    free(toff); free(poff); free(ev); free(Q); free(A); free(ct);
     return ORC_OK;
 }
 

@@ -36,6 +36,8 @@ PAIRS_ALL = 0
 PAIRS_EGO = 1
 OVERLAP_EXACT = 0   # closed shapes intersect
 OVERLAP_PIP = 1     # the paper's point-in-polygon test, both ways (vehicles only)
+RISK_EXCLUSIVE = 0    # one object's trajectories mutually exclusive (default)
+RISK_INDEPENDENT = 1  # every trajectory combination an independent event
 
 
 @dataclasses.dataclass
@@ -64,6 +66,8 @@ class Scene:
     dt: float
     pairs: int = PAIRS_ALL
     overlap: int = OVERLAP_EXACT
+    risk: int = RISK_EXCLUSIVE
+    timeline: int = 0     # 1: also the criticality over time and its attribution
 
     @property
     def n_objects(self) -> int:
@@ -283,4 +287,4 @@ def paper_shaped_sizes(n_co: int, n_acc: int = 6, ego_paths: int = 343, co_paths
 def uniform_scores(scene: Scene) -> Scene:
     """Same scene with score arrays dropped (uniform probabilities)."""
     objs = [dataclasses.replace(o, score=None) for o in scene.objects]
-    return Scene(objs, scene.horizon, scene.dt, scene.pairs, scene.overlap)
+    return dataclasses.replace(scene, objects=objs)

@@ -63,6 +63,19 @@ enum { MHC_PAIRS_ALL = 0, MHC_PAIRS_EGO = 1 };
  *   rectangle's boundary counts as inside. It misses overlaps in which no
  *   vertex of either lies inside the other (two bars crossing). */
 enum { MHC_OVERLAP_EXACT = 0, MHC_OVERLAP_PIP = 1 };
+/* Reading of the conditional-probability approximation (Sec. IV-D.2): how
+ * the colliding combinations of one trajectory of object a with the
+ * trajectories j of another object b make up the probability q_{a,i;b} that
+ * the collision with b happens.
+ * EXCLUSIVE: b follows exactly one of its trajectories, so the colliding
+ *   ones add up: q = sum_j [hit] p_{b,j} (with one collision object this is
+ *   the paper's p_cra double sum of Sec. IV-D).
+ * INDEPENDENT: every combination is an independent event, scaled by the
+ *   no-collision probability of the ones before it:
+ *   q = 1 - prod_j (1 - [hit] p_{b,j}).
+ * In both readings collision objects are independent of one another and
+ * crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b}). */
+enum { MHC_RISK_EXCLUSIVE = 0, MHC_RISK_INDEPENDENT = 1 };
 
 /* One traffic participant. Vehicles are rectangles (length along the heading,
  * width across it) moving on the kinematic special case of the Euler pose
@@ -88,6 +101,9 @@ typedef struct {
     double dt;                    /* step length tau > 0 */
     int32_t pairs;                /* MHC_PAIRS_ALL or MHC_PAIRS_EGO */
     int32_t overlap;              /* MHC_OVERLAP_EXACT or MHC_OVERLAP_PIP */
+    int32_t risk;                 /* MHC_RISK_EXCLUSIVE or MHC_RISK_INDEPENDENT */
+    int32_t timeline;             /* 1: also the criticality over time and its
+                                     attribution (crit_t ... traj_attrib below) */
 } mhc_scene;
 
 typedef struct {
@@ -104,20 +120,42 @@ typedef struct {
  *   object_crit [n_objects]      C_a = sum_i p_{a,i} crit_{a,i}
  *   traj_crit   [n_traj]         crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})
  *   traj_prob   [n_traj]         p_{a,i}, the normalised scores
- *   q           [n_traj*n_objects] q_{a,i;b} = sum_j [hit] p_{b,j}; 0 for b == a
+ *   q           [n_traj*n_objects] q_{a,i;b} (see MHC_RISK_*); 0 for b == a
  *                                  and for pairs outside the pair set
  *   first_hit   [n_traj_pairs]   per pair (a < b, lexicographic), entry i*T_b + j:
  *                                  earliest colliding slot, or -1
  * Trajectories of object a start at index sum_{c<a} T_c. With a single
  * collision object C_0 equals the paper's p_cra double sum (Sec. IV-D); with
  * several, the chronological scaling of Sec. IV-D.2 is applied, collision
- * objects being independent and one object's trajectories exclusive. */
+ * objects being independent.
+ *
+ * Over time (only for scenes with `timeline` = 1; must be NULL otherwise).
+ * The colliding combinations of trajectory (a, i) are taken in the order of
+ * their first colliding slot (ties: ascending object, then trajectory index);
+ * each counts with its probability scaled by the probability that no
+ * collision happened before it (Sec. IV-D.2):
+ *   crit_t      [n_objects*horizon]  C_a(s) = sum_i p_{a,i} crit_{a,i}(s), the
+ *                                  probability of a collision of a at or
+ *                                  before slot s (time (s+1)*dt); the rise of
+ *                                  C over the horizon is what the anticipation
+ *                                  time of Sec. IV-D / VI-A is read from
+ *   traj_crit_t [n_traj*horizon]     crit_{a,i}(s), entry (i, s) at i*horizon + s
+ *   attrib      [n_objects*n_objects] A_{a,b} = sum_i p_{a,i} A_{a,i;b}, the
+ *                                  probability that a's first collision is
+ *                                  with b; sum_b A_{a,b} = C_a
+ *   traj_attrib [n_traj*n_objects]   A_{a,i;b}, entry (i, b) like q
+ * crit_t at slot horizon-1 and sum_b attrib equal object_crit up to rounding
+ * (they are summed in another order). */
 typedef struct {
     double *object_crit;
     double *traj_crit;
     double *traj_prob;
     double *q;
     int16_t *first_hit;
+    double *crit_t;
+    double *traj_crit_t;
+    double *attrib;
+    double *traj_attrib;
 } mhc_result;
 
 /* ---- context ---------------------------------------------------------- */
@@ -133,6 +171,19 @@ const char *mhc_last_error(const mhc_ctx *ctx);
  * The trajectory count corresponds to r_tra of Sec. IV-B.4 and n_traj_pairs to
  * r_col of Sec. IV-C.2 in the EGO pair mode. */
 mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out);
+
+/* Host only (no GPU needed). Anticipation time (Sec. IV-D, Sec. VI-A): how
+ * long before an event the criticality of a situation is recognised.
+ * crit[f] is the criticality of frame f of an evolving scene, frames
+ * frame_dt seconds apart (for instance object_crit[0] of successive
+ * evaluations); the event (the collision) happens at frame event_frame,
+ * 1 <= event_frame <= n_frames. The criticality counts as recognised from the
+ * first frame f* from which crit[g] >= threshold for every g in
+ * [f*, event_frame); *out_seconds = (event_frame - f*) * frame_dt, and 0 when
+ * crit[event_frame - 1] < threshold. MHC_E_INVAL for NULL pointers, a frame
+ * index out of range, frame_dt <= 0, or a non-finite threshold or crit. */
+mhc_status mhc_anticipation_time(int32_t n_frames, const double *crit, double frame_dt, double threshold,
+                                 int32_t event_frame, double *out_seconds);
 
 /* ---- plain single scene ------------------------------------------------ */
 

@@ -35,6 +35,24 @@ namespace mhc {
 // float2 (x, y) for pedestrians, layout [t][i], slot t = step t+1.
 // ===========================================================================
 
+// The integer summand of one colliding combination of probability p: p itself
+// in units of 2^-62 (EXCLUSIVE reading: an object's trajectories exclude one
+// another, so the q of an object is a sum of p), or -log(1 - p), capped at
+// 64, in units of 2^-56 (INDEPENDENT reading: q = 1 - prod(1 - p) =
+// 1 - exp(-sum of -log(1 - p))).
+__device__ __forceinline__ unsigned long long fixed_term(int risk, double p)
+{
+    if (risk == RISK_EXCLUSIVE) return __double2ull_rn(p * kQScale);
+    return __double2ull_rn(fmin(-log1p(-p), kLCap) * kLScale);
+}
+
+// q from its integer sum, under the object's reading.
+__device__ __forceinline__ double q_of(int risk, unsigned long long v)
+{
+    if (risk == RISK_EXCLUSIVE) return fmin((double)v * kQInvScale, 1.0);
+    return -expm1(-(double)v * kLInvScale);
+}
+
 // Thread tid adds the scores tid, tid + 256, ... in ascending order, eight
 // loads in flight at a time, then the workgroup adds the 256 partial sums in a
 // fixed tree: the order depends on T only.
@@ -79,7 +97,7 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
             if (idx < o.T) {
                 const double pk = o.has_score ? v[k] / total : 1.0 / (double)o.T;
                 p[o.traj_off + idx] = pk;
-                pfix[o.traj_off + idx] = __double2ull_rn(pk * kQScale);
+                pfix[o.traj_off + idx] = fixed_term(o.risk, pk);
             }
         }
     }
@@ -93,16 +111,26 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
 // Grid: y = object; x = 0 is the object's probability normalisation (the
 // longest block for large T, so it is dispatched first), x >= 1 are
 // trajectory blocks of K1_TPB trajectories, one wave each.
+// For time-resolved scenes, trajectory block c also zeroes the c-th stretch
+// of K1_TPB * n * H entries of the object's per-slot q sums.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
-                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
+                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done,
+                                                 unsigned long long *__restrict__ hist)
 {
     const int obj = (int)blockIdx.y;
     const DObj o = objs[obj];
     if (blockIdx.x == 0) {
         normalise_probabilities(o, obj, vals, p, pfix, qacc, done);
         return;
+    }
+    if (o.timeline) {
+        const int64_t per = (int64_t)K1_TPB * o.n_scene_obj * o.H;
+        const int64_t total = (int64_t)o.T * o.n_scene_obj * o.H;
+        const int64_t lo = ((int64_t)blockIdx.x - 1) * per;
+        const int64_t hi = min(total, lo + per);
+        for (int64_t k = lo + (int64_t)threadIdx.x; k < hi; k += WG) hist[o.hist_off + k] = 0ull;
     }
     const int lane = threadIdx.x & 63;
     const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
@@ -300,10 +328,11 @@ __device__ __forceinline__ float2 load_pose<float2>(__amdgpu_buffer_rsrc_t r, ui
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-template <int RI, int RJ, class PA, class PB, class Check>
+template <int RI, int RJ, bool TL, class PA, class PB, class Check>
 __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const char *__restrict__ poses,
                                               int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
-                                              unsigned long long *__restrict__ qacc, const Check chk)
+                                              unsigned long long *__restrict__ qacc,
+                                              unsigned long long *__restrict__ hist, const Check chk)
 {
     const int n_ig = pr.n_ig, n_jg = pr.n_jg;
     // time split: E = 64 >> tshift items per unit, part p of the steps per lane
@@ -391,6 +420,20 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
         for (int r = 0; r < RI; ++r) pa[r] = pfix[pr.pa_off + ia[r]];
 #pragma unroll
         for (int s = 0; s < RJ; ++s) pb[s] = pfix[pr.pb_off + jb[s]];
+        if (TL && pr.timeline) {
+            // time-resolved: each colliding pair adds to the sums of its
+            // first colliding slot
+#pragma unroll
+            for (int r = 0; r < RI; ++r)
+#pragma unroll
+                for (int s = 0; s < RJ; ++s)
+                    if (first[r][s] >= 0) {
+                        const int64_t k = first[r][s];
+                        atomicAdd(&hist[pr.ha0 + k * Ta + (ig + r * n_ig)], pb[s]);
+                        atomicAdd(&hist[pr.hb0 + k * Tb + (jg + s * n_jg)], pa[r]);
+                    }
+            return;
+        }
 #pragma unroll
         for (int r = 0; r < RI; ++r) {
             unsigned long long row = 0;
@@ -413,34 +456,37 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
 // PIP: whether this kernel instance carries the point-in-polygon class. Its
 // larger tile needs more registers, which would lower the occupancy of the
 // exact classes; launches without such pairs use the instance without it.
-template <int V, bool PIP>
+// TL: whether it can add to per-slot sums (time-resolved scenes); likewise
+// kept out of the instances that launches without such scenes use.
+template <int V, bool PIP, bool TL>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
-                                             unsigned long long *__restrict__ qacc)
+                                             unsigned long long *__restrict__ qacc,
+                                             unsigned long long *__restrict__ hist)
 {
     if constexpr (PIP) {
         if (pr.cls == CLS_VV_PIP) {
-            collide_items<kTiles[V][CLS_VV_PIP].ri, kTiles[V][CLS_VV_PIP].rj, float4, float4>(
-                pr, item0, poses, hits, pfix, qacc, CheckVVPip{pr.la, pr.wa, pr.lb, pr.wb});
+            collide_items<kTiles[V][CLS_VV_PIP].ri, kTiles[V][CLS_VV_PIP].rj, TL, float4, float4>(
+                pr, item0, poses, hits, pfix, qacc, hist, CheckVVPip{pr.la, pr.wa, pr.lb, pr.wb});
             return;
         }
     }
     switch (pr.cls) {
     case CLS_VV:
-        collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, float4, float4>(
-            pr, item0, poses, hits, pfix, qacc, CheckVV{pr.la, pr.wa, pr.lb, pr.wb});
+        collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, TL, float4, float4>(
+            pr, item0, poses, hits, pfix, qacc, hist, CheckVV{pr.la, pr.wa, pr.lb, pr.wb});
         break;
     case CLS_VP:
-        collide_items<kTiles[V][CLS_VP].ri, kTiles[V][CLS_VP].rj, float4, float2>(
-            pr, item0, poses, hits, pfix, qacc, CheckVP{pr.la, pr.wa, pr.rr});
+        collide_items<kTiles[V][CLS_VP].ri, kTiles[V][CLS_VP].rj, TL, float4, float2>(
+            pr, item0, poses, hits, pfix, qacc, hist, CheckVP{pr.la, pr.wa, pr.rr});
         break;
     case CLS_PV:
-        collide_items<kTiles[V][CLS_PV].ri, kTiles[V][CLS_PV].rj, float2, float4>(
-            pr, item0, poses, hits, pfix, qacc, CheckPV{pr.lb, pr.wb, pr.rr});
+        collide_items<kTiles[V][CLS_PV].ri, kTiles[V][CLS_PV].rj, TL, float2, float4>(
+            pr, item0, poses, hits, pfix, qacc, hist, CheckPV{pr.lb, pr.wb, pr.rr});
         break;
     default:
-        collide_items<kTiles[V][CLS_PP].ri, kTiles[V][CLS_PP].rj, float2, float2>(
-            pr, item0, poses, hits, pfix, qacc, CheckPP{pr.rr});
+        collide_items<kTiles[V][CLS_PP].ri, kTiles[V][CLS_PP].rj, TL, float2, float2>(
+            pr, item0, poses, hits, pfix, qacc, hist, CheckPP{pr.rr});
         break;
     }
 }
@@ -453,12 +499,13 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 // load-heavy and arithmetic-heavy test classes on every CU. The host
 // balances the slots by the exact instruction cost of the work, so every
 // SIMD finishes together without any cross-XCD atomics.
-template <int V, bool PIP>
+template <int V, bool PIP, bool TL>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,
-                                                 unsigned long long *__restrict__ qacc)
+                                                 unsigned long long *__restrict__ qacc,
+                                                 unsigned long long *__restrict__ hist)
 {
     const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int blocks = (int)gridDim.x;
@@ -475,15 +522,17 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
         const WorkItem w = work[k];
         const DPair pr = pairs[w.pair];
         const int per = WAVE >> pr.tshift;
-        for (int u = 0; u < w.n_units; ++u) collide_work<V, PIP>(pr, w.item0 + u * per, poses, hits, pfix, qacc);
+        for (int u = 0; u < w.n_units; ++u) collide_work<V, PIP, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist);
     }
 }
 
 // ===========================================================================
 // K3: risk assessment (Sec. IV-D, IV-D.2).
 //
-// The collision kernel has left q_{a,i;b} = sum_j [hit] p_{b,j} as exact
-// integer sums (units of 2^-62). Grid: y = object, x = chunk of 256
+// The collision kernel has left the q_{a,i;b} as exact integer sums (p in
+// units of 2^-62, or -log(1 - p) in units of 2^-56 for the INDEPENDENT
+// reading; for time-resolved scenes the k3_timeline kernel has added up the
+// per-slot sums into the same accumulators). Grid: y = object, x = chunk of 256
 // trajectories; thread tid of chunk c takes trajectory i = 256 c + tid,
 // converts its sums (rounding once), clamps to 1, writes q and forms
 //   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b).
@@ -526,7 +575,7 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 if (b0 + k < n) {
-                    const double qv = fmin((double)v[k] * kQInvScale, 1.0);
+                    const double qv = q_of(o.risk, v[k]);
                     if (qi) qi[b0 + k] = qv;
                     no_collision *= 1.0 - qv;
                 }
@@ -559,6 +608,113 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
 }
 
 // ===========================================================================
+// Time-resolved risk (Sec. IV-D.2 over the horizon; the criticality curve the
+// anticipation time of Sec. IV-D / VI-A is read from).
+//
+// For time-resolved scenes the collision kernel adds the summand of every
+// colliding trajectory pair to the sums of its first colliding slot s:
+// hist_a[b][s][i] (object a's block; consecutive i contiguous). Then, for
+// trajectory (a, i) with running sums Q_b(s) = sum_{s' <= s} hist_a[b][s'][i]
+// and no-collision factors f_b(s) = 1 - q(Q_b(s)), the combinations are taken
+// slot by slot, ascending b within a slot; the probability that the first
+// collision happens with b at slot s is
+//   (f_b(s-1) - f_b(s)) * prod_{b' < b} f_{b'}(s) * prod_{b' > b} f_{b'}(s-1)
+// which is the running no-collision product N (with b's old factor) divided
+// by f_b(s-1), times (f_b(s-1) - f_b(s)). Adding these up over slots gives
+// the attribution A_{a,i;b}; 1 - N after slot s is crit_{a,i}(s).
+// ===========================================================================
+
+// K3t: grid y = object, x = chunk of 256 trajectories, a thread per
+// trajectory; reads the per-slot sums (coalesced over i), keeps running sums
+// and attributions in [b][i] scratch, writes the criticality over time as
+// [s][i] scratch (and traj_crit_t (i, s) if asked for), the attribution
+// (i, b) if asked for, and finally the total sums of every b into the
+// integer accumulators k3_crit reads.
+__global__ __launch_bounds__(WG) void k3_timeline(const DObj *__restrict__ objs,
+                                                  const unsigned long long *__restrict__ hist,
+                                                  unsigned long long *__restrict__ qacc,
+                                                  unsigned long long *__restrict__ qrun, double *__restrict__ att_w,
+                                                  double *__restrict__ ct_w, double *__restrict__ traj_crit_t,
+                                                  double *__restrict__ traj_attrib)
+{
+    const DObj o = objs[blockIdx.y];
+    if (!o.timeline) return;
+    const int i = (int)blockIdx.x * WG + (int)threadIdx.x;
+    if (i >= o.T) return;  // no barriers below
+    const int n = o.n_scene_obj, H = o.H;
+    const int64_t T = o.T;
+    const unsigned long long *__restrict__ h = hist + o.hist_off + i;   // (b, s) at (b*H + s)*T
+    unsigned long long *__restrict__ run = qrun + o.q_row + i;          // (b) at b*T
+    double *__restrict__ A = att_w + o.q_row + i;
+    for (int b = 0; b < n; ++b) {
+        run[b * T] = 0ull;
+        A[b * T] = 0.0;
+    }
+    double *__restrict__ ct = ct_w + o.tl_traj + i;                      // (s) at s*T
+    double *__restrict__ tct = traj_crit_t ? traj_crit_t + o.tl_traj + (int64_t)i * H : nullptr;
+    double N = 1.0;  // probability that no collision has happened so far
+    for (int s = 0; s < H; ++s) {
+        for (int b = 0; b < n; ++b) {
+            const unsigned long long v = h[((int64_t)b * H + s) * T];
+            if (v == 0ull) continue;
+            const unsigned long long q0 = run[b * T], q1 = q0 + v;
+            run[b * T] = q1;
+            const double f = 1.0 - q_of(o.risk, q0), g = 1.0 - q_of(o.risk, q1);
+            if (g < f) {  // then f > 0
+                const double X = N / f;
+                A[b * T] += X * (f - g);
+                N = X * g;
+            }
+        }
+        ct[(int64_t)s * T] = 1.0 - N;
+        if (tct) tct[s] = 1.0 - N;
+    }
+    unsigned long long *__restrict__ tot = qacc + o.q_row + (int64_t)i * n;
+    double *__restrict__ ta = traj_attrib ? traj_attrib + o.q_row + (int64_t)i * n : nullptr;
+    for (int b = 0; b < n; ++b) {
+        tot[b] = run[b * T];
+        if (ta) ta[b] = A[b * T];
+    }
+}
+
+// Sum of a double over the 64 lanes of a wave in a fixed butterfly order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// K4t: grid x = object; wave w of the workgroup takes slots s = w, w + 4, ...
+// (then collision objects b = w, w + 4, ...): lane l adds p_{a,i} times the
+// trajectory value over i = l, l + 64, ... in ascending order, and the wave
+// adds its 64 lane sums in a fixed butterfly. Every sum has a fixed order.
+__global__ __launch_bounds__(WG) void k4_timeline(const DObj *__restrict__ objs, const double *__restrict__ p,
+                                                  const double *__restrict__ ct_w, const double *__restrict__ att_w,
+                                                  double *__restrict__ crit_t, double *__restrict__ attrib)
+{
+    const DObj o = objs[blockIdx.x];
+    if (!o.timeline) return;
+    const int wave = (int)(threadIdx.x / WAVE), lane = (int)(threadIdx.x & (WAVE - 1));
+    const int n = o.n_scene_obj, H = o.H, T = o.T;
+    const double *__restrict__ pp = p + o.traj_off;
+    for (int s = wave; s < H; s += WG / WAVE) {
+        const double *__restrict__ row = ct_w + o.tl_traj + (int64_t)s * T;
+        double acc = 0.0;
+        for (int i = lane; i < T; i += WAVE) acc += pp[i] * row[i];
+        acc = wave_sum(acc);
+        if (lane == 0) crit_t[o.tl_obj + s] = acc;
+    }
+    for (int b = wave; b < n; b += WG / WAVE) {
+        const double *__restrict__ row = att_w + o.q_row + (int64_t)b * T;
+        double acc = 0.0;
+        for (int i = lane; i < T; i += WAVE) acc += pp[i] * row[i];
+        acc = wave_sum(acc);
+        if (lane == 0) attrib[o.tl_att + b] = acc;
+    }
+}
+
+// ===========================================================================
 // Launchers
 // ===========================================================================
 
@@ -566,61 +722,84 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
     hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc,
-                       L.done);
+                       L.done, L.hist);
     return hipGetLastError();
 }
 
-template <int V, bool PIP>
+template <int V, bool PIP, bool TL>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL((k2_collide<V, PIP>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins, L.xcd_major,
-                       L.poses, L.hits, L.pfix, L.qacc);
+    hipLaunchKernelGGL((k2_collide<V, PIP, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
+                       L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist);
     return hipGetLastError();
 }
 
-hipError_t launch_collide(const Launch &L, hipStream_t s)
-{
-    if (L.n_work <= 0) return hipSuccess;
-    switch (L.variant * 2 + (L.pip ? 1 : 0)) {
-    case 0: return launch_k2<0, false>(L, s);
-    case 1: return launch_k2<0, true>(L, s);
-    case 2: return launch_k2<1, false>(L, s);
-    case 3: return launch_k2<1, true>(L, s);
-    case 4: return launch_k2<2, false>(L, s);
-    case 5: return launch_k2<2, true>(L, s);
-    case 6: return launch_k2<3, false>(L, s);
-    case 7: return launch_k2<3, true>(L, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <int V, bool PIP>
+template <int V, bool PIP, bool TL>
 static int k2_resident_blocks()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, PIP>, WG, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, PIP, TL>, WG, 0) != hipSuccess ||
+        per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-int collide_blocks_per_cu(int variant, bool pip)
+// The kernel instance of (variant, point-in-polygon class, per-slot sums):
+// F::run<V, PIP, TL>() is called for the instance.
+template <bool PIP, bool TL, class F>
+static auto with_variant(int variant, const F &f)
 {
-    switch (variant * 2 + (pip ? 1 : 0)) {
-    case 0: return k2_resident_blocks<0, false>();
-    case 1: return k2_resident_blocks<0, true>();
-    case 2: return k2_resident_blocks<1, false>();
-    case 3: return k2_resident_blocks<1, true>();
-    case 4: return k2_resident_blocks<2, false>();
-    case 5: return k2_resident_blocks<2, true>();
-    case 6: return k2_resident_blocks<3, false>();
-    default: return k2_resident_blocks<3, true>();
+    switch (variant) {
+    case 0: return f.template run<0, PIP, TL>();
+    case 1: return f.template run<1, PIP, TL>();
+    case 2: return f.template run<2, PIP, TL>();
+    default: return f.template run<3, PIP, TL>();
     }
+}
+
+template <class F>
+static auto with_instance(int variant, bool pip, bool tl, const F &f)
+{
+    if (pip) return tl ? with_variant<true, true>(variant, f) : with_variant<true, false>(variant, f);
+    return tl ? with_variant<false, true>(variant, f) : with_variant<false, false>(variant, f);
+}
+
+struct LaunchK2 {
+    const Launch &L;
+    hipStream_t s;
+    template <int V, bool PIP, bool TL>
+    hipError_t run() const { return launch_k2<V, PIP, TL>(L, s); }
+};
+
+struct ResidentK2 {
+    template <int V, bool PIP, bool TL>
+    int run() const { return k2_resident_blocks<V, PIP, TL>(); }
+};
+
+hipError_t launch_collide(const Launch &L, hipStream_t s)
+{
+    if (L.n_work <= 0) return hipSuccess;
+    if (L.variant < 0 || L.variant >= N_VARIANTS) return hipErrorInvalidValue;
+    return with_instance(L.variant, L.pip != 0, L.timeline != 0, LaunchK2{L, s});
+}
+
+int collide_blocks_per_cu(int variant, bool pip, bool timeline)
+{
+    return with_instance(variant, pip, timeline, ResidentK2{});
 }
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
+    if (L.timeline) {
+        hipLaunchKernelGGL(k3_timeline, dim3(L.k3_x, L.n_obj), dim3(WG), 0, s, L.objs, L.hist, L.qacc, L.qrun, L.att_w,
+                           L.ct_w, L.traj_crit_t, L.traj_attrib);
+        hipLaunchKernelGGL(k4_timeline, dim3(L.n_obj), dim3(WG), 0, s, L.objs, L.p, L.ct_w, L.att_w, L.crit_t,
+                           L.attrib);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k3_crit, dim3(L.k3_x, L.n_obj), dim3(WG), 0, s, L.objs, L.qacc, L.p, L.q, L.traj_crit,
                        L.obj_crit, L.k3_part, L.done);
     return hipGetLastError();

@@ -17,17 +17,26 @@ enum Kind : int32_t { KIND_VEHICLE = 0, KIND_PEDESTRIAN = 1 };
 // CLS_VV_PIP: two rectangles under the point-in-polygon test.
 enum PairClass : int32_t { CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, CLS_VV_PIP = 4, N_CLS = 5 };
 
+// Reading of the conditional-probability approximation (mhc.h MHC_RISK_*).
+enum RiskModel : int32_t { RISK_EXCLUSIVE = 0, RISK_INDEPENDENT = 1 };
+
 // One object of one scene. Offsets are global across all scenes of a launch.
 struct DObj {
     int32_t kind, n_u, n_w, T;
     int32_t has_score, H;
     int32_t local, n_scene_obj;   // index within its scene, object count of the scene
+    int32_t risk, timeline;       // RiskModel of its scene; 1: time-resolved risk
     int64_t traj_off;             // index of trajectory 0 in the p / traj_crit arrays
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
     int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
     int64_t part_off;             // first partial sum of the risk kernel's chunks
     int64_t obj_out;              // index in the object_crit array
+    // time-resolved risk (timeline scenes only)
+    int64_t hist_off;             // slot sums [b][s][i]: index of (b = 0, s = 0, i = 0)
+    int64_t tl_traj;              // [s][i] criticality over time, and traj_crit_t (i, s): index of i = 0, s = 0
+    int64_t tl_obj;               // crit_t index of (this object, s = 0)
+    int64_t tl_att;               // attrib index of (this object, b = 0)
     double x, y, heading, speed;
     double tau;
 };
@@ -50,6 +59,10 @@ struct DPair {
     int64_t qa0;                  // q index of (a, i = 0, b)
     int64_t qb0;                  // q index of (b, j = 0, a)
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
+    int32_t timeline;             // 1: q sums go to the per-slot sums below
+    int32_t pad1;
+    int64_t ha0;                  // slot-sum index of (a: b, s = 0, i = 0); slot s, trajectory i at + s*Ta + i
+    int64_t hb0;                  // slot-sum index of (b: a, s = 0, j = 0); + s*Tb + j
 };
 
 // A run of collision work for one wave: n_units consecutive units of a pair.
@@ -70,9 +83,15 @@ constexpr int WAVE = 64;          // wavefront size
 constexpr int MAX_TSHIFT = 2;     // time split of a collision unit: S <= 4
 constexpr int N_XCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
-// q sums are accumulated exactly as integers: p scaled by 2^62 and rounded.
+// q sums are accumulated exactly as integers. EXCLUSIVE reading: p scaled by
+// 2^62 and rounded (sum <= 1). INDEPENDENT reading: -log(1 - p), capped at 64,
+// scaled by 2^56 and rounded; over one object's trajectories (sum p = 1) the
+// sum stays below 66 * 2^56 < 2^63.
 constexpr double kQScale = 4611686018427387904.0;        // 2^62
 constexpr double kQInvScale = 2.168404344971009e-19;     // 2^-62
+constexpr double kLScale = 72057594037927936.0;          // 2^56
+constexpr double kLInvScale = 1.3877787807814457e-17;    // 2^-56
+constexpr double kLCap = 64.0;                           // exp(-64) rounds 1 - q to 0
 
 // Micro-tile shape per class, selected by a kernel variant id.
 struct TileShape {
@@ -110,6 +129,13 @@ struct Launch {
     int k3_x;                     // risk kernel grid x: 256-trajectory chunks of the largest object
     double *k3_part;              // risk kernel partial sums, one per chunk
     unsigned int *done;           // per object: risk chunks finished
+    // time-resolved risk (null / 0 when no scene of the launch asks for it)
+    int timeline;
+    unsigned long long *hist;     // per-slot integer q sums
+    unsigned long long *qrun;     // running sums [b][i] per object
+    double *att_w;                // attribution [b][i] per object
+    double *ct_w;                 // criticality over time [s][i] per object
+    double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
     int pip;                      // some pair uses the point-in-polygon test
@@ -117,9 +143,10 @@ struct Launch {
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s);
 hipError_t launch_collide(const Launch &L, hipStream_t s);
+// risk: the time-resolved kernels (timeline launches) and the risk kernel
 hipError_t launch_risk(const Launch &L, hipStream_t s);
 // resident workgroups per CU of the collision kernel for a variant, with or
-// without the point-in-polygon class
-int collide_blocks_per_cu(int variant, bool pip);
+// without the point-in-polygon class and the per-slot sums
+int collide_blocks_per_cu(int variant, bool pip, bool timeline);
 
 }  // namespace mhc

@@ -67,6 +67,9 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
     if (s->pairs != MHC_PAIRS_ALL && s->pairs != MHC_PAIRS_EGO) return fail("pairs must be 0 or 1 (got %d)", s->pairs);
     if (s->overlap != MHC_OVERLAP_EXACT && s->overlap != MHC_OVERLAP_PIP)
         return fail("overlap must be 0 or 1 (got %d)", s->overlap);
+    if (s->risk != MHC_RISK_EXCLUSIVE && s->risk != MHC_RISK_INDEPENDENT)
+        return fail("risk must be 0 or 1 (got %d)", s->risk);
+    if (s->timeline != 0 && s->timeline != 1) return fail("timeline must be 0 or 1 (got %d)", s->timeline);
     for (int a = 0; a < s->n_objects; ++a) {
         const mhc_object &o = s->objects[a];
         if (o.kind != MHC_VEHICLE && o.kind != MHC_PEDESTRIAN) return fail("object %d: kind must be 0 or 1", a);
@@ -107,6 +110,17 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
     return true;
 }
 
+bool validate_outputs(const mhc_scene *s, const mhc_result *r, std::string &err, int scene_index)
+{
+    if (!r || s->timeline) return true;
+    if (r->crit_t || r->traj_crit_t || r->attrib || r->traj_attrib) {
+        err = (scene_index >= 0 ? "scene " + std::to_string(scene_index) + ": " : std::string()) +
+              "crit_t, traj_crit_t, attrib and traj_attrib need a scene with timeline = 1";
+        return false;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Ingest: pair list, work list and the packed scene image.
 // ---------------------------------------------------------------------------
@@ -140,6 +154,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         ext.traj0 = L.n_traj;
         ext.hit0 = L.n_hits;
         ext.q0 = L.n_q;
+        ext.timeline = s.timeline != 0;
+        ext.tl_obj0 = L.n_tl_obj;
+        ext.tl_traj0 = L.n_tl_traj;
+        ext.tl_att0 = L.n_tl_att;
+        L.timeline |= ext.timeline;
         const int obj_base = (int)L.objs.size();
         int64_t toff = 0;
         for (int a = 0; a < n; ++a) {
@@ -153,6 +172,18 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.H = s.horizon;
             d.local = a;
             d.n_scene_obj = n;
+            d.risk = s.risk;
+            d.timeline = s.timeline;
+            if (s.timeline) {
+                d.hist_off = L.n_hist;
+                d.tl_traj = L.n_tl_traj;
+                d.tl_obj = L.n_tl_obj;
+                d.tl_att = L.n_tl_att;
+                L.n_hist += (int64_t)n * s.horizon * d.T;
+                L.n_tl_traj += (int64_t)s.horizon * d.T;
+                L.n_tl_obj += s.horizon;
+                L.n_tl_att += n;
+            }
             d.traj_off = L.n_traj + toff;
             d.q_row = L.n_q + toff * n;
             d.pose_off = (int64_t)L.pose_bytes;
@@ -193,6 +224,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             pr.qb0 = L.objs[obj_base + b].q_row + a;
             pr.pa_off = L.objs[obj_base + a].traj_off;
             pr.pb_off = L.objs[obj_base + b].traj_off;
+            pr.timeline = s.timeline;
+            if (s.timeline) {
+                pr.ha0 = L.objs[obj_base + a].hist_off + (int64_t)b * s.horizon * pr.Ta;
+                pr.hb0 = L.objs[obj_base + b].hist_off + (int64_t)a * s.horizon * pr.Tb;
+            }
             L.pairs.push_back(pr);
             hoff += (int64_t)pr.Ta * pr.Tb;
             ext.checks += (int64_t)pr.Ta * pr.Tb * s.horizon;
@@ -351,6 +387,15 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_q = put((size_t)L.n_q * sizeof(double));
     L.o_tc = put((size_t)L.n_traj * sizeof(double));
     L.o_oc = put((size_t)L.n_obj * sizeof(double));
+    const size_t tq = L.timeline ? (size_t)L.n_q : 0;
+    L.o_hist = put((size_t)L.n_hist * sizeof(unsigned long long));
+    L.o_qrun = put(tq * sizeof(unsigned long long));
+    L.o_attw = put(tq * sizeof(double));
+    L.o_ctw = put((size_t)L.n_tl_traj * sizeof(double));
+    L.o_ct = put((size_t)L.n_tl_obj * sizeof(double));
+    L.o_tct = put((size_t)L.n_tl_traj * sizeof(double));
+    L.o_at = put((size_t)L.n_tl_att * sizeof(double));
+    L.o_tat = put(tq * sizeof(double));
     L.total_bytes = off;
     fill_values(scenes, n_scenes, L);
 }
@@ -423,12 +468,29 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.traj_crit = reinterpret_cast<double *>(base + L.o_tc);
     X.obj_crit = reinterpret_cast<double *>(base + L.o_oc);
     if (!keep_hits || !L.with_hits) X.hits = nullptr;
+    X.timeline = L.timeline ? 1 : 0;
+    if (L.timeline) {
+        X.hist = reinterpret_cast<unsigned long long *>(base + L.o_hist);
+        X.qrun = reinterpret_cast<unsigned long long *>(base + L.o_qrun);
+        X.att_w = reinterpret_cast<double *>(base + L.o_attw);
+        X.ct_w = reinterpret_cast<double *>(base + L.o_ctw);
+        X.crit_t = reinterpret_cast<double *>(base + L.o_ct);
+        X.traj_crit_t = reinterpret_cast<double *>(base + L.o_tct);
+        X.attrib = reinterpret_cast<double *>(base + L.o_at);
+        X.traj_attrib = reinterpret_cast<double *>(base + L.o_tat);
+    }
     if (dev_out) {
         if (dev_out->traj_prob) X.p = dev_out->traj_prob;
         if (dev_out->first_hit) X.hits = dev_out->first_hit;
         if (dev_out->q) X.q = dev_out->q;
         if (dev_out->traj_crit) X.traj_crit = dev_out->traj_crit;
         if (dev_out->object_crit) X.obj_crit = dev_out->object_crit;
+        if (L.timeline) {
+            if (dev_out->crit_t) X.crit_t = dev_out->crit_t;
+            if (dev_out->traj_crit_t) X.traj_crit_t = dev_out->traj_crit_t;
+            if (dev_out->attrib) X.attrib = dev_out->attrib;
+            if (dev_out->traj_attrib) X.traj_attrib = dev_out->traj_attrib;
+        }
     }
     X.n_obj = (int)L.objs.size();
     X.n_pairs = (int)L.pairs.size();
@@ -512,10 +574,14 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
 int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
 {
     if (v < 0 || v >= N_VARIANTS) v = 0;
-    int pip = 0;
-    for (int k = 0; k < n; ++k) pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
-    if (!waves_cache[v][pip]) waves_cache[v][pip] = n_cu * collide_blocks_per_cu(v, pip != 0) * (WG / WAVE);
-    return waves_cache[v][pip];
+    int pip = 0, tl = 0;
+    for (int k = 0; k < n; ++k) {
+        pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
+        tl |= scenes[k].timeline != 0;
+    }
+    int &w = waves_cache[v][pip][tl];
+    if (!w) w = n_cu * collide_blocks_per_cu(v, pip != 0, tl != 0) * (WG / WAVE);
+    return w;
 }
 
 extern "C" const char *mhc_last_error(const mhc_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
@@ -542,9 +608,24 @@ extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
     return MHC_OK;
 }
 
+extern "C" mhc_status mhc_anticipation_time(int32_t n_frames, const double *crit, double frame_dt, double threshold,
+                                            int32_t event_frame, double *out_seconds)
+{
+    if (!crit || !out_seconds || n_frames < 1 || event_frame < 1 || event_frame > n_frames) return MHC_E_INVAL;
+    if (!std::isfinite(frame_dt) || !(frame_dt > 0.0) || !std::isfinite(threshold)) return MHC_E_INVAL;
+    for (int32_t f = 0; f < event_frame; ++f)
+        if (!std::isfinite(crit[f])) return MHC_E_INVAL;
+    // walk back from the last frame before the event while the criticality
+    // stays at or above the threshold
+    int32_t first = event_frame;
+    while (first > 0 && crit[first - 1] >= threshold) --first;
+    *out_seconds = (double)(event_frame - first) * frame_dt;
+    return MHC_OK;
+}
+
 std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
 {
-    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs, s->overlap};
+    std::vector<int32_t> v{s->n_objects, s->horizon, s->pairs, s->overlap, s->risk, s->timeline};
     for (int a = 0; a < s->n_objects; ++a) {
         v.push_back(s->objects[a].kind);
         v.push_back(s->objects[a].n_u);
@@ -662,6 +743,12 @@ mhc_status copy_results(mhc_ctx *ctx, const Layout &L, int k, const char *dbase,
     HIPC(d2h(res->traj_prob, L.o_p + e.traj0 * sizeof(double), e.n_traj * sizeof(double)));
     HIPC(d2h(res->q, L.o_q + e.q0 * sizeof(double), (size_t)e.n_traj * e.n_obj * sizeof(double)));
     HIPC(d2h(res->first_hit, L.o_hits + e.hit0 * sizeof(int16_t), e.n_hits * sizeof(int16_t)));
+    if (e.timeline) {
+        HIPC(d2h(res->crit_t, L.o_ct + e.tl_obj0 * sizeof(double), (size_t)e.n_obj * e.H * sizeof(double)));
+        HIPC(d2h(res->traj_crit_t, L.o_tct + e.tl_traj0 * sizeof(double), (size_t)e.n_traj * e.H * sizeof(double)));
+        HIPC(d2h(res->attrib, L.o_at + e.tl_att0 * sizeof(double), (size_t)e.n_obj * e.n_obj * sizeof(double)));
+        HIPC(d2h(res->traj_attrib, L.o_tat + e.q0 * sizeof(double), (size_t)e.n_traj * e.n_obj * sizeof(double)));
+    }
     return MHC_OK;
 }
 
@@ -672,7 +759,7 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
         ctx->err = "result and result->object_crit must not be NULL";
         return MHC_E_INVAL;
     }
-    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    if (!validate_scene(scene, ctx->err) || !validate_outputs(scene, res, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Layout &L = ctx->layout;
     layout_for(ctx, scene, L, res->first_hit != nullptr);
@@ -701,7 +788,7 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
         ctx->err = "dev_workspace must be 256-byte aligned";
         return MHC_E_INVAL;
     }
-    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    if (!validate_scene(scene, ctx->err) || !validate_outputs(scene, dev_out, ctx->err)) return MHC_E_INVAL;
     Layout L;
     build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), L, true);
     if (workspace_bytes < L.total_bytes) {
@@ -775,6 +862,7 @@ hipError_t GraphCache::get(const std::vector<int64_t> &key, const std::function<
 struct mhc_plan {
     mhc_ctx *ctx = nullptr;
     Layout L;
+    mhc_scene flags{};            // pair mode, overlap, risk and timeline of the planned scene
     char *dbuf = nullptr;
     std::vector<int32_t> shape;   // kinds, grid sizes, horizon, pair mode
     GraphCache graphs;            // K1 -> K2 -> K3 per set of output pointers
@@ -793,6 +881,8 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), pl->L,
                  true);
     pl->shape = shape_of(scene);
+    pl->flags = *scene;
+    pl->flags.objects = nullptr;
     if (ctx->budget && pl->L.total_bytes > ctx->budget) {
         ctx->err = "plan needs more device memory than the context budget";
         delete pl;
@@ -832,6 +922,8 @@ extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
     HIPC(hipDeviceSynchronize());
     HIPC(hipMemcpy(pl->dbuf, img.data(), L.image_bytes, hipMemcpyHostToDevice));
     pl->L = std::move(L);
+    pl->flags = *scene;
+    pl->flags.objects = nullptr;
     return MHC_OK;
 }
 
@@ -839,6 +931,7 @@ extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, 
 {
     if (!pl) return MHC_E_INVAL;
     mhc_ctx *ctx = pl->ctx;
+    if (!validate_outputs(&pl->flags, dev_out, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Launch X = make_launch(pl->L, pl->dbuf, dev_out, true, ctx->n_cu);
     const hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -852,7 +945,9 @@ extern "C" mhc_status mhc_plan_execute(mhc_plan *pl, const mhc_result *dev_out, 
     if (dev_out)
         for (const void *ptr : {(const void *)dev_out->object_crit, (const void *)dev_out->traj_crit,
                                 (const void *)dev_out->traj_prob, (const void *)dev_out->q,
-                                (const void *)dev_out->first_hit})
+                                (const void *)dev_out->first_hit, (const void *)dev_out->crit_t,
+                                (const void *)dev_out->traj_crit_t, (const void *)dev_out->attrib,
+                                (const void *)dev_out->traj_attrib})
             key.push_back((int64_t)(uintptr_t)ptr);
     hipGraphExec_t exec = nullptr;
     HIPC(pl->graphs.get(key, [&](hipStream_t cs) { return launch_all(X, cs); }, &exec));
@@ -869,6 +964,7 @@ extern "C" mhc_status mhc_plan_execute_stages(mhc_plan *pl, const mhc_result *de
         ctx->err = "stages must be a non-empty combination of MHC_STAGE_* bits";
         return MHC_E_INVAL;
     }
+    if (!validate_outputs(&pl->flags, dev_out, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     const hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Launch X = make_launch(pl->L, pl->dbuf, dev_out, true, ctx->n_cu);
@@ -889,6 +985,7 @@ extern "C" mhc_status mhc_plan_download(mhc_plan *pl, mhc_result *host_out)
 {
     if (!pl || !host_out) return MHC_E_INVAL;
     mhc_ctx *ctx = pl->ctx;
+    if (!validate_outputs(&pl->flags, host_out, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     HIPC(hipDeviceSynchronize());
     mhc_status st = copy_results(ctx, pl->L, 0, pl->dbuf, host_out, ctx->stream);
@@ -930,6 +1027,7 @@ extern "C" mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scen
             ctx->err = "result " + std::to_string(k) + ": object_crit must not be NULL";
             return MHC_E_INVAL;
         }
+        if (!validate_outputs(&scenes[k], &res[k], ctx->err, k)) return MHC_E_INVAL;
     }
     HIPC(hipSetDevice(ctx->device));
     return batch_run(ctx, n, scenes, res);

@@ -24,11 +24,16 @@ struct SceneExt {
     int n_obj = 0, H = 0;
     int64_t obj0 = 0, traj0 = 0, n_traj = 0, hit0 = 0, n_hits = 0, q0 = 0;
     int64_t n_pairs = 0, checks = 0;
+    bool timeline = false;
+    int64_t tl_obj0 = 0, tl_traj0 = 0, tl_att0 = 0;  // first crit_t, traj_crit_t, attrib entries
 };
 
 // Host tables of one launch plus the byte layout of its device workspace:
 // [scene image: tables uploaded in one copy][poses][p * 2^62][integer q sums][per-object counters]
 // [p][first hits][q][traj crit][object crit]
+// and, when a scene asks for the risk over time:
+// [per-slot q sums][running sums][attribution scratch][criticality-over-time scratch]
+// [crit_t][traj_crit_t][attrib][traj_attrib]
 struct Layout {
     std::vector<DObj> objs;
     std::vector<double> vals;
@@ -40,9 +45,12 @@ struct Layout {
     int k1_x = 0;                 // trajectory kernel grid x
     int k3_x = 0;                 // risk kernel grid x (chunks of the largest object)
     int64_t n_part = 0;           // risk kernel partial sums (chunks over all objects)
+    bool timeline = false;        // some scene asks for the risk over time
+    int64_t n_hist = 0, n_tl_traj = 0, n_tl_obj = 0, n_tl_att = 0;
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, image_bytes = 0;
-    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0, total_bytes = 0;
+    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
+    size_t o_hist = 0, o_qrun = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
     bool pip = false;             // some pair uses the point-in-polygon test
@@ -62,6 +70,9 @@ struct GraphCache {
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
+// The time-resolved outputs of `r` (crit_t, traj_crit_t, attrib, traj_attrib)
+// are only allowed for a scene with the timeline flag.
+bool validate_outputs(const mhc_scene *s, const mhc_result *r, std::string &err, int scene_index = -1);
 // Test class (CLS_*) of an object pair of kinds ka, kb under an overlap mode.
 int pair_class(int ka, int kb, int overlap);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
@@ -91,7 +102,7 @@ struct mhc_ctx {
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;
-    int waves_cache[mhc::N_VARIANTS][2] = {};
+    int waves_cache[mhc::N_VARIANTS][2][2] = {};  // [variant][point-in-polygon][time-resolved]
     // resident waves on this GPU of the collision kernel that `scenes` need
     int max_waves(int variant, const mhc_scene *scenes, int n);
 };

@@ -138,6 +138,13 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     bytes += pose + align256(n_traj * 8) * 3 + align256(n_q * 8) * 2;  // p*2^62, p, traj crit; q sums, q
     bytes += align256((n_traj / WG + n) * 8) + align256(n * 4);         // risk partials and counters
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);
+    if (s->timeline) {
+        // per-slot sums, running sums, attribution scratch and output, the
+        // criticality over time (scratch and output), crit_t and attrib
+        bytes += align256((size_t)n_q * s->horizon * 8) + align256(n_q * 8) * 3;
+        bytes += align256((size_t)n_traj * s->horizon * 8) * 2 + align256((size_t)n * s->horizon * 8) +
+                 align256((size_t)n * n * 8);
+    }
     bytes += 16 * 256;                              // alignment slack of the tables
     bytes += align256(((size_t)max_waves + 1) * 4);  // the collision plan's slot table
     f.n_traj = n_traj;
@@ -173,6 +180,11 @@ size_t result_bytes(const Frame &f)
     if (f.dst.traj_prob) b += align256(f.n_traj * 8);
     if (f.dst.q) b += align256((size_t)f.n_traj * n * 8);
     if (f.dst.first_hit) b += align256(f.n_hits * 2);
+    const size_t H = (size_t)f.scene.horizon;
+    if (f.dst.crit_t) b += align256(n * H * 8);
+    if (f.dst.traj_crit_t) b += align256(f.n_traj * H * 8);
+    if (f.dst.attrib) b += align256((size_t)n * n * 8);
+    if (f.dst.traj_attrib) b += align256((size_t)f.n_traj * n * 8);
     return b;
 }
 
@@ -231,6 +243,11 @@ hipError_t launch_tick(mhc_server *srv, TickSlot &t)
         if (e == hipSuccess && f.dst.traj_prob) e = d2h(t.L.o_p + x.traj0 * 8, x.n_traj * 8);
         if (e == hipSuccess && f.dst.q) e = d2h(t.L.o_q + x.q0 * 8, (size_t)x.n_traj * x.n_obj * 8);
         if (e == hipSuccess && f.dst.first_hit) e = d2h(t.L.o_hits + x.hit0 * 2, x.n_hits * 2);
+        const size_t H = (size_t)x.H;
+        if (e == hipSuccess && f.dst.crit_t) e = d2h(t.L.o_ct + x.tl_obj0 * 8, (size_t)x.n_obj * H * 8);
+        if (e == hipSuccess && f.dst.traj_crit_t) e = d2h(t.L.o_tct + x.tl_traj0 * 8, (size_t)x.n_traj * H * 8);
+        if (e == hipSuccess && f.dst.attrib) e = d2h(t.L.o_at + x.tl_att0 * 8, (size_t)x.n_obj * x.n_obj * 8);
+        if (e == hipSuccess && f.dst.traj_attrib) e = d2h(t.L.o_tat + x.q0 * 8, (size_t)x.n_traj * x.n_obj * 8);
         if (e != hipSuccess) return e;
     }
     return hipEventRecord(t.done, t.stream);
@@ -253,6 +270,11 @@ void finish_tick(mhc_server *srv, TickSlot &t, mhc_status st)
             if (f.dst.traj_prob) take(f.dst.traj_prob, f.n_traj * 8);
             if (f.dst.q) take(f.dst.q, (size_t)f.n_traj * n * 8);
             if (f.dst.first_hit) take(f.dst.first_hit, f.n_hits * 2);
+            const size_t H = (size_t)f.scene.horizon;
+            if (f.dst.crit_t) take(f.dst.crit_t, (size_t)n * H * 8);
+            if (f.dst.traj_crit_t) take(f.dst.traj_crit_t, f.n_traj * H * 8);
+            if (f.dst.attrib) take(f.dst.attrib, (size_t)n * n * 8);
+            if (f.dst.traj_attrib) take(f.dst.traj_attrib, (size_t)f.n_traj * n * 8);
         }
         f.timing.launch_ns = t.launched_ns;
         f.timing.done_ns = now_ns();
@@ -427,7 +449,7 @@ extern "C" mhc_status mhc_submit(mhc_server *srv, int32_t stream_id, const mhc_s
         ++srv->rejected;
         return MHC_E_INVAL;
     }
-    if (!dst || !dst->object_crit) return MHC_E_INVAL;
+    if (!dst || !dst->object_crit || !validate_outputs(scene, dst, err)) return MHC_E_INVAL;
     auto f = copy_frame(scene);
     f->dst = *dst;
     frame_sizes(&f->scene, 0, dst->first_hit != nullptr, *f);

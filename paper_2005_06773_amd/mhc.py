@@ -24,11 +24,13 @@ MHC_E_BUSY = -4
 MHC_E_TIMEOUT = -5
 MHC_OVERLAP_EXACT = 0
 MHC_OVERLAP_PIP = 1
+MHC_RISK_EXCLUSIVE = 0
+MHC_RISK_INDEPENDENT = 1
 _STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE",
            -4: "MHC_E_BUSY", -5: "MHC_E_TIMEOUT"}
 
 EXPORTED = [
-    "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes",
+    "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes", "mhc_anticipation_time",
     "mhc_evaluate", "mhc_evaluate_async",
     "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages", "mhc_plan_set_graph",
     "mhc_plan_download", "mhc_plan_destroy",
@@ -61,7 +63,7 @@ class mhc_object(ctypes.Structure):
 class mhc_scene(ctypes.Structure):
     _fields_ = [("n_objects", ctypes.c_int32), ("objects", ctypes.POINTER(mhc_object)),
                 ("horizon", ctypes.c_int32), ("dt", _D), ("pairs", ctypes.c_int32),
-                ("overlap", ctypes.c_int32)]
+                ("overlap", ctypes.c_int32), ("risk", ctypes.c_int32), ("timeline", ctypes.c_int32)]
 
 
 class mhc_sizes(ctypes.Structure):
@@ -69,9 +71,13 @@ class mhc_sizes(ctypes.Structure):
                 ("n_checks", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
 
 
+RESULT_FIELDS = ("object_crit", "traj_crit", "traj_prob", "q", "first_hit",
+                 "crit_t", "traj_crit_t", "attrib", "traj_attrib")
+TIMELINE_FIELDS = ("crit_t", "traj_crit_t", "attrib", "traj_attrib")
+
+
 class mhc_result(ctypes.Structure):
-    _fields_ = [("object_crit", ctypes.c_void_p), ("traj_crit", ctypes.c_void_p),
-                ("traj_prob", ctypes.c_void_p), ("q", ctypes.c_void_p), ("first_hit", ctypes.c_void_p)]
+    _fields_ = [(k, ctypes.c_void_p) for k in RESULT_FIELDS]
 
 
 class mhc_server_cfg(ctypes.Structure):
@@ -111,6 +117,8 @@ def _load():
         "mhc_destroy": [V],
         "mhc_last_error": [V],
         "mhc_query_sizes": [ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_sizes)],
+        "mhc_anticipation_time": [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
         "mhc_evaluate": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
         "mhc_evaluate_async": [V, ctypes.POINTER(mhc_scene), V, S, ctypes.POINTER(mhc_result), V],
         "mhc_plan_create": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(V)],
@@ -168,7 +176,10 @@ class CScene:
             objs[k].score = sc.ctypes.data_as(_DP) if sc is not None else None
         self.objs = objs
         self.c = mhc_scene(scene.n_objects, objs, int(scene.horizon), float(scene.dt), int(scene.pairs),
-                           int(getattr(scene, "overlap", MHC_OVERLAP_EXACT)))
+                           int(getattr(scene, "overlap", MHC_OVERLAP_EXACT)),
+                           int(getattr(scene, "risk", MHC_RISK_EXCLUSIVE)), int(getattr(scene, "timeline", 0)))
+        self.H = int(scene.horizon)
+        self.timeline = bool(getattr(scene, "timeline", 0))
         self.T = [len(o.u) * len(o.w) for o in scene.objects]
         self.n = scene.n_objects
         self.pairs = [(a, b) for a in range(self.n) for b in range(a + 1, self.n)
@@ -183,16 +194,25 @@ def _check(ctx, st: int):
         raise MhcError(st, msg)
 
 
-def host_result(cs: CScene, first_hit: bool = True, q: bool = True):
-    out = {
-        "object_crit": np.full(cs.n, np.nan),
-        "traj_crit": np.full(cs.n_traj, np.nan),
-        "traj_prob": np.full(cs.n_traj, np.nan),
-        "q": np.full((cs.n_traj, cs.n), np.nan) if q else None,
-        "first_hit": np.full(cs.n_hits, -2, np.int16) if first_hit else None,
+def _shapes(cs: CScene, first_hit: bool, q: bool, timeline: Optional[bool]):
+    tl = cs.timeline if timeline is None else timeline
+    return {
+        "object_crit": (cs.n,), "traj_crit": (cs.n_traj,), "traj_prob": (cs.n_traj,),
+        "q": (cs.n_traj, cs.n) if q else None,
+        "first_hit": (cs.n_hits,) if first_hit else None,
+        "crit_t": (cs.n, cs.H) if tl else None,
+        "traj_crit_t": (cs.n_traj, cs.H) if tl else None,
+        "attrib": (cs.n, cs.n) if tl else None,
+        "traj_attrib": (cs.n_traj, cs.n) if tl else None,
     }
-    r = mhc_result(*(None if out[k] is None else out[k].ctypes.data for k in
-                     ("object_crit", "traj_crit", "traj_prob", "q", "first_hit")))
+
+
+def host_result(cs: CScene, first_hit: bool = True, q: bool = True, timeline: Optional[bool] = None):
+    """NaN-filled host outputs (first hits -2) for every field asked for; the
+    time-resolved ones by default when the scene asks for the risk over time."""
+    out = {k: None if sh is None else (np.full(sh, -2, np.int16) if k == "first_hit" else np.full(sh, np.nan))
+           for k, sh in _shapes(cs, first_hit, q, timeline).items()}
+    r = mhc_result(*(None if out[k] is None else out[k].ctypes.data for k in RESULT_FIELDS))
     return out, r
 
 
@@ -225,9 +245,19 @@ def mhc_query_sizes(scene) -> dict:
     return {k: getattr(s, k) for k, _ in mhc_sizes._fields_}
 
 
-def mhc_evaluate(ctx, scene, first_hit: bool = True, q: bool = True) -> dict:
+def mhc_anticipation_time(crit: Sequence[float], frame_dt: float, threshold: float, event_frame: int) -> float:
+    c = np.ascontiguousarray(crit, np.float64)
+    out = ctypes.c_double()
+    st = lib.mhc_anticipation_time(len(c), c.ctypes.data_as(_DP), float(frame_dt), float(threshold),
+                                   int(event_frame), ctypes.byref(out))
+    if st != MHC_OK:
+        raise MhcError(st, "mhc_anticipation_time: invalid arguments")
+    return out.value
+
+
+def mhc_evaluate(ctx, scene, first_hit: bool = True, q: bool = True, timeline: Optional[bool] = None) -> dict:
     cs = scene if isinstance(scene, CScene) else CScene(scene)
-    out, r = host_result(cs, first_hit, q)
+    out, r = host_result(cs, first_hit, q, timeline)
     _check(ctx, lib.mhc_evaluate(ctx, ctypes.byref(cs.c), ctypes.byref(r)))
     return out
 
@@ -241,18 +271,19 @@ def mhc_evaluate_batch(ctx, scenes: Sequence, first_hit: bool = True, q: bool = 
     return list(outs)
 
 
-def device_result(cs: CScene, device="cuda", first_hit: bool = True, q: bool = True):
+def device_result(cs: CScene, device="cuda", first_hit: bool = True, q: bool = True,
+                  timeline: Optional[bool] = None):
     """Torch-owned device outputs for the asynchronous and plan paths."""
     import torch
-    out = {
-        "object_crit": torch.full((cs.n,), float("nan"), dtype=torch.float64, device=device),
-        "traj_crit": torch.full((cs.n_traj,), float("nan"), dtype=torch.float64, device=device),
-        "traj_prob": torch.full((cs.n_traj,), float("nan"), dtype=torch.float64, device=device),
-        "q": torch.full((cs.n_traj, cs.n), float("nan"), dtype=torch.float64, device=device) if q else None,
-        "first_hit": torch.full((cs.n_hits,), -2, dtype=torch.int16, device=device) if first_hit else None,
-    }
-    r = mhc_result(*(None if out[k] is None else out[k].data_ptr() for k in
-                     ("object_crit", "traj_crit", "traj_prob", "q", "first_hit")))
+    out = {}
+    for k, sh in _shapes(cs, first_hit, q, timeline).items():
+        if sh is None:
+            out[k] = None
+        elif k == "first_hit":
+            out[k] = torch.full(sh, -2, dtype=torch.int16, device=device)
+        else:
+            out[k] = torch.full(sh, float("nan"), dtype=torch.float64, device=device)
+    r = mhc_result(*(None if out[k] is None else out[k].data_ptr() for k in RESULT_FIELDS))
     return out, r
 
 

@@ -26,7 +26,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import Tuple, List, Optional
 
 import numpy as np
 
@@ -276,6 +276,35 @@ def paper_scene(seed: int = 5, n_co: int = 10, n_acc: int = 6, overlap: int = OV
         objs.append(SceneObject(VEHICLE, float(x), float(y), float(h), float(v), 4.5 * lf, 1.8 * wf, 0.0,
                                 u, w_co, vehicle_scores(u, w_co)))
     return Scene(objs, 100, 0.02, pairs=PAIRS_EGO, overlap=overlap)
+
+
+def approach_sequence(seed: int = 8, frame_dt: float = 0.1, horizon: int = 30, dt: float = 0.1,
+                      side: int = 9) -> Tuple[List[Scene], int]:
+    """An EGO vehicle driving at constant speed U(12, 18) m/s straight at a
+    stopped vehicle U(35, 55) m ahead in its lane (lateral offset U(-0.3, 0.3)
+    m), observed every frame_dt seconds as it would be if it never reacted:
+    frame f has the EGO f * frame_dt * v0 further on. Both have side x side
+    grids (accelerations by the paper's rule on [-8, 3], yaw rates on
+    [-0.5, 0.5]); the two vehicles are 4.5 x 1.8 m +-10 %. Returns the frames
+    up to (not including) the event frame, the first at which the two
+    rectangles touch, and that frame index. The stand-in for the designed
+    scenarios with static objects ahead of the EGO (Sec. VI-A), whose
+    geometry is not published."""
+    rng = np.random.default_rng(seed)
+    v0 = float(rng.uniform(12.0, 18.0))
+    D = float(rng.uniform(35.0, 55.0))
+    y_co = float(rng.uniform(-0.3, 0.3))
+    L0, W0 = 4.5 * rng.uniform(0.9, 1.1), 1.8 * rng.uniform(0.9, 1.1)
+    L1, W1 = 4.5 * rng.uniform(0.9, 1.1), 1.8 * rng.uniform(0.9, 1.1)
+    u, w = accel_grid(side), yaw_grid(side)
+    gap = D - (L0 + L1) / 2.0
+    event = int(math.ceil(gap / (v0 * frame_dt)))
+    frames = []
+    for f in range(event):
+        ego = SceneObject(VEHICLE, v0 * f * frame_dt, 0.0, 0.0, v0, L0, W0, 0.0, u, w, vehicle_scores(u, w))
+        co = SceneObject(VEHICLE, D, y_co, 0.0, 0.0, L1, W1, 0.0, u, w, vehicle_scores(u, w))
+        frames.append(Scene([ego, co], horizon, dt, timeline=1))
+    return frames, event
 
 
 def paper_shaped_sizes(n_co: int, n_acc: int = 6, ego_paths: int = 343, co_paths: int = 7):

@@ -131,6 +131,8 @@ def _bad_scenes():
     s = base(); s.horizon = 30000; s.objects[0].u = np.zeros(100); s.objects[0].w = np.zeros(100)
     out["pose_block_too_large"] = s
     s = base(); s.overlap = 2; out["bad_overlap_mode"] = s
+    s = base(); s.risk = 2; out["bad_risk_reading"] = s
+    s = base(); s.timeline = 3; out["bad_timeline_flag"] = s
     s = base(); s.overlap = sg.OVERLAP_PIP
     s.objects[1] = sg.SceneObject(sg.PEDESTRIAN, 1, 0, 0, 1, 0, 0, 0.3, np.array([1.0]), np.array([0.0]))
     out["pip_mode_with_a_pedestrian"] = s
@@ -160,3 +162,39 @@ def test_create_without_gpu_reports_device_error(mhc):
     with pytest.raises(mhc.MhcError) as ei:
         mhc.mhc_create(0)
     assert ei.value.status == mhc.MHC_E_DEVICE
+
+
+def test_timeline_workspace_holds_the_time_resolved_arrays(mhc):
+    """A time-resolved scene needs the per-slot sums (n_traj * n * H
+    integers), the criticality over time (twice n_traj * H: scratch and
+    output) and the attribution on top of the plain workspace."""
+    s = sg.eleven_object_scene(1)
+    plain = mhc.mhc_query_sizes(s)["device_bytes"]
+    s.timeline = 1
+    tl = mhc.mhc_query_sizes(s)["device_bytes"]
+    n, H, nt = s.n_objects, s.horizon, sum(s.traj_counts())
+    assert tl - plain >= 8 * (nt * n * H + 2 * nt * H + 3 * nt * n + n * H + n * n)
+    s.risk = sg.RISK_INDEPENDENT
+    assert mhc.mhc_query_sizes(s)["device_bytes"] == tl
+
+
+def test_anticipation_time_by_hand(mhc):
+    """Sec. VI-A: the time before the event from which the criticality stays
+    at or above the threshold."""
+    at = mhc.mhc_anticipation_time
+    crit = [0.0, 0.2, 0.6, 0.9, 0.95, 1.0]
+    assert at(crit, 0.1, 0.9, 6) == pytest.approx(0.3)        # frames 3, 4, 5
+    assert at(crit, 0.1, 0.5, 6) == pytest.approx(0.4)        # frames 2..5
+    assert at(crit, 0.1, 0.0, 6) == pytest.approx(0.6)        # all frames
+    assert at(crit, 0.1, 0.99, 6) == pytest.approx(0.1)       # only the last
+    assert at(crit, 0.1, 0.9, 4) == pytest.approx(0.1)        # event at frame 4: frame 3 only
+    assert at(crit, 0.1, 0.96, 5) == 0.0                      # frame 4 below: not recognised
+    assert at([0.95, 0.5, 0.95, 0.97], 0.05, 0.9, 4) == pytest.approx(0.1)   # a dip resets it
+    for bad in (dict(crit=[], frame_dt=0.1, threshold=0.5, event_frame=1),
+                dict(crit=[0.5], frame_dt=0.0, threshold=0.5, event_frame=1),
+                dict(crit=[0.5, 0.6], frame_dt=0.1, threshold=0.5, event_frame=3),
+                dict(crit=[0.5, 0.6], frame_dt=0.1, threshold=0.5, event_frame=0),
+                dict(crit=[float("nan"), 0.6], frame_dt=0.1, threshold=0.5, event_frame=2),
+                dict(crit=[0.5, 0.6], frame_dt=0.1, threshold=float("nan"), event_frame=2)):
+        with pytest.raises(mhc.MhcError):
+            at(**bad)

@@ -97,6 +97,78 @@ def table_one(mhc, ctx, sg, torch, steps=50):
     return rows
 
 
+def timeline_extra(mhc, ctx, sg, torch, steps=50):
+    """The risk over time (criticality per slot and its attribution) against
+    the plain path, per risk reading, on the 11-object and the Table I S2
+    scenes: whole-path step and each module's time (HIP events on the launch
+    stream); the risk module then reads the per-slot sums once. Then the
+    approach sequence (an EGO driving at a stopped vehicle, a frame every
+    100 ms until contact) as one batch, and the anticipation times read from
+    its criticality series."""
+    stream = torch.cuda.current_stream()
+    T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
+    rows = []
+    for wname, make in (("eleven_object", lambda: sg.eleven_object_scene(1)),
+                        ("table_one_s2", lambda: sg.paper_scene(5, n_co=10))):
+        for risk in (sg.RISK_EXCLUSIVE, sg.RISK_INDEPENDENT):
+            row = {"workload": wname, "risk": "exclusive" if risk == sg.RISK_EXCLUSIVE else "independent"}
+            for tl in (0, 1):
+                s = make()
+                s.risk, s.timeline = risk, tl
+                cs = mhc.CScene(s)
+                plan = mhc.mhc_plan_create(ctx, cs)
+                out, r = mhc.device_result(cs, first_hit=True, q=True)
+                for _ in range(5):
+                    mhc.mhc_plan_execute(plan, r, stream)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                for _ in range(steps):
+                    mhc.mhc_plan_execute(plan, r, stream)
+                torch.cuda.synchronize()
+                step_us = (time.perf_counter() - a) * 1e6 / steps
+                ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+                for k in range(steps):
+                    ev[k][0].record(stream)
+                    mhc.mhc_plan_execute_stages(plan, T, r, stream)
+                    ev[k][1].record(stream)
+                    mhc.mhc_plan_execute_stages(plan, C, r, stream)
+                    ev[k][2].record(stream)
+                    mhc.mhc_plan_execute_stages(plan, R, r, stream)
+                    ev[k][3].record(stream)
+                torch.cuda.synchronize()
+                mods = [sum(e[m].elapsed_time(e[m + 1]) for e in ev) * 1e3 / steps for m in range(3)]
+                plan.close()
+                key = "timeline" if tl else "plain"
+                row[key] = {"step_us": step_us, "traj_us": mods[0], "collide_us": mods[1], "risk_us": mods[2]}
+                if tl:
+                    n, H, nt = s.n_objects, s.horizon, sum(s.traj_counts())
+                    # bytes the risk module must move: the per-slot sums in,
+                    # criticality over time out (scratch + output), the
+                    # attribution and the plain outputs
+                    row["timeline"]["risk_bytes"] = 8 * (nt * n * H + 2 * nt * H + 4 * nt * n + n * H + n * n + 3 * nt)
+                    row["timeline"]["risk_gb_s"] = row["timeline"]["risk_bytes"] / (mods[2] * 1e-6) / 1e9
+            rows.append(row)
+            p_, t_ = row["plain"], row["timeline"]
+            log(f"timeline {wname} {row['risk']}: step {p_['step_us']:.1f} -> {t_['step_us']:.1f} us, collide "
+                f"{p_['collide_us']:.1f} -> {t_['collide_us']:.1f} us, risk {p_['risk_us']:.1f} -> "
+                f"{t_['risk_us']:.1f} us ({t_['risk_gb_s']:.0f} GB/s)")
+    frames, event = sg.approach_sequence(8)
+    cframes = [mhc.CScene(f) for f in frames]
+    mhc.mhc_evaluate_batch(ctx, cframes, first_hit=False, q=False)
+    lat = []
+    for _ in range(10):
+        a = time.perf_counter()
+        outs = mhc.mhc_evaluate_batch(ctx, cframes, first_hit=False, q=False)
+        lat.append((time.perf_counter() - a) * 1e3)
+    crit = [float(o["object_crit"][0]) for o in outs]
+    ant = {str(th): mhc.mhc_anticipation_time(crit, 0.1, th, event) for th in (0.5, 0.9, 0.99)}
+    appr = {"frames": len(frames), "event_frame": event, "frame_dt_s": 0.1, "batch_ms_p50": pct(lat, 50),
+            "ego_crit_last_frames": [round(c, 4) for c in crit[-6:]], "anticipation_s": ant}
+    log(f"approach sequence: {len(frames)} frames in one batch, p50 {appr['batch_ms_p50']:.2f} ms; "
+        f"anticipation time {ant} s")
+    return {"rows": rows, "approach": appr}
+
+
 def class_checks(scene):
     out = {"VV": 0, "VP": 0, "PP": 0, "VV_PIP": 0}
     objs = scene.objects
@@ -409,6 +481,7 @@ def main():
 
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
         result["table_one"] = table_one(mhc, ctx, sg, torch)
+        result["timeline"] = timeline_extra(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)

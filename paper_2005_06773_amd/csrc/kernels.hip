@@ -112,7 +112,7 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
 // longest block for large T, so it is dispatched first), x >= 1 are
 // trajectory blocks of K1_TPB trajectories, one wave each.
 // For time-resolved scenes, trajectory block c also zeroes the c-th stretch
-// of K1_TPB * n * H entries of the object's per-slot q sums.
+// of K1_TPB * W * H entries of the object's per-slot q sums.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
@@ -126,11 +126,13 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
         return;
     }
     if (o.timeline) {
-        const int64_t per = (int64_t)K1_TPB * o.n_scene_obj * o.H;
-        const int64_t total = (int64_t)o.T * o.n_scene_obj * o.H;
+        const int64_t per = (int64_t)K1_TPB * o.tl_w * o.H;
+        const int64_t total = (int64_t)o.T * o.tl_w * o.H;
         const int64_t lo = ((int64_t)blockIdx.x - 1) * per;
         const int64_t hi = min(total, lo + per);
-        for (int64_t k = lo + (int64_t)threadIdx.x; k < hi; k += WG) hist[o.hist_off + k] = 0ull;
+        // 16-byte stores: hist_off, the stretch and the total are even
+        ulonglong2 *h2 = reinterpret_cast<ulonglong2 *>(hist + o.hist_off);
+        for (int64_t k = lo / 2 + (int64_t)threadIdx.x; k < hi / 2; k += WG) h2[k] = make_ulonglong2(0ull, 0ull);
     }
     const int lane = threadIdx.x & 63;
     const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
@@ -429,8 +431,8 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
                 for (int s = 0; s < RJ; ++s)
                     if (first[r][s] >= 0) {
                         const int64_t k = first[r][s];
-                        atomicAdd(&hist[pr.ha0 + k * Ta + (ig + r * n_ig)], pb[s]);
-                        atomicAdd(&hist[pr.hb0 + k * Tb + (jg + s * n_jg)], pa[r]);
+                        atomicAdd(&hist[pr.ha0 + (k * Ta + (ig + r * n_ig)) * pr.hwa], pb[s]);
+                        atomicAdd(&hist[pr.hb0 + (k * Tb + (jg + s * n_jg)) * pr.hwb], pa[r]);
                     }
             return;
         }
@@ -613,68 +615,197 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
 //
 // For time-resolved scenes the collision kernel adds the summand of every
 // colliding trajectory pair to the sums of its first colliding slot s:
-// hist_a[b][s][i] (object a's block; consecutive i contiguous). Then, for
-// trajectory (a, i) with running sums Q_b(s) = sum_{s' <= s} hist_a[b][s'][i]
-// and no-collision factors f_b(s) = 1 - q(Q_b(s)), the combinations are taken
+// hist_a[s][i][b] (object a's block, b padded to W = the power of two >= n,
+// so the W sums of one trajectory and slot are contiguous). For trajectory
+// (a, i) with running sums Q_b(s) = sum_{s' <= s} hist_a[s'][i][b] and
+// no-collision factors f_b(s) = 1 - q(Q_b(s)), the combinations are taken
 // slot by slot, ascending b within a slot; the probability that the first
 // collision happens with b at slot s is
 //   (f_b(s-1) - f_b(s)) * prod_{b' < b} f_{b'}(s) * prod_{b' > b} f_{b'}(s-1)
-// which is the running no-collision product N (with b's old factor) divided
-// by f_b(s-1), times (f_b(s-1) - f_b(s)). Adding these up over slots gives
-// the attribution A_{a,i;b}; 1 - N after slot s is crit_{a,i}(s).
+// Adding these up over slots gives the attribution A_{a,i;b}, and
+// crit_{a,i}(s) = 1 - prod_b f_b(s).
 // ===========================================================================
 
-// K3t: grid y = object, x = chunk of 256 trajectories, a thread per
-// trajectory; reads the per-slot sums (coalesced over i), keeps running sums
-// and attributions in [b][i] scratch, writes the criticality over time as
-// [s][i] scratch (and traj_crit_t (i, s) if asked for), the attribution
-// (i, b) if asked for, and finally the total sums of every b into the
-// integer accumulators k3_crit reads.
+constexpr int K3T_SLOTS = 8;  // slots processed together: loads one group ahead, scans interleaved
+
+// A double from the lane d below (UP) or above (!UP) in the same row of 16
+// lanes (DPP row shift; lanes whose source lies outside the row get 0).
+template <int D, bool UP>
+__device__ __forceinline__ double row_shift(double x)
+{
+    constexpr int ctrl = (UP ? 0x110 : 0x100) | D;  // row_shr:D / row_shl:D
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// One step of the segmented inclusive products: lo over lanes b' <= b,
+// hi over lanes b' >= b, for every slot of the group.
+template <int D>
+__device__ __forceinline__ void scan_step_row(double (&lo)[K3T_SLOTS], double (&hi)[K3T_SLOTS], int b, int W)
+{
+#pragma unroll
+    for (int k = 0; k < K3T_SLOTS; ++k) {
+        const double tl = row_shift<D, true>(lo[k]);
+        const double th = row_shift<D, false>(hi[k]);
+        if (b >= D) lo[k] *= tl;
+        if (b + D < W) hi[k] *= th;
+    }
+}
+
+// The running product of one trajectory's factors over its slots, for one
+// risk reading (a template parameter, so the slot loop has no branch on it).
+template <int RISK>
+__device__ __forceinline__ double keep_of(unsigned long long v)
+{
+    if constexpr (RISK == RISK_EXCLUSIVE) return 1.0 - fmin((double)v * kQInvScale, 1.0);
+    else return 1.0 + expm1(-(double)v * kLInvScale);
+}
+
+template <int RISK>
+__device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigned long long *__restrict__ hist,
+                                                    unsigned long long *__restrict__ qacc, double *__restrict__ att_w,
+                                                    double *__restrict__ ct_w, double *__restrict__ traj_crit_t,
+                                                    double *__restrict__ traj_attrib, int i, int b, int W)
+{
+    const int n = o.n_scene_obj, H = o.H;
+    const int64_t T = o.T;
+    const bool valid = i < o.T && b < n;
+    const bool writer = b == W - 1 && i < o.T;
+    const int64_t slot_stride = T * W;
+    // every lane loads (padding lanes b >= n hold zeros; lanes past the last
+    // trajectory read trajectory 0 and slots past H read slot H-1), and the
+    // values that do not belong to the lane are masked: no branch per load
+    const unsigned long long *__restrict__ h = hist + o.hist_off + (int64_t)(i < o.T ? i : 0) * W + b;
+    unsigned long long Q = 0ull;
+    double f_carry = 1.0, A = 0.0;
+    double all_carry = 1.0;  // writer lane: prod_b f_b of the last slot so far
+    unsigned long long v[K3T_SLOTS];
+#pragma unroll
+    for (int k = 0; k < K3T_SLOTS; ++k) v[k] = h[(int64_t)min(k, H - 1) * slot_stride];
+    for (int s0 = 0; s0 < H; s0 += K3T_SLOTS) {
+        unsigned long long vn[K3T_SLOTS];
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) vn[k] = h[(int64_t)min(s0 + K3T_SLOTS + k, H - 1) * slot_stride];
+        bool change = false;
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) change |= valid && s0 + k < H && v[k] != 0ull;
+        if (!__any(change)) {
+            // no first hit in these slots for any trajectory of the wave: the
+            // factors, the attribution and the criticality stay as they are
+            if (writer) {
+#pragma unroll
+                for (int k = 0; k < K3T_SLOTS; ++k) {
+                    const int s = s0 + k;
+                    if (s < H) {
+                        ct_w[o.tl_traj + (int64_t)s * T + i] = 1.0 - all_carry;
+                        if (traj_crit_t) traj_crit_t[o.tl_traj + (int64_t)i * H + s] = 1.0 - all_carry;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K3T_SLOTS; ++k) v[k] = vn[k];
+            continue;
+        }
+        // factors after (g) and before (f) each slot; slots past H repeat the last
+        double g[K3T_SLOTS], f[K3T_SLOTS];
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) {
+            f[k] = k == 0 ? f_carry : g[k - 1];
+            Q += (valid && s0 + k < H) ? v[k] : 0ull;
+            g[k] = valid ? keep_of<RISK>(Q) : 1.0;
+        }
+        f_carry = g[K3T_SLOTS - 1];
+        double lo[K3T_SLOTS], hi[K3T_SLOTS];
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) {
+            lo[k] = g[k];
+            hi[k] = f[k];
+        }
+        double below[K3T_SLOTS], above[K3T_SLOTS];
+        if (W <= 16) {
+            if (W > 1) scan_step_row<1>(lo, hi, b, W);
+            if (W > 2) scan_step_row<2>(lo, hi, b, W);
+            if (W > 4) scan_step_row<4>(lo, hi, b, W);
+            if (W > 8) scan_step_row<8>(lo, hi, b, W);
+#pragma unroll
+            for (int k = 0; k < K3T_SLOTS; ++k) {
+                below[k] = row_shift<1, true>(lo[k]);
+                above[k] = row_shift<1, false>(hi[k]);
+            }
+        } else {
+            for (int d = 1; d < W; d <<= 1) {
+#pragma unroll
+                for (int k = 0; k < K3T_SLOTS; ++k) {
+                    const double tl = __shfl_up(lo[k], d, W);
+                    const double th = __shfl_down(hi[k], d, W);
+                    if (b >= d) lo[k] *= tl;
+                    if (b + d < W) hi[k] *= th;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < K3T_SLOTS; ++k) {
+                below[k] = __shfl_up(lo[k], 1, W);
+                above[k] = __shfl_down(hi[k], 1, W);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) {
+            const double bl = b > 0 ? below[k] : 1.0;      // inclusive -> exclusive
+            const double ab = b + 1 < W ? above[k] : 1.0;
+            A += (f[k] - g[k]) * bl * ab;                   // 0 past H: f == g there
+        }
+        if (writer) {  // lo at the last lane = prod_b f_b(s)
+#pragma unroll
+            for (int k = 0; k < K3T_SLOTS; ++k) {
+                const int s = s0 + k;
+                if (s < H) {
+                    ct_w[o.tl_traj + (int64_t)s * T + i] = 1.0 - lo[k];
+                    if (traj_crit_t) traj_crit_t[o.tl_traj + (int64_t)i * H + s] = 1.0 - lo[k];
+                }
+            }
+        }
+        all_carry = lo[K3T_SLOTS - 1];
+#pragma unroll
+        for (int k = 0; k < K3T_SLOTS; ++k) v[k] = vn[k];
+    }
+    if (!valid) return;
+    qacc[o.q_row + (int64_t)i * n + b] = Q;
+    att_w[o.q_row + (int64_t)b * T + i] = A;
+    if (traj_attrib) traj_attrib[o.q_row + (int64_t)i * n + b] = A;
+}
+
+// K3t: grid y = object, x = group of 4 waves; a wave takes 64 / W consecutive
+// trajectories, lane = (trajectory, b). Slots go in groups of K3T_SLOTS: the
+// lanes load the group's sums (one group ahead), form the running sums and
+// factors, and the segment of W lanes of every trajectory forms, for all
+// slots of the group at once (independent chains, so their latencies
+// overlap), the products of the factors below b (new) and above b (old):
+// DPP row shifts for W <= 16, lane permutes for W = 32, 64. Lane b then adds
+// its attribution terms; the last lane of the segment holds prod_b f_b(s).
+// Writes the criticality over time as [s][i] scratch (and traj_crit_t
+// (i, s) if asked for), the attribution as [b][i] scratch (and (i, b) if
+// asked for), and the total sums of every b into the integer accumulators
+// k3_crit reads. Timeline scenes have at most 64 objects.
 __global__ __launch_bounds__(WG) void k3_timeline(const DObj *__restrict__ objs,
                                                   const unsigned long long *__restrict__ hist,
-                                                  unsigned long long *__restrict__ qacc,
-                                                  unsigned long long *__restrict__ qrun, double *__restrict__ att_w,
+                                                  unsigned long long *__restrict__ qacc, double *__restrict__ att_w,
                                                   double *__restrict__ ct_w, double *__restrict__ traj_crit_t,
                                                   double *__restrict__ traj_attrib)
 {
     const DObj o = objs[blockIdx.y];
     if (!o.timeline) return;
-    const int i = (int)blockIdx.x * WG + (int)threadIdx.x;
-    if (i >= o.T) return;  // no barriers below
-    const int n = o.n_scene_obj, H = o.H;
-    const int64_t T = o.T;
-    const unsigned long long *__restrict__ h = hist + o.hist_off + i;   // (b, s) at (b*H + s)*T
-    unsigned long long *__restrict__ run = qrun + o.q_row + i;          // (b) at b*T
-    double *__restrict__ A = att_w + o.q_row + i;
-    for (int b = 0; b < n; ++b) {
-        run[b * T] = 0ull;
-        A[b * T] = 0.0;
-    }
-    double *__restrict__ ct = ct_w + o.tl_traj + i;                      // (s) at s*T
-    double *__restrict__ tct = traj_crit_t ? traj_crit_t + o.tl_traj + (int64_t)i * H : nullptr;
-    double N = 1.0;  // probability that no collision has happened so far
-    for (int s = 0; s < H; ++s) {
-        for (int b = 0; b < n; ++b) {
-            const unsigned long long v = h[((int64_t)b * H + s) * T];
-            if (v == 0ull) continue;
-            const unsigned long long q0 = run[b * T], q1 = q0 + v;
-            run[b * T] = q1;
-            const double f = 1.0 - q_of(o.risk, q0), g = 1.0 - q_of(o.risk, q1);
-            if (g < f) {  // then f > 0
-                const double X = N / f;
-                A[b * T] += X * (f - g);
-                N = X * g;
-            }
-        }
-        ct[(int64_t)s * T] = 1.0 - N;
-        if (tct) tct[s] = 1.0 - N;
-    }
-    unsigned long long *__restrict__ tot = qacc + o.q_row + (int64_t)i * n;
-    double *__restrict__ ta = traj_attrib ? traj_attrib + o.q_row + (int64_t)i * n : nullptr;
-    for (int b = 0; b < n; ++b) {
-        tot[b] = run[b * T];
-        if (ta) ta[b] = A[b * T];
-    }
+    const int W = o.tl_w;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int per_wave = WAVE / W;
+    const int first_i = ((int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE)) * per_wave;
+    if (first_i >= o.T) return;  // whole wave: every lane below takes part in the lane exchanges
+    const int i = first_i + lane / W;
+    const int b = lane & (W - 1);
+    if (o.risk == RISK_EXCLUSIVE)
+        timeline_trajectory<RISK_EXCLUSIVE>(o, hist, qacc, att_w, ct_w, traj_crit_t, traj_attrib, i, b, W);
+    else
+        timeline_trajectory<RISK_INDEPENDENT>(o, hist, qacc, att_w, ct_w, traj_crit_t, traj_attrib, i, b, W);
 }
 
 // Sum of a double over the 64 lanes of a wave in a fixed butterfly order.
@@ -685,33 +816,49 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// K4t: grid x = object; wave w of the workgroup takes slots s = w, w + 4, ...
-// (then collision objects b = w, w + 4, ...): lane l adds p_{a,i} times the
-// trajectory value over i = l, l + 64, ... in ascending order, and the wave
-// adds its 64 lane sums in a fixed butterfly. Every sum has a fixed order.
+// K4t: grid x = object, y = row: rows 0..H-1 are the slots (C_a(s)), rows
+// H..H+n-1 the collision objects (A_{a,b}). Thread t adds p_{a,i} times the
+// trajectory value over i = t, t + 256, ... in ascending order (loads four
+// ahead), and the workgroup adds the 256 partial sums in a fixed tree: every
+// sum has a fixed order.
 __global__ __launch_bounds__(WG) void k4_timeline(const DObj *__restrict__ objs, const double *__restrict__ p,
                                                   const double *__restrict__ ct_w, const double *__restrict__ att_w,
                                                   double *__restrict__ crit_t, double *__restrict__ attrib)
 {
+    __shared__ double red[WG];
     const DObj o = objs[blockIdx.x];
     if (!o.timeline) return;
-    const int wave = (int)(threadIdx.x / WAVE), lane = (int)(threadIdx.x & (WAVE - 1));
+    const int row = (int)blockIdx.y;
     const int n = o.n_scene_obj, H = o.H, T = o.T;
+    if (row >= H + n) return;  // whole workgroup
+    const int tid = (int)threadIdx.x;
     const double *__restrict__ pp = p + o.traj_off;
-    for (int s = wave; s < H; s += WG / WAVE) {
-        const double *__restrict__ row = ct_w + o.tl_traj + (int64_t)s * T;
-        double acc = 0.0;
-        for (int i = lane; i < T; i += WAVE) acc += pp[i] * row[i];
-        acc = wave_sum(acc);
-        if (lane == 0) crit_t[o.tl_obj + s] = acc;
+    const double *__restrict__ r =
+        row < H ? ct_w + o.tl_traj + (int64_t)row * T : att_w + o.q_row + (int64_t)(row - H) * T;
+    double acc = 0.0;
+    for (int base = 0; base < T; base += 4 * WG) {
+        double x[4], w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int idx = base + k * WG + tid;
+            x[k] = idx < T ? r[idx] : 0.0;
+            w[k] = idx < T ? pp[idx] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (base + k * WG + tid < T) acc += w[k] * x[k];
     }
-    for (int b = wave; b < n; b += WG / WAVE) {
-        const double *__restrict__ row = att_w + o.q_row + (int64_t)b * T;
-        double acc = 0.0;
-        for (int i = lane; i < T; i += WAVE) acc += pp[i] * row[i];
-        acc = wave_sum(acc);
-        if (lane == 0) attrib[o.tl_att + b] = acc;
+    red[tid] = acc;
+    __syncthreads();
+    for (int st = WG / 2; st > 0; st >>= 1) {
+        if (tid < st) red[tid] += red[tid + st];
+        __syncthreads();
     }
+    if (tid != 0) return;
+    if (row < H)
+        crit_t[o.tl_obj + row] = red[0];
+    else
+        attrib[o.tl_att + (row - H)] = red[0];
 }
 
 // ===========================================================================
@@ -793,10 +940,10 @@ hipError_t launch_risk(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
     if (L.timeline) {
-        hipLaunchKernelGGL(k3_timeline, dim3(L.k3_x, L.n_obj), dim3(WG), 0, s, L.objs, L.hist, L.qacc, L.qrun, L.att_w,
+        hipLaunchKernelGGL(k3_timeline, dim3(L.k3t_x, L.n_obj), dim3(WG), 0, s, L.objs, L.hist, L.qacc, L.att_w,
                            L.ct_w, L.traj_crit_t, L.traj_attrib);
-        hipLaunchKernelGGL(k4_timeline, dim3(L.n_obj), dim3(WG), 0, s, L.objs, L.p, L.ct_w, L.att_w, L.crit_t,
-                           L.attrib);
+        hipLaunchKernelGGL(k4_timeline, dim3(L.n_obj, L.k4t_y), dim3(WG), 0, s, L.objs, L.p, L.ct_w, L.att_w,
+                           L.crit_t, L.attrib);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

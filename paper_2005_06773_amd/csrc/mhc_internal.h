@@ -26,6 +26,7 @@ struct DObj {
     int32_t has_score, H;
     int32_t local, n_scene_obj;   // index within its scene, object count of the scene
     int32_t risk, timeline;       // RiskModel of its scene; 1: time-resolved risk
+    int32_t tl_w, pad0;           // time-resolved: lanes per trajectory, the power of two >= n_scene_obj
     int64_t traj_off;             // index of trajectory 0 in the p / traj_crit arrays
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
@@ -33,7 +34,7 @@ struct DObj {
     int64_t part_off;             // first partial sum of the risk kernel's chunks
     int64_t obj_out;              // index in the object_crit array
     // time-resolved risk (timeline scenes only)
-    int64_t hist_off;             // slot sums [b][s][i]: index of (b = 0, s = 0, i = 0)
+    int64_t hist_off;             // slot sums [s][i][b < tl_w]: index of (s = 0, i = 0, b = 0)
     int64_t tl_traj;              // [s][i] criticality over time, and traj_crit_t (i, s): index of i = 0, s = 0
     int64_t tl_obj;               // crit_t index of (this object, s = 0)
     int64_t tl_att;               // attrib index of (this object, b = 0)
@@ -60,9 +61,10 @@ struct DPair {
     int64_t qb0;                  // q index of (b, j = 0, a)
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
     int32_t timeline;             // 1: q sums go to the per-slot sums below
+    int32_t hwa, hwb;             // lanes per trajectory of a's and of b's per-slot sums
     int32_t pad1;
-    int64_t ha0;                  // slot-sum index of (a: b, s = 0, i = 0); slot s, trajectory i at + s*Ta + i
-    int64_t hb0;                  // slot-sum index of (b: a, s = 0, j = 0); + s*Tb + j
+    int64_t ha0;                  // slot-sum index of (a: s = 0, i = 0, b); slot s, trajectory i at + (s*Ta + i)*hwa
+    int64_t hb0;                  // slot-sum index of (b: s = 0, j = 0, a); + (s*Tb + j)*hwb
 };
 
 // A run of collision work for one wave: n_units consecutive units of a pair.
@@ -131,8 +133,8 @@ struct Launch {
     unsigned int *done;           // per object: risk chunks finished
     // time-resolved risk (null / 0 when no scene of the launch asks for it)
     int timeline;
+    int k3t_x, k4t_y;             // time-resolved kernel grids: 4-wave groups of the largest object; rows
     unsigned long long *hist;     // per-slot integer q sums
-    unsigned long long *qrun;     // running sums [b][i] per object
     double *att_w;                // attribution [b][i] per object
     double *ct_w;                 // criticality over time [s][i] per object
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;

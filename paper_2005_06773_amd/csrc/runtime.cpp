@@ -70,6 +70,8 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
     if (s->risk != MHC_RISK_EXCLUSIVE && s->risk != MHC_RISK_INDEPENDENT)
         return fail("risk must be 0 or 1 (got %d)", s->risk);
     if (s->timeline != 0 && s->timeline != 1) return fail("timeline must be 0 or 1 (got %d)", s->timeline);
+    if (s->timeline && s->n_objects > kMaxTimelineObjects)
+        return fail("a time-resolved scene has at most %d objects", kMaxTimelineObjects);
     for (int a = 0; a < s->n_objects; ++a) {
         const mhc_object &o = s->objects[a];
         if (o.kind != MHC_VEHICLE && o.kind != MHC_PEDESTRIAN) return fail("object %d: kind must be 0 or 1", a);
@@ -175,11 +177,16 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.risk = s.risk;
             d.timeline = s.timeline;
             if (s.timeline) {
+                int W = 1;
+                while (W < n) W <<= 1;
+                d.tl_w = W;
                 d.hist_off = L.n_hist;
                 d.tl_traj = L.n_tl_traj;
                 d.tl_obj = L.n_tl_obj;
                 d.tl_att = L.n_tl_att;
-                L.n_hist += (int64_t)n * s.horizon * d.T;
+                L.n_hist += (int64_t)W * s.horizon * d.T;
+                L.k3t_x = std::max<int64_t>(L.k3t_x, ((int64_t)d.T * W + WG - 1) / WG);
+                L.k4t_y = std::max(L.k4t_y, s.horizon + n);
                 L.n_tl_traj += (int64_t)s.horizon * d.T;
                 L.n_tl_obj += s.horizon;
                 L.n_tl_att += n;
@@ -226,8 +233,10 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             pr.pb_off = L.objs[obj_base + b].traj_off;
             pr.timeline = s.timeline;
             if (s.timeline) {
-                pr.ha0 = L.objs[obj_base + a].hist_off + (int64_t)b * s.horizon * pr.Ta;
-                pr.hb0 = L.objs[obj_base + b].hist_off + (int64_t)a * s.horizon * pr.Tb;
+                pr.hwa = L.objs[obj_base + a].tl_w;
+                pr.hwb = L.objs[obj_base + b].tl_w;
+                pr.ha0 = L.objs[obj_base + a].hist_off + b;
+                pr.hb0 = L.objs[obj_base + b].hist_off + a;
             }
             L.pairs.push_back(pr);
             hoff += (int64_t)pr.Ta * pr.Tb;
@@ -389,7 +398,6 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_oc = put((size_t)L.n_obj * sizeof(double));
     const size_t tq = L.timeline ? (size_t)L.n_q : 0;
     L.o_hist = put((size_t)L.n_hist * sizeof(unsigned long long));
-    L.o_qrun = put(tq * sizeof(unsigned long long));
     L.o_attw = put(tq * sizeof(double));
     L.o_ctw = put((size_t)L.n_tl_traj * sizeof(double));
     L.o_ct = put((size_t)L.n_tl_obj * sizeof(double));
@@ -471,7 +479,6 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.timeline = L.timeline ? 1 : 0;
     if (L.timeline) {
         X.hist = reinterpret_cast<unsigned long long *>(base + L.o_hist);
-        X.qrun = reinterpret_cast<unsigned long long *>(base + L.o_qrun);
         X.att_w = reinterpret_cast<double *>(base + L.o_attw);
         X.ct_w = reinterpret_cast<double *>(base + L.o_ctw);
         X.crit_t = reinterpret_cast<double *>(base + L.o_ct);
@@ -497,6 +504,8 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.n_work = (int)L.work.size();
     X.k1_x = L.k1_x;
     X.k3_x = L.k3_x;
+    X.k3t_x = (int)L.k3t_x;
+    X.k4t_y = L.k4t_y;
     X.variant = L.variant;
     X.pip = L.pip ? 1 : 0;
     X.n_bins = (int)L.bins.size() - 1;

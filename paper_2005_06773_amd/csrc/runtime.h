@@ -14,6 +14,7 @@
 namespace mhc {
 
 constexpr int kMaxObjects = 4096;
+constexpr int kMaxTimelineObjects = 64;   // one lane per collision object in the time-resolved risk kernel
 constexpr int64_t kMaxObjectsPerLaunch = 65535;  // trajectory kernel grid y
 constexpr int64_t kMaxTraj = 1 << 15;     // trajectories per object (T_a*T_b < 2^31)
 constexpr int64_t kMaxPosesPerObject = int64_t(1) << 27;  // pose block < 2 GiB (32-bit buffer offsets)
@@ -32,7 +33,7 @@ struct SceneExt {
 // [scene image: tables uploaded in one copy][poses][p * 2^62][integer q sums][per-object counters]
 // [p][first hits][q][traj crit][object crit]
 // and, when a scene asks for the risk over time:
-// [per-slot q sums][running sums][attribution scratch][criticality-over-time scratch]
+// [per-slot q sums][attribution scratch][criticality-over-time scratch]
 // [crit_t][traj_crit_t][attrib][traj_attrib]
 struct Layout {
     std::vector<DObj> objs;
@@ -47,10 +48,12 @@ struct Layout {
     int64_t n_part = 0;           // risk kernel partial sums (chunks over all objects)
     bool timeline = false;        // some scene asks for the risk over time
     int64_t n_hist = 0, n_tl_traj = 0, n_tl_obj = 0, n_tl_att = 0;
+    int64_t k3t_x = 0;            // time-resolved risk kernel grid x (4-wave groups of the largest object)
+    int k4t_y = 0;                // time-resolved reduction grid y (rows: slots + objects)
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, image_bytes = 0;
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
-    size_t o_hist = 0, o_qrun = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
+    size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
     bool pip = false;             // some pair uses the point-in-polygon test

@@ -139,9 +139,12 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     bytes += align256((n_traj / WG + n) * 8) + align256(n * 4);         // risk partials and counters
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);
     if (s->timeline) {
-        // per-slot sums, running sums, attribution scratch and output, the
-        // criticality over time (scratch and output), crit_t and attrib
-        bytes += align256((size_t)n_q * s->horizon * 8) + align256(n_q * 8) * 3;
+        // per-slot sums (W >= n lanes per trajectory), attribution scratch
+        // and output, the criticality over time (scratch and output), crit_t
+        // and attrib
+        int64_t W = 1;
+        while (W < n) W <<= 1;
+        bytes += align256((size_t)n_traj * W * s->horizon * 8) + align256(n_q * 8) * 2;
         bytes += align256((size_t)n_traj * s->horizon * 8) * 2 + align256((size_t)n * s->horizon * 8) +
                  align256((size_t)n * n * 8);
     }

@@ -133,6 +133,8 @@ def _bad_scenes():
     s = base(); s.overlap = 2; out["bad_overlap_mode"] = s
     s = base(); s.risk = 2; out["bad_risk_reading"] = s
     s = base(); s.timeline = 3; out["bad_timeline_flag"] = s
+    s = base(); s.timeline = 1; s.objects = [s.objects[k % 2] for k in range(65)]
+    out["timeline_with_65_objects"] = s
     s = base(); s.overlap = sg.OVERLAP_PIP
     s.objects[1] = sg.SceneObject(sg.PEDESTRIAN, 1, 0, 0, 1, 0, 0, 0.3, np.array([1.0]), np.array([0.0]))
     out["pip_mode_with_a_pedestrian"] = s
@@ -165,15 +167,16 @@ def test_create_without_gpu_reports_device_error(mhc):
 
 
 def test_timeline_workspace_holds_the_time_resolved_arrays(mhc):
-    """A time-resolved scene needs the per-slot sums (n_traj * n * H
-    integers), the criticality over time (twice n_traj * H: scratch and
-    output) and the attribution on top of the plain workspace."""
+    """A time-resolved scene needs the per-slot sums (n_traj * W * H
+    integers, W the power of two >= n), the criticality over time (twice
+    n_traj * H: scratch and output) and the attribution on top of the plain
+    workspace."""
     s = sg.eleven_object_scene(1)
     plain = mhc.mhc_query_sizes(s)["device_bytes"]
     s.timeline = 1
     tl = mhc.mhc_query_sizes(s)["device_bytes"]
     n, H, nt = s.n_objects, s.horizon, sum(s.traj_counts())
-    assert tl - plain >= 8 * (nt * n * H + 2 * nt * H + 3 * nt * n + n * H + n * n)
+    assert tl - plain >= 8 * (nt * 16 * H + 2 * nt * H + 2 * nt * n + n * H + n * n)
     s.risk = sg.RISK_INDEPENDENT
     assert mhc.mhc_query_sizes(s)["device_bytes"] == tl
 

@@ -82,7 +82,11 @@ def lib():
         L.orc_margin_pip.restype = D
         L.orc_margin_rect_rect_pip.argtypes = [D] * 10
         L.orc_margin_rect_rect_pip.restype = D
-        L.orc_first_hits.argtypes = [I, I, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
+        L.orc_first_hits.argtypes = [I, I, P, P, P, P, P, P, P, P, I, P, P, P, I, P, P, D, I, P, P, P, P]
+        L.orc_margin_poly_poly.argtypes = [I, P, P, I, P, P]
+        L.orc_margin_poly_poly.restype = D
+        L.orc_margin_poly_circle.argtypes = [I, P, P, D, D, D]
+        L.orc_margin_poly_circle.restype = D
         L.orc_risk.argtypes = [I, I, P, P, I, P, P, P, P, P, P]
         L.orc_risk_timeline.argtypes = [I, I, P, P, I, I, P, P, P, P, P, P, P]
         L.orc_point_in_polygon.argtypes = [D, D, I, P, P]
@@ -150,6 +154,27 @@ def margin_pip(polyP: np.ndarray, polyQ: np.ndarray) -> float:
     px, py = np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1])
     qx, qy = np.ascontiguousarray(Q[:, 0]), np.ascontiguousarray(Q[:, 1])
     return lib().orc_margin_pip(len(px), _ptr(px), _ptr(py), len(qx), _ptr(qx), _ptr(qy))
+
+
+#: most vertices of a vehicle outline
+MAX_VERTICES = 8
+
+
+def margin_poly_poly(polyP: np.ndarray, polyQ: np.ndarray) -> float:
+    """Separating-axis margin of two convex CCW polygons [n, 2] (world
+    coordinates): the largest gap along a unit edge normal, <= 0 iff they
+    intersect."""
+    P = np.ascontiguousarray(polyP, np.float64)
+    Q = np.ascontiguousarray(polyQ, np.float64)
+    px, py = np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1])
+    qx, qy = np.ascontiguousarray(Q[:, 0]), np.ascontiguousarray(Q[:, 1])
+    return lib().orc_margin_poly_poly(len(px), _ptr(px), _ptr(py), len(qx), _ptr(qx), _ptr(qy))
+
+
+def margin_poly_circle(poly: np.ndarray, c, r: float) -> float:
+    P = np.ascontiguousarray(poly, np.float64)
+    px, py = np.ascontiguousarray(P[:, 0]), np.ascontiguousarray(P[:, 1])
+    return lib().orc_margin_poly_circle(len(px), _ptr(px), _ptr(py), float(c[0]), float(c[1]), float(r))
 
 
 def margin_rect_rect_pip(P, Q) -> float:
@@ -236,6 +261,26 @@ def scene_arrays(scene):
     return kind, length, width, radius, T
 
 
+def outline_arrays(scene):
+    """Per object: vertex count (0 = no outline) and the body-frame outline
+    padded to MAX_VERTICES, or (None, None, None) when no object has one."""
+    outs = [getattr(o, "outline", None) for o in scene.objects]
+    if all(o is None for o in outs):
+        return None, None, None
+    n = len(outs)
+    nv = np.zeros(n, np.int32)
+    ox = np.zeros((n, MAX_VERTICES), np.float64)
+    oy = np.zeros((n, MAX_VERTICES), np.float64)
+    for a, o in enumerate(outs):
+        if o is None:
+            continue
+        o = np.asarray(o, np.float64)
+        nv[a] = len(o)
+        ox[a, :len(o)] = o[:, 0]
+        oy[a, :len(o)] = o[:, 1]
+    return nv, ox, oy
+
+
 def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: float = EPS,
              threads: int = 0, masks: bool = True, risk: bool = True) -> OracleResult:
     """Run the whole path on ``scene`` (a ``scenegen.Scene``).
@@ -273,7 +318,9 @@ def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: 
     loose = np.empty((entries, W), np.uint64) if masks else None
     strict = np.empty((entries, W), np.uint64) if masks else None
     overlap = int(getattr(scene, "overlap", OVERLAP_EXACT))
-    _check(lib().orc_first_hits(overlap, n, _ptr(kind), _ptr(length), _ptr(width), _ptr(radius), _ptr(T), H,
+    nv, ox, oy = outline_arrays(scene)
+    _check(lib().orc_first_hits(overlap, n, _ptr(kind), _ptr(length), _ptr(width), _ptr(radius),
+                                _ptr(nv), _ptr(ox), _ptr(oy), _ptr(T), H,
                                 _ptr(px), _ptr(py), _ptr(ppsi), len(pa), _ptr(pa), _ptr(pb),
                                 float(eps), int(threads), _ptr(k64), _ptr(kst),
                                 _ptr(loose), _ptr(strict)), "first_hits")

@@ -27,11 +27,12 @@
  *     acceleration of step n acts within step n (no one-step lag) and the
  *     speed is clamped at zero, the acceleration that step being the one that
  *     stops the vehicle;
- *   - vehicles are rectangles, pedestrians circles; touching counts as a
- *     collision (margin <= 0). The default overlap test is the exact
- *     intersection of the closed shapes; the paper's point-in-polygon test,
- *     run both ways, is the second mode (rectangles only), with a vertex on
- *     the other polygon's boundary counting as inside;
+ *   - vehicles are rectangles, or convex polygons when given an outline (at
+ *     most 8 vertices in the body frame), pedestrians circles; touching
+ *     counts as a collision (margin <= 0). The default overlap test is the
+ *     exact intersection of the closed shapes; the paper's point-in-polygon
+ *     test, run both ways, is the second mode (vehicles only), with a vertex
+ *     on the other polygon's boundary counting as inside;
  *   - poses are predicted for n = 1..H and stored at slot n-1; the measured
  *     state (n = 0) is never checked;
  *   - the chronological scaling is read as: collision objects independent of
@@ -300,17 +301,121 @@ double orc_margin_rect_rect_pip(double xP, double yP, double psiP, double LP, do
     return orc_margin_pip(4, px, py, 4, qx, qy);
 }
 
-static double margin_at(int overlap, int kindP, double xP, double yP, double psiP, double LP, double WP, double rP,
-                        int kindQ, double xQ, double yQ, double psiQ, double LQ, double WQ, double rQ)
+/* ------------------------------------------------------------------------ */
+/* General convex polygons (Sec. IV-C.1: "as complex as necessary"). A      */
+/* vehicle may carry an outline: the vertices of a convex polygon in its     */
+/* body frame (x along the heading, y to the left), counter-clockwise, at    */
+/* most ORC_MAX_VERTICES. Polygons below are in world coordinates, CCW.      */
+/* ------------------------------------------------------------------------ */
+#define ORC_MAX_VERTICES 8
+
+/* Vertices of an outline placed at pose (x, y, psi). */
+static void place_outline(int n, const double *bx, const double *by, double x, double y, double psi,
+                          double *wx, double *wy)
 {
-    if (overlap == ORC_OVERLAP_PIP)
-        return orc_margin_rect_rect_pip(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
-    if (kindP == ORC_VEHICLE && kindQ == ORC_VEHICLE)
-        return orc_margin_rect_rect(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
-    if (kindP == ORC_VEHICLE)
-        return orc_margin_rect_circle(xP, yP, psiP, LP, WP, xQ, yQ, rQ);
-    if (kindQ == ORC_VEHICLE)
-        return orc_margin_rect_circle(xQ, yQ, psiQ, LQ, WQ, xP, yP, rP);
+    double c = cos(psi), s = sin(psi);
+    for (int k = 0; k < n; ++k) {
+        wx[k] = x + c * bx[k] - s * by[k];
+        wy[k] = y + s * bx[k] + c * by[k];
+    }
+}
+
+/* Separating axis theorem for two convex polygons: they are disjoint iff
+ * the other polygon lies strictly outside the supporting line of some edge
+ * of one of them. With unit outward edge normals n_e and edge starts a_e the
+ * margin is max over all edges e of min over the other polygon's vertices v
+ * of n_e . (v - a_e): the largest gap along an edge normal; <= 0 exactly when
+ * the closed polygons intersect. For rectangles it is orc_margin_rect_rect. */
+static double edge_gap(int nP, const double *px, const double *py, int nQ, const double *qx, const double *qy)
+{
+    double best = -INFINITY;
+    for (int e = 0; e < nP; ++e) {
+        int f = (e + 1) % nP;
+        double ex = px[f] - px[e], ey = py[f] - py[e];
+        double len = hypot(ex, ey);
+        double nx = ey / len, ny = -ex / len;   /* outward for a CCW polygon */
+        double lo = INFINITY;
+        for (int k = 0; k < nQ; ++k) {
+            double v = nx * (qx[k] - px[e]) + ny * (qy[k] - py[e]);
+            if (v < lo) lo = v;
+        }
+        if (lo > best) best = lo;
+    }
+    return best;
+}
+
+double orc_margin_poly_poly(int nP, const double *px, const double *py, int nQ, const double *qx, const double *qy)
+{
+    return fmax(edge_gap(nP, px, py, nQ, qx, qy), edge_gap(nQ, qx, qy, nP, px, py));
+}
+
+/* Convex polygon P and circle (c, r): the distance from c to the closed
+ * polygon (0 inside) minus r. */
+double orc_margin_poly_circle(int nP, const double *px, const double *py, double cx, double cy, double r)
+{
+    int inside = 1;
+    double d = INFINITY;
+    for (int e = 0; e < nP; ++e) {
+        int f = (e + 1) % nP;
+        double ex = px[f] - px[e], ey = py[f] - py[e];
+        if (ex * (cy - py[e]) - ey * (cx - px[e]) < 0.0) inside = 0;   /* right of a CCW edge */
+        double de = point_segment_distance(cx, cy, px[e], py[e], px[f], py[f]);
+        if (de < d) d = de;
+    }
+    return (inside ? 0.0 : d) - r;
+}
+
+/* Shape of an object at one pose, as a polygon (vehicles) or a circle. */
+typedef struct {
+    int kind, n;                      /* n > 0: polygon of n vertices */
+    double x[ORC_MAX_VERTICES], y[ORC_MAX_VERTICES];
+    double cx, cy, r;
+} orc_shape;
+
+static void shape_at(orc_shape *sh, int kind, int nv, const double *bx, const double *by, double L, double W,
+                     double r, double x, double y, double psi)
+{
+    sh->kind = kind;
+    sh->cx = x;
+    sh->cy = y;
+    sh->r = r;
+    sh->n = 0;
+    if (kind != ORC_VEHICLE) return;
+    if (nv > 0) {
+        sh->n = nv;
+        place_outline(nv, bx, by, x, y, psi, sh->x, sh->y);
+    } else {
+        sh->n = 4;
+        rect_corners(x, y, psi, L, W, sh->x, sh->y);
+    }
+}
+
+static double margin_at(int overlap, int kindP, double xP, double yP, double psiP, double LP, double WP, double rP,
+                        int nvP, const double *bxP, const double *byP,
+                        int kindQ, double xQ, double yQ, double psiQ, double LQ, double WQ, double rQ,
+                        int nvQ, const double *bxQ, const double *byQ)
+{
+    if (nvP == 0 && nvQ == 0) {
+        /* rectangles and circles */
+        if (overlap == ORC_OVERLAP_PIP)
+            return orc_margin_rect_rect_pip(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
+        if (kindP == ORC_VEHICLE && kindQ == ORC_VEHICLE)
+            return orc_margin_rect_rect(xP, yP, psiP, LP, WP, xQ, yQ, psiQ, LQ, WQ);
+        if (kindP == ORC_VEHICLE)
+            return orc_margin_rect_circle(xP, yP, psiP, LP, WP, xQ, yQ, rQ);
+        if (kindQ == ORC_VEHICLE)
+            return orc_margin_rect_circle(xQ, yQ, psiQ, LQ, WQ, xP, yP, rP);
+        return orc_margin_circle_circle(xP, yP, rP, xQ, yQ, rQ);
+    }
+    /* at least one outline: every vehicle is a polygon (a rectangle by its
+     * four corners) */
+    orc_shape P, Q;
+    shape_at(&P, kindP, nvP, bxP, byP, LP, WP, rP, xP, yP, psiP);
+    shape_at(&Q, kindQ, nvQ, bxQ, byQ, LQ, WQ, rQ, xQ, yQ, psiQ);
+    if (overlap == ORC_OVERLAP_PIP) return orc_margin_pip(P.n, P.x, P.y, Q.n, Q.x, Q.y);
+    if (P.n && Q.n) return orc_margin_poly_poly(P.n, P.x, P.y, Q.n, Q.x, Q.y);
+    if (P.n) return orc_margin_poly_circle(P.n, P.x, P.y, Q.cx, Q.cy, Q.r);
+    if (Q.n) return orc_margin_poly_circle(Q.n, Q.x, Q.y, P.cx, P.cy, P.r);
     return orc_margin_circle_circle(xP, yP, rP, xQ, yQ, rQ);
 }
 
@@ -360,11 +465,15 @@ int64_t orc_count_combinations(int n_objects, const int32_t *T, int ego_only)
 /*   kstrict[e] = min{ t : m(t) <= -eps }, else -1                           */
 /*   loose[e*W + t/64]  bit t%64 set iff m(t) <= +eps   (W = ceil(H/64))    */
 /*   strict[e*W + t/64] bit t%64 set iff m(t) <= -eps                       */
+/* Vehicle a with n_vertices[a] > 0 has the outline (outline_x, outline_y)   */
+/* [a * 8 ...] (body frame, CCW) instead of its rectangle; n_vertices may be */
+/* NULL (no outlines).                                                        */
 /* Any output pointer may be NULL. eps is the tolerance band within which an */
 /* FP32 evaluation of the same test may legitimately decide either way.      */
 /* ------------------------------------------------------------------------ */
 int orc_first_hits(int overlap, int n_objects, const int32_t *kind, const double *length, const double *width,
-                   const double *radius, const int32_t *T, int H,
+                   const double *radius, const int32_t *n_vertices, const double *outline_x,
+                   const double *outline_y, const int32_t *T, int H,
                    const double *px, const double *py, const double *ppsi,
                    int n_pairs, const int32_t *pair_a, const int32_t *pair_b,
                    double eps, int threads,
@@ -372,9 +481,13 @@ int orc_first_hits(int overlap, int n_objects, const int32_t *kind, const double
 {
     if (n_objects < 1 || H < 1 || n_pairs < 0) return ORC_EINVAL;
     if (overlap != ORC_OVERLAP_EXACT && overlap != ORC_OVERLAP_PIP) return ORC_EINVAL;
-    if (overlap == ORC_OVERLAP_PIP)          /* polygons: rectangles only */
+    if (overlap == ORC_OVERLAP_PIP)          /* polygons: vehicles only */
         for (int a = 0; a < n_objects; ++a)
             if (kind[a] != ORC_VEHICLE) return ORC_EINVAL;
+    if (n_vertices)
+        for (int a = 0; a < n_objects; ++a)
+            if (n_vertices[a] < 0 || n_vertices[a] > ORC_MAX_VERTICES || (n_vertices[a] && kind[a] != ORC_VEHICLE))
+                return ORC_EINVAL;
     int W = (H + 63) / 64;
     int64_t *obj_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_objects + 1));
     int64_t *pair_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_pairs + 1));
@@ -414,8 +527,11 @@ int orc_first_hits(int overlap, int n_objects, const int32_t *kind, const double
             for (int t = 0; t < H; ++t) {
                 size_t ia = (size_t)(obj_off[a] + (int64_t)t * Ta + i);
                 size_t ib = (size_t)(obj_off[b] + (int64_t)t * Tb + j);
+                int nva = n_vertices ? n_vertices[a] : 0, nvb = n_vertices ? n_vertices[b] : 0;
                 double m = margin_at(overlap, kind[a], px[ia], py[ia], ppsi[ia], length[a], width[a], radius[a],
-                                     kind[b], px[ib], py[ib], ppsi[ib], length[b], width[b], radius[b]);
+                                     nva, outline_x + a * ORC_MAX_VERTICES, outline_y + a * ORC_MAX_VERTICES,
+                                     kind[b], px[ib], py[ib], ppsi[ib], length[b], width[b], radius[b],
+                                     nvb, outline_x + b * ORC_MAX_VERTICES, outline_y + b * ORC_MAX_VERTICES);
                 if (m <= 0.0 && first < 0) first = t;
                 if (m <= -eps && first_strict < 0) first_strict = t;
                 if (loose && m <= eps) loose[e * W + t / 64] |= (uint64_t)1 << (t % 64);

@@ -53,6 +53,7 @@ class SceneObject:
     u: np.ndarray = None  # vehicles: accelerations; pedestrians: speeds
     w: np.ndarray = None  # vehicles: yaw rates;     pedestrians: heading offsets
     score: Optional[np.ndarray] = None  # n_u*n_w non-negative, index k*n_w+l
+    outline: Optional[np.ndarray] = None  # vehicles: [k, 2] convex CCW polygon in the body frame (3 <= k <= 8)
 
     @property
     def n_traj(self) -> int:
@@ -276,6 +277,54 @@ def paper_scene(seed: int = 5, n_co: int = 10, n_acc: int = 6, overlap: int = OV
         objs.append(SceneObject(VEHICLE, float(x), float(y), float(h), float(v), 4.5 * lf, 1.8 * wf, 0.0,
                                 u, w_co, vehicle_scores(u, w_co)))
     return Scene(objs, 100, 0.02, pairs=PAIRS_EGO, overlap=overlap)
+
+
+def car_outline(length: float, width: float, chamfer: float = 0.35) -> np.ndarray:
+    """Octagonal footprint of a car: the length x width rectangle (centred on
+    the pose, x along the heading) with its corners cut by `chamfer` metres
+    along both sides, counter-clockwise."""
+    l, w, c = length / 2.0, width / 2.0, chamfer
+    return np.array([[l, -w + c], [l, w - c], [l - c, w], [-l + c, w],
+                     [-l, w - c], [-l, -w + c], [-l + c, -w], [l - c, -w]], np.float64)
+
+
+def random_convex_outline(rng, k: int, radius: float = 2.0, stretch: float = 2.0) -> np.ndarray:
+    """A random strictly convex polygon of k vertices, counter-clockwise,
+    around the origin: k sorted angles with gaps in [0.5, 1.5] x 2 pi / k on
+    an ellipse of semi-axes radius*stretch x radius, drawn again until every
+    interior angle is at least 45 degrees."""
+    while True:
+        gaps = rng.uniform(0.5, 1.5, k)
+        ang = np.cumsum(gaps) / gaps.sum() * 2 * math.pi + rng.uniform(0, 2 * math.pi)
+        pts = np.stack([radius * stretch * np.cos(ang), radius * np.sin(ang)], axis=1)
+        pts = pts - pts.mean(axis=0) * rng.uniform(0.0, 0.5)
+        if outline_ok(pts):
+            return pts
+
+
+def outline_ok(poly: np.ndarray, min_angle_deg: float = 45.0) -> bool:
+    """Strictly convex, counter-clockwise, interior angles >= min_angle_deg."""
+    k = len(poly)
+    for e in range(k):
+        a, b, c = poly[e - 1], poly[e], poly[(e + 1) % k]
+        u, v = a - b, c - b
+        if (b[0] - a[0]) * (c[1] - b[1]) - (b[1] - a[1]) * (c[0] - b[0]) <= 0:
+            return False
+        cosang = np.dot(u, v) / (np.linalg.norm(u) * np.linalg.norm(v))
+        if math.degrees(math.acos(max(-1.0, min(1.0, cosang)))) < min_angle_deg:
+            return False
+    return True
+
+
+def polygon_scene(seed: int = 9, horizon: int = 30) -> Scene:
+    """The 11-object scene with every vehicle given the octagonal outline of a
+    car (corners chamfered 0.35 m): vehicle-vehicle pairs become polygon
+    pairs (8 x 8 edges) and vehicle-pedestrian pairs polygon-circle pairs."""
+    s = eleven_object_scene(seed, horizon)
+    for o in s.objects:
+        if o.kind == VEHICLE:
+            o.outline = car_outline(o.length, o.width)
+    return s
 
 
 def approach_sequence(seed: int = 8, frame_dt: float = 0.1, horizon: int = 30, dt: float = 0.1,

@@ -385,8 +385,14 @@ static void shape_at(orc_shape *sh, int kind, int nv, const double *bx, const do
         sh->n = nv;
         place_outline(nv, bx, by, x, y, psi, sh->x, sh->y);
     } else {
+        /* rect_corners lists the corners clockwise; polygons here are CCW */
+        double cx[4], cy[4];
+        rect_corners(x, y, psi, L, W, cx, cy);
         sh->n = 4;
-        rect_corners(x, y, psi, L, W, sh->x, sh->y);
+        for (int k = 0; k < 4; ++k) {
+            sh->x[k] = cx[3 - k];
+            sh->y[k] = cy[3 - k];
+        }
     }
 }
 

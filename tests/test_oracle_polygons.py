@@ -143,6 +143,41 @@ def test_outline_placement_matches_the_rectangle():
     assert np.array_equal(ref.k64, oracle.evaluate(s, masks=False).k64)
 
 
+def test_one_outline_against_rectangles_matches_exact_clipping():
+    """Only the EGO has an outline; the other vehicles are rectangles turned
+    into polygons by the oracle. At sampled slots the oracle's first hits
+    agree with exact rational clipping of the placed shapes."""
+    from tests.exact_geometry import convex_intersect, to_frac, rect_corners_np
+    s = sg.eleven_object_scene(6)
+    s.objects = s.objects[:6]
+    s.objects[0].outline = sg.car_outline(s.objects[0].length, s.objects[0].width, 0.5)
+    r = oracle.evaluate(s, masks=False, threads=8)
+    H, dt = s.horizon, s.dt
+    T = s.traj_counts()
+    xa, ya, pa = oracle.trajectories(s.objects[0], H, dt)
+    rng = np.random.default_rng(7)
+    checked = hits = 0
+    for p, (a, b) in enumerate(zip(r.pair_a, r.pair_b)):
+        if a != 0:
+            continue
+        xb, yb, pb = oracle.trajectories(s.objects[b], H, dt)
+        blk = r.k64[r.pair_off[p]:r.pair_off[p + 1]].reshape(T[0], T[b])
+        cand = list(zip(*np.nonzero(blk >= 0)))[:40] + [tuple(x) for x in rng.integers(0, [T[0], T[b]], (40, 2))]
+        for i, j in cand:
+            k = blk[i, j]
+            slots = [k] if k >= 0 else []
+            slots += [t for t in (0, H // 2, H - 1) if k < 0 or t < k]
+            for t in slots:
+                P = place(s.objects[0].outline, xa[t, i], ya[t, i], pa[t, i])
+                Q = rect_corners_np(xb[t, j], yb[t, j], pb[t, j], s.objects[b].length, s.objects[b].width)
+                m = oracle.margin_poly_poly(P, Q)
+                if abs(m) > 1e-9:
+                    assert convex_intersect(to_frac(P), to_frac(Q)) == (t == k), (a, b, i, j, t, k)
+                    checked += 1
+                    hits += t == k
+    assert checked > 300 and hits > 20
+
+
 def test_head_on_diamonds_closed_form():
     """Two diamond outlines (tips a1, a2 along the heading) driving at each
     other on one line touch tip to tip: n* = ceil((D - a1 - a2) / ((v1+v2) tau)),

@@ -83,15 +83,26 @@ enum { MHC_RISK_EXCLUSIVE = 0, MHC_RISK_INDEPENDENT = 1 };
  * yaw rate w[l]; the speed is clamped at 0. Pedestrians are circles of radius
  * `radius` walking at constant speed u[k] along heading + w[l] (Sec. IV-B.3).
  * Trajectory i = k*n_w + l. `score` holds n_u*n_w non-negative scores that are
- * L1-normalised into probabilities (Sec. IV-D.1); NULL means uniform. */
+ * L1-normalised into probabilities (Sec. IV-D.1); NULL means uniform.
+ * A vehicle may instead be a general convex polygon (Sec. IV-C.1: the
+ * polygons can be as complex as necessary): `vertices` holds n_vertices
+ * (x, y) pairs in the body frame (x along the heading, y to the left, origin
+ * at the tracked position), 3 <= n_vertices <= MHC_MAX_VERTICES, strictly
+ * convex, counter-clockwise, every interior angle at least 45 degrees;
+ * length and width are then ignored. A pair with such an outline is tested
+ * polygon against polygon (a rectangle by its four corners) or polygon
+ * against circle, in either overlap mode. */
+enum { MHC_MAX_VERTICES = 8 };
 typedef struct {
     int32_t kind;                 /* MHC_VEHICLE or MHC_PEDESTRIAN */
     double x, y, heading, speed;  /* measured state at time 0; speed >= 0 */
-    double length, width;         /* vehicles: full extents > 0 (ignored for pedestrians) */
+    double length, width;         /* vehicles without an outline: full extents > 0 */
     double radius;                /* pedestrians: > 0 (ignored for vehicles) */
     int32_t n_u, n_w;             /* grid sizes, >= 1 each */
     const double *u, *w;          /* n_u and n_w finite control values */
     const double *score;          /* n_u*n_w scores or NULL */
+    int32_t n_vertices;           /* 0 (rectangle / circle) or 3..MHC_MAX_VERTICES (vehicles) */
+    const double *vertices;       /* 2*n_vertices body-frame coordinates x0, y0, x1, y1, ... */
 } mhc_object;
 
 typedef struct {

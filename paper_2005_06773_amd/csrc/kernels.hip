@@ -309,6 +309,124 @@ struct CheckPP {
     }
 };
 
+// General convex polygons (vehicle outlines, Sec. IV-C.1: as complex as
+// necessary). Q's vertices in P's frame are c + v_x (C, S) + v_y (-S, C) with
+// c = (d.u_P, d.v_P); P's in Q's frame are c' + v_x (C, -S) + v_y (S, C)
+// with c' = (-d.u_Q, -d.v_Q). With the unit outward edge normals n_e and
+// offsets h_e of a polygon, a point x is inside iff n_e.x <= h_e for all e.
+//   separating axes: disjoint iff for some edge of either polygon every
+//     vertex of the other has n_e.x > h_e;
+//   point-in-polygon (the paper's test, both ways): a hit iff some vertex of
+//     one has n_e.x <= h_e for every edge of the other.
+// Both read the same vertex-edge values; loops are unrolled to the maximum
+// vertex count with uniform guards, so decisions stay in lane masks.
+template <bool PIPMODE>
+struct CheckGG {
+    const DPoly *__restrict__ P, *__restrict__ Q;
+    __device__ __forceinline__ bool operator()(const float4 a, const float4 b) const
+    {
+        const float dx = b.x - a.x;
+        const float dy = b.y - a.y;
+        const float C = fmaf(a.z, b.z, a.w * b.w);       // u_P . u_Q
+        const float S = fmaf(a.z, b.w, -(a.w * b.z));    // v_P . u_Q
+        const float lam = fmaf(dx, a.z, dy * a.w);       // d . u_P
+        const float mu = fmaf(dy, a.z, -(dx * a.w));     // d . v_P
+        const float lam2 = -fmaf(dx, b.z, dy * b.w);     // -d . u_Q
+        const float mu2 = -fmaf(dy, b.z, -(dx * b.w));   // -d . v_Q
+        const int kP = P->k, kQ = Q->k;
+        float qx[MAX_VERTICES], qy[MAX_VERTICES], px[MAX_VERTICES], py[MAX_VERTICES];
+#pragma unroll
+        for (int v = 0; v < MAX_VERTICES; ++v) {
+            if (v < kQ) {
+                qx[v] = fmaf(Q->vx[v], C, fmaf(-Q->vy[v], S, lam));
+                qy[v] = fmaf(Q->vx[v], S, fmaf(Q->vy[v], C, mu));
+            }
+            if (v < kP) {
+                px[v] = fmaf(P->vx[v], C, fmaf(P->vy[v], S, lam2));
+                py[v] = fmaf(-P->vx[v], S, fmaf(P->vy[v], C, mu2));
+            }
+        }
+        if constexpr (!PIPMODE) {
+            bool sep = false;
+#pragma unroll
+            for (int e = 0; e < MAX_VERTICES; ++e) {
+                if (e < kP) {
+                    bool out = true;
+#pragma unroll
+                    for (int v = 0; v < MAX_VERTICES; ++v)
+                        if (v < kQ) out &= fmaf(P->nx[e], qx[v], P->ny[e] * qy[v]) > P->h[e];
+                    sep |= out;
+                }
+                if (e < kQ) {
+                    bool out = true;
+#pragma unroll
+                    for (int v = 0; v < MAX_VERTICES; ++v)
+                        if (v < kP) out &= fmaf(Q->nx[e], px[v], Q->ny[e] * py[v]) > Q->h[e];
+                    sep |= out;
+                }
+            }
+            return !sep;
+        } else {
+            bool hit = false;
+#pragma unroll
+            for (int v = 0; v < MAX_VERTICES; ++v) {
+                if (v < kQ) {
+                    bool in = true;
+#pragma unroll
+                    for (int e = 0; e < MAX_VERTICES; ++e)
+                        if (e < kP) in &= fmaf(P->nx[e], qx[v], P->ny[e] * qy[v]) <= P->h[e];
+                    hit |= in;
+                }
+                if (v < kP) {
+                    bool in = true;
+#pragma unroll
+                    for (int e = 0; e < MAX_VERTICES; ++e)
+                        if (e < kQ) in &= fmaf(Q->nx[e], px[v], Q->ny[e] * py[v]) <= Q->h[e];
+                    hit |= in;
+                }
+            }
+            return hit;
+        }
+    }
+};
+
+// Convex polygon P and circle (centre c, squared radius rr): c in P's frame;
+// a hit iff c is inside or its squared distance to some edge segment is at
+// most rr.
+__device__ __forceinline__ bool poly_circle(const float4 P, const float2 c, const DPoly *__restrict__ G, float rr)
+{
+    const float dx = c.x - P.x;
+    const float dy = c.y - P.y;
+    const float lam = fmaf(dx, P.z, dy * P.w);
+    const float mu = fmaf(dy, P.z, -(dx * P.w));
+    const int k = G->k;
+    bool inside = true;
+    float best = 3.0e38f;
+#pragma unroll
+    for (int e = 0; e < MAX_VERTICES; ++e) {
+        if (e < k) {
+            inside &= fmaf(G->nx[e], lam, G->ny[e] * mu) <= G->h[e];
+            const float ax = lam - G->vx[e], ay = mu - G->vy[e];
+            const float t = fminf(fmaxf(fmaf(ax, G->ex[e], ay * G->ey[e]) * G->il[e], 0.0f), 1.0f);
+            const float cx = fmaf(-t, G->ex[e], ax), cy = fmaf(-t, G->ey[e], ay);
+            best = fminf(best, fmaf(cx, cx, cy * cy));
+        }
+    }
+    return inside | (best <= rr);
+}
+
+struct CheckGC {
+    const DPoly *__restrict__ G;
+    float rr;
+    __device__ __forceinline__ bool operator()(const float4 P, const float2 Q) const { return poly_circle(P, Q, G, rr); }
+};
+
+struct CheckCG {
+    const DPoly *__restrict__ G;
+    float rr;
+    __device__ __forceinline__ bool operator()(const float2 P, const float4 Q) const { return poly_circle(Q, P, G, rr); }
+};
+
 // Raw buffer descriptor (CDNA: dword3 = 0x00020000) over `bytes` bytes.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pose_rsrc(const char *base, uint32_t bytes)
 {
@@ -455,22 +573,42 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     }
 }
 
-// PIP: whether this kernel instance carries the point-in-polygon class. Its
-// larger tile needs more registers, which would lower the occupancy of the
-// exact classes; launches without such pairs use the instance without it.
+// EXT: whether this kernel instance carries the extended classes (the
+// point-in-polygon rectangle test and the polygon classes). Their larger
+// code and tiles need more registers, which would lower the occupancy of the
+// plain classes; launches without such pairs use the instance without them.
 // TL: whether it can add to per-slot sums (time-resolved scenes); likewise
 // kept out of the instances that launches without such scenes use.
-template <int V, bool PIP, bool TL>
+template <int V, bool EXT, bool TL>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
                                              unsigned long long *__restrict__ qacc,
-                                             unsigned long long *__restrict__ hist)
+                                             unsigned long long *__restrict__ hist, const DPoly *__restrict__ polys)
 {
-    if constexpr (PIP) {
-        if (pr.cls == CLS_VV_PIP) {
+    if constexpr (EXT) {
+        switch (pr.cls) {
+        case CLS_VV_PIP:
             collide_items<kTiles[V][CLS_VV_PIP].ri, kTiles[V][CLS_VV_PIP].rj, TL, float4, float4>(
                 pr, item0, poses, hits, pfix, qacc, hist, CheckVVPip{pr.la, pr.wa, pr.lb, pr.wb});
             return;
+        case CLS_GG:
+            collide_items<kTiles[V][CLS_GG].ri, kTiles[V][CLS_GG].rj, TL, float4, float4>(
+                pr, item0, poses, hits, pfix, qacc, hist, CheckGG<false>{polys + pr.poly_a, polys + pr.poly_b});
+            return;
+        case CLS_GG_PIP:
+            collide_items<kTiles[V][CLS_GG_PIP].ri, kTiles[V][CLS_GG_PIP].rj, TL, float4, float4>(
+                pr, item0, poses, hits, pfix, qacc, hist, CheckGG<true>{polys + pr.poly_a, polys + pr.poly_b});
+            return;
+        case CLS_GC:
+            collide_items<kTiles[V][CLS_GC].ri, kTiles[V][CLS_GC].rj, TL, float4, float2>(
+                pr, item0, poses, hits, pfix, qacc, hist, CheckGC{polys + pr.poly_a, pr.rr});
+            return;
+        case CLS_CG:
+            collide_items<kTiles[V][CLS_CG].ri, kTiles[V][CLS_CG].rj, TL, float2, float4>(
+                pr, item0, poses, hits, pfix, qacc, hist, CheckCG{polys + pr.poly_b, pr.rr});
+            return;
+        default:
+            break;
         }
     }
     switch (pr.cls) {
@@ -501,13 +639,13 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 // load-heavy and arithmetic-heavy test classes on every CU. The host
 // balances the slots by the exact instruction cost of the work, so every
 // SIMD finishes together without any cross-XCD atomics.
-template <int V, bool PIP, bool TL>
+template <int V, bool EXT, bool TL>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc,
-                                                 unsigned long long *__restrict__ hist)
+                                                 unsigned long long *__restrict__ hist, const DPoly *__restrict__ polys)
 {
     const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int blocks = (int)gridDim.x;
@@ -524,7 +662,7 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
         const WorkItem w = work[k];
         const DPair pr = pairs[w.pair];
         const int per = WAVE >> pr.tshift;
-        for (int u = 0; u < w.n_units; ++u) collide_work<V, PIP, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist);
+        for (int u = 0; u < w.n_units; ++u) collide_work<V, EXT, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, polys);
     }
 }
 
@@ -873,67 +1011,67 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int V, bool PIP, bool TL>
+template <int V, bool EXT, bool TL>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL((k2_collide<V, PIP, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
-                       L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist);
+    hipLaunchKernelGGL((k2_collide<V, EXT, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
+                       L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys);
     return hipGetLastError();
 }
 
-template <int V, bool PIP, bool TL>
+template <int V, bool EXT, bool TL>
 static int k2_resident_blocks()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, PIP, TL>, WG, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, EXT, TL>, WG, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-// The kernel instance of (variant, point-in-polygon class, per-slot sums):
-// F::run<V, PIP, TL>() is called for the instance.
-template <bool PIP, bool TL, class F>
+// The kernel instance of (variant, extended classes, per-slot sums):
+// F::run<V, EXT, TL>() is called for the instance.
+template <bool EXT, bool TL, class F>
 static auto with_variant(int variant, const F &f)
 {
     switch (variant) {
-    case 0: return f.template run<0, PIP, TL>();
-    case 1: return f.template run<1, PIP, TL>();
-    case 2: return f.template run<2, PIP, TL>();
-    default: return f.template run<3, PIP, TL>();
+    case 0: return f.template run<0, EXT, TL>();
+    case 1: return f.template run<1, EXT, TL>();
+    case 2: return f.template run<2, EXT, TL>();
+    default: return f.template run<3, EXT, TL>();
     }
 }
 
 template <class F>
-static auto with_instance(int variant, bool pip, bool tl, const F &f)
+static auto with_instance(int variant, bool ext, bool tl, const F &f)
 {
-    if (pip) return tl ? with_variant<true, true>(variant, f) : with_variant<true, false>(variant, f);
+    if (ext) return tl ? with_variant<true, true>(variant, f) : with_variant<true, false>(variant, f);
     return tl ? with_variant<false, true>(variant, f) : with_variant<false, false>(variant, f);
 }
 
 struct LaunchK2 {
     const Launch &L;
     hipStream_t s;
-    template <int V, bool PIP, bool TL>
-    hipError_t run() const { return launch_k2<V, PIP, TL>(L, s); }
+    template <int V, bool EXT, bool TL>
+    hipError_t run() const { return launch_k2<V, EXT, TL>(L, s); }
 };
 
 struct ResidentK2 {
-    template <int V, bool PIP, bool TL>
-    int run() const { return k2_resident_blocks<V, PIP, TL>(); }
+    template <int V, bool EXT, bool TL>
+    int run() const { return k2_resident_blocks<V, EXT, TL>(); }
 };
 
 hipError_t launch_collide(const Launch &L, hipStream_t s)
 {
     if (L.n_work <= 0) return hipSuccess;
     if (L.variant < 0 || L.variant >= N_VARIANTS) return hipErrorInvalidValue;
-    return with_instance(L.variant, L.pip != 0, L.timeline != 0, LaunchK2{L, s});
+    return with_instance(L.variant, L.ext != 0, L.timeline != 0, LaunchK2{L, s});
 }
 
-int collide_blocks_per_cu(int variant, bool pip, bool timeline)
+int collide_blocks_per_cu(int variant, bool ext, bool timeline)
 {
-    return with_instance(variant, pip, timeline, ResidentK2{});
+    return with_instance(variant, ext, timeline, ResidentK2{});
 }
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)

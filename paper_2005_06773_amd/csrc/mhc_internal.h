@@ -13,9 +13,31 @@ namespace mhc {
 enum Kind : int32_t { KIND_VEHICLE = 0, KIND_PEDESTRIAN = 1 };
 
 // Shape class of an object pair: which overlap test applies and which side
-// holds the rectangle.
+// holds the rectangle or polygon.
 // CLS_VV_PIP: two rectangles under the point-in-polygon test.
-enum PairClass : int32_t { CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, CLS_VV_PIP = 4, N_CLS = 5 };
+// CLS_GG, CLS_GG_PIP: two convex polygons (at least one a vehicle outline, a
+//   rectangle otherwise by its corners), separating axes / point-in-polygon.
+// CLS_GC, CLS_CG: polygon and circle (polygon first / second).
+enum PairClass : int32_t {
+    CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, CLS_VV_PIP = 4,
+    CLS_GG = 5, CLS_GG_PIP = 6, CLS_GC = 7, CLS_CG = 8, N_CLS = 9
+};
+// The classes beyond the plain rectangle / circle tests, carried only by the
+// collision-kernel instances that need them.
+constexpr bool extended_class(int cls) { return cls >= CLS_VV_PIP; }
+
+constexpr int MAX_VERTICES = 8;
+
+// Convex polygon of a vehicle in a polygon pair, body frame, CCW, as FP32
+// test constants: vertices, unit outward edge normals and offsets (a point
+// is inside iff nx*x + ny*y <= h on every edge), and for the circle test the
+// edge vectors (vertex e to e+1) with 1 / |edge|^2.
+struct DPoly {
+    int32_t k, pad0, pad1, pad2;
+    float vx[MAX_VERTICES], vy[MAX_VERTICES];
+    float nx[MAX_VERTICES], ny[MAX_VERTICES], h[MAX_VERTICES];
+    float ex[MAX_VERTICES], ey[MAX_VERTICES], il[MAX_VERTICES];
+};
 
 // Reading of the conditional-probability approximation (mhc.h MHC_RISK_*).
 enum RiskModel : int32_t { RISK_EXCLUSIVE = 0, RISK_INDEPENDENT = 1 };
@@ -62,6 +84,7 @@ struct DPair {
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
     int32_t timeline;             // 1: q sums go to the per-slot sums below
     int32_t hwa, hwb;             // lanes per trajectory of a's and of b's per-slot sums
+    int32_t poly_a, poly_b;       // DPoly of a and of b (polygon classes), else -1
     int32_t pad1;
     int64_t ha0;                  // slot-sum index of (a: s = 0, i = 0, b); slot s, trajectory i at + (s*Ta + i)*hwa
     int64_t hb0;                  // slot-sum index of (b: s = 0, j = 0, a); + (s*Tb + j)*hwb
@@ -100,15 +123,16 @@ struct TileShape {
     int ri, rj;
 };
 constexpr int N_VARIANTS = 4;
-// variant -> shape per class {VV, VP, PV, PP, VV_PIP}. The shapes keep the
-// VALU cost of one work unit similar across classes (27, 14, 6 and 59 VALU
-// per rect-rect, rect-circle, circle-circle and point-in-polygon test) and
-// the loads per test low.
+// variant -> shape per class {VV, VP, PV, PP, VV_PIP, GG, GG_PIP, GC, CG}.
+// The shapes keep the VALU cost of one work unit similar across classes (27,
+// 14, 6 and 59 VALU per rect-rect, rect-circle, circle-circle and
+// point-in-polygon test; 100-500 for polygon pairs) and the loads per test
+// low.
 constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {
-    {{2, 2}, {2, 2}, {2, 2}, {4, 4}, {2, 2}},
-    {{2, 2}, {4, 2}, {2, 4}, {4, 4}, {2, 1}},
-    {{4, 2}, {4, 2}, {2, 4}, {4, 4}, {4, 2}},
-    {{2, 1}, {2, 2}, {2, 2}, {4, 2}, {1, 1}},
+    {{2, 2}, {2, 2}, {2, 2}, {4, 4}, {2, 2}, {1, 1}, {1, 1}, {2, 1}, {1, 2}},
+    {{2, 2}, {4, 2}, {2, 4}, {4, 4}, {2, 1}, {2, 1}, {2, 1}, {2, 2}, {2, 2}},
+    {{4, 2}, {4, 2}, {2, 4}, {4, 4}, {4, 2}, {2, 1}, {1, 1}, {4, 1}, {1, 4}},
+    {{2, 1}, {2, 2}, {2, 2}, {4, 2}, {1, 1}, {1, 1}, {1, 1}, {1, 1}, {1, 1}},
 };
 
 // Launch entry points (kernels.hip).
@@ -121,6 +145,7 @@ struct Launch {
     unsigned long long *pfix;     // p * 2^62, per trajectory
     unsigned long long *qacc;     // integer q sums [n_q]
     const int32_t *bins;          // [n_bins+1] segment range of each collision wave slot
+    const DPoly *polys;           // polygons of the polygon pairs
     double *p;
     int16_t *hits;
     double *q;
@@ -140,7 +165,7 @@ struct Launch {
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
-    int pip;                      // some pair uses the point-in-polygon test
+    int ext;                      // some pair is of an extended class (point-in-polygon, polygons)
 };
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s);
@@ -148,7 +173,7 @@ hipError_t launch_collide(const Launch &L, hipStream_t s);
 // risk: the time-resolved kernels (timeline launches) and the risk kernel
 hipError_t launch_risk(const Launch &L, hipStream_t s);
 // resident workgroups per CU of the collision kernel for a variant, with or
-// without the point-in-polygon class and the per-slot sums
-int collide_blocks_per_cu(int variant, bool pip, bool timeline);
+// without the extended classes and the per-slot sums
+int collide_blocks_per_cu(int variant, bool ext, bool timeline);
 
 }  // namespace mhc

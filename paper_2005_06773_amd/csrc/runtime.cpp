@@ -17,8 +17,14 @@ namespace mhc {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int pair_class(int ka, int kb, int overlap)
+int pair_class(int ka, int kb, int overlap, bool outline_a, bool outline_b)
 {
+    if (outline_a || outline_b) {
+        // a polygon on either side: vehicles are polygons (rectangles by their corners)
+        if (ka == KIND_VEHICLE && kb == KIND_VEHICLE) return overlap == MHC_OVERLAP_PIP ? CLS_GG_PIP : CLS_GG;
+        if (ka == KIND_VEHICLE) return CLS_GC;
+        return CLS_CG;
+    }
     if (overlap == MHC_OVERLAP_PIP) return CLS_VV_PIP;  // validated: vehicles only
     if (ka == KIND_VEHICLE && kb == KIND_VEHICLE) return CLS_VV;
     if (ka == KIND_VEHICLE) return CLS_VP;
@@ -26,8 +32,32 @@ int pair_class(int ka, int kb, int overlap)
     return CLS_PP;
 }
 
-// Relative VALU cost of one check per class, for longest-first ordering.
-static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4, 60.0};
+bool scene_has_outline(const mhc_scene *s)
+{
+    for (int a = 0; a < s->n_objects; ++a)
+        if (s->objects[a].n_vertices > 0) return true;
+    return false;
+}
+
+bool scene_extended(const mhc_scene *s) { return s->overlap == MHC_OVERLAP_PIP || scene_has_outline(s); }
+
+// Relative VALU cost of one check per class, for longest-first ordering; the
+// polygon classes scale with the vertex counts (class_cost).
+static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
+
+double class_cost(int cls, int k_a, int k_b)
+{
+    switch (cls) {
+    case CLS_GG:
+    case CLS_GG_PIP: return 14.0 + 4.0 * (k_a + k_b) + 6.0 * k_a * k_b;
+    case CLS_GC: return 8.0 + 13.0 * k_a;
+    case CLS_CG: return 8.0 + 13.0 * k_b;
+    default: return kClsCost[cls];
+    }
+}
+
+// Vertex count of an object's polygon in a polygon pair (4 for a rectangle).
+static int poly_vertices(const mhc_object &o) { return o.n_vertices > 0 ? o.n_vertices : 4; }
 // Per-unit cost outside the step loop (setup, result stores), same units.
 static const double kUnitOverhead = 120.0;
 // From this many work units per collision wave on, waves take contiguous
@@ -44,6 +74,29 @@ static bool finite(double v) { return std::isfinite(v); }
 // ---------------------------------------------------------------------------
 // Ingest: validation. Every rule here is checked before anything is launched.
 // ---------------------------------------------------------------------------
+
+// A vehicle outline: finite, strictly convex and counter-clockwise (every
+// turn to the left), each interior angle at least 45 degrees (so that a
+// vertex outside another polygon by more than the test tolerance is outside
+// one of its edge lines by a comparable distance).
+bool outline_ok(int k, const double *v)
+{
+    for (int e = 0; e < 2 * k; ++e)
+        if (!finite(v[e])) return false;
+    const double cos45 = std::sqrt(0.5);
+    for (int e = 0; e < k; ++e) {
+        const int p = (e + k - 1) % k, q = (e + 1) % k;
+        const double ax = v[2 * e] - v[2 * p], ay = v[2 * e + 1] - v[2 * p + 1];   // incoming edge
+        const double bx = v[2 * q] - v[2 * e], by = v[2 * q + 1] - v[2 * e + 1];   // outgoing edge
+        if (!(ax * by - ay * bx > 0.0)) return false;                              // left turn
+        // interior angle between -a and b
+        const double la = std::hypot(ax, ay), lb = std::hypot(bx, by);
+        if (!(la > 0.0) || !(lb > 0.0)) return false;
+        const double cosint = (-ax * bx - ay * by) / (la * lb);
+        if (cosint > cos45) return false;
+    }
+    return true;
+}
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
 {
     char buf[256];
@@ -78,7 +131,15 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
         if (!finite(o.x) || !finite(o.y) || !finite(o.heading) || !finite(o.speed))
             return fail("object %d: state must be finite", a);
         if (!(o.speed >= 0.0)) return fail("object %d: speed must be >= 0", a);
-        if (o.kind == MHC_VEHICLE) {
+        if (o.n_vertices != 0) {
+            if (o.kind != MHC_VEHICLE) return fail("object %d: only vehicles take an outline", a);
+            if (o.n_vertices < 3 || o.n_vertices > MHC_MAX_VERTICES)
+                return fail("object %d: an outline has 3 to 8 vertices", a);
+            if (!o.vertices) return fail("object %d: outline vertices must not be NULL", a);
+            if (!outline_ok(o.n_vertices, o.vertices))
+                return fail("object %d: the outline must be finite, strictly convex, counter-clockwise, "
+                            "with interior angles >= 45 degrees", a);
+        } else if (o.kind == MHC_VEHICLE) {
             if (!finite(o.length) || !(o.length > 0.0) || !finite(o.width) || !(o.width > 0.0))
                 return fail("object %d: vehicle length and width must be finite and > 0", a);
         } else {
@@ -146,6 +207,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     };
     std::vector<PairCost> costs;
     std::vector<std::pair<int, int>> plist;
+    std::vector<int> pair_vertices;   // per pair: polygon vertex counts of a and b
     for (int k = 0; k < n_scenes; ++k) {
         const mhc_scene &s = scenes[k];
         const int n = s.n_objects;
@@ -207,6 +269,15 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
             toff += d.T;
         }
+        // polygons: with an outline anywhere in the scene, every vehicle of the
+        // scene gets one (its rectangle's corners if it has no outline)
+        std::vector<int32_t> poly_of(n, -1);
+        if (scene_has_outline(&s))
+            for (int a = 0; a < n; ++a)
+                if (s.objects[a].kind == MHC_VEHICLE) {
+                    poly_of[a] = (int32_t)L.polys.size();
+                    L.polys.push_back(DPoly{});
+                }
         pair_list(&s, plist);
         int64_t hoff = 0;
         for (auto &ab : plist) {
@@ -215,8 +286,12 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             DPair pr{};
             pr.a = obj_base + a;
             pr.b = obj_base + b;
-            pr.cls = pair_class(oa.kind, ob.kind, s.overlap);
-            L.pip |= pr.cls == CLS_VV_PIP;
+            pr.cls = pair_class(oa.kind, ob.kind, s.overlap, oa.n_vertices > 0, ob.n_vertices > 0);
+            pr.poly_a = poly_of[a];
+            pr.poly_b = poly_of[b];
+            pair_vertices.push_back(poly_vertices(oa));
+            pair_vertices.push_back(poly_vertices(ob));
+            L.ext |= extended_class(pr.cls);
             pr.H = s.horizon;
             pr.Ta = oa.n_u * oa.n_w;
             pr.Tb = ob.n_u * ob.n_w;
@@ -276,9 +351,10 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         while (sh > 0 && (pr.H % (1 << sh)) != 0) --sh;
         pr.tshift = sh;
         const TileShape ts = kTiles[variant][pr.cls];
+        const int ka = pr.poly_a >= 0 ? pair_vertices[2 * pidx] : 0, kb = pr.poly_b >= 0 ? pair_vertices[2 * pidx + 1] : 0;
         // a wave executes every step of every test of a unit, whether or
         // not all of its lanes hold an item
-        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * kClsCost[pr.cls] + kUnitOverhead;
+        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * class_cost(pr.cls, ka, kb) + kUnitOverhead;
         costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)units_with(pr, sh)});
     }
 
@@ -385,6 +461,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_pairs = put(L.pairs.size() * sizeof(DPair));
     L.o_work = put(L.work.size() * sizeof(WorkItem));
     L.o_bins = put(L.bins.size() * sizeof(int32_t));
+    L.o_polys = put(L.polys.size() * sizeof(DPoly));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
@@ -410,9 +487,48 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
 
 // The value part of a layout: states, control grids, scores and extents.
 // Everything else in a layout depends only on the scene shapes.
+// The test constants of a vehicle's polygon: its outline, or the corners of
+// its rectangle, counter-clockwise in the body frame (FP64, then FP32).
+static void fill_poly(const mhc_object &o, DPoly &g)
+{
+    double vx[MAX_VERTICES], vy[MAX_VERTICES];
+    int k;
+    if (o.n_vertices > 0) {
+        k = o.n_vertices;
+        for (int e = 0; e < k; ++e) {
+            vx[e] = o.vertices[2 * e];
+            vy[e] = o.vertices[2 * e + 1];
+        }
+    } else {
+        const double l = o.length / 2.0, w = o.width / 2.0;
+        k = 4;
+        const double cx[4] = {l, l, -l, -l}, cy[4] = {-w, w, w, -w};
+        for (int e = 0; e < 4; ++e) {
+            vx[e] = cx[e];
+            vy[e] = cy[e];
+        }
+    }
+    g = DPoly{};
+    g.k = k;
+    for (int e = 0; e < k; ++e) {
+        const int f = (e + 1) % k;
+        const double ex = vx[f] - vx[e], ey = vy[f] - vy[e];
+        const double len = std::hypot(ex, ey);
+        const double nx = ey / len, ny = -ex / len;   // outward for a CCW polygon
+        g.vx[e] = (float)vx[e];
+        g.vy[e] = (float)vy[e];
+        g.nx[e] = (float)nx;
+        g.ny[e] = (float)ny;
+        g.h[e] = (float)(nx * vx[e] + ny * vy[e]);
+        g.ex[e] = (float)ex;
+        g.ey[e] = (float)ey;
+        g.il[e] = (float)(1.0 / (ex * ex + ey * ey));
+    }
+}
+
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
 {
-    size_t oi = 0, pi = 0;
+    size_t oi = 0, pi = 0, gi = 0;
     std::vector<std::pair<int, int>> plist;
     for (int k = 0; k < n_scenes; ++k) {
         const mhc_scene &s = scenes[k];
@@ -428,6 +544,9 @@ void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
             std::copy(o.w, o.w + o.n_w, L.vals.begin() + d.w_off);
             if (o.score) std::copy(o.score, o.score + d.T, L.vals.begin() + d.score_off);
         }
+        if (scene_has_outline(&s))
+            for (int a = 0; a < s.n_objects; ++a)
+                if (s.objects[a].kind == MHC_VEHICLE) fill_poly(s.objects[a], L.polys[gi++]);
         pair_list(&s, plist);
         for (auto &ab : plist) {
             const mhc_object &oa = s.objects[ab.first], &ob = s.objects[ab.second];
@@ -437,8 +556,8 @@ void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
             pr.lb = (float)(ob.length / 2.0);
             pr.wb = (float)(ob.width / 2.0);
             pr.rr = 0.0f;
-            if (pr.cls == CLS_VP) pr.rr = (float)(ob.radius * ob.radius);
-            else if (pr.cls == CLS_PV) pr.rr = (float)(oa.radius * oa.radius);
+            if (pr.cls == CLS_VP || pr.cls == CLS_GC) pr.rr = (float)(ob.radius * ob.radius);
+            else if (pr.cls == CLS_PV || pr.cls == CLS_CG) pr.rr = (float)(oa.radius * oa.radius);
             else if (pr.cls == CLS_PP) pr.rr = (float)((oa.radius + ob.radius) * (oa.radius + ob.radius));
         }
     }
@@ -455,6 +574,7 @@ void pack_image(const Layout &L, char *dst)
     cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair));
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem));
     cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t));
+    cp(L.o_polys, L.polys.data(), L.polys.size() * sizeof(DPoly));
 }
 
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu)
@@ -470,6 +590,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.k3_part = reinterpret_cast<double *>(base + L.o_part);
     X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
+    X.polys = reinterpret_cast<const DPoly *>(base + L.o_polys);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
     X.q = reinterpret_cast<double *>(base + L.o_q);
@@ -507,7 +628,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.k3t_x = (int)L.k3t_x;
     X.k4t_y = L.k4t_y;
     X.variant = L.variant;
-    X.pip = L.pip ? 1 : 0;
+    X.ext = L.ext ? 1 : 0;
     X.n_bins = (int)L.bins.size() - 1;
     X.xcd_major = L.contiguous ? 1 : 0;
     (void)n_cu;
@@ -583,13 +704,13 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
 int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
 {
     if (v < 0 || v >= N_VARIANTS) v = 0;
-    int pip = 0, tl = 0;
+    int ext = 0, tl = 0;
     for (int k = 0; k < n; ++k) {
-        pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
+        ext |= scene_extended(&scenes[k]) ? 1 : 0;
         tl |= scenes[k].timeline != 0;
     }
-    int &w = waves_cache[v][pip][tl];
-    if (!w) w = n_cu * collide_blocks_per_cu(v, pip != 0, tl != 0) * (WG / WAVE);
+    int &w = waves_cache[v][ext][tl];
+    if (!w) w = n_cu * collide_blocks_per_cu(v, ext != 0, tl != 0) * (WG / WAVE);
     return w;
 }
 
@@ -640,6 +761,7 @@ std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
         v.push_back(s->objects[a].n_u);
         v.push_back(s->objects[a].n_w);
         v.push_back(s->objects[a].score != nullptr);
+        v.push_back(s->objects[a].n_vertices);
     }
     return v;
 }

@@ -41,6 +41,7 @@ struct Layout {
     std::vector<DPair> pairs;
     std::vector<WorkItem> work;     // grouped by collision wave
     std::vector<int32_t> bins;       // [n_bins+1] range of each collision wave in `work`
+    std::vector<DPoly> polys;        // polygons of the polygon pairs
     std::vector<SceneExt> sc;
     int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
     int k1_x = 0;                 // trajectory kernel grid x
@@ -51,12 +52,12 @@ struct Layout {
     int64_t k3t_x = 0;            // time-resolved risk kernel grid x (4-wave groups of the largest object)
     int k4t_y = 0;                // time-resolved reduction grid y (rows: slots + objects)
     size_t pose_bytes = 0;
-    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, image_bytes = 0;
+    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_polys = 0, image_bytes = 0;
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
     size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
-    bool pip = false;             // some pair uses the point-in-polygon test
+    bool ext = false;             // some pair is of an extended class (point-in-polygon, polygons)
     bool with_hits = true;        // the workspace holds the first-hit matrix
 };
 
@@ -76,8 +77,15 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
 // The time-resolved outputs of `r` (crit_t, traj_crit_t, attrib, traj_attrib)
 // are only allowed for a scene with the timeline flag.
 bool validate_outputs(const mhc_scene *s, const mhc_result *r, std::string &err, int scene_index = -1);
-// Test class (CLS_*) of an object pair of kinds ka, kb under an overlap mode.
-int pair_class(int ka, int kb, int overlap);
+// Test class (CLS_*) of an object pair of kinds ka, kb under an overlap mode,
+// given whether each has an outline.
+int pair_class(int ka, int kb, int overlap, bool outline_a, bool outline_b);
+// Relative VALU cost of one test of a class (k_a, k_b: polygon vertex counts).
+double class_cost(int cls, int k_a, int k_b);
+bool outline_ok(int k, const double *v);
+bool scene_has_outline(const mhc_scene *s);
+// The scene needs the extended classes (point-in-polygon or outlines).
+bool scene_extended(const mhc_scene *s);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
@@ -105,13 +113,14 @@ struct mhc_ctx {
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;
-    int waves_cache[mhc::N_VARIANTS][2][2] = {};  // [variant][point-in-polygon][time-resolved]
+    int waves_cache[mhc::N_VARIANTS][2][2] = {};  // [variant][extended classes][time-resolved]
     // resident waves on this GPU of the collision kernel that `scenes` need
     int max_waves(int variant, const mhc_scene *scenes, int n);
 };
 
 // Autotuning class of a launch: log2 of the mean trajectory count, log2 of
-// the mean horizon, and whether any scene uses the point-in-polygon test.
+// the mean horizon, and the test family: 0 rectangles and circles, 1 the
+// point-in-polygon rectangle test, 2 outlines (polygon classes).
 std::array<int, 3> size_class(const mhc_scene *scenes, int n);
 
 mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);

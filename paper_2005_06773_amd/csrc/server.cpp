@@ -120,7 +120,9 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
             // one collision segment per work unit, for the variant and the
             // time split (up to 4 parts, 16 items a unit) that cut this pair
             // into the most units
-            const int cls = pair_class(s->objects[a].kind, s->objects[b].kind, s->overlap);
+            const bool poly = scene_has_outline(s);
+            const int cls = pair_class(s->objects[a].kind, s->objects[b].kind, s->overlap,
+                                       poly && s->objects[a].n_vertices > 0, poly && s->objects[b].n_vertices > 0);
             int64_t most = 0;
             for (int v = 0; v < N_VARIANTS; ++v) {
                 const int64_t items = (Ta + kTiles[v][cls].ri - 1) / kTiles[v][cls].ri *
@@ -134,6 +136,7 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     const int64_t n_q = n_traj * n;
     size_t bytes = 0;
     bytes += align256(n * sizeof(DObj)) + align256(vals * 8) + align256(n_pairs * sizeof(DPair));
+    bytes += align256((scene_has_outline(s) ? n : 0) * sizeof(DPoly));
     bytes += align256((n_units + 1) * sizeof(WorkItem));
     bytes += pose + align256(n_traj * 8) * 3 + align256(n_q * 8) * 2;  // p*2^62, p, traj crit; q sums, q
     bytes += align256((n_traj / WG + n) * 8) + align256(n * 4);         // risk partials and counters
@@ -168,6 +171,10 @@ std::shared_ptr<Frame> copy_frame(const mhc_scene *s)
         if (o.score) {
             f->arrays.emplace_back(o.score, o.score + (size_t)o.n_u * o.n_w);
             o.score = f->arrays.back().data();
+        }
+        if (o.n_vertices > 0) {
+            f->arrays.emplace_back(o.vertices, o.vertices + 2 * (size_t)o.n_vertices);
+            o.vertices = f->arrays.back().data();
         }
     }
     f->scene = *s;

@@ -23,15 +23,18 @@ static int ilog2_floor(double x)
 std::array<int, 3> size_class(const mhc_scene *scenes, int n)
 {
     double traj = 0.0, objs = 0.0, hsum = 0.0;
-    int pip = 0;
+    int family = 0;
     for (int k = 0; k < n; ++k) {
-        pip |= scenes[k].overlap == MHC_OVERLAP_PIP;
+        if (scene_has_outline(&scenes[k]))
+            family = 2;
+        else if (scenes[k].overlap == MHC_OVERLAP_PIP && family < 1)
+            family = 1;
         for (int a = 0; a < scenes[k].n_objects; ++a)
             traj += (double)scenes[k].objects[a].n_u * scenes[k].objects[a].n_w;
         objs += scenes[k].n_objects;
         hsum += scenes[k].horizon;
     }
-    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n)), pip};
+    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n)), family};
 }
 
 int mhc_ctx::variant_for(const mhc_scene *scenes, int n) const
@@ -163,18 +166,19 @@ extern "C" mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path)
     while (true) {
         const size_t q = s.find('"', pos + 1);
         if (q == std::string::npos || q > end) break;
-        // keys are "T bucket,H bucket,pip"; a key without the third field is
-        // an exact-overlap class
-        int tb = 0, hb = 0, pip = 0, v = 0;
-        if (std::sscanf(s.c_str() + q, "\"%d,%d,%d\": %d", &tb, &hb, &pip, &v) != 4) {
-            pip = 0;
+        // keys are "T bucket,H bucket,family" (family 0 rectangles and
+        // circles, 1 point-in-polygon rectangles, 2 outlines); a key without
+        // the third field is of family 0
+        int tb = 0, hb = 0, family = 0, v = 0;
+        if (std::sscanf(s.c_str() + q, "\"%d,%d,%d\": %d", &tb, &hb, &family, &v) != 4) {
+            family = 0;
             if (std::sscanf(s.c_str() + q, "\"%d,%d\": %d", &tb, &hb, &v) != 3) v = -1;
         }
-        if (v < 0 || v >= N_VARIANTS || (pip != 0 && pip != 1)) {
+        if (v < 0 || v >= N_VARIANTS || family < 0 || family > 2) {
             ctx->err = "malformed tune file entry";
             return MHC_E_INVAL;
         }
-        got[{tb, hb, pip}] = v;
+        got[{tb, hb, family}] = v;
         pos = s.find('"', q + 1);
         if (pos == std::string::npos) break;
     }

@@ -53,11 +53,15 @@ _D = ctypes.c_double
 _DP = ctypes.POINTER(ctypes.c_double)
 
 
+MHC_MAX_VERTICES = 8
+
+
 class mhc_object(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("x", _D), ("y", _D), ("heading", _D), ("speed", _D),
                 ("length", _D), ("width", _D), ("radius", _D),
                 ("n_u", ctypes.c_int32), ("n_w", ctypes.c_int32),
-                ("u", _DP), ("w", _DP), ("score", _DP)]
+                ("u", _DP), ("w", _DP), ("score", _DP),
+                ("n_vertices", ctypes.c_int32), ("vertices", _DP)]
 
 
 class mhc_scene(ctypes.Structure):
@@ -174,6 +178,12 @@ class CScene:
             objs[k].u = u.ctypes.data_as(_DP)
             objs[k].w = w.ctypes.data_as(_DP)
             objs[k].score = sc.ctypes.data_as(_DP) if sc is not None else None
+            outline = getattr(o, "outline", None)
+            if outline is not None:
+                ov = np.ascontiguousarray(np.asarray(outline, np.float64).reshape(-1))
+                self.keep.append(ov)
+                objs[k].n_vertices = len(ov) // 2
+                objs[k].vertices = ov.ctypes.data_as(_DP)
         self.objs = objs
         self.c = mhc_scene(scene.n_objects, objs, int(scene.horizon), float(scene.dt), int(scene.pairs),
                            int(getattr(scene, "overlap", MHC_OVERLAP_EXACT)),

@@ -133,6 +133,17 @@ def _bad_scenes():
     s = base(); s.overlap = 2; out["bad_overlap_mode"] = s
     s = base(); s.risk = 2; out["bad_risk_reading"] = s
     s = base(); s.timeline = 3; out["bad_timeline_flag"] = s
+    s = base(); s.objects[0].outline = sg.car_outline(4.5, 1.8)[::-1].copy(); out["clockwise_outline"] = s
+    s = base(); s.objects[0].outline = np.array([[0, 0], [1, 0], [0, 1], [1, 1.0]]); out["self_crossing_outline"] = s
+    s = base(); s.objects[0].outline = np.array([[2, 0], [-1, 0.2], [-1, -0.2]]); out["sharp_outline"] = s
+    s = base(); s.objects[0].outline = np.array([[1, 0], [0, 1.0]]); out["two_vertex_outline"] = s
+    s = base(); s.objects[0].outline = np.tile(sg.car_outline(4.5, 1.8), (2, 1))[:9]; out["nine_vertex_outline"] = s
+    s = base(); s.objects[0].outline = np.array([[1, 0], [0, 1], [-1, 0], [0, float("nan")]])
+    out["nan_outline"] = s
+    s = base(); s.objects[0].outline = np.array([[1, 0], [1, 0], [0, 1], [-1, 0], [0, -1.0]])
+    out["repeated_vertex_outline"] = s
+    s = sg.eleven_object_scene(0); s.objects = [s.objects[0], s.objects[7]]
+    s.objects[1].outline = sg.car_outline(1.0, 1.0, 0.1); out["pedestrian_outline"] = s
     s = base(); s.timeline = 1; s.objects = [s.objects[k % 2] for k in range(65)]
     out["timeline_with_65_objects"] = s
     s = base(); s.overlap = sg.OVERLAP_PIP
@@ -201,3 +212,18 @@ def test_anticipation_time_by_hand(mhc):
                 dict(crit=[0.5, 0.6], frame_dt=0.1, threshold=float("nan"), event_frame=2)):
         with pytest.raises(mhc.MhcError):
             at(**bad)
+
+
+def test_outlines_accepted_and_sized(mhc):
+    """Valid outlines (triangle to octagon, any placement of the origin) are
+    accepted; length and width are not needed with an outline; the workspace
+    grows by the polygon table."""
+    rng = np.random.default_rng(0)
+    for k in range(3, 9):
+        s = sg.two_vehicle_scene(1)
+        s.objects[1].outline = sg.random_convex_outline(rng, k)
+        s.objects[1].length = s.objects[1].width = 0.0
+        q = mhc.mhc_query_sizes(s)
+        assert q["n_checks"] == 18_750
+    s = sg.polygon_scene(9)
+    assert mhc.mhc_query_sizes(s)["device_bytes"] > mhc.mhc_query_sizes(sg.eleven_object_scene(9))["device_bytes"]

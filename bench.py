@@ -53,7 +53,8 @@ def table_one(mhc, ctx, sg, torch, steps=50):
     stream = torch.cuda.current_stream()
     for name, n_co, n_acc, paper_ms in TABLE_ONE:
         for overlap in (sg.OVERLAP_EXACT, sg.OVERLAP_PIP):
-            cs = mhc.CScene(sg.paper_scene(5, n_co=n_co, n_acc=n_acc, overlap=overlap))
+            cs_scene = sg.paper_scene(5, n_co=n_co, n_acc=n_acc, overlap=overlap)
+            cs = mhc.CScene(cs_scene)
             checks = mhc.mhc_query_sizes(cs)["n_checks"]
             best, us = mhc.mhc_autotune(ctx, cs, reps=10)
             plan = mhc.mhc_plan_create(ctx, cs)
@@ -82,7 +83,7 @@ def table_one(mhc, ctx, sg, torch, steps=50):
                 mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
                 if k >= 5:
                     lat.append((time.perf_counter() - a) * 1e3)
-            flops = FLOPS_PER_CHECK["VV_PIP" if overlap == sg.OVERLAP_PIP else "VV"] * checks
+            flops = class_checks(cs_scene)[1]
             row = {"scenario": name, "cos": n_co, "accel_profiles": n_acc,
                    "overlap": "pip" if overlap == sg.OVERLAP_PIP else "exact", "checks": checks,
                    "step_ms": step_ms, "checks_per_s": checks / (step_ms * 1e-3),
@@ -169,19 +170,103 @@ def timeline_extra(mhc, ctx, sg, torch, steps=50):
     return {"rows": rows, "approach": appr}
 
 
+def polygon_flops(ka: int, kb: int, circle: bool) -> int:
+    """Algorithmic FP32 work of one polygon test (FMA = 2, compare 1).
+    Polygon-polygon (both modes): offset 2, relative rotation 6, both centres
+    in the other's frame 12, every vertex into the other's frame 8, every
+    vertex-edge value 3 + its compare 1, both ways: 20 + 8 (ka + kb) + 8 ka kb.
+    Polygon-circle: centre in the polygon's frame 8, per edge the inside test
+    4 and the clamped segment distance 16, final compare 1."""
+    if circle:
+        return 9 + 20 * ka
+    return 20 + 8 * (ka + kb) + 8 * ka * kb
+
+
+def polygon_extra(mhc, ctx, sg, torch, steps=50):
+    """General convex outlines: every vehicle an octagonal car (corners
+    chamfered 0.35 m). The 11-object scene (vehicle pairs 8 x 8 polygons,
+    vehicle-pedestrian pairs polygon-circle) and the Table I S2 scene in both
+    overlap modes: whole-path step and collision kernel alone (HIP events on
+    the launch stream), against the same scene with rectangles."""
+    stream = torch.cuda.current_stream()
+    rows = []
+
+    def octagons(s):
+        for o in s.objects:
+            if o.kind == sg.VEHICLE:
+                o.outline = sg.car_outline(o.length, o.width)
+        return s
+    cases = [("eleven_object", lambda: sg.eleven_object_scene(1)),
+             ("table_one_s2", lambda: sg.paper_scene(5, n_co=10)),
+             ("table_one_s2_pip", lambda: sg.paper_scene(5, n_co=10, overlap=sg.OVERLAP_PIP))]
+    for name, make in cases:
+        row = {"workload": name}
+        for shape in ("rectangles", "octagons"):
+            s = make() if shape == "rectangles" else octagons(make())
+            cs = mhc.CScene(s)
+            checks = mhc.mhc_query_sizes(cs)["n_checks"]
+            best, _ = mhc.mhc_autotune(ctx, cs, reps=10)
+            plan = mhc.mhc_plan_create(ctx, cs)
+            out, r = mhc.device_result(cs, first_hit=True, q=True)
+            for _ in range(5):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(steps):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            step_us = (time.perf_counter() - a) * 1e6 / steps
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+            for k in range(steps):
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_TRAJ, r, stream)
+                ev[k][0].record(stream)
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_COLLIDE, r, stream)
+                ev[k][1].record(stream)
+                mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_RISK, r, stream)
+            torch.cuda.synchronize()
+            k2_us = sum(x.elapsed_time(y) for x, y in ev) * 1e3 / steps
+            plan.close()
+            flops = class_checks(s)[1]
+            row[shape] = {"checks": checks, "step_us": step_us, "checks_per_s": checks / (step_us * 1e-6),
+                          "collide_us": k2_us, "collide_tflops": flops / (k2_us * 1e-6) / 1e12,
+                          "flops_per_check": flops / checks, "tile_variant": best}
+        rows.append(row)
+        r_, o_ = row["rectangles"], row["octagons"]
+        log(f"polygons {name}: rectangles step {r_['step_us']:.1f} us collide {r_['collide_us']:.1f} us; octagons step "
+            f"{o_['step_us']:.1f} us ({o_['checks_per_s']:.3g} checks/s), collide {o_['collide_us']:.1f} us "
+            f"({o_['collide_tflops']:.1f} TFLOP/s at {o_['flops_per_check']:.0f} flops/check)")
+    return rows
+
+
 def class_checks(scene):
-    out = {"VV": 0, "VP": 0, "PP": 0, "VV_PIP": 0}
+    """Checks per test class and the algorithmic flops of one pass."""
+    out = {"VV": 0, "VP": 0, "PP": 0, "VV_PIP": 0, "POLY": 0}
+    flops = 0
     objs = scene.objects
+    outlines = any(getattr(o, "outline", None) is not None for o in objs)
+    pip = getattr(scene, "overlap", 0) == 1
+
+    def nv(o):
+        return len(o.outline) if getattr(o, "outline", None) is not None else 4
     for a in range(len(objs)):
         for b in range(a + 1, len(objs)):
             if scene.pairs == 1 and a != 0:
                 continue
+            n = objs[a].n_traj * objs[b].n_traj * scene.horizon
             ka, kb = objs[a].kind, objs[b].kind
+            if outlines and (ka == 0 or kb == 0) and not (ka == kb == 1):
+                out["POLY"] += n
+                if ka == kb == 0:
+                    flops += polygon_flops(nv(objs[a]), nv(objs[b]), False) * n
+                else:
+                    flops += polygon_flops(nv(objs[a] if ka == 0 else objs[b]), 0, True) * n
+                continue
             c = "VV" if ka == kb == 0 else ("PP" if ka == kb == 1 else "VP")
-            if getattr(scene, "overlap", 0) == 1:
+            if pip:
                 c = "VV_PIP"
-            out[c] += objs[a].n_traj * objs[b].n_traj * scene.horizon
-    return out
+            out[c] += n
+            flops += FLOPS_PER_CHECK[c] * n
+    return out, flops
 
 
 # Timed workloads: the 11-object scene is the headline; the Table I S2
@@ -345,9 +430,8 @@ def main():
     cs = mhc.CScene(scene)
     sizes = mhc.mhc_query_sizes(cs)
     checks = sizes["n_checks"]
-    cls = class_checks(scene)
+    cls, flops = class_checks(scene)
     assert sum(cls.values()) == checks
-    flops = sum(FLOPS_PER_CHECK[c] * n for c, n in cls.items())
 
     ctx = mhc.mhc_create(0)
     if args.variant >= 0:
@@ -482,6 +566,7 @@ def main():
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
         result["table_one"] = table_one(mhc, ctx, sg, torch)
         result["timeline"] = timeline_extra(mhc, ctx, sg, torch)
+        result["polygons"] = polygon_extra(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)

@@ -318,11 +318,13 @@ struct CheckPP {
 //     vertex of the other has n_e.x > h_e;
 //   point-in-polygon (the paper's test, both ways): a hit iff some vertex of
 //     one has n_e.x <= h_e for every edge of the other.
-// Both read the same vertex-edge values; loops are unrolled to the maximum
-// vertex count with uniform guards, so decisions stay in lane masks.
-template <bool PIPMODE>
+// Both read the same vertex-edge values. Polygons come padded to KP, KQ = 4
+// or 8 vertices (repeated vertices and edges change none of the tests), so
+// the loops are straight-line code; their constants are read from the wave's
+// copy of the two polygons in LDS.
+template <int KP, int KQ, bool PIPMODE>
 struct CheckGG {
-    const DPoly *__restrict__ P, *__restrict__ Q;
+    const DPoly *P, *Q;   // LDS
     __device__ __forceinline__ bool operator()(const float4 a, const float4 b) const
     {
         const float dx = b.x - a.x;
@@ -333,98 +335,99 @@ struct CheckGG {
         const float mu = fmaf(dy, a.z, -(dx * a.w));     // d . v_P
         const float lam2 = -fmaf(dx, b.z, dy * b.w);     // -d . u_Q
         const float mu2 = -fmaf(dy, b.z, -(dx * b.w));   // -d . v_Q
-        const int kP = P->k, kQ = Q->k;
-        float qx[MAX_VERTICES], qy[MAX_VERTICES], px[MAX_VERTICES], py[MAX_VERTICES];
+        float qx[KQ], qy[KQ], px[KP], py[KP];
 #pragma unroll
-        for (int v = 0; v < MAX_VERTICES; ++v) {
-            if (v < kQ) {
-                qx[v] = fmaf(Q->vx[v], C, fmaf(-Q->vy[v], S, lam));
-                qy[v] = fmaf(Q->vx[v], S, fmaf(Q->vy[v], C, mu));
-            }
-            if (v < kP) {
-                px[v] = fmaf(P->vx[v], C, fmaf(P->vy[v], S, lam2));
-                py[v] = fmaf(-P->vx[v], S, fmaf(P->vy[v], C, mu2));
-            }
+        for (int v = 0; v < KQ; ++v) {
+            qx[v] = fmaf(Q->vx[v], C, fmaf(-Q->vy[v], S, lam));
+            qy[v] = fmaf(Q->vx[v], S, fmaf(Q->vy[v], C, mu));
+        }
+#pragma unroll
+        for (int v = 0; v < KP; ++v) {
+            px[v] = fmaf(P->vx[v], C, fmaf(P->vy[v], S, lam2));
+            py[v] = fmaf(-P->vx[v], S, fmaf(P->vy[v], C, mu2));
         }
         if constexpr (!PIPMODE) {
             bool sep = false;
 #pragma unroll
-            for (int e = 0; e < MAX_VERTICES; ++e) {
-                if (e < kP) {
-                    bool out = true;
+            for (int e = 0; e < KP; ++e) {
+                const float nx = P->nx[e], ny = P->ny[e], h = P->h[e];
+                bool out = true;
 #pragma unroll
-                    for (int v = 0; v < MAX_VERTICES; ++v)
-                        if (v < kQ) out &= fmaf(P->nx[e], qx[v], P->ny[e] * qy[v]) > P->h[e];
-                    sep |= out;
-                }
-                if (e < kQ) {
-                    bool out = true;
+                for (int v = 0; v < KQ; ++v) out &= fmaf(nx, qx[v], ny * qy[v]) > h;
+                sep |= out;
+            }
 #pragma unroll
-                    for (int v = 0; v < MAX_VERTICES; ++v)
-                        if (v < kP) out &= fmaf(Q->nx[e], px[v], Q->ny[e] * py[v]) > Q->h[e];
-                    sep |= out;
-                }
+            for (int e = 0; e < KQ; ++e) {
+                const float nx = Q->nx[e], ny = Q->ny[e], h = Q->h[e];
+                bool out = true;
+#pragma unroll
+                for (int v = 0; v < KP; ++v) out &= fmaf(nx, px[v], ny * py[v]) > h;
+                sep |= out;
             }
             return !sep;
         } else {
+            bool in_q[KQ], in_p[KP];
+#pragma unroll
+            for (int v = 0; v < KQ; ++v) in_q[v] = true;
+#pragma unroll
+            for (int v = 0; v < KP; ++v) in_p[v] = true;
+#pragma unroll
+            for (int e = 0; e < KP; ++e) {
+                const float nx = P->nx[e], ny = P->ny[e], h = P->h[e];
+#pragma unroll
+                for (int v = 0; v < KQ; ++v) in_q[v] &= fmaf(nx, qx[v], ny * qy[v]) <= h;
+            }
+#pragma unroll
+            for (int e = 0; e < KQ; ++e) {
+                const float nx = Q->nx[e], ny = Q->ny[e], h = Q->h[e];
+#pragma unroll
+                for (int v = 0; v < KP; ++v) in_p[v] &= fmaf(nx, px[v], ny * py[v]) <= h;
+            }
             bool hit = false;
 #pragma unroll
-            for (int v = 0; v < MAX_VERTICES; ++v) {
-                if (v < kQ) {
-                    bool in = true;
+            for (int v = 0; v < KQ; ++v) hit |= in_q[v];
 #pragma unroll
-                    for (int e = 0; e < MAX_VERTICES; ++e)
-                        if (e < kP) in &= fmaf(P->nx[e], qx[v], P->ny[e] * qy[v]) <= P->h[e];
-                    hit |= in;
-                }
-                if (v < kP) {
-                    bool in = true;
-#pragma unroll
-                    for (int e = 0; e < MAX_VERTICES; ++e)
-                        if (e < kQ) in &= fmaf(Q->nx[e], px[v], Q->ny[e] * py[v]) <= Q->h[e];
-                    hit |= in;
-                }
-            }
+            for (int v = 0; v < KP; ++v) hit |= in_p[v];
             return hit;
         }
     }
 };
 
-// Convex polygon P and circle (centre c, squared radius rr): c in P's frame;
-// a hit iff c is inside or its squared distance to some edge segment is at
-// most rr.
-__device__ __forceinline__ bool poly_circle(const float4 P, const float2 c, const DPoly *__restrict__ G, float rr)
+// Convex polygon G (K vertices, padded) and circle (centre c, squared radius
+// rr): c in G's frame; a hit iff c is inside or its squared distance to some
+// edge segment is at most rr.
+template <int K>
+__device__ __forceinline__ bool poly_circle(const float4 P, const float2 c, const DPoly *G, float rr)
 {
     const float dx = c.x - P.x;
     const float dy = c.y - P.y;
     const float lam = fmaf(dx, P.z, dy * P.w);
     const float mu = fmaf(dy, P.z, -(dx * P.w));
-    const int k = G->k;
     bool inside = true;
     float best = 3.0e38f;
 #pragma unroll
-    for (int e = 0; e < MAX_VERTICES; ++e) {
-        if (e < k) {
-            inside &= fmaf(G->nx[e], lam, G->ny[e] * mu) <= G->h[e];
-            const float ax = lam - G->vx[e], ay = mu - G->vy[e];
-            const float t = fminf(fmaxf(fmaf(ax, G->ex[e], ay * G->ey[e]) * G->il[e], 0.0f), 1.0f);
-            const float cx = fmaf(-t, G->ex[e], ax), cy = fmaf(-t, G->ey[e], ay);
-            best = fminf(best, fmaf(cx, cx, cy * cy));
-        }
+    for (int e = 0; e < K; ++e) {
+        inside &= fmaf(G->nx[e], lam, G->ny[e] * mu) <= G->h[e];
+        const float ax = lam - G->vx[e], ay = mu - G->vy[e];
+        const float t = fminf(fmaxf(fmaf(ax, G->ex[e], ay * G->ey[e]) * G->il[e], 0.0f), 1.0f);
+        const float cx = fmaf(-t, G->ex[e], ax), cy = fmaf(-t, G->ey[e], ay);
+        best = fminf(best, fmaf(cx, cx, cy * cy));
     }
     return inside | (best <= rr);
 }
 
+template <int K>
 struct CheckGC {
-    const DPoly *__restrict__ G;
+    const DPoly *G;   // LDS
     float rr;
-    __device__ __forceinline__ bool operator()(const float4 P, const float2 Q) const { return poly_circle(P, Q, G, rr); }
+    __device__ __forceinline__ bool operator()(const float4 P, const float2 Q) const { return poly_circle<K>(P, Q, G, rr); }
 };
 
+template <int K>
 struct CheckCG {
-    const DPoly *__restrict__ G;
+    const DPoly *G;   // LDS
     float rr;
-    __device__ __forceinline__ bool operator()(const float2 P, const float4 Q) const { return poly_circle(Q, P, G, rr); }
+    __device__ __forceinline__ bool operator()(const float2 P, const float4 Q) const { return poly_circle<K>(Q, P, G, rr); }
 };
 
 // Raw buffer descriptor (CDNA: dword3 = 0x00020000) over `bytes` bytes.
@@ -579,33 +582,85 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
 // plain classes; launches without such pairs use the instance without them.
 // TL: whether it can add to per-slot sums (time-resolved scenes); likewise
 // kept out of the instances that launches without such scenes use.
-template <int V, bool EXT, bool TL>
+// Copies the two polygons of a polygon pair into this wave's LDS slot (each
+// lane a few words), so that their constants reach the tests as vector
+// registers instead of competing for scalar ones.
+__device__ __forceinline__ void stage_polygons(DPoly *slot, const DPoly *__restrict__ polys, const DPair &pr)
+{
+    constexpr int words = (int)(sizeof(DPoly) / sizeof(int32_t));
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    int32_t *dst = reinterpret_cast<int32_t *>(slot);
+    const int32_t *pa = reinterpret_cast<const int32_t *>(polys + (pr.poly_a >= 0 ? pr.poly_a : pr.poly_b));
+    const int32_t *pb = reinterpret_cast<const int32_t *>(polys + (pr.poly_b >= 0 ? pr.poly_b : pr.poly_a));
+    for (int k = lane; k < words; k += WAVE) {
+        dst[k] = pa[k];
+        dst[words + k] = pb[k];
+    }
+    // the wave's LDS operations complete in order; keep the compiler from
+    // moving the reads above the writes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// FAM: the test classes this kernel instance carries. FAM_PLAIN: rectangles
+// and circles; FAM_PIP: also the point-in-polygon rectangle test; FAM_POLY:
+// also the polygon classes. The larger code and tiles of the later families
+// need more registers, which would lower the occupancy of the earlier ones;
+// a launch uses the smallest family that covers its pairs.
+// TL: whether it can add to per-slot sums (time-resolved scenes); likewise
+// kept out of the instances that launches without such scenes use.
+template <int V, int FAM, bool TL>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
                                              unsigned long long *__restrict__ qacc,
-                                             unsigned long long *__restrict__ hist, const DPoly *__restrict__ polys)
+                                             unsigned long long *__restrict__ hist, const DPoly *lp)
 {
-    if constexpr (EXT) {
-        switch (pr.cls) {
-        case CLS_VV_PIP:
+    if constexpr (FAM >= FAM_PIP) {
+        if (pr.cls == CLS_VV_PIP) {
             collide_items<kTiles[V][CLS_VV_PIP].ri, kTiles[V][CLS_VV_PIP].rj, TL, float4, float4>(
                 pr, item0, poses, hits, pfix, qacc, hist, CheckVVPip{pr.la, pr.wa, pr.lb, pr.wb});
             return;
+        }
+    }
+    if constexpr (FAM >= FAM_POLY) {
+        const DPoly *P = lp, *Q = lp + 1;  // the pair's polygons (staged)
+        switch (pr.cls) {
         case CLS_GG:
-            collide_items<kTiles[V][CLS_GG].ri, kTiles[V][CLS_GG].rj, TL, float4, float4>(
-                pr, item0, poses, hits, pfix, qacc, hist, CheckGG<false>{polys + pr.poly_a, polys + pr.poly_b});
+        case CLS_GG_PIP: {
+            const int shape = (P->k == 8 ? 2 : 0) + (Q->k == 8 ? 1 : 0) + (pr.cls == CLS_GG_PIP ? 4 : 0);
+            switch (shape) {
+#define MHC_GG(S, KP, KQ, PIPM)                                                                                      \
+    case S:                                                                                                          \
+        collide_items<1, 1, TL, float4, float4>(pr, item0, poses, hits, pfix, qacc, hist, CheckGG<KP, KQ, PIPM>{P, Q}); \
+        return;
+                MHC_GG(0, 4, 4, false)
+                MHC_GG(1, 4, 8, false)
+                MHC_GG(2, 8, 4, false)
+                MHC_GG(3, 8, 8, false)
+                MHC_GG(4, 4, 4, true)
+                MHC_GG(5, 4, 8, true)
+                MHC_GG(6, 8, 4, true)
+                MHC_GG(7, 8, 8, true)
+#undef MHC_GG
+            }
             return;
-        case CLS_GG_PIP:
-            collide_items<kTiles[V][CLS_GG_PIP].ri, kTiles[V][CLS_GG_PIP].rj, TL, float4, float4>(
-                pr, item0, poses, hits, pfix, qacc, hist, CheckGG<true>{polys + pr.poly_a, polys + pr.poly_b});
-            return;
+        }
         case CLS_GC:
-            collide_items<kTiles[V][CLS_GC].ri, kTiles[V][CLS_GC].rj, TL, float4, float2>(
-                pr, item0, poses, hits, pfix, qacc, hist, CheckGC{polys + pr.poly_a, pr.rr});
+            if (P->k == 8)
+                collide_items<kTiles[V][CLS_GC].ri, kTiles[V][CLS_GC].rj, TL, float4, float2>(
+                    pr, item0, poses, hits, pfix, qacc, hist, CheckGC<8>{P, pr.rr});
+            else
+                collide_items<kTiles[V][CLS_GC].ri, kTiles[V][CLS_GC].rj, TL, float4, float2>(
+                    pr, item0, poses, hits, pfix, qacc, hist, CheckGC<4>{P, pr.rr});
             return;
         case CLS_CG:
-            collide_items<kTiles[V][CLS_CG].ri, kTiles[V][CLS_CG].rj, TL, float2, float4>(
-                pr, item0, poses, hits, pfix, qacc, hist, CheckCG{polys + pr.poly_b, pr.rr});
+            if (P->k == 8)
+                collide_items<kTiles[V][CLS_CG].ri, kTiles[V][CLS_CG].rj, TL, float2, float4>(
+                    pr, item0, poses, hits, pfix, qacc, hist, CheckCG<8>{P, pr.rr});
+            else
+                collide_items<kTiles[V][CLS_CG].ri, kTiles[V][CLS_CG].rj, TL, float2, float4>(
+                    pr, item0, poses, hits, pfix, qacc, hist, CheckCG<4>{P, pr.rr});
             return;
         default:
             break;
@@ -639,7 +694,7 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 // load-heavy and arithmetic-heavy test classes on every CU. The host
 // balances the slots by the exact instruction cost of the work, so every
 // SIMD finishes together without any cross-XCD atomics.
-template <int V, bool EXT, bool TL>
+template <int V, int FAM, bool TL>
 __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
@@ -657,12 +712,18 @@ __global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs
     else
         slot = (int)blockIdx.x * (WG / WAVE) + wave_in_block;  // grid not a multiple of the XCD count
     if (slot >= n_bins) return;
+    // per wave: the two polygons of its current polygon pair
+    constexpr bool poly = FAM >= FAM_POLY;
+    __shared__ DPoly lds_polys[poly ? 2 * (WG / WAVE) : 1];
+    DPoly *lp = lds_polys + (poly ? 2 * wave_in_block : 0);
     const int s1 = bins[slot + 1];
     for (int k = bins[slot]; k < s1; ++k) {
         const WorkItem w = work[k];
         const DPair pr = pairs[w.pair];
+        if (poly && pr.cls >= CLS_GG) stage_polygons(lp, polys, pr);
         const int per = WAVE >> pr.tshift;
-        for (int u = 0; u < w.n_units; ++u) collide_work<V, EXT, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, polys);
+        for (int u = 0; u < w.n_units; ++u)
+            collide_work<V, FAM, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, lp);
     }
 }
 
@@ -1011,67 +1072,77 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int V, bool EXT, bool TL>
+template <int V, int FAM, bool TL>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL((k2_collide<V, EXT, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
+    hipLaunchKernelGGL((k2_collide<V, FAM, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
                        L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys);
     return hipGetLastError();
 }
 
-template <int V, bool EXT, bool TL>
+template <int V, int FAM, bool TL>
 static int k2_resident_blocks()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, EXT, TL>, WG, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, FAM, TL>, WG, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-// The kernel instance of (variant, extended classes, per-slot sums):
-// F::run<V, EXT, TL>() is called for the instance.
-template <bool EXT, bool TL, class F>
+// The kernel instance of (variant, class family, per-slot sums):
+// F::run<V, FAM, TL>() is called for the instance.
+template <int FAM, bool TL, class F>
 static auto with_variant(int variant, const F &f)
 {
     switch (variant) {
-    case 0: return f.template run<0, EXT, TL>();
-    case 1: return f.template run<1, EXT, TL>();
-    case 2: return f.template run<2, EXT, TL>();
-    default: return f.template run<3, EXT, TL>();
+    case 0: return f.template run<0, FAM, TL>();
+    case 1: return f.template run<1, FAM, TL>();
+    case 2: return f.template run<2, FAM, TL>();
+    default: return f.template run<3, FAM, TL>();
     }
 }
 
-template <class F>
-static auto with_instance(int variant, bool ext, bool tl, const F &f)
+template <int FAM, class F>
+static auto with_timeline(int variant, bool tl, const F &f)
 {
-    if (ext) return tl ? with_variant<true, true>(variant, f) : with_variant<true, false>(variant, f);
-    return tl ? with_variant<false, true>(variant, f) : with_variant<false, false>(variant, f);
+    return tl ? with_variant<FAM, true>(variant, f) : with_variant<FAM, false>(variant, f);
+}
+
+template <class F>
+static auto with_instance(int variant, int family, bool tl, const F &f)
+{
+    switch (family) {
+    case FAM_PLAIN: return with_timeline<FAM_PLAIN>(variant, tl, f);
+    case FAM_PIP: return with_timeline<FAM_PIP>(variant, tl, f);
+    default: return with_timeline<FAM_POLY>(variant, tl, f);
+    }
 }
 
 struct LaunchK2 {
     const Launch &L;
     hipStream_t s;
-    template <int V, bool EXT, bool TL>
-    hipError_t run() const { return launch_k2<V, EXT, TL>(L, s); }
+    template <int V, int FAM, bool TL>
+    hipError_t run() const { return launch_k2<V, FAM, TL>(L, s); }
 };
 
 struct ResidentK2 {
-    template <int V, bool EXT, bool TL>
-    int run() const { return k2_resident_blocks<V, EXT, TL>(); }
+    template <int V, int FAM, bool TL>
+    int run() const { return k2_resident_blocks<V, FAM, TL>(); }
 };
 
 hipError_t launch_collide(const Launch &L, hipStream_t s)
 {
     if (L.n_work <= 0) return hipSuccess;
-    if (L.variant < 0 || L.variant >= N_VARIANTS) return hipErrorInvalidValue;
-    return with_instance(L.variant, L.ext != 0, L.timeline != 0, LaunchK2{L, s});
+    if (L.variant < 0 || L.variant >= N_VARIANTS || L.family < FAM_PLAIN || L.family > FAM_POLY)
+        return hipErrorInvalidValue;
+    return with_instance(L.variant, L.family, L.timeline != 0, LaunchK2{L, s});
 }
 
-int collide_blocks_per_cu(int variant, bool ext, bool timeline)
+int collide_blocks_per_cu(int variant, int family, bool timeline)
 {
-    return with_instance(variant, ext, timeline, ResidentK2{});
+    return with_instance(variant, family, timeline, ResidentK2{});
 }
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)

@@ -22,16 +22,19 @@ enum PairClass : int32_t {
     CLS_VV = 0, CLS_VP = 1, CLS_PV = 2, CLS_PP = 3, CLS_VV_PIP = 4,
     CLS_GG = 5, CLS_GG_PIP = 6, CLS_GC = 7, CLS_CG = 8, N_CLS = 9
 };
-// The classes beyond the plain rectangle / circle tests, carried only by the
-// collision-kernel instances that need them.
-constexpr bool extended_class(int cls) { return cls >= CLS_VV_PIP; }
+// Families of test classes, each carried by its own collision-kernel
+// instances (a family includes the ones before it).
+enum ClassFamily : int32_t { FAM_PLAIN = 0, FAM_PIP = 1, FAM_POLY = 2 };
+constexpr int class_family(int cls) { return cls >= CLS_GG ? FAM_POLY : (cls == CLS_VV_PIP ? FAM_PIP : FAM_PLAIN); }
 
 constexpr int MAX_VERTICES = 8;
 
 // Convex polygon of a vehicle in a polygon pair, body frame, CCW, as FP32
 // test constants: vertices, unit outward edge normals and offsets (a point
 // is inside iff nx*x + ny*y <= h on every edge), and for the circle test the
-// edge vectors (vertex e to e+1) with 1 / |edge|^2.
+// edge vectors (vertex e to e+1) with 1 / |edge|^2. k is 4 or 8: a polygon
+// of fewer vertices is padded with copies of vertex 0 and of edge 0, which
+// change none of the tests.
 struct DPoly {
     int32_t k, pad0, pad1, pad2;
     float vx[MAX_VERTICES], vy[MAX_VERTICES];
@@ -128,12 +131,22 @@ constexpr int N_VARIANTS = 4;
 // 14, 6 and 59 VALU per rect-rect, rect-circle, circle-circle and
 // point-in-polygon test; 100-500 for polygon pairs) and the loads per test
 // low.
+// Polygon-polygon pairs always take one test per thread (their tests are
+// long, and the kernel has one code path per padded vertex-count pair).
 constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {
     {{2, 2}, {2, 2}, {2, 2}, {4, 4}, {2, 2}, {1, 1}, {1, 1}, {2, 1}, {1, 2}},
-    {{2, 2}, {4, 2}, {2, 4}, {4, 4}, {2, 1}, {2, 1}, {2, 1}, {2, 2}, {2, 2}},
-    {{4, 2}, {4, 2}, {2, 4}, {4, 4}, {4, 2}, {2, 1}, {1, 1}, {4, 1}, {1, 4}},
+    {{2, 2}, {4, 2}, {2, 4}, {4, 4}, {2, 1}, {1, 1}, {1, 1}, {2, 2}, {2, 2}},
+    {{4, 2}, {4, 2}, {2, 4}, {4, 4}, {4, 2}, {1, 1}, {1, 1}, {4, 1}, {1, 4}},
     {{2, 1}, {2, 2}, {2, 2}, {4, 2}, {1, 1}, {1, 1}, {1, 1}, {1, 1}, {1, 1}},
 };
+static_assert(kTiles[0][CLS_GG].ri == 1 && kTiles[1][CLS_GG].ri == 1 && kTiles[2][CLS_GG].ri == 1 &&
+                  kTiles[3][CLS_GG].ri == 1 && kTiles[0][CLS_GG].rj == 1 && kTiles[1][CLS_GG].rj == 1 &&
+                  kTiles[2][CLS_GG].rj == 1 && kTiles[3][CLS_GG].rj == 1,
+              "polygon-polygon tiles are 1 x 1");
+static_assert(kTiles[0][CLS_GG_PIP].ri == 1 && kTiles[1][CLS_GG_PIP].ri == 1 && kTiles[2][CLS_GG_PIP].ri == 1 &&
+                  kTiles[3][CLS_GG_PIP].ri == 1 && kTiles[0][CLS_GG_PIP].rj == 1 && kTiles[1][CLS_GG_PIP].rj == 1 &&
+                  kTiles[2][CLS_GG_PIP].rj == 1 && kTiles[3][CLS_GG_PIP].rj == 1,
+              "polygon-polygon tiles are 1 x 1");
 
 // Launch entry points (kernels.hip).
 struct Launch {
@@ -165,15 +178,15 @@ struct Launch {
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int variant;
-    int ext;                      // some pair is of an extended class (point-in-polygon, polygons)
+    int family;                   // ClassFamily covering every pair of the launch
 };
 
 hipError_t launch_trajgen(const Launch &L, hipStream_t s);
 hipError_t launch_collide(const Launch &L, hipStream_t s);
 // risk: the time-resolved kernels (timeline launches) and the risk kernel
 hipError_t launch_risk(const Launch &L, hipStream_t s);
-// resident workgroups per CU of the collision kernel for a variant, with or
-// without the extended classes and the per-slot sums
-int collide_blocks_per_cu(int variant, bool ext, bool timeline);
+// resident workgroups per CU of the collision kernel for a variant, class
+// family, with or without the per-slot sums
+int collide_blocks_per_cu(int variant, int family, bool timeline);
 
 }  // namespace mhc

@@ -39,7 +39,11 @@ bool scene_has_outline(const mhc_scene *s)
     return false;
 }
 
-bool scene_extended(const mhc_scene *s) { return s->overlap == MHC_OVERLAP_PIP || scene_has_outline(s); }
+int scene_family(const mhc_scene *s)
+{
+    if (scene_has_outline(s)) return FAM_POLY;
+    return s->overlap == MHC_OVERLAP_PIP ? FAM_PIP : FAM_PLAIN;
+}
 
 // Relative VALU cost of one check per class, for longest-first ordering; the
 // polygon classes scale with the vertex counts (class_cost).
@@ -56,8 +60,10 @@ double class_cost(int cls, int k_a, int k_b)
     }
 }
 
-// Vertex count of an object's polygon in a polygon pair (4 for a rectangle).
-static int poly_vertices(const mhc_object &o) { return o.n_vertices > 0 ? o.n_vertices : 4; }
+// Padded vertex count of an object's polygon in a polygon pair (4 for a
+// rectangle, 4 or 8 for an outline).
+static int padded_vertices(int n) { return n <= 4 ? 4 : MAX_VERTICES; }
+static int poly_vertices(const mhc_object &o) { return padded_vertices(o.n_vertices > 0 ? o.n_vertices : 4); }
 // Per-unit cost outside the step loop (setup, result stores), same units.
 static const double kUnitOverhead = 120.0;
 // From this many work units per collision wave on, waves take contiguous
@@ -291,7 +297,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             pr.poly_b = poly_of[b];
             pair_vertices.push_back(poly_vertices(oa));
             pair_vertices.push_back(poly_vertices(ob));
-            L.ext |= extended_class(pr.cls);
+            L.family = std::max(L.family, class_family(pr.cls));
             pr.H = s.horizon;
             pr.Ta = oa.n_u * oa.n_w;
             pr.Tb = ob.n_u * ob.n_w;
@@ -509,8 +515,19 @@ static void fill_poly(const mhc_object &o, DPoly &g)
         }
     }
     g = DPoly{};
-    g.k = k;
-    for (int e = 0; e < k; ++e) {
+    g.k = padded_vertices(k);
+    for (int e = 0; e < g.k; ++e) {
+        if (e >= k) {  // padding: copies of vertex 0 and of edge 0
+            g.vx[e] = g.vx[0];
+            g.vy[e] = g.vy[0];
+            g.nx[e] = g.nx[0];
+            g.ny[e] = g.ny[0];
+            g.h[e] = g.h[0];
+            g.ex[e] = g.ex[0];
+            g.ey[e] = g.ey[0];
+            g.il[e] = g.il[0];
+            continue;
+        }
         const int f = (e + 1) % k;
         const double ex = vx[f] - vx[e], ey = vy[f] - vy[e];
         const double len = std::hypot(ex, ey);
@@ -628,7 +645,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.k3t_x = (int)L.k3t_x;
     X.k4t_y = L.k4t_y;
     X.variant = L.variant;
-    X.ext = L.ext ? 1 : 0;
+    X.family = L.family;
     X.n_bins = (int)L.bins.size() - 1;
     X.xcd_major = L.contiguous ? 1 : 0;
     (void)n_cu;
@@ -704,13 +721,13 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
 int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
 {
     if (v < 0 || v >= N_VARIANTS) v = 0;
-    int ext = 0, tl = 0;
+    int fam = 0, tl = 0;
     for (int k = 0; k < n; ++k) {
-        ext |= scene_extended(&scenes[k]) ? 1 : 0;
+        fam = std::max(fam, scene_family(&scenes[k]));
         tl |= scenes[k].timeline != 0;
     }
-    int &w = waves_cache[v][ext][tl];
-    if (!w) w = n_cu * collide_blocks_per_cu(v, ext != 0, tl != 0) * (WG / WAVE);
+    int &w = waves_cache[v][fam][tl];
+    if (!w) w = n_cu * collide_blocks_per_cu(v, fam, tl != 0) * (WG / WAVE);
     return w;
 }
 

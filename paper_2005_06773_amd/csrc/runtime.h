@@ -57,7 +57,7 @@ struct Layout {
     size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches
-    bool ext = false;             // some pair is of an extended class (point-in-polygon, polygons)
+    int family = 0;               // ClassFamily covering every pair
     bool with_hits = true;        // the workspace holds the first-hit matrix
 };
 
@@ -84,8 +84,8 @@ int pair_class(int ka, int kb, int overlap, bool outline_a, bool outline_b);
 double class_cost(int cls, int k_a, int k_b);
 bool outline_ok(int k, const double *v);
 bool scene_has_outline(const mhc_scene *s);
-// The scene needs the extended classes (point-in-polygon or outlines).
-bool scene_extended(const mhc_scene *s);
+// The class family a scene needs (ClassFamily).
+int scene_family(const mhc_scene *s);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
@@ -113,7 +113,7 @@ struct mhc_ctx {
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)
     int variant_for(const mhc_scene *scenes, int n) const;
-    int waves_cache[mhc::N_VARIANTS][2][2] = {};  // [variant][extended classes][time-resolved]
+    int waves_cache[mhc::N_VARIANTS][3][2] = {};  // [variant][class family][time-resolved]
     // resident waves on this GPU of the collision kernel that `scenes` need
     int max_waves(int variant, const mhc_scene *scenes, int n);
 };

@@ -67,6 +67,7 @@ def lib():
         P = ctypes.c_void_p
         L.orc_probabilities.argtypes = [I, P, P]
         L.orc_trajectories.argtypes = [I, D, D, D, D, I, P, I, P, I, D, P, P, P]
+        L.orc_trajectories_model.argtypes = [I, I, P, D, D, D, D, I, P, I, P, I, D, P, P, P]
         L.orc_margin_rect_rect.argtypes = [D] * 10
         L.orc_margin_rect_rect.restype = D
         L.orc_margin_rect_circle.argtypes = [D] * 8
@@ -116,6 +117,12 @@ def probabilities(obj) -> np.ndarray:
     return p
 
 
+#: motion models of an object (Sec. IV-B)
+MODEL_KINEMATIC = 0   # vehicles acceleration x yaw rate, pedestrians speed x heading offset
+MODEL_PED_ACCEL = 1   # pedestrians acceleration x absolute heading, speed capped (params[0] = v_max)
+MODEL_ONE_TRACK = 2   # vehicles acceleration x steering angle, params (cf, cr, lf, lr, m, Iz)
+
+
 def trajectories(obj, horizon: int, dt: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """(x, y, psi), each [horizon][T]; slot t is the pose of step t+1."""
     T = obj.n_traj
@@ -124,9 +131,14 @@ def trajectories(obj, horizon: int, dt: float) -> Tuple[np.ndarray, np.ndarray, 
     psi = np.empty((horizon, T), np.float64)
     u = np.ascontiguousarray(obj.u, np.float64)
     w = np.ascontiguousarray(obj.w, np.float64)
-    _check(lib().orc_trajectories(int(obj.kind), obj.x, obj.y, obj.heading, obj.speed,
-                                  len(u), _ptr(u), len(w), _ptr(w), horizon, dt,
-                                  _ptr(x), _ptr(y), _ptr(psi)), "trajectories")
+    model = int(getattr(obj, "model", MODEL_KINEMATIC))
+    params = np.zeros(6, np.float64)
+    if getattr(obj, "params", None) is not None:
+        pp = np.asarray(obj.params, np.float64)
+        params[:len(pp)] = pp
+    _check(lib().orc_trajectories_model(int(obj.kind), model, _ptr(params), obj.x, obj.y, obj.heading, obj.speed,
+                                        len(u), _ptr(u), len(w), _ptr(w), horizon, dt,
+                                        _ptr(x), _ptr(y), _ptr(psi)), "trajectories")
     return x, y, psi
 
 

@@ -152,16 +152,147 @@ static void pedestrian_trajectory(double x0, double y0, double psi0,
     }
 }
 
-int orc_trajectories(int kind, double x0, double y0, double psi0, double v0,
-                     int n_u, const double *u, int n_w, const double *w,
-                     int H, double tau, double *ox, double *oy, double *opsi)
+/* Pedestrian with the acceleration grid of Sec. IV-B.3: the heading psi_P
+ * is a sample of [0, 360) degrees (absolute), the acceleration vdot_P a
+ * sample of its range, and the speed is limited to [0, v_max]:
+ *   v_{n+1} = v_n + vdot_n tau, vdot_n cut so that 0 <= v_{n+1} <= v_max,
+ *   x_{n+1} = x_n + c(psi_P) v_n tau + c(psi_P) vdot_n tau^2/2   (same for y, s). */
+static void pedestrian_accel_trajectory(double x0, double y0, double v0, double accel, double heading,
+                                        double v_max, int H, double tau, int T, int i,
+                                        double *ox, double *oy, double *opsi)
+{
+    double c = cos(heading), s = sin(heading);
+    double x = x0, y = y0, v = v0;
+    for (int n = 0; n < H; ++n) {
+        double vdot = accel;
+        double v_next = v + vdot * tau;
+        if (v_next > v_max) { vdot = (v_max - v) / tau; v_next = v_max; }
+        if (v_next < 0.0) { vdot = -v / tau; v_next = 0.0; }
+        x = x + c * v * tau + c * vdot * (tau * tau / 2.0);
+        y = y + s * v * tau + s * vdot * (tau * tau / 2.0);
+        v = v_next;
+        ox[(size_t)n * T + i] = x;
+        oy[(size_t)n * T + i] = y;
+        opsi[(size_t)n * T + i] = heading;
+    }
+}
+
+/* Vehicle on the linear one-track model of Sec. IV-B.1 (the model the paper
+ * uses for the collision objects):
+ *   beta_dot  = -(cf + cr)/(m v) beta + ((cr lr - cf lf)/(m v^2) - 1) psi_dot + cf/(m v) delta
+ *   psi_ddot  = (cr lr - cf lf)/Iz beta - (cf lf^2 + cr lr^2)/(Iz v) psi_dot + cf lf/Iz delta
+ * with a constant front steering angle delta (the lateral controller needs
+ * lanes, which this build leaves out) and a constant acceleration vdot (the
+ * speed stopping at 0 as for the kinematic model), integrated with the Euler
+ * update of Sec. IV-B.1:
+ *   v_{n+1} = v_n + vdot_n tau,  beta_{n+1} = beta_n + beta_dot_n tau,
+ *   psi_{n+1} = psi_n + psi_dot_n tau + psi_ddot_n tau^2/2,
+ *   a_x = c(beta) vdot - s(beta) v (beta_dot + psi_dot),
+ *   a_y = s(beta) vdot + c(beta) v (beta_dot + psi_dot),
+ *   x_{n+1} = x_n + c(psi + beta) v tau + c(psi) a_x tau^2/2 - s(psi) a_y tau^2/2 (y likewise),
+ * all from step n (no one-step lag, as for the kinematic model). The explicit
+ * Euler step is unstable at low speed (the model's time constants scale with
+ * v); where the step matrix I + tau A(v_n) has an eigenvalue of modulus >= 1
+ * the lateral state is instead set to the model's steady state at v_{n+1}:
+ *   psi_dot = v delta / (L (1 + K v^2)),
+ *   beta    = delta (lr / L - m lf v^2 / (cr L^2)) / (1 + K v^2),
+ * L = lf + lr, K = m (lr cr - lf cf) / (L^2 cf cr) >= 0 (understeer), and
+ * beta_dot, psi_ddot of that step are the differences over tau. The state
+ * starts at beta = psi_dot = 0. p = {cf, cr, lf, lr, m, Iz}. */
+static void one_track_steady(const double *p, double v, double delta, double *beta, double *psi_dot)
+{
+    double cf = p[0], cr = p[1], lf = p[2], lr = p[3], m = p[4];
+    double L = lf + lr;
+    double K = m * (lr * cr - lf * cf) / (L * L * cf * cr);
+    double g = 1.0 + K * v * v;
+    *psi_dot = v * delta / (L * g);
+    *beta = delta * (lr / L - m * lf * v * v / (cr * L * L)) / g;
+}
+
+static int one_track_euler_stable(const double *p, double v, double tau)
+{
+    if (!(v > 0.0)) return 0;
+    double cf = p[0], cr = p[1], lf = p[2], lr = p[3], m = p[4], Iz = p[5];
+    double a11 = -(cf + cr) / (m * v), a12 = (cr * lr - cf * lf) / (m * v * v) - 1.0;
+    double a21 = (cr * lr - cf * lf) / Iz, a22 = -(cf * lf * lf + cr * lr * lr) / (Iz * v);
+    /* M = I + tau A; both eigenvalues inside the unit circle (Jury): */
+    double m11 = 1.0 + tau * a11, m12 = tau * a12, m21 = tau * a21, m22 = 1.0 + tau * a22;
+    double tr = m11 + m22, det = m11 * m22 - m12 * m21;
+    return det < 1.0 && tr < 1.0 + det && tr > -(1.0 + det);
+}
+
+static void one_track_trajectory(double x0, double y0, double psi0, double v0, double accel, double delta,
+                                 const double *p, int H, double tau, int T, int i,
+                                 double *ox, double *oy, double *opsi)
+{
+    double cf = p[0], cr = p[1], lf = p[2], lr = p[3], m = p[4], Iz = p[5];
+    double x = x0, y = y0, psi = psi0, v = v0, beta = 0.0, r = 0.0;   /* r = psi_dot */
+    for (int n = 0; n < H; ++n) {
+        double vdot = accel;
+        double v_next = v + vdot * tau;
+        if (v_next < 0.0) { vdot = -v / tau; v_next = 0.0; }
+        double beta_next, r_next, beta_dot, r_dot;
+        if (one_track_euler_stable(p, v, tau)) {
+            beta_dot = -(cf + cr) / (m * v) * beta + ((cr * lr - cf * lf) / (m * v * v) - 1.0) * r + cf / (m * v) * delta;
+            r_dot = (cr * lr - cf * lf) / Iz * beta - (cf * lf * lf + cr * lr * lr) / (Iz * v) * r + cf * lf / Iz * delta;
+            beta_next = beta + beta_dot * tau;
+            r_next = r + r_dot * tau;
+        } else {
+            one_track_steady(p, v_next, delta, &beta_next, &r_next);
+            beta_dot = (beta_next - beta) / tau;
+            r_dot = (r_next - r) / tau;
+        }
+        double ax = cos(beta) * vdot - sin(beta) * v * (beta_dot + r);
+        double ay = sin(beta) * vdot + cos(beta) * v * (beta_dot + r);
+        double h2 = tau * tau / 2.0;
+        double x_next = x + cos(psi + beta) * v * tau + cos(psi) * ax * h2 - sin(psi) * ay * h2;
+        double y_next = y + sin(psi + beta) * v * tau + sin(psi) * ax * h2 + cos(psi) * ay * h2;
+        double psi_next = psi + r * tau + r_dot * h2;
+        x = x_next;
+        y = y_next;
+        psi = psi_next;
+        v = v_next;
+        beta = beta_next;
+        r = r_next;
+        ox[(size_t)n * T + i] = x;
+        oy[(size_t)n * T + i] = y;
+        opsi[(size_t)n * T + i] = psi;
+    }
+}
+
+/* Motion models of an object (per object):
+ *   ORC_MODEL_KINEMATIC:  vehicles acceleration x yaw rate, pedestrians speed
+ *                         x heading offset (the readings above);
+ *   ORC_MODEL_PED_ACCEL:  pedestrians acceleration x absolute heading with
+ *                         params[0] = v_max;
+ *   ORC_MODEL_ONE_TRACK:  vehicles acceleration x front steering angle on the
+ *                         one-track model, params = {cf, cr, lf, lr, m, Iz}. */
+#define ORC_MODEL_KINEMATIC 0
+#define ORC_MODEL_PED_ACCEL 1
+#define ORC_MODEL_ONE_TRACK 2
+
+int orc_trajectories_model(int kind, int model, const double *params, double x0, double y0, double psi0,
+                           double v0, int n_u, const double *u, int n_w, const double *w,
+                           int H, double tau, double *ox, double *oy, double *opsi)
 {
     if (n_u < 1 || n_w < 1 || H < 1 || !(tau > 0.0)) return ORC_EINVAL;
+    if (model == ORC_MODEL_PED_ACCEL && (kind != ORC_PEDESTRIAN || !(params[0] > 0.0))) return ORC_EINVAL;
+    if (model == ORC_MODEL_ONE_TRACK) {
+        if (kind != ORC_VEHICLE) return ORC_EINVAL;
+        for (int k = 0; k < 6; ++k)
+            if (!(params[k] > 0.0) || !isfinite(params[k])) return ORC_EINVAL;
+        if (params[3] * params[1] < params[2] * params[0]) return ORC_EINVAL;   /* understeer */
+    }
+    if (model < ORC_MODEL_KINEMATIC || model > ORC_MODEL_ONE_TRACK) return ORC_EINVAL;
     int T = n_u * n_w;
     for (int k = 0; k < n_u; ++k)
         for (int l = 0; l < n_w; ++l) {
             int i = k * n_w + l;
-            if (kind == ORC_VEHICLE)
+            if (model == ORC_MODEL_PED_ACCEL)
+                pedestrian_accel_trajectory(x0, y0, v0, u[k], w[l], params[0], H, tau, T, i, ox, oy, opsi);
+            else if (model == ORC_MODEL_ONE_TRACK)
+                one_track_trajectory(x0, y0, psi0, v0, u[k], w[l], params, H, tau, T, i, ox, oy, opsi);
+            else if (kind == ORC_VEHICLE)
                 vehicle_trajectory(x0, y0, psi0, v0, u[k], w[l], H, tau, T, i, ox, oy, opsi);
             else if (kind == ORC_PEDESTRIAN)
                 pedestrian_trajectory(x0, y0, psi0, u[k], w[l], H, tau, T, i, ox, oy, opsi);
@@ -169,6 +300,15 @@ int orc_trajectories(int kind, double x0, double y0, double psi0, double v0,
                 return ORC_EINVAL;
         }
     return ORC_OK;
+}
+
+int orc_trajectories(int kind, double x0, double y0, double psi0, double v0,
+                     int n_u, const double *u, int n_w, const double *w,
+                     int H, double tau, double *ox, double *oy, double *opsi)
+{
+    const double none[6] = {0, 0, 0, 0, 0, 0};
+    return orc_trajectories_model(kind, ORC_MODEL_KINEMATIC, none, x0, y0, psi0, v0, n_u, u, n_w, w, H, tau,
+                                  ox, oy, opsi);
 }
 
 /* ------------------------------------------------------------------------ */

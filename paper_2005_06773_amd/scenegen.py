@@ -36,6 +36,9 @@ PAIRS_ALL = 0
 PAIRS_EGO = 1
 OVERLAP_EXACT = 0   # closed shapes intersect
 OVERLAP_PIP = 1     # the paper's point-in-polygon test, both ways (vehicles only)
+MODEL_KINEMATIC = 0   # vehicles acceleration x yaw rate, pedestrians speed x heading offset
+MODEL_PED_ACCEL = 1   # pedestrians acceleration x absolute heading, speed in [0, v_max]; params = [v_max]
+MODEL_ONE_TRACK = 2   # vehicles acceleration x front steering angle; params = [cf, cr, lf, lr, m, Iz]
 RISK_EXCLUSIVE = 0    # one object's trajectories mutually exclusive (default)
 RISK_INDEPENDENT = 1  # every trajectory combination an independent event
 
@@ -54,6 +57,8 @@ class SceneObject:
     w: np.ndarray = None  # vehicles: yaw rates;     pedestrians: heading offsets
     score: Optional[np.ndarray] = None  # n_u*n_w non-negative, index k*n_w+l
     outline: Optional[np.ndarray] = None  # vehicles: [k, 2] convex CCW polygon in the body frame (3 <= k <= 8)
+    model: int = 0                        # MODEL_*: motion model of the trajectory grid
+    params: Optional[np.ndarray] = None   # model parameters (see MODEL_*)
 
     @property
     def n_traj(self) -> int:
@@ -277,6 +282,65 @@ def paper_scene(seed: int = 5, n_co: int = 10, n_acc: int = 6, overlap: int = OV
         objs.append(SceneObject(VEHICLE, float(x), float(y), float(h), float(v), 4.5 * lf, 1.8 * wf, 0.0,
                                 u, w_co, vehicle_scores(u, w_co)))
     return Scene(objs, 100, 0.02, pairs=PAIRS_EGO, overlap=overlap)
+
+
+def ped_accel_grid(n: int, a_max: float = 12.0) -> np.ndarray:
+    """Pedestrian accelerations equally distributed on [-a_max, a_max]
+    (Sec. IV-B.3: -12 to 12 m/s^2)."""
+    return np.linspace(-a_max, a_max, n)
+
+
+def abs_heading_grid(n: int) -> np.ndarray:
+    """Absolute headings equally distributed on [0, 2 pi), no duplicated end
+    point (Sec. IV-B.3: 0 to 360 degrees)."""
+    return 2.0 * math.pi * np.arange(n) / n
+
+
+def steer_grid(n: int, delta_max: float = 0.1) -> np.ndarray:
+    """Front steering angles on [-delta_max, delta_max] rad."""
+    return np.linspace(-delta_max, delta_max, n)
+
+
+# Assumed one-track parameters (the paper takes its values from handbooks it
+# cites, without printing them): by length, a small, a mid-size and a large
+# car; cornering stiffness per axle in N/rad, lf / lr from the centre of
+# gravity to the axles, mass, yaw inertia. All understeer (lr cr > lf cf).
+ONE_TRACK_CLASSES = (
+    (4.0, np.array([50_000.0, 55_000.0, 1.00, 1.35, 1100.0, 1500.0])),
+    (4.7, np.array([67_500.0, 75_000.0, 1.20, 1.50, 1500.0, 2500.0])),
+    (1e9, np.array([90_000.0, 100_000.0, 1.35, 1.65, 2000.0, 3800.0])),
+)
+
+
+def one_track_params(length: float) -> np.ndarray:
+    for max_len, p in ONE_TRACK_CLASSES:
+        if length < max_len:
+            return p.copy()
+    return ONE_TRACK_CLASSES[-1][1].copy()
+
+
+def models_scene(seed: int = 10, horizon: int = 30, dt: float = 0.1) -> Scene:
+    """The 11-object scene on the paper's other motion models: vehicles on
+    the one-track model (15 accelerations on [-9.7, 9.7] by the paper's rule
+    x 15 steering angles on [-0.1, 0.1] rad, parameters by length), the
+    pedestrians on the acceleration model (15 accelerations on [-12, 12] x 15
+    absolute headings, speed capped at 2.7 m/s)."""
+    s = eleven_object_scene(seed, horizon)
+    s.dt = dt
+    for o in s.objects:
+        if o.kind == VEHICLE:
+            o.model = MODEL_ONE_TRACK
+            o.params = one_track_params(o.length)
+            o.u = accel_grid(15, -9.7, 9.7)
+            o.w = steer_grid(15)
+            o.score = vehicle_scores(o.u, o.w)
+        else:
+            o.model = MODEL_PED_ACCEL
+            o.params = np.array([2.7])
+            o.u = ped_accel_grid(15)
+            o.w = abs_heading_grid(15)
+            o.score = None
+    return s
 
 
 def car_outline(length: float, width: float, chamfer: float = 0.35) -> np.ndarray:

@@ -93,6 +93,21 @@ enum { MHC_RISK_EXCLUSIVE = 0, MHC_RISK_INDEPENDENT = 1 };
  * polygon against polygon (a rectangle by its four corners) or polygon
  * against circle, in either overlap mode. */
 enum { MHC_MAX_VERTICES = 8 };
+/* Motion model of an object's trajectory grid (Sec. IV-B).
+ * KINEMATIC (0, default): as described above.
+ * PED_ACCEL (1, pedestrians, Sec. IV-B.3): u[k] constant accelerations,
+ *   w[l] absolute headings; the speed follows v_{n+1} = v_n + a tau, the
+ *   acceleration of a step cut so that 0 <= v_{n+1} <= params[0] (v_max,
+ *   2.7 m/s in the paper), the position the Euler update of the paper.
+ * ONE_TRACK (2, vehicles, Sec. IV-B.1): the linear one-track model with
+ *   params = {c_alpha_f, c_alpha_r [N/rad], l_f, l_r [m], m [kg], I_z
+ *   [kg m^2]} (all > 0, understeer: l_r c_alpha_r >= l_f c_alpha_f), u[k]
+ *   constant accelerations (speed stopping at 0), w[l] constant front
+ *   steering angles [rad]; side slip and yaw rate start at 0 and follow the
+ *   model's Euler update, except that where that explicit step is unstable
+ *   (low speed: an eigenvalue of I + tau A(v) of modulus >= 1) they take the
+ *   model's steady state at the new speed. */
+enum { MHC_MODEL_KINEMATIC = 0, MHC_MODEL_PED_ACCEL = 1, MHC_MODEL_ONE_TRACK = 2 };
 typedef struct {
     int32_t kind;                 /* MHC_VEHICLE or MHC_PEDESTRIAN */
     double x, y, heading, speed;  /* measured state at time 0; speed >= 0 */
@@ -103,6 +118,8 @@ typedef struct {
     const double *score;          /* n_u*n_w scores or NULL */
     int32_t n_vertices;           /* 0 (rectangle / circle) or 3..MHC_MAX_VERTICES (vehicles) */
     const double *vertices;       /* 2*n_vertices body-frame coordinates x0, y0, x1, y1, ... */
+    int32_t model;                /* MHC_MODEL_* motion model of the trajectory grid */
+    double params[6];             /* parameters of the motion model (see MHC_MODEL_*) */
 } mhc_object;
 
 typedef struct {

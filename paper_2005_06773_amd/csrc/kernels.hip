@@ -111,6 +111,77 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
 // Grid: y = object; x = 0 is the object's probability normalisation (the
 // longest block for large T, so it is dispatched first), x >= 1 are
 // trajectory blocks of K1_TPB trajectories, one wave each.
+// Vehicle trajectory i on the linear one-track model (Sec. IV-B.1): side slip
+// beta and yaw rate r obey
+//   beta' = -(cf+cr)/(m v) beta + ((cr lr - cf lf)/(m v^2) - 1) r + cf/(m v) delta
+//   r'    = (cr lr - cf lf)/Iz beta - (cf lf^2 + cr lr^2)/(Iz v) r + cf lf/Iz delta
+// for the constant steering angle delta = w[l], integrated with the paper's
+// Euler pose update (accelerations a_x, a_y in the vehicle frame from step
+// n, the speed stopping at 0). Where the explicit step is unstable (an
+// eigenvalue of I + tau A(v_n) of modulus >= 1, tested by the Jury
+// conditions) the lateral state takes the steady state at v_{n+1} instead:
+//   r = v delta / (L (1 + K v^2)), beta = delta (lr/L - m lf v^2/(cr L^2)) / (1 + K v^2),
+// L = lf + lr, K = m (lr cr - lf cf) / (L^2 cf cr). FP64; poses stored as
+// FP32 (x, y, cos psi, sin psi), [t][i].
+__device__ void one_track_trajectory(const DObj &o, const double *__restrict__ vals, char *__restrict__ poses, int i)
+{
+    const double cf = o.params[0], cr = o.params[1], lf = o.params[2], lr = o.params[3];
+    const double m = o.params[4], Iz = o.params[5];
+    const double L = lf + lr;
+    const double K = m * (lr * cr - lf * cf) / (L * L * cf * cr);
+    const double cd = cr * lr - cf * lf;
+    const double cq = cf * lf * lf + cr * lr * lr;
+    const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
+    const double accel = vals[o.u_off + k];
+    const double delta = vals[o.w_off + l];
+    const double tau = o.tau, h2 = tau * tau / 2.0;
+    double x = o.x, y = o.y, psi = o.heading, v = o.speed, beta = 0.0, r = 0.0;
+    float4 *out = reinterpret_cast<float4 *>(poses + o.pose_off);
+    for (int n = 0; n < o.H; ++n) {
+        double vdot = accel;
+        double v1 = v + vdot * tau;
+        if (v1 < 0.0) {
+            vdot = -v / tau;
+            v1 = 0.0;
+        }
+        bool stable = false;
+        if (v > 0.0) {
+            const double m11 = 1.0 - tau * (cf + cr) / (m * v), m12 = tau * (cd / (m * v * v) - 1.0);
+            const double m21 = tau * cd / Iz, m22 = 1.0 - tau * cq / (Iz * v);
+            const double tr = m11 + m22, det = m11 * m22 - m12 * m21;
+            stable = det < 1.0 && tr < 1.0 + det && tr > -(1.0 + det);
+        }
+        double beta1, r1, beta_dot, r_dot;
+        if (stable) {
+            beta_dot = -(cf + cr) / (m * v) * beta + (cd / (m * v * v) - 1.0) * r + cf / (m * v) * delta;
+            r_dot = cd / Iz * beta - cq / (Iz * v) * r + cf * lf / Iz * delta;
+            beta1 = beta + beta_dot * tau;
+            r1 = r + r_dot * tau;
+        } else {
+            const double g = 1.0 + K * v1 * v1;
+            r1 = v1 * delta / (L * g);
+            beta1 = delta * (lr / L - m * lf * v1 * v1 / (cr * L * L)) / g;
+            beta_dot = (beta1 - beta) / tau;
+            r_dot = (r1 - r) / tau;
+        }
+        double sb, cb, sp, cp;
+        sincos(beta, &sb, &cb);
+        sincos(psi, &sp, &cp);
+        const double spb = sp * cb + cp * sb, cpb = cp * cb - sp * sb;   // psi + beta
+        const double ax = cb * vdot - sb * v * (beta_dot + r);
+        const double ay = sb * vdot + cb * v * (beta_dot + r);
+        x = x + cpb * v * tau + cp * ax * h2 - sp * ay * h2;
+        y = y + spb * v * tau + sp * ax * h2 + cp * ay * h2;
+        psi = psi + r * tau + r_dot * h2;
+        v = v1;
+        beta = beta1;
+        r = r1;
+        double s1, c1;
+        sincos(psi, &s1, &c1);
+        out[(size_t)n * o.T + i] = make_float4((float)x, (float)y, (float)c1, (float)s1);
+    }
+}
+
 // For time-resolved scenes, trajectory block c also zeroes the c-th stretch
 // of K1_TPB * W * H entries of the object's per-slot q sums.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
@@ -134,6 +205,12 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
         ulonglong2 *h2 = reinterpret_cast<ulonglong2 *>(hist + o.hist_off);
         for (int64_t k = lo / 2 + (int64_t)threadIdx.x; k < hi / 2; k += WG) h2[k] = make_ulonglong2(0ull, 0ull);
     }
+    if (o.model == MODEL_ONE_TRACK) {
+        // a thread per trajectory: the one-track state is a recursion
+        const int it = ((int)blockIdx.x - 1) * WG + (int)threadIdx.x;
+        if (it < o.T) one_track_trajectory(o, vals, poses, it);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
@@ -144,8 +221,14 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
     const bool vehicle = o.kind == KIND_VEHICLE;
     const double u = vals[o.u_off + k];
     const double w = vals[o.w_off + l];
+    // pedestrians: kinematic model (speed u, heading offset w) or the
+    // acceleration model (acceleration u, absolute heading w, speed clamped
+    // to [0, v_max]: after the first step v_n = clamp(v_1 + (n-1) u tau))
+    const bool ped_accel = o.model == MODEL_PED_ACCEL;
     double ped_c = 0.0, ped_s = 0.0;
-    if (!vehicle) sincos(o.heading + w, &ped_s, &ped_c);
+    if (!vehicle) sincos(ped_accel ? w : o.heading + w, &ped_s, &ped_c);
+    const double v_max = o.params[0];
+    const double v_first = ped_accel ? fmin(fmax(o.speed + u * tau, 0.0), v_max) : 0.0;
     double cx = o.x, cy = o.y;
     for (int n0 = 0; n0 < H; n0 += 64) {
         const int n = n0 + lane;
@@ -175,6 +258,13 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
                 dy = sn * v * tau + sn * ax * half_tau2 + cn * ay * half_tau2;
                 c_next = (float)c1;
                 s_next = (float)s1;
+            } else if (ped_accel) {
+                // step n -> n+1 moves by the mean of the two speeds
+                const double vn = n == 0 ? o.speed : fmin(fmax(v_first + (double)(n - 1) * u * tau, 0.0), v_max);
+                const double vn1 = fmin(fmax(v_first + (double)n * u * tau, 0.0), v_max);
+                const double dist = (vn + vn1) * (tau / 2.0);
+                dx = ped_c * dist;
+                dy = ped_s * dist;
             } else {
                 dx = ped_c * u * tau;
                 dy = ped_s * u * tau;

@@ -11,6 +11,7 @@
 namespace mhc {
 
 enum Kind : int32_t { KIND_VEHICLE = 0, KIND_PEDESTRIAN = 1 };
+enum Model : int32_t { MODEL_KINEMATIC = 0, MODEL_PED_ACCEL = 1, MODEL_ONE_TRACK = 2 };
 
 // Shape class of an object pair: which overlap test applies and which side
 // holds the rectangle or polygon.
@@ -51,7 +52,8 @@ struct DObj {
     int32_t has_score, H;
     int32_t local, n_scene_obj;   // index within its scene, object count of the scene
     int32_t risk, timeline;       // RiskModel of its scene; 1: time-resolved risk
-    int32_t tl_w, pad0;           // time-resolved: lanes per trajectory, the power of two >= n_scene_obj
+    int32_t tl_w;                 // time-resolved: lanes per trajectory, the power of two >= n_scene_obj
+    int32_t model;                // motion model (mhc.h MHC_MODEL_*)
     int64_t traj_off;             // index of trajectory 0 in the p / traj_crit arrays
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
@@ -65,6 +67,7 @@ struct DObj {
     int64_t tl_att;               // attrib index of (this object, b = 0)
     double x, y, heading, speed;
     double tau;
+    double params[6];             // motion-model parameters
 };
 
 // One object pair (a < b within its scene). The collision kernel covers the

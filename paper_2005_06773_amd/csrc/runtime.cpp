@@ -137,6 +137,20 @@ bool validate_scene(const mhc_scene *s, std::string &err, int scene_index)
         if (!finite(o.x) || !finite(o.y) || !finite(o.heading) || !finite(o.speed))
             return fail("object %d: state must be finite", a);
         if (!(o.speed >= 0.0)) return fail("object %d: speed must be >= 0", a);
+        if (o.model != MHC_MODEL_KINEMATIC && o.model != MHC_MODEL_PED_ACCEL && o.model != MHC_MODEL_ONE_TRACK)
+            return fail("object %d: model must be 0, 1 or 2", a);
+        if (o.model == MHC_MODEL_PED_ACCEL) {
+            if (o.kind != MHC_PEDESTRIAN) return fail("object %d: the acceleration model is for pedestrians", a);
+            if (!finite(o.params[0]) || !(o.params[0] > 0.0)) return fail("object %d: v_max must be finite and > 0", a);
+        }
+        if (o.model == MHC_MODEL_ONE_TRACK) {
+            if (o.kind != MHC_VEHICLE) return fail("object %d: the one-track model is for vehicles", a);
+            for (int k = 0; k < 6; ++k)
+                if (!finite(o.params[k]) || !(o.params[k] > 0.0))
+                    return fail("object %d: one-track parameters must be finite and > 0", a);
+            if (o.params[3] * o.params[1] < o.params[2] * o.params[0])
+                return fail("object %d: the one-track parameters must understeer (l_r c_r >= l_f c_f)", a);
+        }
         if (o.n_vertices != 0) {
             if (o.kind != MHC_VEHICLE) return fail("object %d: only vehicles take an outline", a);
             if (o.n_vertices < 3 || o.n_vertices > MHC_MAX_VERTICES)
@@ -244,6 +258,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.n_scene_obj = n;
             d.risk = s.risk;
             d.timeline = s.timeline;
+            d.model = o.model;
             if (s.timeline) {
                 int W = 1;
                 while (W < n) W <<= 1;
@@ -557,6 +572,7 @@ void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
             d.heading = o.heading;
             d.speed = o.speed;
             d.tau = s.dt;
+            for (int k = 0; k < 6; ++k) d.params[k] = o.params[k];
             std::copy(o.u, o.u + o.n_u, L.vals.begin() + d.u_off);
             std::copy(o.w, o.w + o.n_w, L.vals.begin() + d.w_off);
             if (o.score) std::copy(o.score, o.score + d.T, L.vals.begin() + d.score_off);
@@ -779,6 +795,7 @@ std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
         v.push_back(s->objects[a].n_w);
         v.push_back(s->objects[a].score != nullptr);
         v.push_back(s->objects[a].n_vertices);
+        v.push_back(s->objects[a].model);
     }
     return v;
 }

@@ -61,7 +61,8 @@ class mhc_object(ctypes.Structure):
                 ("length", _D), ("width", _D), ("radius", _D),
                 ("n_u", ctypes.c_int32), ("n_w", ctypes.c_int32),
                 ("u", _DP), ("w", _DP), ("score", _DP),
-                ("n_vertices", ctypes.c_int32), ("vertices", _DP)]
+                ("n_vertices", ctypes.c_int32), ("vertices", _DP),
+                ("model", ctypes.c_int32), ("params", ctypes.c_double * 6)]
 
 
 class mhc_scene(ctypes.Structure):
@@ -178,6 +179,11 @@ class CScene:
             objs[k].u = u.ctypes.data_as(_DP)
             objs[k].w = w.ctypes.data_as(_DP)
             objs[k].score = sc.ctypes.data_as(_DP) if sc is not None else None
+            objs[k].model = int(getattr(o, "model", 0))
+            prm = getattr(o, "params", None)
+            if prm is not None:
+                for j, val in enumerate(np.asarray(prm, np.float64).reshape(-1)[:6]):
+                    objs[k].params[j] = float(val)
             outline = getattr(o, "outline", None)
             if outline is not None:
                 ov = np.ascontiguousarray(np.asarray(outline, np.float64).reshape(-1))

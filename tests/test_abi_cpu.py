@@ -144,6 +144,17 @@ def _bad_scenes():
     out["repeated_vertex_outline"] = s
     s = sg.eleven_object_scene(0); s.objects = [s.objects[0], s.objects[7]]
     s.objects[1].outline = sg.car_outline(1.0, 1.0, 0.1); out["pedestrian_outline"] = s
+    s = base(); s.objects[1].model = 3; out["bad_model"] = s
+    s = base(); s.objects[1].model = sg.MODEL_PED_ACCEL; s.objects[1].params = np.array([2.7])
+    out["accel_model_on_a_vehicle"] = s
+    s = sg.models_scene(10); s.objects[7].params = np.array([0.0]); out["zero_v_max"] = s
+    s = sg.models_scene(10); s.objects[7].model = sg.MODEL_ONE_TRACK; out["one_track_on_a_pedestrian"] = s
+    s = sg.models_scene(10); s.objects[0].params = s.objects[0].params.copy(); s.objects[0].params[4] = -1.0
+    out["negative_mass"] = s
+    s = sg.models_scene(10); s.objects[0].params = s.objects[0].params.copy()
+    s.objects[0].params[2], s.objects[0].params[3] = 2.0, 0.5; out["oversteer"] = s
+    s = sg.models_scene(10); s.objects[0].params = s.objects[0].params.copy(); s.objects[0].params[5] = float("nan")
+    out["nan_inertia"] = s
     s = base(); s.timeline = 1; s.objects = [s.objects[k % 2] for k in range(65)]
     out["timeline_with_65_objects"] = s
     s = base(); s.overlap = sg.OVERLAP_PIP

@@ -238,6 +238,62 @@ def polygon_extra(mhc, ctx, sg, torch, steps=50):
     return rows
 
 
+def models_extra(mhc, ctx, sg, torch, steps=50):
+    """The paper's other motion models against the kinematic grids: the
+    11-object scene with one-track vehicles and accelerating pedestrians
+    (same grid sizes), and the Table I S2 scene with one-track vehicles:
+    whole-path step and each module's time (HIP events on the launch
+    stream). The one-track trajectories are a sequential recursion per
+    trajectory (a thread each), the kinematic ones a scan over steps."""
+    stream = torch.cuda.current_stream()
+    T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
+
+    def one_track_table_one():
+        s = sg.paper_scene(5, n_co=10)
+        for o in s.objects:
+            o.model = sg.MODEL_ONE_TRACK
+            o.params = sg.one_track_params(o.length)
+            o.u = sg.accel_grid(6, -9.7, 9.7)
+            o.w = sg.steer_grid(len(o.w))
+            o.score = sg.vehicle_scores(o.u, o.w)
+        return s
+    rows = []
+    for name, kin, mod in (("eleven_object", lambda: sg.eleven_object_scene(10), lambda: sg.models_scene(10)),
+                           ("table_one_s2", lambda: sg.paper_scene(5, n_co=10), one_track_table_one)):
+        row = {"workload": name}
+        for label, make in (("kinematic", kin), ("paper_models", mod)):
+            cs = mhc.CScene(make())
+            plan = mhc.mhc_plan_create(ctx, cs)
+            out, r = mhc.device_result(cs, first_hit=True, q=True)
+            for _ in range(5):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(steps):
+                mhc.mhc_plan_execute(plan, r, stream)
+            torch.cuda.synchronize()
+            step_us = (time.perf_counter() - a) * 1e6 / steps
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+            for k in range(steps):
+                ev[k][0].record(stream)
+                mhc.mhc_plan_execute_stages(plan, T, r, stream)
+                ev[k][1].record(stream)
+                mhc.mhc_plan_execute_stages(plan, C, r, stream)
+                ev[k][2].record(stream)
+                mhc.mhc_plan_execute_stages(plan, R, r, stream)
+                ev[k][3].record(stream)
+            torch.cuda.synchronize()
+            mods = [sum(e[m].elapsed_time(e[m + 1]) for e in ev) * 1e3 / steps for m in range(3)]
+            plan.close()
+            row[label] = {"step_us": step_us, "traj_us": mods[0], "collide_us": mods[1], "risk_us": mods[2]}
+        rows.append(row)
+        k_, m_ = row["kinematic"], row["paper_models"]
+        log(f"models {name}: kinematic step {k_['step_us']:.1f} us (trajectories {k_['traj_us']:.1f} us); "
+            f"one-track / pedestrian acceleration step {m_['step_us']:.1f} us (trajectories {m_['traj_us']:.1f} us, "
+            f"collide {m_['collide_us']:.1f} us)")
+    return rows
+
+
 def class_checks(scene):
     """Checks per test class and the algorithmic flops of one pass."""
     out = {"VV": 0, "VP": 0, "PP": 0, "VV_PIP": 0, "POLY": 0}
@@ -567,6 +623,7 @@ def main():
         result["table_one"] = table_one(mhc, ctx, sg, torch)
         result["timeline"] = timeline_extra(mhc, ctx, sg, torch)
         result["polygons"] = polygon_extra(mhc, ctx, sg, torch)
+        result["models"] = models_extra(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)

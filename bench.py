@@ -327,17 +327,32 @@ def class_checks(scene):
 
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
-WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip")
+WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "eleven_object_octagons",
+             "eleven_object_timeline", "eleven_object_models")
 
 
 def make_workload(name, seed, sg):
     """(scene, metric label, config, description) of a timed workload."""
-    if name == "eleven_object":
-        scene = sg.eleven_object_scene(seed)
+    if name.startswith("eleven_object"):
+        variant = name[len("eleven_object"):].lstrip("_") or "plain"
+        scene = {"plain": sg.eleven_object_scene, "octagons": sg.polygon_scene,
+                 "models": sg.models_scene, "timeline": sg.eleven_object_scene}[variant](seed)
+        if variant == "timeline":
+            scene.timeline = 1
         cfg = {"workload": "eleven_object_scene", "objects": 11, "vehicles": 6, "pedestrians": 5,
                "trajectories_per_object": 225, "horizon": 30, "dt": 0.1, "seed": seed, "pairs": "all",
                "overlap": "exact"}
-        return scene, "11-object scene", cfg, f"11-object scene seed {seed}"
+        label = "11-object scene"
+        if variant == "octagons":
+            cfg["vehicle_shape"] = "octagonal outline (corners cut 0.35 m)"
+            label += ", octagonal cars"
+        elif variant == "timeline":
+            cfg["risk_over_time"] = True
+            label += ", risk over time"
+        elif variant == "models":
+            cfg["motion_models"] = "one-track vehicles, accelerating pedestrians capped at 2.7 m/s"
+            label += ", one-track / pedestrian acceleration models"
+        return scene, label, cfg, f"{label} seed {seed}"
     pip = name.endswith("_pip")
     scene = sg.paper_scene(seed, n_co=10, n_acc=6, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
     cfg = {"workload": "table_one_s2_scene", "objects": 11, "vehicles": 11, "pedestrians": 0,
@@ -477,7 +492,8 @@ def main():
               "(the path would shard object pairs across GPUs, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     if args.seed is None:
-        args.seed = 1 if args.workload == "eleven_object" else 5
+        args.seed = {"eleven_object": 1, "eleven_object_octagons": 1, "eleven_object_timeline": 1,
+                     "eleven_object_models": 10}.get(args.workload, 5)
 
     import torch
     from paper_2005_06773_amd import mhc, scenegen as sg

@@ -131,11 +131,17 @@ __device__ void one_track_trajectory(const DObj &o, const double *__restrict__ v
     const double K = m * (lr * cr - lf * cf) / (L * L * cf * cr);
     const double cd = cr * lr - cf * lf;
     const double cq = cf * lf * lf + cr * lr * lr;
+    // the model's coefficients without their speed factors
+    const double kb = (cf + cr) / m, kc = cd / m, kf = cf / m;       // beta'
+    const double kcz = cd / Iz, kq = cq / Iz, kfz = cf * lf / Iz;   // r'
+    const double lr_L = lr / L, mlf_crL2 = m * lf / (cr * L * L);    // steady state
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double accel = vals[o.u_off + k];
     const double delta = vals[o.w_off + l];
     const double tau = o.tau, h2 = tau * tau / 2.0;
     double x = o.x, y = o.y, psi = o.heading, v = o.speed, beta = 0.0, r = 0.0;
+    double sp, cp;
+    sincos(psi, &sp, &cp);
     float4 *out = reinterpret_cast<float4 *>(poses + o.pose_off);
     for (int n = 0; n < o.H; ++n) {
         double vdot = accel;
@@ -145,28 +151,28 @@ __device__ void one_track_trajectory(const DObj &o, const double *__restrict__ v
             v1 = 0.0;
         }
         bool stable = false;
+        const double iv = v > 0.0 ? 1.0 / v : 0.0;
         if (v > 0.0) {
-            const double m11 = 1.0 - tau * (cf + cr) / (m * v), m12 = tau * (cd / (m * v * v) - 1.0);
-            const double m21 = tau * cd / Iz, m22 = 1.0 - tau * cq / (Iz * v);
+            const double m11 = 1.0 - tau * kb * iv, m12 = tau * (kc * iv * iv - 1.0);
+            const double m21 = tau * kcz, m22 = 1.0 - tau * kq * iv;
             const double tr = m11 + m22, det = m11 * m22 - m12 * m21;
             stable = det < 1.0 && tr < 1.0 + det && tr > -(1.0 + det);
         }
         double beta1, r1, beta_dot, r_dot;
         if (stable) {
-            beta_dot = -(cf + cr) / (m * v) * beta + (cd / (m * v * v) - 1.0) * r + cf / (m * v) * delta;
-            r_dot = cd / Iz * beta - cq / (Iz * v) * r + cf * lf / Iz * delta;
+            beta_dot = -kb * iv * beta + (kc * iv * iv - 1.0) * r + kf * iv * delta;
+            r_dot = kcz * beta - kq * iv * r + kfz * delta;
             beta1 = beta + beta_dot * tau;
             r1 = r + r_dot * tau;
         } else {
             const double g = 1.0 + K * v1 * v1;
             r1 = v1 * delta / (L * g);
-            beta1 = delta * (lr / L - m * lf * v1 * v1 / (cr * L * L)) / g;
+            beta1 = delta * (lr_L - mlf_crL2 * v1 * v1) / g;
             beta_dot = (beta1 - beta) / tau;
             r_dot = (r1 - r) / tau;
         }
-        double sb, cb, sp, cp;
+        double sb, cb;
         sincos(beta, &sb, &cb);
-        sincos(psi, &sp, &cp);
         const double spb = sp * cb + cp * sb, cpb = cp * cb - sp * sb;   // psi + beta
         const double ax = cb * vdot - sb * v * (beta_dot + r);
         const double ay = sb * vdot + cb * v * (beta_dot + r);
@@ -176,9 +182,8 @@ __device__ void one_track_trajectory(const DObj &o, const double *__restrict__ v
         v = v1;
         beta = beta1;
         r = r1;
-        double s1, c1;
-        sincos(psi, &s1, &c1);
-        out[(size_t)n * o.T + i] = make_float4((float)x, (float)y, (float)c1, (float)s1);
+        sincos(psi, &sp, &cp);   // this pose, and the next step's heading
+        out[(size_t)n * o.T + i] = make_float4((float)x, (float)y, (float)cp, (float)sp);
     }
 }
 

@@ -328,7 +328,7 @@ def class_checks(scene):
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
 WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "eleven_object_octagons",
-             "eleven_object_timeline", "eleven_object_models")
+             "eleven_object_timeline", "eleven_object_models", "stress")
 
 
 def make_workload(name, seed, sg):
@@ -353,6 +353,12 @@ def make_workload(name, seed, sg):
             cfg["motion_models"] = "one-track vehicles, accelerating pedestrians capped at 2.7 m/s"
             label += ", one-track / pedestrian acceleration models"
         return scene, label, cfg, f"{label} seed {seed}"
+    if name == "stress":
+        scene = sg.stress_scene(seed)
+        cfg = {"workload": "stress_scene", "objects": 40, "vehicles": 24, "pedestrians": 16,
+               "trajectories_per_object": 1024, "horizon": 50, "dt": 0.1, "seed": seed, "pairs": "all",
+               "overlap": "exact"}
+        return scene, "40-object stress scene", cfg, f"40-object stress scene seed {seed}"
     pip = name.endswith("_pip")
     scene = sg.paper_scene(seed, n_co=10, n_acc=6, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
     cfg = {"workload": "table_one_s2_scene", "objects": 11, "vehicles": 11, "pedestrians": 0,
@@ -393,23 +399,30 @@ def pct(xs, q):
     return xs[k]
 
 
-def cpu_baseline(scene, checks, seconds, described):
-    """The FP64 oracle as it stands, on the host cores (rank 0, N=1 only)."""
+def cpu_baseline(scene, checks, seconds, described, pair_list=None):
+    """The FP64 oracle as it stands, on the host cores (rank 0, N=1 only).
+    ``pair_list`` restricts it to a sample of object pairs (the stress scene,
+    whose full pass takes the oracle minutes); the rate is then the sample's
+    checks per second."""
     import oracle
     oracle.lib()
     cores = min(16, os.cpu_count() or 1)
+    if pair_list is not None:
+        T = scene.traj_counts()
+        checks = sum(T[a] * T[b] for a, b in pair_list) * scene.horizon
     t0 = time.perf_counter()
     runs = 0
     while True:
-        oracle.evaluate(scene, threads=cores, masks=False)
+        oracle.evaluate(scene, pair_list=pair_list, threads=cores, masks=False)
         runs += 1
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
     value = checks * runs / dt
     log(f"cpu baseline: {runs} oracle runs in {dt:.2f} s on {cores} threads -> {value:.4g} checks/s")
+    what = "the full timed scene" if pair_list is None else f"{len(pair_list)} sampled object pairs of"
     return {"value": value, "unit": "checks/s", "cores": cores, "kind": "oracle",
-            "sample": f"the full timed scene ({described}), {runs} complete oracle passes "
+            "sample": f"{what} ({described}), {runs} complete oracle passes "
                       f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s"}
 
 
@@ -469,6 +482,153 @@ def serve(mhc, ctx, sg, seconds):
     return out
 
 
+def stress_extra(mhc, ctx, sg, torch, steps=10):
+    """The 40-object stress scene (24 vehicles + 16 pedestrians, 32 x 32
+    grids, 50 steps, 40,894,464,000 checks): whole-path step and collision
+    kernel alone, with and without the 1.64 GB first-hit output."""
+    stream = torch.cuda.current_stream()
+    s = sg.stress_scene(4)
+    cs = mhc.CScene(s)
+    checks = mhc.mhc_query_sizes(cs)["n_checks"]
+    flops = class_checks(s)[1]
+    best, us = mhc.mhc_autotune(ctx, cs, reps=3)
+    out = {"workload": "stress_scene", "objects": 40, "trajectories_per_object": 1024, "horizon": 50,
+           "checks": checks, "tile_variant": best}
+    for fh in (False, True):
+        plan = mhc.mhc_plan_create(ctx, cs)
+        outs, r = mhc.device_result(cs, first_hit=fh, q=True)
+        for _ in range(2):
+            mhc.mhc_plan_execute(plan, r, stream)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(steps):
+            mhc.mhc_plan_execute(plan, r, stream)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - a) * 1e3 / steps
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for k in range(steps):
+            mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_TRAJ, r, stream)
+            ev[k][0].record(stream)
+            mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_COLLIDE, r, stream)
+            ev[k][1].record(stream)
+            mhc.mhc_plan_execute_stages(plan, mhc.MHC_STAGE_RISK, r, stream)
+        torch.cuda.synchronize()
+        k2_ms = sum(x.elapsed_time(y) for x, y in ev) / steps
+        plan.close()
+        del outs, r
+        key = "with_first_hit" if fh else "criticality_only"
+        out[key] = {"step_ms": step_ms, "checks_per_s": checks / (step_ms * 1e-3), "collide_ms": k2_ms,
+                    "collide_tflops": flops / (k2_ms * 1e-3) / 1e12}
+        log(f"stress scene ({key}): step {step_ms:.2f} ms ({checks / (step_ms * 1e-3):.4g} checks/s), "
+            f"collide {k2_ms:.2f} ms ({flops / (k2_ms * 1e-3) / 1e12:.1f} TFLOP/s)")
+    torch.cuda.empty_cache()
+    return out
+
+
+def serve_sweep(mhc, ctx, sg, seconds, streams_list=(32, 128, 256, 384, 512, 640, 768, 896, 1024, 1280)):
+    """Served load sweep: the serving workload with more and more 10 Hz
+    Poisson streams until the p99 latency passes the 50 ms deadline. Frames
+    come from a pool of 512 drawn as in the batched workload (seed 3) and are
+    submitted in real time; latency runs from each frame's scheduled arrival
+    (the server's own monotonic clock) to its results in host memory, so a
+    submitter that falls behind counts against the server. Reports, per load,
+    p50/p99 and the completed checks per second, and the largest sustained
+    rate whose p99 meets the deadline."""
+    import ctypes
+    import threading
+    import numpy as np
+    scenes = sg.batch_scenes(3, 512)
+    pool = [mhc.CScene(s) for s in scenes]
+    pool_checks = [mhc.mhc_query_sizes(c)["n_checks"] for c in pool]
+    n_max = max(s.n_objects for s in scenes)
+    t_max = max(mhc.mhc_query_sizes(c)["n_traj"] for c in pool)
+    ring = 2048
+    bufs = [(np.empty(n_max), np.empty(t_max)) for _ in range(ring)]
+    dsts = [mhc.mhc_result(oc.ctypes.data, tc.ctypes.data, *([None] * (len(mhc.RESULT_FIELDS) - 2)))
+            for oc, tc in bufs]
+    warm, rate, deadline = 0.5, 10.0, 50.0
+    points, best = [], None
+    for streams in streams_list:
+        rng = np.random.default_rng(1000 + streams)
+        arr, sid = [], []
+        for s in range(streams):
+            t = float(rng.uniform(0.0, 0.1))
+            gaps = rng.exponential(1.0 / rate, int((warm + seconds) * rate * 3) + 20)
+            ts = t + np.concatenate([[0.0], np.cumsum(gaps)])
+            arr.append(ts[ts < warm + seconds])
+            sid.append(np.full(arr[-1].size, s))
+        order = np.argsort(np.concatenate(arr), kind="stable")
+        arrivals = np.concatenate(arr)[order]
+        stream_of = np.concatenate(sid)[order]
+        which = rng.integers(0, len(pool), arrivals.size)
+        srv = mhc.Server(ctx, budget=4 << 30, inflight=2)
+        n = arrivals.size
+        tickets = [0] * n
+        done_ns = [0] * n
+        submitted = [0]
+        completed = [0]
+        busy = [0]
+
+        def waiter():
+            tm = mhc.mhc_timing()
+            for k in range(n):
+                while submitted[0] <= k:
+                    time.sleep(0.0002)
+                if tickets[k] < 0:
+                    completed[0] = k + 1
+                    continue
+                st = mhc.lib.mhc_wait(srv.h, tickets[k], -1, ctypes.byref(tm))
+                if st != mhc.MHC_OK:
+                    raise RuntimeError(f"mhc_wait: {st}")
+                done_ns[k] = tm.done_ns
+                completed[0] = k + 1
+
+        w = threading.Thread(target=waiter)
+        w.start()
+        t0 = time.monotonic_ns()
+        tk = ctypes.c_uint64()
+        for k in range(n):
+            at = t0 + int(arrivals[k] * 1e9)
+            while time.monotonic_ns() < at:
+                time.sleep(0.00005)
+            while completed[0] <= k - ring:          # the ring slot is still in flight
+                if not w.is_alive():
+                    raise RuntimeError("served sweep: waiter thread ended early")
+                time.sleep(0.0002)
+            st = mhc.lib.mhc_submit(srv.h, int(stream_of[k]), ctypes.byref(pool[which[k]].c),
+                                    ctypes.byref(dsts[k % ring]), ctypes.byref(tk))
+            if st == mhc.MHC_E_BUSY:
+                tickets[k] = -1
+                busy[0] += 1
+            elif st != mhc.MHC_OK:
+                raise mhc.MhcError(st, mhc.mhc_last_error(ctx))
+            else:
+                tickets[k] = tk.value
+            submitted[0] = k + 1
+        w.join()
+        srv.stop()
+        sel = [k for k in range(n) if arrivals[k] >= warm]
+        lat = [(done_ns[k] - (t0 + int(arrivals[k] * 1e9))) * 1e-6 if tickets[k] >= 0 else float("inf")
+               for k in sel]
+        span = max(done_ns[k] for k in sel if tickets[k] >= 0) - (t0 + int(warm * 1e9))
+        chk = sum(pool_checks[which[k]] for k in sel if tickets[k] >= 0)
+        pt = {"streams": streams, "frames": len(sel), "rejected_busy": busy[0],
+              "offered_checks_per_s": sum(pool_checks[which[k]] for k in sel) / seconds,
+              "completed_checks_per_s": chk / (span * 1e-9),
+              "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
+              "within_deadline": sum(x <= deadline for x in lat) / len(lat)}
+        points.append(pt)
+        log(f"served sweep: {streams} streams, {len(sel)} frames, p50 {pt['p50_ms']:.2f} ms p99 "
+            f"{pt['p99_ms']:.2f} ms, {pt['completed_checks_per_s']:.4g} checks/s")
+        if pt["p99_ms"] > deadline:
+            break
+        best = pt
+    return {"rate_hz_per_stream": rate, "seconds_per_point": seconds, "deadline_ms": deadline,
+            "pool_frames": len(pool), "points": points,
+            "max_sustained_checks_per_s_within_deadline": None if best is None else best["completed_checks_per_s"],
+            "at_streams": None if best is None else best["streams"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +642,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the latency and batched measurements")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="length of the served-load measurement (after 1 s of warm-up)")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=1.5,
+                    help="length of each point of the served load sweep (0: no sweep)")
     ap.add_argument("--variant", type=int, default=-1,
                     help="force a collision micro-tile variant (default: autotune on the workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -493,7 +655,7 @@ def main():
         sys.exit(2)
     if args.seed is None:
         args.seed = {"eleven_object": 1, "eleven_object_octagons": 1, "eleven_object_timeline": 1,
-                     "eleven_object_models": 10}.get(args.workload, 5)
+                     "eleven_object_models": 10, "stress": 4}.get(args.workload, 5)
 
     import torch
     from paper_2005_06773_amd import mhc, scenegen as sg
@@ -636,16 +798,20 @@ def main():
             f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
 
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
+        if args.serve_sweep_seconds > 0:
+            result["served_sweep"] = serve_sweep(mhc, ctx, sg, args.serve_sweep_seconds)
         result["table_one"] = table_one(mhc, ctx, sg, torch)
         result["timeline"] = timeline_extra(mhc, ctx, sg, torch)
         result["polygons"] = polygon_extra(mhc, ctx, sg, torch)
         result["models"] = models_extra(mhc, ctx, sg, torch)
+        result["stress"] = stress_extra(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scene, checks, args.cpu_seconds, described)
+        sample = sg.stress_sample_pairs(scene.n_objects, 20, 1004) if args.workload == "stress" else None
+        result["cpu_baseline"] = cpu_baseline(scene, checks, args.cpu_seconds, described, sample)
     print(json.dumps(result), flush=True)
 
 

@@ -279,6 +279,33 @@ mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int3
 mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path);
 mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path);
 
+/* ---- collision plan check (host only) ----------------------------------- */
+
+/* The collision work of n scenes is cut into units (a wave's items of one
+ * object pair: row-major runs of the pair's item grid, or 2-D blocks of it)
+ * that the host deals to the waves of the collision kernel (Sec. IV-C: every
+ * trajectory of one object against every trajectory of another, at every
+ * step). mhc_plan_check builds the plan the library would launch for tile
+ * variant `variant` (0 .. MHC_N_VARIANTS-1) with `max_waves` resident waves
+ * (0: one wave per unit) and walks it on the host the way the kernel decodes
+ * it. It needs no GPU. MHC_OK when every trajectory pair of every object pair
+ * is tested by exactly one thread and every index a thread derives (items,
+ * trajectories, steps, first-hit entries) lies inside its pair; MHC_E_INVAL
+ * for an invalid scene or argument (info untouched) or a plan that fails the
+ * check (info filled). */
+typedef struct {
+    int64_t n_units;        /* collision units of the plan */
+    int64_t n_waves;        /* wave slots the units are dealt to */
+    int64_t blocked_pairs;  /* object pairs whose units are 2-D blocks of items */
+    int64_t uncovered;      /* items tested by no thread (0 when the plan is sound) */
+    int64_t repeated;       /* items tested more than once (0 when sound) */
+    int64_t out_of_range;   /* threads deriving an index outside their pair (0 when sound) */
+    int32_t contiguous;     /* 1: waves take contiguous stretches of the unit sequence */
+    int32_t pad;
+} mhc_plan_info;
+mhc_status mhc_plan_check(int32_t n_scenes, const mhc_scene *scenes, int32_t variant, int32_t max_waves,
+                          mhc_plan_info *info);
+
 /* ---- batched ----------------------------------------------------------- */
 
 /* Evaluates n scenes of any shapes in one persistent collision launch inside a

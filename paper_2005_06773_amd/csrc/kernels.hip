@@ -559,7 +559,25 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     const int per = WAVE >> tshift;
     const int part = lane >> (6 - tshift);
     const int chunk = pr.H >> tshift;
-    const int f = item0 + (lane & (per - 1));
+    const int e = lane & (per - 1);
+    // Item of this lane. Row-major units (bshift = 0) hold the items
+    // item0 .. item0 + E-1; a block unit v is the block (v / nb, v % nb) of
+    // E / 2^bshift rows and 2^bshift columns, which is the same as the
+    // row-major decode of item (first row of the block) * n_jg + first column
+    // + (e / 2^bshift) * n_jg + e % 2^bshift.
+    const int bs = pr.bshift;
+    int f;
+    if (bs == 0) {
+        f = item0 + e;
+    } else {
+        const int v = item0 >> (6 - tshift);
+        const int nb = (n_jg + (1 << bs) - 1) >> bs;
+        const int bi = v / nb;
+        const int c0 = (v - bi * nb) << bs;                // first column of the block
+        const int col = c0 + (e & ((1 << bs) - 1));
+        // a column past the grid's edge is an idle lane
+        f = col < n_jg ? (((bi << (6 - tshift)) >> bs) + (e >> bs)) * n_jg + col : INT_MAX;
+    }
     if (f >= n_ig * n_jg) return;  // every part of an item leaves together
     const int ig = f / n_jg;
     const int jg = f - ig * n_jg;
@@ -789,8 +807,15 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 // load-heavy and arithmetic-heavy test classes on every CU. The host
 // balances the slots by the exact instruction cost of the work, so every
 // SIMD finishes together without any cross-XCD atomics.
+// The plain-class instances are held to at least 5 waves per SIMD and the
+// point-in-polygon ones to 4: with fewer the vector ALU idles on pose loads,
+// and without the bound the compiler's occupancy heuristic may trade a wave
+// for registers it does not need.
+template <int FAM>
+constexpr int kCollideMinWaves = FAM == FAM_PLAIN ? 5 : FAM == FAM_PIP ? 4 : 1;
+
 template <int V, int FAM, bool TL>
-__global__ __launch_bounds__(WG) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinWaves<FAM>))) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,

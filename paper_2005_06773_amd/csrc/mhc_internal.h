@@ -91,17 +91,23 @@ struct DPair {
     int32_t timeline;             // 1: q sums go to the per-slot sums below
     int32_t hwa, hwb;             // lanes per trajectory of a's and of b's per-slot sums
     int32_t poly_a, poly_b;       // DPoly of a and of b (polygon classes), else -1
-    int32_t pad1;
+    int32_t bshift;               // unit shape: 0 = E consecutive items of the row-major item grid;
+                                  // else blocks of (E >> bshift) item rows x 2^bshift item columns
     int64_t ha0;                  // slot-sum index of (a: s = 0, i = 0, b); slot s, trajectory i at + (s*Ta + i)*hwa
     int64_t hb0;                  // slot-sum index of (b: s = 0, j = 0, a); + (s*Tb + j)*hwb
 };
 
 // A run of collision work for one wave: n_units consecutive units of a pair.
-// A unit is the E = 64 / S consecutive items item0 + E*u .. item0 + E*u + E-1
-// of a pair with time split S: lane l takes item item0 + E*u + l % E and the
-// steps [p*H/S, (p+1)*H/S) of part p = l / E, so the S parts of an item run
-// side by side in one wave (items past the pair's end are idle lanes). The
-// host assigns every wave of the collision kernel a range of segments.
+// A pair's items (ig, jg) form an n_ig x n_jg grid; with time split S a unit
+// holds E = 64 / S of them, and lane l takes item l % E of unit item0 / E + u
+// and the steps [p*H/S, (p+1)*H/S) of part p = l / E, so the S parts of an
+// item run side by side in one wave. With bshift = 0 the items of unit v are
+// E*v .. E*v + E-1 in row-major order; otherwise unit v is the block
+// (v / nb, v % nb) of the grid cut into blocks of E / 2^bshift rows and
+// 2^bshift columns (nb blocks per block row), so that a wave reads few
+// distinct poses of either object per step. Items past the grid are idle
+// lanes. The host assigns every wave of the collision kernel a range of
+// segments.
 struct WorkItem {
     int32_t pair;
     int32_t item0;

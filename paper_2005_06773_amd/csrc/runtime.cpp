@@ -75,6 +75,38 @@ static const int kContiguousUnitsPerWave = 8;
 // (measured on the 11-object scene: 40.5 us with S = 2 against 37.0 us).
 static const double kSplitBelowUnitsPerWave = 0.75;
 
+// Collision units of a pair with time split 2^tshift (E = 64 >> tshift items
+// per unit): E consecutive items of the row-major item grid (bshift = 0), or
+// blocks of E >> bshift item rows by 2^bshift item columns.
+static int64_t pair_units(const DPair &pr, int tshift, int bshift)
+{
+    const int64_t per = WAVE >> tshift;
+    if (bshift == 0) return ((int64_t)pr.n_ig * pr.n_jg + per - 1) / per;
+    const int64_t rows = per >> bshift, cols = (int64_t)1 << bshift;
+    return ((pr.n_ig + rows - 1) / rows) * ((pr.n_jg + cols - 1) / cols);
+}
+
+// Unit shape of a pair. A row-major unit reads, at every step, the poses of
+// one or two a-items and of E b-items; a block of 8 x 8 items reads 8 of each,
+// about a third of the cache lines, which matters once the scene's poses no
+// longer fit in an XCD's L2. Blocks are taken where they add at most 1/32 of
+// idle lanes (grids whose sides are near multiples of the block's).
+static int unit_shape(const DPair &pr, int tshift)
+{
+    const int64_t lin = pair_units(pr, tshift, 0);
+    int best = 0;
+    int64_t best_u = 0;
+    for (int bs = 3; bs <= 4; ++bs) {  // 8 or 16 item columns
+        if (((WAVE >> tshift) >> bs) < 1) break;
+        const int64_t u = pair_units(pr, tshift, bs);
+        if (u * 32 <= lin * 33 && (best == 0 || u < best_u)) {
+            best = bs;
+            best_u = u;
+        }
+    }
+    return best;
+}
+
 static bool finite(double v) { return std::isfinite(v); }
 
 // ---------------------------------------------------------------------------
@@ -354,15 +386,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     // packing below can spread evenly and which fill the GPU. S is the
     // smallest of 1, 2, 4 that gives enough units (4 for the size bound,
     // max_waves = 0), lowered per pair until it divides the horizon.
-    auto units_with = [](const DPair &pr, int tshift) {
-        const int64_t per = WAVE >> tshift;
-        return ((int64_t)pr.n_ig * pr.n_jg + per - 1) / per;
-    };
     int want = MAX_TSHIFT;
     if (max_waves > 0) {
         for (want = 0; want < MAX_TSHIFT; ++want) {
             int64_t u = 0;
-            for (const DPair &pr : L.pairs) u += units_with(pr, want);
+            for (const DPair &pr : L.pairs) u += pair_units(pr, want, 0);
             if ((double)u >= kSplitBelowUnitsPerWave * max_waves) break;
         }
     }
@@ -371,12 +399,13 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         int sh = want;
         while (sh > 0 && (pr.H % (1 << sh)) != 0) --sh;
         pr.tshift = sh;
+        pr.bshift = unit_shape(pr, sh);
         const TileShape ts = kTiles[variant][pr.cls];
         const int ka = pr.poly_a >= 0 ? pair_vertices[2 * pidx] : 0, kb = pr.poly_b >= 0 ? pair_vertices[2 * pidx + 1] : 0;
         // a wave executes every step of every test of a unit, whether or
         // not all of its lanes hold an item
         const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * class_cost(pr.cls, ka, kb) + kUnitOverhead;
-        costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)units_with(pr, sh)});
+        costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)pair_units(pr, sh, pr.bshift)});
     }
 
     // Collision plan: every wave slot gets a list of segments of work units.
@@ -769,6 +798,115 @@ extern "C" mhc_status mhc_query_sizes(const mhc_scene *scene, mhc_sizes *out)
     out->n_checks = L.n_checks;
     out->device_bytes = bytes;
     return MHC_OK;
+}
+
+// Walks a collision plan the way k2_collide decodes it: wave slot -> segments
+// -> units -> lanes -> items -> trajectory pairs and steps, counting how often
+// each item is tested and every index that leaves its pair.
+static void walk_plan(const Layout &L, mhc_plan_info &info)
+{
+    std::vector<int64_t> item_base(L.pairs.size() + 1, 0);
+    for (size_t p = 0; p < L.pairs.size(); ++p)
+        item_base[p + 1] = item_base[p] + (int64_t)L.pairs[p].n_ig * L.pairs[p].n_jg;
+    std::vector<uint8_t> seen((size_t)item_base.back(), 0);
+    const int n_bins = (int)L.bins.size() - 1;
+    int64_t bad = 0, units = 0;
+    if (n_bins < 1 || L.bins[0] != 0 || L.bins[n_bins] != (int32_t)L.work.size()) ++bad;
+    for (int b = 0; b < n_bins && !bad; ++b) {
+        if (L.bins[b + 1] < L.bins[b]) {
+            ++bad;
+            break;
+        }
+        for (int32_t wi = L.bins[b]; wi < L.bins[b + 1]; ++wi) {
+            const WorkItem &w = L.work[wi];
+            if (w.pair < 0 || w.pair >= (int32_t)L.pairs.size() || w.n_units < 0) {
+                ++bad;
+                continue;
+            }
+            const DPair &pr = L.pairs[w.pair];
+            const int per = WAVE >> pr.tshift;
+            const int chunk = pr.H >> pr.tshift;
+            const TileShape ts = kTiles[L.variant][pr.cls];
+            const int ri = ts.ri, rj = ts.rj;
+            if (chunk << pr.tshift != pr.H || w.item0 % per != 0) ++bad;
+            const int64_t n_units = pair_units(pr, pr.tshift, pr.bshift);
+            for (int32_t u = 0; u < w.n_units; ++u) {
+                ++units;
+                const int64_t item0 = (int64_t)w.item0 + (int64_t)u * per;
+                const int64_t v = item0 / per;
+                if (v >= n_units) ++bad;
+                for (int lane = 0; lane < WAVE; ++lane) {
+                    const int part = lane >> (6 - pr.tshift);
+                    const int e = lane & (per - 1);
+                    int64_t ig, jg;
+                    if (pr.bshift == 0) {
+                        const int64_t f = item0 + e;
+                        if (f >= (int64_t)pr.n_ig * pr.n_jg) continue;
+                        ig = f / pr.n_jg;
+                        jg = f - ig * pr.n_jg;
+                    } else {
+                        const int bs = pr.bshift;
+                        const int64_t nb = (pr.n_jg + (1 << bs) - 1) >> bs;
+                        const int64_t bi = v / nb;
+                        ig = ((bi << (6 - pr.tshift)) >> bs) + (e >> bs);
+                        jg = ((v - bi * nb) << bs) + (e & ((1 << bs) - 1));
+                        if (ig >= pr.n_ig || jg >= pr.n_jg) continue;
+                    }
+                    if (ig < 0 || jg < 0) {
+                        ++bad;
+                        continue;
+                    }
+                    // steps of this part: [part * chunk, part * chunk + chunk)
+                    if ((int64_t)(part + 1) * chunk > pr.H) ++bad;
+                    for (int r = 0; r < ri; ++r)
+                        for (int sidx = 0; sidx < rj; ++sidx) {
+                            const int64_t i = ig + (int64_t)r * pr.n_ig, j = jg + (int64_t)sidx * pr.n_jg;
+                            if (i >= pr.Ta || j >= pr.Tb) continue;  // idle tile slot
+                            const int64_t h = pr.hit_off + i * pr.Tb + j;
+                            if (h < 0 || h >= L.n_hits) ++bad;
+                            if (pr.qa0 + i * pr.qn >= L.n_q || pr.qb0 + j * pr.qn >= L.n_q) ++bad;
+                        }
+                    if (part == 0) {
+                        uint8_t &c = seen[(size_t)(item_base[w.pair] + ig * pr.n_jg + jg)];
+                        if (c < 255) ++c;
+                    }
+                }
+            }
+        }
+    }
+    int64_t uncovered = 0, repeated = 0;
+    for (uint8_t c : seen) {
+        uncovered += c == 0;
+        repeated += c > 1;
+    }
+    int64_t blocked = 0;
+    for (const DPair &pr : L.pairs) blocked += pr.bshift != 0;
+    info.n_units = units;
+    info.n_waves = n_bins;
+    info.blocked_pairs = blocked;
+    info.uncovered = uncovered;
+    info.repeated = repeated;
+    info.out_of_range = bad;
+    info.contiguous = L.contiguous ? 1 : 0;
+    info.pad = 0;
+}
+
+extern "C" mhc_status mhc_plan_check(int32_t n_scenes, const mhc_scene *scenes, int32_t variant, int32_t max_waves,
+                                     mhc_plan_info *info)
+{
+    if (n_scenes < 1 || !scenes || !info || variant < 0 || variant >= N_VARIANTS || max_waves < 0)
+        return MHC_E_INVAL;
+    std::string err;
+    int64_t total_objects = 0;
+    for (int k = 0; k < n_scenes; ++k) {
+        if (!validate_scene(&scenes[k], err, k)) return MHC_E_INVAL;
+        total_objects += scenes[k].n_objects;
+    }
+    if (total_objects > kMaxObjectsPerLaunch) return MHC_E_INVAL;
+    Layout L;
+    build_layout(scenes, n_scenes, variant, max_waves, L, true);
+    walk_plan(L, *info);
+    return info->uncovered == 0 && info->repeated == 0 && info->out_of_range == 0 ? MHC_OK : MHC_E_INVAL;
 }
 
 extern "C" mhc_status mhc_anticipation_time(int32_t n_frames, const double *crit, double frame_dt, double threshold,

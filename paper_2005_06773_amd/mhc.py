@@ -34,7 +34,7 @@ EXPORTED = [
     "mhc_evaluate", "mhc_evaluate_async",
     "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages", "mhc_plan_set_graph",
     "mhc_plan_download", "mhc_plan_destroy",
-    "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load",
+    "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load", "mhc_plan_check",
     "mhc_evaluate_batch",
     "mhc_server_start", "mhc_submit", "mhc_wait", "mhc_server_stats", "mhc_server_stop",
 ]
@@ -74,6 +74,12 @@ class mhc_scene(ctypes.Structure):
 class mhc_sizes(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("n_traj_pairs", ctypes.c_int64),
                 ("n_checks", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+class mhc_plan_info(ctypes.Structure):
+    _fields_ = [("n_units", ctypes.c_int64), ("n_waves", ctypes.c_int64), ("blocked_pairs", ctypes.c_int64),
+                ("uncovered", ctypes.c_int64), ("repeated", ctypes.c_int64), ("out_of_range", ctypes.c_int64),
+                ("contiguous", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 RESULT_FIELDS = ("object_crit", "traj_crit", "traj_prob", "q", "first_hit",
@@ -138,6 +144,8 @@ def _load():
                          ctypes.POINTER(ctypes.c_double)],
         "mhc_tune_save": [V, ctypes.c_char_p],
         "mhc_tune_load": [V, ctypes.c_char_p],
+        "mhc_plan_check": [ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(mhc_plan_info)],
         "mhc_evaluate_batch": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
         "mhc_server_start": [V, ctypes.POINTER(mhc_server_cfg), ctypes.POINTER(V)],
         "mhc_submit": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result),
@@ -250,6 +258,19 @@ def mhc_destroy(ctx):
 
 def mhc_last_error(ctx) -> str:
     return lib.mhc_last_error(ctx).decode()
+
+
+def mhc_plan_check(scenes, variant: int, max_waves: int = 0):
+    """(status, info dict) of the host-side walk of the collision plan for
+    ``scenes`` (a scene or a list) with tile variant ``variant`` and
+    ``max_waves`` resident waves (0: one wave per unit). No GPU needed."""
+    if not isinstance(scenes, (list, tuple)):
+        scenes = [scenes]
+    cs = [s if isinstance(s, CScene) else CScene(s) for s in scenes]
+    arr = (mhc_scene * len(cs))(*[c.c for c in cs])
+    info = mhc_plan_info()
+    st = lib.mhc_plan_check(len(cs), arr, variant, max_waves, ctypes.byref(info))
+    return st, {k: getattr(info, k) for k, _ in mhc_plan_info._fields_ if k != "pad"}
 
 
 def mhc_query_sizes(scene) -> dict:

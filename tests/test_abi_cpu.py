@@ -238,3 +238,46 @@ def test_outlines_accepted_and_sized(mhc):
         assert q["n_checks"] == 18_750
     s = sg.polygon_scene(9)
     assert mhc.mhc_query_sizes(s)["device_bytes"] > mhc.mhc_query_sizes(sg.eleven_object_scene(9))["device_bytes"]
+
+
+def _grid_scene(seed, n_veh, n_ped, side, horizon):
+    rng = np.random.default_rng(seed)
+    objs = [sg.draw_vehicle(rng, 30.0, 0.0, 15.0, side, side) for _ in range(n_veh)]
+    objs += [sg.draw_pedestrian(rng, 30.0, 0.0, 2.0, side, side) for _ in range(n_ped)]
+    return sg.Scene(objs, horizon, 0.1)
+
+
+@pytest.mark.parametrize("variant", range(4))
+def test_collision_plan_covers_every_item_once(mhc, variant):
+    """The host walk of the collision plan (as the kernel decodes it): every
+    trajectory pair of every object pair tested by exactly one thread, every
+    index inside its pair, for row-major and block units, time splits,
+    individually packed and contiguous plans, and batches."""
+    scenes = [sg.eleven_object_scene(1), sg.paper_scene(5, n_co=3), sg.polygon_scene(2),
+              _grid_scene(1, 4, 2, 32, 50),      # 32 x 32 grids: block units
+              _grid_scene(2, 3, 3, 24, 36),      # 24 x 24: block units with time splits
+              _grid_scene(3, 2, 2, 13, 20)]      # ragged grids: row-major units
+    blocked = 0
+    for s in scenes:
+        for waves in (0, 256, 2048, 6144):
+            st, info = mhc.mhc_plan_check(s, variant, waves)
+            assert st == mhc.MHC_OK, (variant, waves, info)
+            assert info["uncovered"] == info["repeated"] == info["out_of_range"] == 0
+            blocked += info["blocked_pairs"]
+    assert blocked > 0
+    batch = sg.batch_scenes(2, 12)
+    for waves in (0, 512, 8192):
+        st, info = mhc.mhc_plan_check(batch, variant, waves)
+        assert st == mhc.MHC_OK, (variant, waves, info)
+    st, info = mhc.mhc_plan_check(batch, variant, 256)
+    assert st == mhc.MHC_OK and info["contiguous"] == 1
+
+
+def test_collision_plan_check_rejects_bad_arguments(mhc):
+    s = sg.eleven_object_scene(0)
+    assert mhc.mhc_plan_check(s, -1, 0)[0] == mhc.MHC_E_INVAL
+    assert mhc.mhc_plan_check(s, mhc.MHC_N_VARIANTS, 0)[0] == mhc.MHC_E_INVAL
+    assert mhc.mhc_plan_check(s, 0, -5)[0] == mhc.MHC_E_INVAL
+    bad = sg.eleven_object_scene(0)
+    bad.horizon = 0
+    assert mhc.mhc_plan_check(bad, 0, 0)[0] == mhc.MHC_E_INVAL

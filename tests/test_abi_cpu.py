@@ -259,7 +259,7 @@ def test_collision_plan_covers_every_item_once(mhc, variant):
               _grid_scene(3, 2, 2, 13, 20)]      # ragged grids: row-major units
     blocked = 0
     for s in scenes:
-        for waves in (0, 256, 2048, 6144):
+        for waves in (0, 256, 2048, 5120, 6144, 7168):
             st, info = mhc.mhc_plan_check(s, variant, waves)
             assert st == mhc.MHC_OK, (variant, waves, info)
             assert info["uncovered"] == info["repeated"] == info["out_of_range"] == 0

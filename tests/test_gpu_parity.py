@@ -3,7 +3,8 @@
 Sizes: the 2-vehicle scene over many seeds, the 11-object scene (the size
 the benchmark times) in full, ragged and degenerate shapes, the Table I
 workload (86.4 M checks) in both overlap modes, point-in-polygon edge cases,
-and a seeded sample of 20 object pairs of the 40-object stress scene.
+a seeded sample of 20 object pairs of the 40-object stress scene, and grids cut
+into 2-D blocks of items (with and without time splits).
 """
 import math
 import os
@@ -355,3 +356,44 @@ def test_graph_replays_match_eager(mhc, ctx):
     # a shape change between calls is a different graph
     small = sg.two_vehicle_scene(5)
     parity.check(small, mhc.mhc_evaluate(ctx, small), oracle.evaluate(small), "shape change")
+
+
+def _block_scenes():
+    """Scenes whose item grids have sides that are multiples of 8, so the plan
+    cuts them into 2-D blocks of items; short horizons leave few units for the
+    resident waves, so the blocks also run with time splits."""
+    rng = np.random.default_rng(404)
+    out = {}
+    objs = [sg.draw_vehicle(rng, 15.0, 0.0, 12.0, 16, 16) for _ in range(3)]
+    objs += [sg.draw_pedestrian(rng, 15.0, 0.0, 2.0, 16, 16) for _ in range(2)]
+    out["sixteen_grids_H40"] = sg.Scene(objs, 40, 0.1)
+    out["two_vehicles_32_grids_H20"] = sg.Scene([sg.draw_vehicle(rng, 8.0, 0.0, 10.0, 32, 32) for _ in range(2)], 20, 0.1)
+    objs = [sg.draw_vehicle(rng, 25.0, 0.0, 15.0, 32, 32) for _ in range(4)]
+    objs += [sg.draw_pedestrian(rng, 25.0, 0.0, 2.0, 32, 32) for _ in range(4)]
+    out["eight_objects_32_grids_H24"] = sg.Scene(objs, 24, 0.1)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_block_scenes().keys()))
+def test_block_units_parity(mhc, ctx, name):
+    """Block units (alone and with time splits) against the oracle, and every
+    tile variant bit for bit; the host walk of each plan first."""
+    s = _block_scenes()[name]
+    for v in range(mhc.MHC_N_VARIANTS):
+        st, info = mhc.mhc_plan_check(s, v, 5120)
+        assert st == mhc.MHC_OK and info["blocked_pairs"] > 0, (name, v, info)
+    say(f"block units: {name}")
+    o = oracle.evaluate(s, threads=THREADS)
+    try:
+        ref = None
+        for v in range(mhc.MHC_N_VARIANTS):
+            mhc.mhc_set_variant(ctx, v)
+            g = mhc.mhc_evaluate(ctx, s)
+            if ref is None:
+                parity.check(s, g, o, f"{name} variant {v}")
+                ref = g
+            else:
+                parity.same_results(ref, g, f"{name} variant {v}")
+    finally:
+        mhc.mhc_set_variant(ctx, -1)
+    assert (o.k64 >= 0).sum() > 100

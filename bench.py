@@ -525,7 +525,8 @@ def stress_extra(mhc, ctx, sg, torch, steps=10):
     return out
 
 
-def serve_sweep(mhc, ctx, sg, seconds, streams_list=(32, 128, 256, 384, 512, 640, 768, 896, 1024, 1280)):
+def serve_sweep(mhc, ctx, sg, seconds,
+                streams_list=(32, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 2304, 2560, 3072, 3584, 4096)):
     """Served load sweep: the serving workload with more and more 10 Hz
     Poisson streams until the p99 latency passes the 50 ms deadline. Frames
     come from a pool of 512 drawn as in the batched workload (seed 3) and are
@@ -542,7 +543,7 @@ def serve_sweep(mhc, ctx, sg, seconds, streams_list=(32, 128, 256, 384, 512, 640
     pool_checks = [mhc.mhc_query_sizes(c)["n_checks"] for c in pool]
     n_max = max(s.n_objects for s in scenes)
     t_max = max(mhc.mhc_query_sizes(c)["n_traj"] for c in pool)
-    ring = 2048
+    ring = 4096
     bufs = [(np.empty(n_max), np.empty(t_max)) for _ in range(ring)]
     dsts = [mhc.mhc_result(oc.ctypes.data, tc.ctypes.data, *([None] * (len(mhc.RESULT_FIELDS) - 2)))
             for oc, tc in bufs]

@@ -47,7 +47,7 @@ int scene_family(const mhc_scene *s)
 
 // Relative VALU cost of one check per class, for longest-first ordering; the
 // polygon classes scale with the vertex counts (class_cost).
-static const double kClsCost[N_CLS] = {28.0, 14.0, 14.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
+static const double kClsCost[N_CLS] = {28.0, 13.0, 13.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
 
 double class_cost(int cls, int k_a, int k_b)
 {
@@ -404,7 +404,11 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         const int ka = pr.poly_a >= 0 ? pair_vertices[2 * pidx] : 0, kb = pr.poly_b >= 0 ? pair_vertices[2 * pidx + 1] : 0;
         // a wave executes every step of every test of a unit, whether or
         // not all of its lanes hold an item
-        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * class_cost(pr.cls, ka, kb) + kUnitOverhead;
+        // rectangle-circle tests: 12 VALU each plus 4 per prepared rectangle pose
+        const double per_test = pr.cls == CLS_VP   ? 12.0 + 4.0 / ts.rj
+                                : pr.cls == CLS_PV ? 12.0 + 4.0 / ts.ri
+                                                   : class_cost(pr.cls, ka, kb);
+        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * per_test + kUnitOverhead;
         costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)pair_units(pr, sh, pr.bshift)});
     }
 

@@ -108,9 +108,6 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
     if (tid == 0) done[obj] = 0u;
 }
 
-// Grid: y = object; x = 0 is the object's probability normalisation (the
-// longest block for large T, so it is dispatched first), x >= 1 are
-// trajectory blocks of K1_TPB trajectories, one wave each.
 // Vehicle trajectory i on the linear one-track model (Sec. IV-B.1): side slip
 // beta and yaw rate r obey
 //   beta' = -(cf+cr)/(m v) beta + ((cr lr - cf lf)/(m v^2) - 1) r + cf/(m v) delta
@@ -123,7 +120,32 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
 //   r = v delta / (L (1 + K v^2)), beta = delta (lr/L - m lf v^2/(cr L^2)) / (1 + K v^2),
 // L = lf + lr, K = m (lr cr - lf cf) / (L^2 cf cr). FP64; poses stored as
 // FP32 (x, y, cos psi, sin psi), [t][i].
-__device__ void one_track_trajectory(const DObj &o, const double *__restrict__ vals, char *__restrict__ poses, int i)
+//
+// Evaluation: one wave per trajectory, a lane per step, chunks of 64 steps
+// with the state carried across chunks. The speed has a closed form,
+// v_n = max(v_0 + n a tau, 0), and it alone decides each step's
+// update of s = (beta, r): an explicit Euler step s_{n+1} = M_n s_n + c_n
+// where that step is stable, else the steady state of the speed reached,
+// s_{n+1} = s*(v_{n+1}) (M_n = 0). These affine maps compose, so an
+// inclusive scan over the lanes gives every s_n of the chunk at once; the
+// rates of step n follow from s_n and s_{n+1} as in the serial update, and
+// the heading and the position are prefix sums of the per-step increments.
+// Only the order of the additions differs from the serial recursion.
+
+// Inclusive prefix sum over the 64 lanes of a wave (lane l gets the sum of
+// lanes 0..l).
+__device__ __forceinline__ double scan_add(double v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, char *__restrict__ poses, int i,
+                               int lane)
 {
     const double cf = o.params[0], cr = o.params[1], lf = o.params[2], lr = o.params[3];
     const double m = o.params[4], Iz = o.params[5];
@@ -138,55 +160,109 @@ __device__ void one_track_trajectory(const DObj &o, const double *__restrict__ v
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double accel = vals[o.u_off + k];
     const double delta = vals[o.w_off + l];
-    const double tau = o.tau, h2 = tau * tau / 2.0;
-    double x = o.x, y = o.y, psi = o.heading, v = o.speed, beta = 0.0, r = 0.0;
-    double sp, cp;
-    sincos(psi, &sp, &cp);
+    const double tau = o.tau, h2 = tau * tau / 2.0, at = accel * tau;
+    // state at the chunk's first step
+    double cx = o.x, cy = o.y, cpsi = o.heading, cbeta = 0.0, crate = 0.0, csp, ccp;
+    sincos(cpsi, &csp, &ccp);
     float4 *out = reinterpret_cast<float4 *>(poses + o.pose_off);
-    for (int n = 0; n < o.H; ++n) {
-        double vdot = accel;
-        double v1 = v + vdot * tau;
+    for (int n0 = 0; n0 < o.H; n0 += 64) {
+        const int n = n0 + lane;
+        const bool active = n < o.H;
+        const double v = fmax(o.speed + (double)n * at, 0.0);
+        double vdot = accel, v1 = v + at;
         if (v1 < 0.0) {
             vdot = -v / tau;
             v1 = 0.0;
         }
         bool stable = false;
         const double iv = v > 0.0 ? 1.0 / v : 0.0;
-        if (v > 0.0) {
-            const double m11 = 1.0 - tau * kb * iv, m12 = tau * (kc * iv * iv - 1.0);
-            const double m21 = tau * kcz, m22 = 1.0 - tau * kq * iv;
-            const double tr = m11 + m22, det = m11 * m22 - m12 * m21;
-            stable = det < 1.0 && tr < 1.0 + det && tr > -(1.0 + det);
+        double a11 = 1.0, a12 = 0.0, a21 = 0.0, a22 = 1.0, b1 = 0.0, b2 = 0.0;  // identity past the horizon
+        if (active) {
+            if (v > 0.0) {
+                const double m11 = 1.0 - tau * kb * iv, m12 = tau * (kc * iv * iv - 1.0);
+                const double m21 = tau * kcz, m22 = 1.0 - tau * kq * iv;
+                const double tr = m11 + m22, det = m11 * m22 - m12 * m21;
+                stable = det < 1.0 && tr < 1.0 + det && tr > -(1.0 + det);
+                if (stable) {
+                    a11 = m11;
+                    a12 = m12;
+                    a21 = m21;
+                    a22 = m22;
+                    b1 = tau * kf * iv * delta;
+                    b2 = tau * kfz * delta;
+                }
+            }
+            if (!stable) {
+                const double g = 1.0 + K * v1 * v1;
+                a11 = a12 = a21 = a22 = 0.0;
+                b1 = delta * (lr_L - mlf_crL2 * v1 * v1) / g;
+                b2 = v1 * delta / (L * g);
+            }
         }
-        double beta1, r1, beta_dot, r_dot;
+        // lane n: the composition f_n o ... o f_{n0}; (A, b) o (P, q) = (AP, Aq + b)
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double p11 = __shfl_up(a11, d, 64), p12 = __shfl_up(a12, d, 64);
+            const double p21 = __shfl_up(a21, d, 64), p22 = __shfl_up(a22, d, 64);
+            const double q1 = __shfl_up(b1, d, 64), q2 = __shfl_up(b2, d, 64);
+            if (lane >= d) {
+                const double n11 = a11 * p11 + a12 * p21, n12 = a11 * p12 + a12 * p22;
+                const double n21 = a21 * p11 + a22 * p21, n22 = a21 * p12 + a22 * p22;
+                const double nb1 = a11 * q1 + a12 * q2 + b1, nb2 = a21 * q1 + a22 * q2 + b2;
+                a11 = n11;
+                a12 = n12;
+                a21 = n21;
+                a22 = n22;
+                b1 = nb1;
+                b2 = nb2;
+            }
+        }
+        // (beta, r) after step n, and before it (the previous lane's, or the carry)
+        const double beta1 = a11 * cbeta + a12 * crate + b1;
+        const double r1 = a21 * cbeta + a22 * crate + b2;
+        double beta = __shfl_up(beta1, 1, 64), r = __shfl_up(r1, 1, 64);
+        if (lane == 0) {
+            beta = cbeta;
+            r = crate;
+        }
+        double beta_dot, r_dot;
         if (stable) {
             beta_dot = -kb * iv * beta + (kc * iv * iv - 1.0) * r + kf * iv * delta;
             r_dot = kcz * beta - kq * iv * r + kfz * delta;
-            beta1 = beta + beta_dot * tau;
-            r1 = r + r_dot * tau;
         } else {
-            const double g = 1.0 + K * v1 * v1;
-            r1 = v1 * delta / (L * g);
-            beta1 = delta * (lr_L - mlf_crL2 * v1 * v1) / g;
             beta_dot = (beta1 - beta) / tau;
             r_dot = (r1 - r) / tau;
+        }
+        // heading after step n; the step itself turns with the heading before it
+        const double psi1 = cpsi + scan_add(active ? r * tau + r_dot * h2 : 0.0, lane);
+        double sp1, cp1;
+        sincos(psi1, &sp1, &cp1);
+        double sp = __shfl_up(sp1, 1, 64), cp = __shfl_up(cp1, 1, 64);
+        if (lane == 0) {
+            sp = csp;
+            cp = ccp;
         }
         double sb, cb;
         sincos(beta, &sb, &cb);
         const double spb = sp * cb + cp * sb, cpb = cp * cb - sp * sb;   // psi + beta
         const double ax = cb * vdot - sb * v * (beta_dot + r);
         const double ay = sb * vdot + cb * v * (beta_dot + r);
-        x = x + cpb * v * tau + cp * ax * h2 - sp * ay * h2;
-        y = y + spb * v * tau + sp * ax * h2 + cp * ay * h2;
-        psi = psi + r * tau + r_dot * h2;
-        v = v1;
-        beta = beta1;
-        r = r1;
-        sincos(psi, &sp, &cp);   // this pose, and the next step's heading
-        out[(size_t)n * o.T + i] = make_float4((float)x, (float)y, (float)cp, (float)sp);
+        const double x1 = cx + scan_add(active ? cpb * v * tau + cp * ax * h2 - sp * ay * h2 : 0.0, lane);
+        const double y1 = cy + scan_add(active ? spb * v * tau + sp * ax * h2 + cp * ay * h2 : 0.0, lane);
+        if (active) out[(size_t)n * o.T + i] = make_float4((float)x1, (float)y1, (float)cp1, (float)sp1);
+        cx = __shfl(x1, 63, 64);
+        cy = __shfl(y1, 63, 64);
+        cpsi = __shfl(psi1, 63, 64);
+        csp = __shfl(sp1, 63, 64);
+        ccp = __shfl(cp1, 63, 64);
+        cbeta = __shfl(beta1, 63, 64);
+        crate = __shfl(r1, 63, 64);
     }
 }
 
+// Grid: y = object; x = 0 is the object's probability normalisation (the
+// longest block for large T, so it is dispatched first), x >= 1 are
+// trajectory blocks of K1_TPB trajectories, one wave each.
 // For time-resolved scenes, trajectory block c also zeroes the c-th stretch
 // of K1_TPB * W * H entries of the object's per-slot q sums.
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
@@ -210,15 +286,13 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
         ulonglong2 *h2 = reinterpret_cast<ulonglong2 *>(hist + o.hist_off);
         for (int64_t k = lo / 2 + (int64_t)threadIdx.x; k < hi / 2; k += WG) h2[k] = make_ulonglong2(0ull, 0ull);
     }
-    if (o.model == MODEL_ONE_TRACK) {
-        // a thread per trajectory: the one-track state is a recursion
-        const int it = ((int)blockIdx.x - 1) * WG + (int)threadIdx.x;
-        if (it < o.T) one_track_trajectory(o, vals, poses, it);
-        return;
-    }
     const int lane = threadIdx.x & 63;
     const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
+    if (o.model == MODEL_ONE_TRACK) {
+        one_track_wave(o, vals, poses, i, lane);
+        return;
+    }
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double tau = o.tau;
     const double half_tau2 = tau * tau / 2.0;

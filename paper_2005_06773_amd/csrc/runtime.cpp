@@ -9,6 +9,7 @@
 #include <cmath>
 #include <numeric>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -762,6 +763,7 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
     hipEventSynchronize(ctx->staging_ev);
     if (ctx->dbuf) hipFree(ctx->dbuf);
     if (ctx->staging) hipHostFree(ctx->staging);
+    if (ctx->res_pin) hipHostFree(ctx->res_pin);
     hipEventDestroy(ctx->staging_ev);
     hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1037,24 +1039,83 @@ static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *d
     return MHC_OK;
 }
 
-mhc_status copy_results(mhc_ctx *ctx, const Layout &L, int k, const char *dbase, const mhc_result *res,
-                        hipStream_t s)
+// Every output is one region of the workspace in which scene k's part starts
+// at a known offset, so each requested output of all scenes comes down in one
+// transfer into pinned host memory (one DMA instead of one staged copy into
+// pageable memory per scene and output), and the host then copies each
+// scene's part to its buffer. Regions above kResultStageMax (the first hits
+// of large scenes) are copied per scene straight to the callers' buffers.
+static const size_t kResultStageMax = size_t(64) << 20;
+
+mhc_status download_results(mhc_ctx *ctx, const Layout &L, int n, const char *dbase, const mhc_result *res,
+                            hipStream_t s)
 {
-    const SceneExt &e = L.sc[k];
-    auto d2h = [&](void *dst, size_t off, size_t bytes) -> hipError_t {
-        if (!dst || !bytes) return hipSuccess;
-        return hipMemcpyAsync(dst, dbase + off, bytes, hipMemcpyDeviceToHost, s);
+    struct Part {
+        size_t off, bytes;  // in the workspace
     };
-    HIPC(d2h(res->object_crit, L.o_oc + e.obj0 * sizeof(double), e.n_obj * sizeof(double)));
-    HIPC(d2h(res->traj_crit, L.o_tc + e.traj0 * sizeof(double), e.n_traj * sizeof(double)));
-    HIPC(d2h(res->traj_prob, L.o_p + e.traj0 * sizeof(double), e.n_traj * sizeof(double)));
-    HIPC(d2h(res->q, L.o_q + e.q0 * sizeof(double), (size_t)e.n_traj * e.n_obj * sizeof(double)));
-    HIPC(d2h(res->first_hit, L.o_hits + e.hit0 * sizeof(int16_t), e.n_hits * sizeof(int16_t)));
-    if (e.timeline) {
-        HIPC(d2h(res->crit_t, L.o_ct + e.tl_obj0 * sizeof(double), (size_t)e.n_obj * e.H * sizeof(double)));
-        HIPC(d2h(res->traj_crit_t, L.o_tct + e.tl_traj0 * sizeof(double), (size_t)e.n_traj * e.H * sizeof(double)));
-        HIPC(d2h(res->attrib, L.o_at + e.tl_att0 * sizeof(double), (size_t)e.n_obj * e.n_obj * sizeof(double)));
-        HIPC(d2h(res->traj_attrib, L.o_tat + e.q0 * sizeof(double), (size_t)e.n_traj * e.n_obj * sizeof(double)));
+    // output f of scene k: its host buffer and its part of the region
+    auto part = [&](int f, int k, void **dst) -> Part {
+        const SceneExt &e = L.sc[k];
+        const mhc_result &r = res[k];
+        const size_t H = (size_t)e.H, nq = (size_t)e.n_traj * e.n_obj;
+        switch (f) {
+        case 0: *dst = r.object_crit; return {L.o_oc + e.obj0 * 8, (size_t)e.n_obj * 8};
+        case 1: *dst = r.traj_crit; return {L.o_tc + e.traj0 * 8, (size_t)e.n_traj * 8};
+        case 2: *dst = r.traj_prob; return {L.o_p + e.traj0 * 8, (size_t)e.n_traj * 8};
+        case 3: *dst = r.q; return {L.o_q + e.q0 * 8, nq * 8};
+        case 4: *dst = r.first_hit; return {L.o_hits + e.hit0 * 2, (size_t)e.n_hits * 2};
+        case 5: *dst = e.timeline ? r.crit_t : nullptr; return {L.o_ct + e.tl_obj0 * 8, (size_t)e.n_obj * H * 8};
+        case 6: *dst = e.timeline ? r.traj_crit_t : nullptr; return {L.o_tct + e.tl_traj0 * 8, (size_t)e.n_traj * H * 8};
+        case 7: *dst = e.timeline ? r.attrib : nullptr; return {L.o_at + e.tl_att0 * 8, (size_t)e.n_obj * e.n_obj * 8};
+        default: *dst = e.timeline ? r.traj_attrib : nullptr; return {L.o_tat + e.q0 * 8, nq * 8};
+        }
+    };
+    constexpr int kOutputs = 9;
+    size_t lo[kOutputs], hi[kOutputs], at[kOutputs], staged = 0;
+    for (int f = 0; f < kOutputs; ++f) {
+        lo[f] = SIZE_MAX;
+        hi[f] = 0;
+        for (int k = 0; k < n; ++k) {
+            void *dst = nullptr;
+            const Part pt = part(f, k, &dst);
+            if (!dst || !pt.bytes) continue;
+            lo[f] = std::min(lo[f], pt.off);
+            hi[f] = std::max(hi[f], pt.off + pt.bytes);
+        }
+        at[f] = SIZE_MAX;
+        if (hi[f] > lo[f] && hi[f] - lo[f] <= kResultStageMax) {
+            at[f] = staged;
+            staged += (hi[f] - lo[f] + 255) & ~size_t(255);
+        }
+    }
+    if (staged > ctx->res_pin_bytes) {
+        if (ctx->res_pin) HIPC(hipHostFree(ctx->res_pin));
+        ctx->res_pin = nullptr;
+        ctx->res_pin_bytes = 0;
+        const size_t want = std::max(staged, size_t(1) << 20);
+        HIPC(hipHostMalloc(reinterpret_cast<void **>(&ctx->res_pin), want, hipHostMallocDefault));
+        ctx->res_pin_bytes = want;
+    }
+    for (int f = 0; f < kOutputs; ++f) {
+        if (hi[f] <= lo[f]) continue;
+        if (at[f] != SIZE_MAX) {
+            HIPC(hipMemcpyAsync(ctx->res_pin + at[f], dbase + lo[f], hi[f] - lo[f], hipMemcpyDeviceToHost, s));
+            continue;
+        }
+        for (int k = 0; k < n; ++k) {
+            void *dst = nullptr;
+            const Part pt = part(f, k, &dst);
+            if (dst && pt.bytes) HIPC(hipMemcpyAsync(dst, dbase + pt.off, pt.bytes, hipMemcpyDeviceToHost, s));
+        }
+    }
+    HIPC(hipStreamSynchronize(s));
+    for (int f = 0; f < kOutputs; ++f) {
+        if (hi[f] <= lo[f] || at[f] == SIZE_MAX) continue;
+        for (int k = 0; k < n; ++k) {
+            void *dst = nullptr;
+            const Part pt = part(f, k, &dst);
+            if (dst && pt.bytes) std::memcpy(dst, ctx->res_pin + at[f] + (pt.off - lo[f]), pt.bytes);
+        }
     }
     return MHC_OK;
 }
@@ -1077,10 +1138,7 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     key.push_back(-1);  // single scene
     st = graph_upload_and_launch(ctx, L, dbase, res->first_hit != nullptr, key, ctx->stream);
     if (st != MHC_OK) return st;
-    st = copy_results(ctx, L, 0, dbase, res, ctx->stream);
-    if (st != MHC_OK) return st;
-    HIPC(hipStreamSynchronize(ctx->stream));
-    return MHC_OK;
+    return download_results(ctx, L, 1, dbase, res, ctx->stream);
 }
 
 extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, void *dev_workspace,
@@ -1295,10 +1353,7 @@ extern "C" mhc_status mhc_plan_download(mhc_plan *pl, mhc_result *host_out)
     if (!validate_outputs(&pl->flags, host_out, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     HIPC(hipDeviceSynchronize());
-    mhc_status st = copy_results(ctx, pl->L, 0, pl->dbuf, host_out, ctx->stream);
-    if (st != MHC_OK) return st;
-    HIPC(hipStreamSynchronize(ctx->stream));
-    return MHC_OK;
+    return download_results(ctx, pl->L, 1, static_cast<const char *>(pl->dbuf), host_out, ctx->stream);
 }
 
 extern "C" void mhc_plan_destroy(mhc_plan *pl)
@@ -1360,10 +1415,5 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
     }
     st = graph_upload_and_launch(ctx, L, dbase, keep, key, ctx->stream);
     if (st != MHC_OK) return st;
-    for (int k = 0; k < n; ++k) {
-        st = copy_results(ctx, L, k, dbase, &res[k], ctx->stream);
-        if (st != MHC_OK) return st;
-    }
-    HIPC(hipStreamSynchronize(ctx->stream));
-    return MHC_OK;
+    return download_results(ctx, L, n, dbase, res, ctx->stream);
 }

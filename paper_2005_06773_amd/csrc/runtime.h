@@ -107,6 +107,8 @@ struct mhc_ctx {
     char *staging = nullptr;      // pinned host copy of the last scene image
     size_t staging_bytes = 0;
     hipEvent_t staging_ev = nullptr;
+    char *res_pin = nullptr;      // pinned host staging of the results of the synchronous calls
+    size_t res_pin_bytes = 0;
     mhc::Layout layout;           // reused by mhc_evaluate
     std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
     mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
@@ -124,6 +126,9 @@ struct mhc_ctx {
 std::array<int, 3> size_class(const mhc_scene *scenes, int n);
 
 mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);
-mhc_status copy_results(mhc_ctx *ctx, const mhc::Layout &L, int k, const char *dbase, const mhc_result *res,
-                        hipStream_t s);
+// Copies the results of the n scenes of layout L (device workspace dbase,
+// written on stream s) to the callers' host buffers res[0..n) and waits for
+// them.
+mhc_status download_results(mhc_ctx *ctx, const mhc::Layout &L, int n, const char *dbase, const mhc_result *res,
+                            hipStream_t s);
 mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *res);

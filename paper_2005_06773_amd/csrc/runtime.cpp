@@ -1044,8 +1044,10 @@ static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *d
 // transfer into pinned host memory (one DMA instead of one staged copy into
 // pageable memory per scene and output), and the host then copies each
 // scene's part to its buffer. Regions above kResultStageMax (the first hits
-// of large scenes) are copied per scene straight to the callers' buffers.
+// of large scenes), and the largest ones while the staged total exceeds
+// kResultStageTotal, are copied per scene straight to the callers' buffers.
 static const size_t kResultStageMax = size_t(64) << 20;
+static const size_t kResultStageTotal = size_t(256) << 20;
 
 mhc_status download_results(mhc_ctx *ctx, const Layout &L, int n, const char *dbase, const mhc_result *res,
                             hipStream_t s)
@@ -1082,8 +1084,23 @@ mhc_status download_results(mhc_ctx *ctx, const Layout &L, int n, const char *db
             lo[f] = std::min(lo[f], pt.off);
             hi[f] = std::max(hi[f], pt.off + pt.bytes);
         }
+    }
+    bool stage[kOutputs];
+    size_t total = 0;
+    for (int f = 0; f < kOutputs; ++f) {
+        stage[f] = hi[f] > lo[f] && hi[f] - lo[f] <= kResultStageMax;
+        if (stage[f]) total += hi[f] - lo[f];
+    }
+    while (total > kResultStageTotal) {
+        int big = -1;
+        for (int f = 0; f < kOutputs; ++f)
+            if (stage[f] && (big < 0 || hi[f] - lo[f] > hi[big] - lo[big])) big = f;
+        stage[big] = false;
+        total -= hi[big] - lo[big];
+    }
+    for (int f = 0; f < kOutputs; ++f) {
         at[f] = SIZE_MAX;
-        if (hi[f] > lo[f] && hi[f] - lo[f] <= kResultStageMax) {
+        if (stage[f]) {
             at[f] = staged;
             staged += (hi[f] - lo[f] + 255) & ~size_t(255);
         }

@@ -397,3 +397,33 @@ def test_block_units_parity(mhc, ctx, name):
     finally:
         mhc.mhc_set_variant(ctx, -1)
     assert (o.k64 >= 0).sum() > 100
+
+
+def test_batch_with_different_outputs_per_scene(mhc, ctx):
+    """A batch whose scenes ask for different outputs (first hits, q, the
+    per-trajectory arrays, the risk over time, each for some scenes only):
+    every requested output equals that scene evaluated alone, bit for bit."""
+    import ctypes
+    scenes = sg.batch_scenes(7, 10)
+    for k, s in enumerate(scenes):
+        s.timeline = 1 if k % 4 == 1 else 0
+    css = [mhc.CScene(s) for s in scenes]
+    outs, rs = [], []
+    for k, cs in enumerate(css):
+        out, r = mhc.host_result(cs, first_hit=k % 2 == 0, q=k % 3 == 0)
+        if k % 5 == 2:
+            out["traj_crit"], r.traj_crit = None, None
+        if k % 3 == 1:
+            out["traj_prob"], r.traj_prob = None, None
+        outs.append(out)
+        rs.append(r)
+    arr = (mhc.mhc_scene * len(css))(*[c.c for c in css])
+    rarr = (mhc.mhc_result * len(css))(*rs)
+    say("batch of 10 scenes with different outputs per scene")
+    assert mhc.lib.mhc_evaluate_batch(ctx, len(css), arr, rarr) == mhc.MHC_OK, mhc.mhc_last_error(ctx)
+    for k, (s, cs) in enumerate(zip(scenes, css)):
+        ref = mhc.mhc_evaluate(ctx, cs, first_hit=True, q=True)
+        for name, got in outs[k].items():
+            if got is None:
+                continue
+            assert np.array_equal(got, ref[name].reshape(got.shape)), f"scene {k}: {name}"

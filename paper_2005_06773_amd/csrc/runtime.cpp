@@ -1043,97 +1043,123 @@ static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *d
 // at a known offset, so each requested output of all scenes comes down in one
 // transfer into pinned host memory (one DMA instead of one staged copy into
 // pageable memory per scene and output), and the host then copies each
-// scene's part to its buffer. Regions above kResultStageMax (the first hits
-// of large scenes), and the largest ones while the staged total exceeds
-// kResultStageTotal, are copied per scene straight to the callers' buffers.
+// scene's part to its buffer. Unless every output is to be staged, regions
+// above kResultStageMax (the first hits of large scenes), and the largest
+// ones while the staged total exceeds kResultStageTotal, are copied per scene
+// straight to the callers' buffers.
 static const size_t kResultStageMax = size_t(64) << 20;
 static const size_t kResultStageTotal = size_t(256) << 20;
+
+namespace mhc {
+
+// Output f (RESULT order, then the time-resolved ones) of scene k: its host
+// buffer (NULL when not asked for) and its bytes in the workspace.
+static void result_part(const Layout &L, const mhc_result *res, int f, int k, void **dst, size_t *off,
+                        size_t *bytes)
+{
+    const SceneExt &e = L.sc[k];
+    const mhc_result &r = res[k];
+    const size_t H = (size_t)e.H, nq = (size_t)e.n_traj * e.n_obj;
+    switch (f) {
+    case 0: *dst = r.object_crit; *off = L.o_oc + e.obj0 * 8; *bytes = (size_t)e.n_obj * 8; break;
+    case 1: *dst = r.traj_crit; *off = L.o_tc + e.traj0 * 8; *bytes = (size_t)e.n_traj * 8; break;
+    case 2: *dst = r.traj_prob; *off = L.o_p + e.traj0 * 8; *bytes = (size_t)e.n_traj * 8; break;
+    case 3: *dst = r.q; *off = L.o_q + e.q0 * 8; *bytes = nq * 8; break;
+    case 4: *dst = r.first_hit; *off = L.o_hits + e.hit0 * 2; *bytes = (size_t)e.n_hits * 2; break;
+    case 5: *dst = e.timeline ? r.crit_t : nullptr; *off = L.o_ct + e.tl_obj0 * 8; *bytes = (size_t)e.n_obj * H * 8; break;
+    case 6: *dst = e.timeline ? r.traj_crit_t : nullptr; *off = L.o_tct + e.tl_traj0 * 8; *bytes = (size_t)e.n_traj * H * 8; break;
+    case 7: *dst = e.timeline ? r.attrib : nullptr; *off = L.o_at + e.tl_att0 * 8; *bytes = (size_t)e.n_obj * e.n_obj * 8; break;
+    default: *dst = e.timeline ? r.traj_attrib : nullptr; *off = L.o_tat + e.q0 * 8; *bytes = nq * 8; break;
+    }
+    if (!*bytes) *dst = nullptr;
+}
+
+ResultPlan plan_results(const Layout &L, int n, const mhc_result *res, bool stage_all)
+{
+    ResultPlan R;
+    size_t total = 0;
+    for (int f = 0; f < ResultPlan::kOutputs; ++f) {
+        R.lo[f] = SIZE_MAX;
+        R.hi[f] = 0;
+        for (int k = 0; k < n; ++k) {
+            void *dst;
+            size_t off, bytes;
+            result_part(L, res, f, k, &dst, &off, &bytes);
+            if (!dst) continue;
+            R.lo[f] = std::min(R.lo[f], off);
+            R.hi[f] = std::max(R.hi[f], off + bytes);
+        }
+        R.stage[f] = R.hi[f] > R.lo[f] && (stage_all || R.hi[f] - R.lo[f] <= kResultStageMax);
+        if (R.stage[f]) total += R.hi[f] - R.lo[f];
+    }
+    while (!stage_all && total > kResultStageTotal) {
+        int big = -1;
+        for (int f = 0; f < ResultPlan::kOutputs; ++f)
+            if (R.stage[f] && (big < 0 || R.hi[f] - R.lo[f] > R.hi[big] - R.lo[big])) big = f;
+        R.stage[big] = false;
+        total -= R.hi[big] - R.lo[big];
+    }
+    R.staged = 0;
+    for (int f = 0; f < ResultPlan::kOutputs; ++f) {
+        R.at[f] = R.staged;
+        if (R.stage[f]) R.staged += (R.hi[f] - R.lo[f] + 255) & ~size_t(255);
+    }
+    return R;
+}
+
+hipError_t enqueue_results(const ResultPlan &R, const Layout &L, int n, const char *dbase, char *pinned,
+                           const mhc_result *res, hipStream_t s)
+{
+    for (int f = 0; f < ResultPlan::kOutputs; ++f) {
+        if (R.hi[f] <= R.lo[f]) continue;
+        if (R.stage[f]) {
+            const hipError_t e =
+                hipMemcpyAsync(pinned + R.at[f], dbase + R.lo[f], R.hi[f] - R.lo[f], hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+            continue;
+        }
+        for (int k = 0; k < n; ++k) {
+            void *dst;
+            size_t off, bytes;
+            result_part(L, res, f, k, &dst, &off, &bytes);
+            if (!dst) continue;
+            const hipError_t e = hipMemcpyAsync(dst, dbase + off, bytes, hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+void scatter_results(const ResultPlan &R, const Layout &L, int n, const char *pinned, const mhc_result *res)
+{
+    for (int f = 0; f < ResultPlan::kOutputs; ++f) {
+        if (!R.stage[f]) continue;
+        for (int k = 0; k < n; ++k) {
+            void *dst;
+            size_t off, bytes;
+            result_part(L, res, f, k, &dst, &off, &bytes);
+            if (dst) std::memcpy(dst, pinned + R.at[f] + (off - R.lo[f]), bytes);
+        }
+    }
+}
+
+}  // namespace mhc
 
 mhc_status download_results(mhc_ctx *ctx, const Layout &L, int n, const char *dbase, const mhc_result *res,
                             hipStream_t s)
 {
-    struct Part {
-        size_t off, bytes;  // in the workspace
-    };
-    // output f of scene k: its host buffer and its part of the region
-    auto part = [&](int f, int k, void **dst) -> Part {
-        const SceneExt &e = L.sc[k];
-        const mhc_result &r = res[k];
-        const size_t H = (size_t)e.H, nq = (size_t)e.n_traj * e.n_obj;
-        switch (f) {
-        case 0: *dst = r.object_crit; return {L.o_oc + e.obj0 * 8, (size_t)e.n_obj * 8};
-        case 1: *dst = r.traj_crit; return {L.o_tc + e.traj0 * 8, (size_t)e.n_traj * 8};
-        case 2: *dst = r.traj_prob; return {L.o_p + e.traj0 * 8, (size_t)e.n_traj * 8};
-        case 3: *dst = r.q; return {L.o_q + e.q0 * 8, nq * 8};
-        case 4: *dst = r.first_hit; return {L.o_hits + e.hit0 * 2, (size_t)e.n_hits * 2};
-        case 5: *dst = e.timeline ? r.crit_t : nullptr; return {L.o_ct + e.tl_obj0 * 8, (size_t)e.n_obj * H * 8};
-        case 6: *dst = e.timeline ? r.traj_crit_t : nullptr; return {L.o_tct + e.tl_traj0 * 8, (size_t)e.n_traj * H * 8};
-        case 7: *dst = e.timeline ? r.attrib : nullptr; return {L.o_at + e.tl_att0 * 8, (size_t)e.n_obj * e.n_obj * 8};
-        default: *dst = e.timeline ? r.traj_attrib : nullptr; return {L.o_tat + e.q0 * 8, nq * 8};
-        }
-    };
-    constexpr int kOutputs = 9;
-    size_t lo[kOutputs], hi[kOutputs], at[kOutputs], staged = 0;
-    for (int f = 0; f < kOutputs; ++f) {
-        lo[f] = SIZE_MAX;
-        hi[f] = 0;
-        for (int k = 0; k < n; ++k) {
-            void *dst = nullptr;
-            const Part pt = part(f, k, &dst);
-            if (!dst || !pt.bytes) continue;
-            lo[f] = std::min(lo[f], pt.off);
-            hi[f] = std::max(hi[f], pt.off + pt.bytes);
-        }
-    }
-    bool stage[kOutputs];
-    size_t total = 0;
-    for (int f = 0; f < kOutputs; ++f) {
-        stage[f] = hi[f] > lo[f] && hi[f] - lo[f] <= kResultStageMax;
-        if (stage[f]) total += hi[f] - lo[f];
-    }
-    while (total > kResultStageTotal) {
-        int big = -1;
-        for (int f = 0; f < kOutputs; ++f)
-            if (stage[f] && (big < 0 || hi[f] - lo[f] > hi[big] - lo[big])) big = f;
-        stage[big] = false;
-        total -= hi[big] - lo[big];
-    }
-    for (int f = 0; f < kOutputs; ++f) {
-        at[f] = SIZE_MAX;
-        if (stage[f]) {
-            at[f] = staged;
-            staged += (hi[f] - lo[f] + 255) & ~size_t(255);
-        }
-    }
-    if (staged > ctx->res_pin_bytes) {
+    const ResultPlan R = plan_results(L, n, res, false);
+    if (R.staged > ctx->res_pin_bytes) {
         if (ctx->res_pin) HIPC(hipHostFree(ctx->res_pin));
         ctx->res_pin = nullptr;
         ctx->res_pin_bytes = 0;
-        const size_t want = std::max(staged, size_t(1) << 20);
+        const size_t want = std::max(R.staged, size_t(1) << 20);
         HIPC(hipHostMalloc(reinterpret_cast<void **>(&ctx->res_pin), want, hipHostMallocDefault));
         ctx->res_pin_bytes = want;
     }
-    for (int f = 0; f < kOutputs; ++f) {
-        if (hi[f] <= lo[f]) continue;
-        if (at[f] != SIZE_MAX) {
-            HIPC(hipMemcpyAsync(ctx->res_pin + at[f], dbase + lo[f], hi[f] - lo[f], hipMemcpyDeviceToHost, s));
-            continue;
-        }
-        for (int k = 0; k < n; ++k) {
-            void *dst = nullptr;
-            const Part pt = part(f, k, &dst);
-            if (dst && pt.bytes) HIPC(hipMemcpyAsync(dst, dbase + pt.off, pt.bytes, hipMemcpyDeviceToHost, s));
-        }
-    }
+    HIPC(enqueue_results(R, L, n, dbase, ctx->res_pin, res, s));
     HIPC(hipStreamSynchronize(s));
-    for (int f = 0; f < kOutputs; ++f) {
-        if (hi[f] <= lo[f] || at[f] == SIZE_MAX) continue;
-        for (int k = 0; k < n; ++k) {
-            void *dst = nullptr;
-            const Part pt = part(f, k, &dst);
-            if (dst && pt.bytes) std::memcpy(dst, ctx->res_pin + at[f] + (pt.off - lo[f]), pt.bytes);
-        }
-    }
+    scatter_results(R, L, n, ctx->res_pin, res);
     return MHC_OK;
 }
 

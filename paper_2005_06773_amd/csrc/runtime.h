@@ -88,6 +88,23 @@ bool scene_has_outline(const mhc_scene *s);
 int scene_family(const mhc_scene *s);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
+
+// The host side of the results of the n scenes of a layout: per output, the
+// workspace range [lo, hi) of every requested part and, where staged, its
+// offset in a pinned buffer of `staged` bytes (else copied per scene straight
+// to the callers' buffers). stage_all stages every output.
+struct ResultPlan {
+    static constexpr int kOutputs = 9;
+    size_t lo[kOutputs], hi[kOutputs], at[kOutputs];
+    bool stage[kOutputs];
+    size_t staged = 0;
+};
+ResultPlan plan_results(const Layout &L, int n, const mhc_result *res, bool stage_all);
+// Enqueues the transfers on s: staged outputs into `pinned`, the others to res.
+hipError_t enqueue_results(const ResultPlan &R, const Layout &L, int n, const char *dbase, char *pinned,
+                           const mhc_result *res, hipStream_t s);
+// After the transfers: copies each scene's staged parts from `pinned` to res.
+void scatter_results(const ResultPlan &R, const Layout &L, int n, const char *pinned, const mhc_result *res);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
 void pack_image(const Layout &L, char *dst);
 std::vector<int32_t> shape_of(const mhc_scene *s);

@@ -72,7 +72,8 @@ struct TickSlot {
     int64_t tick = 0;
     Layout L;
     std::vector<std::shared_ptr<Frame>> frames;
-    std::vector<size_t> out_off;  // per frame: offset of its results in pin_out
+    std::vector<mhc_result> dsts;  // per frame: its host buffers
+    ResultPlan results;            // the tick's outputs staged in pin_out
 };
 
 }  // namespace
@@ -182,22 +183,6 @@ std::shared_ptr<Frame> copy_frame(const mhc_scene *s)
     return f;
 }
 
-size_t result_bytes(const Frame &f)
-{
-    const int n = f.scene.n_objects;
-    size_t b = align256(n * 8);
-    if (f.dst.traj_crit) b += align256(f.n_traj * 8);
-    if (f.dst.traj_prob) b += align256(f.n_traj * 8);
-    if (f.dst.q) b += align256((size_t)f.n_traj * n * 8);
-    if (f.dst.first_hit) b += align256(f.n_hits * 2);
-    const size_t H = (size_t)f.scene.horizon;
-    if (f.dst.crit_t) b += align256(n * H * 8);
-    if (f.dst.traj_crit_t) b += align256(f.n_traj * H * 8);
-    if (f.dst.attrib) b += align256((size_t)n * n * 8);
-    if (f.dst.traj_attrib) b += align256((size_t)f.n_traj * n * 8);
-    return b;
-}
-
 hipError_t grow_pinned(char **p, size_t *have, size_t want)
 {
     if (*have >= want) return hipSuccess;
@@ -225,13 +210,12 @@ hipError_t launch_tick(mhc_server *srv, TickSlot &t)
     if (t.L.total_bytes > t.dbytes) return hipErrorOutOfMemory;  // admission bounds exclude this
     hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes);
     if (e != hipSuccess) return e;
-    size_t out = 0;
-    t.out_off.clear();
-    for (auto &f : t.frames) {
-        t.out_off.push_back(out);
-        out += result_bytes(*f);
-    }
-    e = grow_pinned(&t.pin_out, &t.pin_out_bytes, out);
+    t.dsts.clear();
+    for (auto &f : t.frames) t.dsts.push_back(f->dst);
+    // every output of the tick in one transfer per output region, staged in
+    // pinned memory so that nothing blocks this thread
+    t.results = plan_results(t.L, (int)t.frames.size(), t.dsts.data(), true);
+    e = grow_pinned(&t.pin_out, &t.pin_out_bytes, t.results.staged);
     if (e != hipSuccess) return e;
     pack_image(t.L, t.pin_in);
     e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
@@ -239,57 +223,19 @@ hipError_t launch_tick(mhc_server *srv, TickSlot &t)
     Launch X = make_launch(t.L, t.dbuf, nullptr, keep_hits, ctx->n_cu);
     e = launch_all(X, t.stream);
     if (e != hipSuccess) return e;
-    for (size_t k = 0; k < t.frames.size(); ++k) {
-        const Frame &f = *t.frames[k];
-        const SceneExt &x = t.L.sc[k];
-        char *o = t.pin_out + t.out_off[k];
-        auto d2h = [&](size_t dev_off, size_t bytes) -> hipError_t {
-            hipError_t r = hipMemcpyAsync(o, t.dbuf + dev_off, bytes, hipMemcpyDeviceToHost, t.stream);
-            o += align256(bytes);
-            return r;
-        };
-        e = d2h(t.L.o_oc + x.obj0 * 8, x.n_obj * 8);
-        if (e == hipSuccess && f.dst.traj_crit) e = d2h(t.L.o_tc + x.traj0 * 8, x.n_traj * 8);
-        if (e == hipSuccess && f.dst.traj_prob) e = d2h(t.L.o_p + x.traj0 * 8, x.n_traj * 8);
-        if (e == hipSuccess && f.dst.q) e = d2h(t.L.o_q + x.q0 * 8, (size_t)x.n_traj * x.n_obj * 8);
-        if (e == hipSuccess && f.dst.first_hit) e = d2h(t.L.o_hits + x.hit0 * 2, x.n_hits * 2);
-        const size_t H = (size_t)x.H;
-        if (e == hipSuccess && f.dst.crit_t) e = d2h(t.L.o_ct + x.tl_obj0 * 8, (size_t)x.n_obj * H * 8);
-        if (e == hipSuccess && f.dst.traj_crit_t) e = d2h(t.L.o_tct + x.tl_traj0 * 8, (size_t)x.n_traj * H * 8);
-        if (e == hipSuccess && f.dst.attrib) e = d2h(t.L.o_at + x.tl_att0 * 8, (size_t)x.n_obj * x.n_obj * 8);
-        if (e == hipSuccess && f.dst.traj_attrib) e = d2h(t.L.o_tat + x.q0 * 8, (size_t)x.n_traj * x.n_obj * 8);
-        if (e != hipSuccess) return e;
-    }
+    e = enqueue_results(t.results, t.L, (int)t.frames.size(), t.dbuf, t.pin_out, t.dsts.data(), t.stream);
+    if (e != hipSuccess) return e;
     return hipEventRecord(t.done, t.stream);
 }
 
 void finish_tick(mhc_server *srv, TickSlot &t, mhc_status st)
 {
-    const int64_t done = now_ns();
-    for (size_t k = 0; k < t.frames.size(); ++k) {
-        Frame &f = *t.frames[k];
-        if (st == MHC_OK) {
-            const char *o = t.pin_out + t.out_off[k];
-            const int n = f.scene.n_objects;
-            auto take = [&](void *dst, size_t bytes) {
-                std::memcpy(dst, o, bytes);
-                o += align256(bytes);
-            };
-            take(f.dst.object_crit, n * 8);
-            if (f.dst.traj_crit) take(f.dst.traj_crit, f.n_traj * 8);
-            if (f.dst.traj_prob) take(f.dst.traj_prob, f.n_traj * 8);
-            if (f.dst.q) take(f.dst.q, (size_t)f.n_traj * n * 8);
-            if (f.dst.first_hit) take(f.dst.first_hit, f.n_hits * 2);
-            const size_t H = (size_t)f.scene.horizon;
-            if (f.dst.crit_t) take(f.dst.crit_t, (size_t)n * H * 8);
-            if (f.dst.traj_crit_t) take(f.dst.traj_crit_t, f.n_traj * H * 8);
-            if (f.dst.attrib) take(f.dst.attrib, (size_t)n * n * 8);
-            if (f.dst.traj_attrib) take(f.dst.traj_attrib, (size_t)f.n_traj * n * 8);
-        }
-        f.timing.launch_ns = t.launched_ns;
-        f.timing.done_ns = now_ns();
-        f.timing.tick = t.tick;
-        (void)done;
+    if (st == MHC_OK) scatter_results(t.results, t.L, (int)t.frames.size(), t.pin_out, t.dsts.data());
+    const int64_t done = now_ns();  // every result is in its host buffer
+    for (auto &fp : t.frames) {
+        fp->timing.launch_ns = t.launched_ns;
+        fp->timing.done_ns = done;
+        fp->timing.tick = t.tick;
     }
     std::lock_guard<std::mutex> lk(srv->mu);
     for (auto &fp : t.frames) {

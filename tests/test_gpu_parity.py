@@ -427,3 +427,26 @@ def test_batch_with_different_outputs_per_scene(mhc, ctx):
             if got is None:
                 continue
             assert np.array_equal(got, ref[name].reshape(got.shape)), f"scene {k}: {name}"
+
+
+def test_size_limits(mhc, ctx):
+    """The largest horizon (32767 steps: first hits near the top of the int16
+    slot range) and the largest trajectory count of one object (32768)."""
+    # two vehicles 66 m apart closing at 0.02 m/s touch after ~30,750 steps
+    # of 0.1 s; a slow pedestrian walks towards their meeting point
+    s = sg.Scene([veh(0.0, 0.0, 0.0, 0.01, [0.0], [0.0]),
+                  veh(66.0, 0.3, math.pi, 0.01, [0.0], [0.0]),
+                  ped(33.0, 40.0, -math.pi / 2, 0.02, [0.0, 0.013], [0.0, 0.01])], 32767, 0.1)
+    say("horizon 32767")
+    g = mhc.mhc_evaluate(ctx, s)
+    o = oracle.evaluate(s, threads=THREADS)
+    parity.check(s, g, o, "horizon 32767")
+    assert int(g["first_hit"][0]) > 25000, g["first_hit"][0]
+    # one vehicle with 256 x 128 = 32768 trajectories against a small vehicle
+    s = sg.Scene([veh(0.0, 0.0, 0.0, 8.0, sg.accel_grid(256), sg.yaw_grid(128)),
+                  veh(9.0, 1.0, 2.8, 3.0, sg.accel_grid(3), sg.yaw_grid(1))], 8, 0.1)
+    say("32768 trajectories")
+    g = mhc.mhc_evaluate(ctx, s)
+    o = oracle.evaluate(s, threads=THREADS)
+    parity.check(s, g, o, "32768 trajectories")
+    assert (o.k64 >= 0).sum() > 1000 and (o.k64 < 0).sum() > 1000

@@ -327,7 +327,7 @@ def class_checks(scene):
 
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
-WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "eleven_object_octagons",
+WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "table_one_s2_timeline", "eleven_object_octagons",
              "eleven_object_timeline", "eleven_object_models", "stress")
 
 
@@ -360,12 +360,17 @@ def make_workload(name, seed, sg):
                "overlap": "exact"}
         return scene, "40-object stress scene", cfg, f"40-object stress scene seed {seed}"
     pip = name.endswith("_pip")
+    tl = name.endswith("_timeline")
     scene = sg.paper_scene(seed, n_co=10, n_acc=6, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
+    scene.timeline = 1 if tl else 0
     cfg = {"workload": "table_one_s2_scene", "objects": 11, "vehicles": 11, "pedestrians": 0,
            "trajectories": {"ego": 2058, "co": 42}, "horizon": 100, "dt": 0.02, "seed": seed, "pairs": "ego",
            "overlap": "pip" if pip else "exact"}
-    label = "Table I S2 scene" + (", point-in-polygon" if pip else "")
-    return scene, label, cfg, f"Table I S2 scene seed {seed} ({'point-in-polygon' if pip else 'exact'} overlap)"
+    label = "Table I S2 scene" + (", point-in-polygon" if pip else "") + (", risk over time" if tl else "")
+    if tl:
+        cfg["risk_over_time"] = True
+    return scene, label, cfg, (f"Table I S2 scene seed {seed} ({'point-in-polygon' if pip else 'exact'} overlap"
+                               f"{', risk over time' if tl else ''})")
 
 
 def recorded_traffic(variant, workload):

@@ -425,10 +425,16 @@ def cpu_baseline(scene, checks, seconds, described, pair_list=None):
     dt = time.perf_counter() - t0
     value = checks * runs / dt
     log(f"cpu baseline: {runs} oracle runs in {dt:.2f} s on {cores} threads -> {value:.4g} checks/s")
+    # the same oracle on one thread, one pass
+    t1 = time.perf_counter()
+    oracle.evaluate(scene, pair_list=pair_list, threads=1, masks=False)
+    dt1 = time.perf_counter() - t1
+    log(f"cpu baseline, one thread: one oracle run in {dt1:.2f} s -> {checks / dt1:.4g} checks/s")
     what = "the full timed scene" if pair_list is None else f"{len(pair_list)} sampled object pairs of"
     return {"value": value, "unit": "checks/s", "cores": cores, "kind": "oracle",
             "sample": f"{what} ({described}), {runs} complete oracle passes "
-                      f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s"}
+                      f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s",
+            "value_one_thread": checks / dt1}
 
 
 def serve(mhc, ctx, sg, seconds):

@@ -662,8 +662,8 @@ def main():
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard object pairs across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard object pairs across GPUs)", file=sys.stderr)
         sys.exit(2)
     if args.seed is None:
         args.seed = {"eleven_object": 1, "eleven_object_octagons": 1, "eleven_object_timeline": 1,

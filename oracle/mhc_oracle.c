@@ -182,7 +182,7 @@ static void pedestrian_accel_trajectory(double x0, double y0, double v0, double 
  *   beta_dot  = -(cf + cr)/(m v) beta + ((cr lr - cf lf)/(m v^2) - 1) psi_dot + cf/(m v) delta
  *   psi_ddot  = (cr lr - cf lf)/Iz beta - (cf lf^2 + cr lr^2)/(Iz v) psi_dot + cf lf/Iz delta
  * with a constant front steering angle delta (the lateral controller needs
- * lanes, which this build leaves out) and a constant acceleration vdot (the
+ * lanes, which are not modelled) and a constant acceleration vdot (the
  * speed stopping at 0 as for the kinematic model), integrated with the Euler
  * update of Sec. IV-B.1:
  *   v_{n+1} = v_n + vdot_n tau,  beta_{n+1} = beta_n + beta_dot_n tau,

@@ -1091,34 +1091,59 @@ __device__ __forceinline__ double keep_of(unsigned long long v)
     else return 1.0 + expm1(-(double)v * kLInvScale);
 }
 
-template <int RISK>
-__device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigned long long *__restrict__ hist,
-                                                    unsigned long long *__restrict__ qacc, double *__restrict__ att_w,
-                                                    double *__restrict__ ct_w, double *__restrict__ traj_crit_t,
-                                                    double *__restrict__ traj_attrib, int i, int b, int W)
+// Inclusive product over the lanes b' <= b of each trajectory's segment of W
+// lanes (DPP row shifts for W <= 16, lane permutes for W = 32, 64).
+__device__ __forceinline__ double segment_product(double x, int b, int W)
 {
-    const int n = o.n_scene_obj, H = o.H;
+    if (W <= 16) {
+        double t;
+        if (W > 1) { t = row_shift<1, true>(x); if (b >= 1) x *= t; }
+        if (W > 2) { t = row_shift<2, true>(x); if (b >= 2) x *= t; }
+        if (W > 4) { t = row_shift<4, true>(x); if (b >= 4) x *= t; }
+        if (W > 8) { t = row_shift<8, true>(x); if (b >= 8) x *= t; }
+        return x;
+    }
+    for (int d = 1; d < W; d <<= 1) {
+        const double t = __shfl_up(x, d, W);
+        if (b >= d) x *= t;
+    }
+    return x;
+}
+
+// Slots [s_begin, s_end) of trajectory (a, i), lane b, from the running sum
+// Q of all slots before s_begin (the last lane of the segment also gets
+// all_carry = prod_b f_b(s_begin - 1)). Writes the criticality of these
+// slots and returns this lane's attribution terms over them; the sums of
+// each group of slots are loaded one group ahead of their use.
+template <int RISK>
+__device__ __forceinline__ double timeline_chunk(const DObj &o, const unsigned long long *__restrict__ hist,
+                                                 double *__restrict__ ct_w, double *__restrict__ traj_crit_t, int i,
+                                                 int b, int W, int s_begin, int s_end, unsigned long long Q,
+                                                 double all_carry)
+{
+    const int H = o.H;
     const int64_t T = o.T;
-    const bool valid = i < o.T && b < n;
+    const bool valid = i < o.T && b < o.n_scene_obj;
     const bool writer = b == W - 1 && i < o.T;
     const int64_t slot_stride = T * W;
+    if (s_begin >= s_end) return 0.0;
     // every lane loads (padding lanes b >= n hold zeros; lanes past the last
-    // trajectory read trajectory 0 and slots past H read slot H-1), and the
-    // values that do not belong to the lane are masked: no branch per load
+    // trajectory read trajectory 0 and slots past the chunk read its last
+    // slot), and the values that do not belong to the lane are masked: no
+    // branch per load
     const unsigned long long *__restrict__ h = hist + o.hist_off + (int64_t)(i < o.T ? i : 0) * W + b;
-    unsigned long long Q = 0ull;
-    double f_carry = 1.0, A = 0.0;
-    double all_carry = 1.0;  // writer lane: prod_b f_b of the last slot so far
+    double f_carry = valid ? keep_of<RISK>(Q) : 1.0, A = 0.0;
+    const int last = s_end - 1;
     unsigned long long v[K3T_SLOTS];
 #pragma unroll
-    for (int k = 0; k < K3T_SLOTS; ++k) v[k] = h[(int64_t)min(k, H - 1) * slot_stride];
-    for (int s0 = 0; s0 < H; s0 += K3T_SLOTS) {
+    for (int k = 0; k < K3T_SLOTS; ++k) v[k] = h[(int64_t)min(s_begin + k, last) * slot_stride];
+    for (int s0 = s_begin; s0 < s_end; s0 += K3T_SLOTS) {
         unsigned long long vn[K3T_SLOTS];
 #pragma unroll
-        for (int k = 0; k < K3T_SLOTS; ++k) vn[k] = h[(int64_t)min(s0 + K3T_SLOTS + k, H - 1) * slot_stride];
+        for (int k = 0; k < K3T_SLOTS; ++k) vn[k] = h[(int64_t)min(s0 + K3T_SLOTS + k, last) * slot_stride];
         bool change = false;
 #pragma unroll
-        for (int k = 0; k < K3T_SLOTS; ++k) change |= valid && s0 + k < H && v[k] != 0ull;
+        for (int k = 0; k < K3T_SLOTS; ++k) change |= valid && s0 + k < s_end && v[k] != 0ull;
         if (!__any(change)) {
             // no first hit in these slots for any trajectory of the wave: the
             // factors, the attribution and the criticality stay as they are
@@ -1126,7 +1151,7 @@ __device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigne
 #pragma unroll
                 for (int k = 0; k < K3T_SLOTS; ++k) {
                     const int s = s0 + k;
-                    if (s < H) {
+                    if (s < s_end) {
                         ct_w[o.tl_traj + (int64_t)s * T + i] = 1.0 - all_carry;
                         if (traj_crit_t) traj_crit_t[o.tl_traj + (int64_t)i * H + s] = 1.0 - all_carry;
                     }
@@ -1136,12 +1161,12 @@ __device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigne
             for (int k = 0; k < K3T_SLOTS; ++k) v[k] = vn[k];
             continue;
         }
-        // factors after (g) and before (f) each slot; slots past H repeat the last
+        // factors after (g) and before (f) each slot; slots past the chunk repeat the last
         double g[K3T_SLOTS], f[K3T_SLOTS];
 #pragma unroll
         for (int k = 0; k < K3T_SLOTS; ++k) {
             f[k] = k == 0 ? f_carry : g[k - 1];
-            Q += (valid && s0 + k < H) ? v[k] : 0ull;
+            Q += (valid && s0 + k < s_end) ? v[k] : 0ull;
             g[k] = valid ? keep_of<RISK>(Q) : 1.0;
         }
         f_carry = g[K3T_SLOTS - 1];
@@ -1182,13 +1207,13 @@ __device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigne
         for (int k = 0; k < K3T_SLOTS; ++k) {
             const double bl = b > 0 ? below[k] : 1.0;      // inclusive -> exclusive
             const double ab = b + 1 < W ? above[k] : 1.0;
-            A += (f[k] - g[k]) * bl * ab;                   // 0 past H: f == g there
+            A += (f[k] - g[k]) * bl * ab;                   // 0 past the chunk: f == g there
         }
         if (writer) {  // lo at the last lane = prod_b f_b(s)
 #pragma unroll
             for (int k = 0; k < K3T_SLOTS; ++k) {
                 const int s = s0 + k;
-                if (s < H) {
+                if (s < s_end) {
                     ct_w[o.tl_traj + (int64_t)s * T + i] = 1.0 - lo[k];
                     if (traj_crit_t) traj_crit_t[o.tl_traj + (int64_t)i * H + s] = 1.0 - lo[k];
                 }
@@ -1198,43 +1223,87 @@ __device__ __forceinline__ void timeline_trajectory(const DObj &o, const unsigne
 #pragma unroll
         for (int k = 0; k < K3T_SLOTS; ++k) v[k] = vn[k];
     }
-    if (!valid) return;
-    qacc[o.q_row + (int64_t)i * n + b] = Q;
-    att_w[o.q_row + (int64_t)b * T + i] = A;
-    if (traj_attrib) traj_attrib[o.q_row + (int64_t)i * n + b] = A;
+    return A;
 }
 
-// K3t: grid y = object, x = group of 4 waves; a wave takes 64 / W consecutive
-// trajectories, lane = (trajectory, b). Slots go in groups of K3T_SLOTS: the
-// lanes load the group's sums (one group ahead), form the running sums and
-// factors, and the segment of W lanes of every trajectory forms, for all
-// slots of the group at once (independent chains, so their latencies
-// overlap), the products of the factors below b (new) and above b (old):
-// DPP row shifts for W <= 16, lane permutes for W = 32, 64. Lane b then adds
-// its attribution terms; the last lane of the segment holds prod_b f_b(s).
-// Writes the criticality over time as [s][i] scratch (and traj_crit_t
-// (i, s) if asked for), the attribution as [b][i] scratch (and (i, b) if
-// asked for), and the total sums of every b into the integer accumulators
-// k3_crit reads. Timeline scenes have at most 64 objects.
+// K3t: grid y = object, x = group of 64 / W trajectories, lane = (trajectory,
+// b); the four waves of a workgroup take the same lanes and split the slots
+// into four consecutive chunks, so that every trajectory's slots are walked
+// by four waves side by side. Wave c first adds up the per-slot sums of its
+// chunk (one load per slot and lane); after a barrier it starts from the sums
+// of the chunks before it (added in chunk order), their factors and, in the
+// segment's last lane, their product, and walks its chunk: slots go in
+// groups of K3T_SLOTS, the lanes load the group's sums (one group ahead),
+// form the running sums and factors, and the segment of W lanes of every
+// trajectory forms, for all slots of the group at once (independent chains,
+// so their latencies overlap), the products of the factors below b (new) and
+// above b (old): DPP row shifts for W <= 16, lane permutes for W = 32, 64.
+// Lane b then adds its attribution terms; the last lane of the segment holds
+// prod_b f_b(s). After a second barrier wave 0 adds the four chunks'
+// attribution terms in chunk order. Writes the criticality over time as
+// [s][i] scratch (and traj_crit_t (i, s) if asked for), the attribution as
+// [b][i] scratch (and (i, b) if asked for), and the total sums of every b
+// into the integer accumulators k3_crit reads. Timeline scenes have at most
+// 64 objects.
 __global__ __launch_bounds__(WG) void k3_timeline(const DObj *__restrict__ objs,
                                                   const unsigned long long *__restrict__ hist,
                                                   unsigned long long *__restrict__ qacc, double *__restrict__ att_w,
                                                   double *__restrict__ ct_w, double *__restrict__ traj_crit_t,
                                                   double *__restrict__ traj_attrib)
 {
+    constexpr int CHUNKS = WG / WAVE;
+    __shared__ unsigned long long chunk_sum[CHUNKS][WAVE];
+    __shared__ double chunk_att[CHUNKS][WAVE];
     const DObj o = objs[blockIdx.y];
-    if (!o.timeline) return;
+    if (!o.timeline) return;  // whole workgroup
     const int W = o.tl_w;
     const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int c = (int)(threadIdx.x / WAVE);
     const int per_wave = WAVE / W;
-    const int first_i = ((int)blockIdx.x * (WG / WAVE) + (int)(threadIdx.x / WAVE)) * per_wave;
-    if (first_i >= o.T) return;  // whole wave: every lane below takes part in the lane exchanges
+    const int first_i = (int)blockIdx.x * per_wave;
+    if (first_i >= o.T) return;  // whole workgroup: every lane below takes part in the exchanges
     const int i = first_i + lane / W;
     const int b = lane & (W - 1);
-    if (o.risk == RISK_EXCLUSIVE)
-        timeline_trajectory<RISK_EXCLUSIVE>(o, hist, qacc, att_w, ct_w, traj_crit_t, traj_attrib, i, b, W);
-    else
-        timeline_trajectory<RISK_INDEPENDENT>(o, hist, qacc, att_w, ct_w, traj_crit_t, traj_attrib, i, b, W);
+    const bool valid = i < o.T && b < o.n_scene_obj;
+    const int H = o.H;
+    const int len = (H + CHUNKS - 1) / CHUNKS;
+    const int s_begin = min(c * len, H), s_end = min(s_begin + len, H);
+    // this chunk's sums, eight loads in flight at a time
+    const unsigned long long *__restrict__ h = hist + o.hist_off + (int64_t)(i < o.T ? i : 0) * W + b;
+    const int64_t slot_stride = (int64_t)o.T * W;
+    unsigned long long sum = 0ull;
+    for (int s0 = s_begin; s0 < s_end; s0 += 8) {
+        unsigned long long v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = h[(int64_t)min(s0 + k, s_end - 1) * slot_stride];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sum += s0 + k < s_end ? v[k] : 0ull;
+    }
+    chunk_sum[c][lane] = valid ? sum : 0ull;
+    __syncthreads();
+    unsigned long long Q = 0ull;
+    for (int k = 0; k < c; ++k) Q += chunk_sum[k][lane];
+    const double f0 =
+        valid ? (o.risk == RISK_EXCLUSIVE ? keep_of<RISK_EXCLUSIVE>(Q) : keep_of<RISK_INDEPENDENT>(Q)) : 1.0;
+    const double all_carry = segment_product(f0, b, W);
+    const double A = o.risk == RISK_EXCLUSIVE
+                         ? timeline_chunk<RISK_EXCLUSIVE>(o, hist, ct_w, traj_crit_t, i, b, W, s_begin, s_end, Q,
+                                                          all_carry)
+                         : timeline_chunk<RISK_INDEPENDENT>(o, hist, ct_w, traj_crit_t, i, b, W, s_begin, s_end, Q,
+                                                            all_carry);
+    chunk_att[c][lane] = A;
+    __syncthreads();
+    if (c != 0 || !valid) return;
+    double At = 0.0;
+    unsigned long long Qt = 0ull;
+    for (int k = 0; k < CHUNKS; ++k) {
+        At += chunk_att[k][lane];
+        Qt += chunk_sum[k][lane];
+    }
+    const int n = o.n_scene_obj;
+    qacc[o.q_row + (int64_t)i * n + b] = Qt;
+    att_w[o.q_row + (int64_t)b * o.T + i] = At;
+    if (traj_attrib) traj_attrib[o.q_row + (int64_t)i * n + b] = At;
 }
 
 // Sum of a double over the 64 lanes of a wave in a fixed butterfly order.

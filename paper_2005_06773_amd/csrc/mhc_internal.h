@@ -183,7 +183,7 @@ struct Launch {
     unsigned int *done;           // per object: risk chunks finished
     // time-resolved risk (null / 0 when no scene of the launch asks for it)
     int timeline;
-    int k3t_x, k4t_y;             // time-resolved kernel grids: 4-wave groups of the largest object; rows
+    int k3t_x, k4t_y;             // time-resolved kernel grids: a wave of lanes of the largest object per workgroup; rows
     unsigned long long *hist;     // per-slot integer q sums
     double *att_w;                // attribution [b][i] per object
     double *ct_w;                 // criticality over time [s][i] per object

@@ -301,7 +301,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
                 d.tl_obj = L.n_tl_obj;
                 d.tl_att = L.n_tl_att;
                 L.n_hist += (int64_t)W * s.horizon * d.T;
-                L.k3t_x = std::max<int64_t>(L.k3t_x, ((int64_t)d.T * W + WG - 1) / WG);
+                L.k3t_x = std::max<int64_t>(L.k3t_x, ((int64_t)d.T * W + WAVE - 1) / WAVE);
                 L.k4t_y = std::max(L.k4t_y, s.horizon + n);
                 L.n_tl_traj += (int64_t)s.horizon * d.T;
                 L.n_tl_obj += s.horizon;

@@ -49,7 +49,7 @@ struct Layout {
     int64_t n_part = 0;           // risk kernel partial sums (chunks over all objects)
     bool timeline = false;        // some scene asks for the risk over time
     int64_t n_hist = 0, n_tl_traj = 0, n_tl_obj = 0, n_tl_att = 0;
-    int64_t k3t_x = 0;            // time-resolved risk kernel grid x (4-wave groups of the largest object)
+    int64_t k3t_x = 0;            // time-resolved risk kernel grid x (one wave of lanes of the largest object per workgroup)
     int k4t_y = 0;                // time-resolved reduction grid y (rows: slots + objects)
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_polys = 0, image_bytes = 0;

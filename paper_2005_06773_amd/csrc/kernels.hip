@@ -58,7 +58,7 @@ __device__ __forceinline__ double q_of(int risk, unsigned long long v)
 // fixed tree: the order depends on T only.
 __device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals,
                                         double *__restrict__ p, unsigned long long *__restrict__ pfix,
-                                        unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done)
+                                        unsigned int *__restrict__ done)
 {
     __shared__ double red[WG];
     const int tid = threadIdx.x;
@@ -101,10 +101,8 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
             }
         }
     }
-    // this object's rows of the integer q accumulators start from zero, and
-    // so does its completion counter of the risk kernel
-    const int64_t nq = (int64_t)o.T * o.n_scene_obj;
-    for (int64_t k = tid; k < nq; k += WG) qacc[o.q_row + k] = 0ull;
+    // the object's completion counter of the risk kernel starts from zero
+    // (each trajectory's wave clears its row of the q accumulators)
     if (tid == 0) done[obj] = 0u;
 }
 
@@ -274,7 +272,7 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
     const int obj = (int)blockIdx.y;
     const DObj o = objs[obj];
     if (blockIdx.x == 0) {
-        normalise_probabilities(o, obj, vals, p, pfix, qacc, done);
+        normalise_probabilities(o, obj, vals, p, pfix, done);
         return;
     }
     if (o.timeline) {
@@ -289,6 +287,8 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
     const int lane = threadIdx.x & 63;
     const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
+    // this trajectory's row of the integer q accumulators starts from zero
+    for (int k = lane; k < o.n_scene_obj; k += 64) qacc[o.q_row + (int64_t)i * o.n_scene_obj + k] = 0ull;
     if (o.model == MODEL_ONE_TRACK) {
         one_track_wave(o, vals, poses, i, lane);
         return;

@@ -387,19 +387,33 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
 // against the other rectangle (the paper's test, both ways).
 // ===========================================================================
 
+// A rectangle's pose (x, y, cos, sin) prepared for tests in its frame: K =
+// (x cos + y sin, y cos - x sin) is its centre in its own frame.
+__device__ __forceinline__ float4 rect_frame(const float4 P)
+{
+    return make_float4(fmaf(P.x, P.z, P.y * P.w), fmaf(P.y, P.z, -(P.x * P.w)), P.z, P.w);
+}
+
+// Rectangle-rectangle (separating axes). With C = u_P.u_Q and S = v_P.u_Q
+// (so u_P = C u_Q - S v_Q, v_P = S u_Q + C v_Q) and d = c_Q - c_P, the
+// rectangles overlap iff
+//   |d.u_P| <= lP + lQ|C| + wQ|S|,   |d.v_P| <= wP + lQ|S| + wQ|C|,
+//   |d.u_Q| <= lQ + lP|C| + wP|S|,   |d.v_Q| <= wQ + lP|S| + wP|C|.
+// Q's pose is prepared once per step (rect_frame: K = c_Q in its own frame),
+// so d.u_Q = K.x - (x_P cos_Q + y_P sin_Q) and d.v_Q = K.y - (y_P cos_Q - x_P
+// sin_Q) are two FMA chains each, and d.u_P, d.v_P follow from them by the
+// rotation (C, S): 25 VALU per test and 4 per prepared pose.
 struct CheckVV {
     float lP, wP, lQ, wQ;
-    __device__ __forceinline__ bool operator()(const float4 P, const float4 Q) const
+    __device__ __forceinline__ bool operator()(const float4 P, const float4 Qk) const
     {
-        const float dx = Q.x - P.x;
-        const float dy = Q.y - P.y;
-        const float C = fmaf(P.z, Q.z, P.w * Q.w);    // u_P . u_Q = v_P . v_Q
-        const float S = fmaf(P.z, Q.w, -(P.w * Q.z)); // v_P . u_Q = -u_P . v_Q
+        const float C = fmaf(P.z, Qk.z, P.w * Qk.w);    // u_P . u_Q = v_P . v_Q
+        const float S = fmaf(P.z, Qk.w, -(P.w * Qk.z)); // v_P . u_Q = -u_P . v_Q
         const float aC = fabsf(C), aS = fabsf(S);
-        const float p1 = fmaf(dx, P.z, dy * P.w);     // d . u_P
-        const float p2 = fmaf(dy, P.z, -(dx * P.w));  // d . v_P
-        const float p3 = fmaf(dx, Q.z, dy * Q.w);     // d . u_Q
-        const float p4 = fmaf(dy, Q.z, -(dx * Q.w));  // d . v_Q
+        const float p3 = fmaf(-P.x, Qk.z, fmaf(-P.y, Qk.w, Qk.x));  // d . u_Q
+        const float p4 = fmaf(-P.y, Qk.z, fmaf(P.x, Qk.w, Qk.y));   // d . v_Q
+        const float p1 = fmaf(C, p3, -(S * p4));                     // d . u_P
+        const float p2 = fmaf(S, p3, C * p4);                        // d . v_P
         const float r1 = fmaf(lQ, aC, fmaf(wQ, aS, lP));
         const float r2 = fmaf(lQ, aS, fmaf(wQ, aC, wP));
         const float r3 = fmaf(lP, aC, fmaf(wP, aS, lQ));
@@ -457,11 +471,6 @@ struct CheckVVPip {
 // the difference Q - c_P: 12 VALU per test and 4 per prepared pose. Every
 // tile computes each test with the same operations, so results do not
 // depend on the tile.
-__device__ __forceinline__ float4 rect_frame(const float4 P)
-{
-    return make_float4(fmaf(P.x, P.z, P.y * P.w), fmaf(P.y, P.z, -(P.x * P.w)), P.z, P.w);
-}
-
 __device__ __forceinline__ bool rect_circle(const float4 Pk, const float2 Q, float lP, float wP, float rr)
 {
     const float lam = fmaf(Q.x, Pk.z, fmaf(Q.y, Pk.w, -Pk.x));
@@ -482,14 +491,21 @@ struct CheckPV {  // b: the rectangle, prepared
 };
 
 // Per-pose preparation before the tests of a step, once per loaded pose and
-// shared by all tests of that pose: the identity, except for the rectangle
-// of a rectangle-circle pair (rect_frame).
+// shared by all tests of that pose: the identity, except for the second
+// rectangle of a rectangle-rectangle pair and the rectangle of a
+// rectangle-circle pair (rect_frame).
 template <class C>
 struct Prep {
     template <class P>
     __device__ __forceinline__ static P a(const P p) { return p; }
     template <class P>
     __device__ __forceinline__ static P b(const P p) { return p; }
+};
+
+template <>
+struct Prep<CheckVV> {
+    __device__ __forceinline__ static float4 a(const float4 p) { return p; }
+    __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
 };
 
 template <>

@@ -48,7 +48,7 @@ int scene_family(const mhc_scene *s)
 
 // Relative VALU cost of one check per class, for longest-first ordering; the
 // polygon classes scale with the vertex counts (class_cost).
-static const double kClsCost[N_CLS] = {28.0, 13.0, 13.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
+static const double kClsCost[N_CLS] = {26.0, 13.0, 13.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
 
 double class_cost(int cls, int k_a, int k_b)
 {
@@ -405,8 +405,10 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         const int ka = pr.poly_a >= 0 ? pair_vertices[2 * pidx] : 0, kb = pr.poly_b >= 0 ? pair_vertices[2 * pidx + 1] : 0;
         // a wave executes every step of every test of a unit, whether or
         // not all of its lanes hold an item
-        // rectangle-circle tests: 12 VALU each plus 4 per prepared rectangle pose
-        const double per_test = pr.cls == CLS_VP   ? 12.0 + 4.0 / ts.rj
+        // rectangle-rectangle and rectangle-circle tests: 25 and 12 VALU each
+        // plus 4 per prepared rectangle pose
+        const double per_test = pr.cls == CLS_VV   ? 25.0 + 4.0 / ts.ri
+                                : pr.cls == CLS_VP ? 12.0 + 4.0 / ts.rj
                                 : pr.cls == CLS_PV ? 12.0 + 4.0 / ts.ri
                                                    : class_cost(pr.cls, ka, kb);
         const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * per_test + kUnitOverhead;

@@ -745,11 +745,12 @@ def main():
     log(f"step {ms_step * 1e3:.1f} us -> {value:.4g} checks/s; collision kernel {k2_ms * 1e3:.1f} us -> "
         f"{achieved:.2f} TFLOP/s ({checks / (k2_ms / 1e3):.4g} checks/s)")
 
-    # VALU instructions per check in the inner loops (27 rect-rect; 13
-    # rect-circle: 12 per test and 4 per rectangle pose shared by 4 circles;
-    # 6 circle-circle; 60 point-in-polygon; first-hit bookkeeping included)
-    # against the lane-op rate.
-    lane_ops = 27 * cls["VV"] + 13 * cls["VP"] + 6 * cls["PP"] + 60 * cls["VV_PIP"]
+    # VALU instructions per check in the inner loops (26 rect-rect: 25 per test
+    # and 4 per prepared rectangle pose shared by 4 rows; 13 rect-circle: 12
+    # per test and 4 per rectangle pose shared by 4 circles; 6 circle-circle;
+    # 60 point-in-polygon; first-hit bookkeeping included) against the
+    # lane-op rate.
+    lane_ops = 26 * cls["VV"] + 13 * cls["VP"] + 6 * cls["PP"] + 60 * cls["VV_PIP"]
     result = {
         "metric": f"pose-pair checks/sec ({label})",
         "value": value,

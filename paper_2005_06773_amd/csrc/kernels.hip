@@ -429,18 +429,18 @@ struct CheckVV {
 // |x| <= lP and |y| <= wP. The corners of P in Q's frame follow with the roles
 // swapped; flipping both signs of a corner leaves |x| and |y| unchanged, so
 // they are (d.u_Q + al*lP*C + be*wP*S, d.v_Q - al*lP*S + be*wP*C).
+// Q's pose is prepared once per step (rect_frame) and the projections are
+// formed as in the separating-axes test.
 struct CheckVVPip {
     float lP, wP, lQ, wQ;
-    __device__ __forceinline__ bool operator()(const float4 P, const float4 Q) const
+    __device__ __forceinline__ bool operator()(const float4 P, const float4 Qk) const
     {
-        const float dx = Q.x - P.x;
-        const float dy = Q.y - P.y;
-        const float C = fmaf(P.z, Q.z, P.w * Q.w);
-        const float S = fmaf(P.z, Q.w, -(P.w * Q.z));
-        const float p1 = fmaf(dx, P.z, dy * P.w);     // d . u_P
-        const float p2 = fmaf(dy, P.z, -(dx * P.w));  // d . v_P
-        const float p3 = fmaf(dx, Q.z, dy * Q.w);     // d . u_Q
-        const float p4 = fmaf(dy, Q.z, -(dx * Q.w));  // d . v_Q
+        const float C = fmaf(P.z, Qk.z, P.w * Qk.w);
+        const float S = fmaf(P.z, Qk.w, -(P.w * Qk.z));
+        const float p3 = fmaf(-P.x, Qk.z, fmaf(-P.y, Qk.w, Qk.x));  // d . u_Q
+        const float p4 = fmaf(-P.y, Qk.z, fmaf(P.x, Qk.w, Qk.y));   // d . v_Q
+        const float p1 = fmaf(C, p3, -(S * p4));                     // d . u_P
+        const float p2 = fmaf(S, p3, C * p4);                        // d . v_P
         // Q's corners in P: (p1 +- g, p2 +- k) and (p1 +- h, p2 +- m), signs paired
         const float wQS = wQ * S, wQC = wQ * C;
         const float g = fmaf(lQ, C, -wQS), h = fmaf(lQ, C, wQS);
@@ -504,6 +504,12 @@ struct Prep {
 
 template <>
 struct Prep<CheckVV> {
+    __device__ __forceinline__ static float4 a(const float4 p) { return p; }
+    __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
+};
+
+template <>
+struct Prep<CheckVVPip> {
     __device__ __forceinline__ static float4 a(const float4 p) { return p; }
     __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
 };

@@ -8,6 +8,7 @@ fails loudly when it has not been built; there is no fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import List, Optional, Sequence
 
@@ -231,9 +232,34 @@ def _shapes(cs: CScene, first_hit: bool, q: bool, timeline: Optional[bool]):
     }
 
 
+def host_results(css: Sequence[CScene], first_hit: bool = True, q: bool = True,
+                 timeline: Optional[bool] = None):
+    """NaN-filled host outputs (first hits -2) for every field asked for, per
+    scene; the time-resolved ones by default when a scene asks for the risk
+    over time. Each field of all scenes is one array and each scene's output a
+    view of it, and the result structs are one array of pointers, so a batch
+    costs a few allocations rather than several per scene."""
+    shapes = [_shapes(c, first_hit, q, timeline) for c in css]
+    ptrs = np.zeros((len(css), len(RESULT_FIELDS)), np.uint64)
+    outs = [dict.fromkeys(sh) for sh in shapes]
+    for f, k in enumerate(RESULT_FIELDS):
+        sizes = [0 if sh[k] is None else math.prod(sh[k]) for sh in shapes]
+        if not any(sh[k] is not None for sh in shapes):
+            continue
+        buf = np.full(sum(sizes), -2, np.int16) if k == "first_hit" else np.full(sum(sizes), np.nan)
+        base = buf.__array_interface__["data"][0]
+        off = 0
+        for i, sh in enumerate(shapes):
+            if sh[k] is not None:
+                outs[i][k] = buf[off:off + sizes[i]].reshape(sh[k])
+                ptrs[i, f] = base + off * buf.itemsize
+                off += sizes[i]
+    return outs, (mhc_result * len(css)).from_buffer(ptrs)
+
+
 def host_result(cs: CScene, first_hit: bool = True, q: bool = True, timeline: Optional[bool] = None):
-    """NaN-filled host outputs (first hits -2) for every field asked for; the
-    time-resolved ones by default when the scene asks for the risk over time."""
+    """``host_results`` of one scene (its outputs and its result struct), with
+    an array per field."""
     out = {k: None if sh is None else (np.full(sh, -2, np.int16) if k == "first_hit" else np.full(sh, np.nan))
            for k, sh in _shapes(cs, first_hit, q, timeline).items()}
     r = mhc_result(*(None if out[k] is None else out[k].ctypes.data for k in RESULT_FIELDS))
@@ -302,10 +328,9 @@ def mhc_evaluate(ctx, scene, first_hit: bool = True, q: bool = True, timeline: O
 def mhc_evaluate_batch(ctx, scenes: Sequence, first_hit: bool = True, q: bool = True) -> List[dict]:
     css = [s if isinstance(s, CScene) else CScene(s) for s in scenes]
     arr = (mhc_scene * len(css))(*[c.c for c in css])
-    outs, rs = zip(*[host_result(c, first_hit, q) for c in css])
-    rarr = (mhc_result * len(css))(*rs)
+    outs, rarr = host_results(css, first_hit, q)
     _check(ctx, lib.mhc_evaluate_batch(ctx, len(css), arr, rarr))
-    return list(outs)
+    return outs
 
 
 def device_result(cs: CScene, device="cuda", first_hit: bool = True, q: bool = True,

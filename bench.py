@@ -325,6 +325,9 @@ def class_checks(scene):
     return out, flops
 
 
+# Measurements after the timed workload, in this order (--extras).
+EXTRAS = ("latency", "batched", "served", "table_one", "timeline", "polygons", "models", "stress")
+
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
 WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "table_one_s2_timeline", "eleven_object_octagons",
@@ -652,6 +655,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the latency and batched measurements")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated extras to run (default: all of " + ", ".join(EXTRAS) + ")")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="length of the served-load measurement (after 1 s of warm-up)")
     ap.add_argument("--serve-sweep-seconds", type=float, default=1.5,
@@ -661,6 +666,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    if extras - set(EXTRAS):
+        sys.exit(f"bench.py: unknown extras {sorted(extras - set(EXTRAS))}; choose from {', '.join(EXTRAS)}")
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the path would shard object pairs across GPUs)", file=sys.stderr)
@@ -778,7 +786,7 @@ def main():
     oc = out["object_crit"].cpu()
     assert torch.isfinite(oc).all() and (oc >= 0).all() and (oc <= 1).all(), "bad criticality"
 
-    if not args.no_extras:
+    if "latency" in extras:
         # Plain end-to-end latency: host scene in -> host criticality out.
         lat = []
         for _ in range(10):
@@ -790,6 +798,7 @@ def main():
         result["plain_latency_ms"] = {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
                                       "note": "mhc_evaluate, host scene in, host criticality out (PCIe included)"}
         log(f"plain end-to-end latency p50 {pct(lat, 50):.3f} ms p99 {pct(lat, 99):.3f} ms")
+    if "batched" in extras:
         # Batched vs plain loop over the same 64 scenes.
         scenes = [mhc.CScene(s) for s in sg.batch_scenes(2, 64)]
         bchecks = sum(mhc.mhc_query_sizes(s)["n_checks"] for s in scenes)
@@ -812,14 +821,14 @@ def main():
         log(f"batched 64 scenes: {tb * 1e3:.2f} ms ({bchecks / tb:.4g} checks/s) vs plain loop "
             f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
 
+    if "served" in extras:
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
         if args.serve_sweep_seconds > 0:
             result["served_sweep"] = serve_sweep(mhc, ctx, sg, args.serve_sweep_seconds)
-        result["table_one"] = table_one(mhc, ctx, sg, torch)
-        result["timeline"] = timeline_extra(mhc, ctx, sg, torch)
-        result["polygons"] = polygon_extra(mhc, ctx, sg, torch)
-        result["models"] = models_extra(mhc, ctx, sg, torch)
-        result["stress"] = stress_extra(mhc, ctx, sg, torch)
+    for name, fn in (("table_one", table_one), ("timeline", timeline_extra), ("polygons", polygon_extra),
+                     ("models", models_extra), ("stress", stress_extra)):
+        if name in extras:
+            result[name] = fn(mhc, ctx, sg, torch)
 
     plan.close()
     mhc.mhc_destroy(ctx)

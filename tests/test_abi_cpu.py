@@ -281,3 +281,13 @@ def test_collision_plan_check_rejects_bad_arguments(mhc):
     bad = sg.eleven_object_scene(0)
     bad.horizon = 0
     assert mhc.mhc_plan_check(bad, 0, 0)[0] == mhc.MHC_E_INVAL
+
+
+def test_bench_command_line_guards():
+    """bench.py refuses more than one GPU and unknown extras before it touches a GPU."""
+    import subprocess
+    import sys
+    for argv, msg in ((["--gpus", "2"], "one GPU only"), (["--extras", "batched,nonesuch"], "unknown extras")):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], capture_output=True,
+                           text=True, timeout=120)
+        assert r.returncode != 0 and msg in r.stderr, (argv, r.returncode, r.stderr[-300:])

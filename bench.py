@@ -805,7 +805,7 @@ def main():
         mhc.mhc_evaluate_batch(ctx, scenes, first_hit=False, q=False)
         for s in scenes[:4]:
             mhc.mhc_evaluate(ctx, s, first_hit=False, q=False)
-        reps = 5
+        reps = 10
         a = time.perf_counter()
         for _ in range(reps):
             mhc.mhc_evaluate_batch(ctx, scenes, first_hit=False, q=False)

@@ -545,11 +545,12 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
     L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
     L.o_part = put((size_t)L.n_part * sizeof(double));
     L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
+    // the outputs most calls ask for are neighbours, so they come down together
     L.o_p = put((size_t)L.n_traj * sizeof(double));
-    L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
-    L.o_q = put((size_t)L.n_q * sizeof(double));
     L.o_tc = put((size_t)L.n_traj * sizeof(double));
     L.o_oc = put((size_t)L.n_obj * sizeof(double));
+    L.o_q = put((size_t)L.n_q * sizeof(double));
+    L.o_hits = put(with_hits ? (size_t)L.n_hits * sizeof(int16_t) : 0);
     const size_t tq = L.timeline ? (size_t)L.n_q : 0;
     L.o_hist = put((size_t)L.n_hist * sizeof(unsigned long long));
     L.o_attw = put(tq * sizeof(double));
@@ -1040,7 +1041,8 @@ static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, 
 
 // Upload + trajectory/collision/risk launches of a context-owned layout,
 // replayed as one graph per shape key (the scene image's values change from
-// call to call, its layout and every launch argument do not).
+// call to call, its layout and every launch argument do not). A key's first
+// launch is direct: capturing costs more than it saves for a shape seen once.
 static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, bool keep_hits,
                                           std::vector<int64_t> key, hipStream_t s)
 {
@@ -1052,12 +1054,17 @@ static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *d
     key.push_back(keep_hits);
     key.push_back((int64_t)L.image_bytes);
     Launch X = make_launch(L, dbase, nullptr, keep_hits, ctx->n_cu);
-    hipGraphExec_t exec = nullptr;
-    HIPC(ctx->batch_graphs.get(key, [&](hipStream_t cs) {
-        hipError_t e = hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, cs);
-        return e == hipSuccess ? launch_all(X, cs) : e;
-    }, &exec));
-    HIPC(hipGraphLaunch(exec, s));
+    if (ctx->batch_graphs.repeated(key)) {
+        hipGraphExec_t exec = nullptr;
+        HIPC(ctx->batch_graphs.get(key, [&](hipStream_t cs) {
+            hipError_t e = hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, cs);
+            return e == hipSuccess ? launch_all(X, cs) : e;
+        }, &exec));
+        HIPC(hipGraphLaunch(exec, s));
+    } else {
+        HIPC(hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, s));
+        HIPC(launch_all(X, s));
+    }
     HIPC(hipEventRecord(ctx->staging_ev, s));
     return MHC_OK;
 }
@@ -1072,6 +1079,9 @@ static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *d
 // straight to the callers' buffers.
 static const size_t kResultStageMax = size_t(64) << 20;
 static const size_t kResultStageTotal = size_t(256) << 20;
+// Staged outputs at most this far apart in the workspace share one transfer
+// (the bytes between them come along).
+static const size_t kResultMergeGap = size_t(64) << 10;
 
 namespace mhc {
 
@@ -1122,10 +1132,33 @@ ResultPlan plan_results(const Layout &L, int n, const mhc_result *res, bool stag
         R.stage[big] = false;
         total -= R.hi[big] - R.lo[big];
     }
+    // staged outputs in workspace order; one transfer for each run of them
+    // separated by at most kResultMergeGap bytes
+    int ord[ResultPlan::kOutputs], m = 0;
+    for (int f = 0; f < ResultPlan::kOutputs; ++f)
+        if (R.stage[f]) ord[m++] = f;
+    std::sort(ord, ord + m, [&](int x, int y) { return R.lo[x] < R.lo[y]; });
     R.staged = 0;
-    for (int f = 0; f < ResultPlan::kOutputs; ++f) {
-        R.at[f] = R.staged;
-        if (R.stage[f]) R.staged += (R.hi[f] - R.lo[f] + 255) & ~size_t(255);
+    R.n_copies = 0;
+    for (int i = 0; i < m; ++i) {
+        const int f = ord[i];
+        if (R.n_copies > 0 && R.lo[f] <= R.copy_hi[R.n_copies - 1] + kResultMergeGap) {
+            R.copy_hi[R.n_copies - 1] = std::max(R.copy_hi[R.n_copies - 1], R.hi[f]);
+        } else {
+            R.copy_lo[R.n_copies] = R.lo[f];
+            R.copy_hi[R.n_copies] = R.hi[f];
+            ++R.n_copies;
+        }
+    }
+    for (int c = 0; c < R.n_copies; ++c) {
+        R.copy_at[c] = R.staged;
+        R.staged += (R.copy_hi[c] - R.copy_lo[c] + 255) & ~size_t(255);
+    }
+    for (int i = 0; i < m; ++i) {
+        const int f = ord[i];
+        int c = 0;
+        while (!(R.copy_lo[c] <= R.lo[f] && R.hi[f] <= R.copy_hi[c])) ++c;
+        R.at[f] = R.copy_at[c] + (R.lo[f] - R.copy_lo[c]);
     }
     return R;
 }
@@ -1133,14 +1166,13 @@ ResultPlan plan_results(const Layout &L, int n, const mhc_result *res, bool stag
 hipError_t enqueue_results(const ResultPlan &R, const Layout &L, int n, const char *dbase, char *pinned,
                            const mhc_result *res, hipStream_t s)
 {
+    for (int c = 0; c < R.n_copies; ++c) {
+        const hipError_t e = hipMemcpyAsync(pinned + R.copy_at[c], dbase + R.copy_lo[c],
+                                            R.copy_hi[c] - R.copy_lo[c], hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+    }
     for (int f = 0; f < ResultPlan::kOutputs; ++f) {
-        if (R.hi[f] <= R.lo[f]) continue;
-        if (R.stage[f]) {
-            const hipError_t e =
-                hipMemcpyAsync(pinned + R.at[f], dbase + R.lo[f], R.hi[f] - R.lo[f], hipMemcpyDeviceToHost, s);
-            if (e != hipSuccess) return e;
-            continue;
-        }
+        if (R.hi[f] <= R.lo[f] || R.stage[f]) continue;
         for (int k = 0; k < n; ++k) {
             void *dst;
             size_t off, bytes;
@@ -1243,8 +1275,22 @@ void GraphCache::clear()
     for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
     graphs.clear();
     order.clear();
+    seen.clear();
     if (capture) hipStreamDestroy(capture);
     capture = nullptr;
+}
+
+bool GraphCache::repeated(const std::vector<int64_t> &key)
+{
+    if (graphs.count(key)) return true;
+    for (auto it = seen.begin(); it != seen.end(); ++it)
+        if (*it == key) {
+            seen.erase(it);
+            return true;
+        }
+    if (seen.size() >= kMaxSeen) seen.pop_front();
+    seen.push_back(key);
+    return false;
 }
 
 hipError_t GraphCache::get(const std::vector<int64_t> &key, const std::function<hipError_t(hipStream_t)> &enqueue,

@@ -3,6 +3,7 @@
 
 #include <array>
 #include <functional>
+#include <deque>
 #include <map>
 #include <string>
 #include <utility>
@@ -64,13 +65,19 @@ struct Layout {
 // Instantiated HIP graphs keyed by what their launch sequence depends on.
 struct GraphCache {
     static constexpr size_t kMaxGraphs = 16;
+    static constexpr size_t kMaxSeen = 64;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<int64_t>> order;  // insertion order, for eviction
+    std::deque<std::vector<int64_t>> seen;     // keys launched once without a graph, newest last
     hipStream_t capture = nullptr;
     ~GraphCache();
     void clear();
     hipError_t get(const std::vector<int64_t> &key, const std::function<hipError_t(hipStream_t)> &enqueue,
                    hipGraphExec_t *out);
+    // Whether `key` has a graph or was launched before. A key's first launch
+    // goes without a graph (and is remembered), so shapes used once never pay
+    // for a capture; from its second launch on it is captured and replayed.
+    bool repeated(const std::vector<int64_t> &key);
 };
 
 bool validate_scene(const mhc_scene *s, std::string &err, int scene_index = -1);
@@ -98,6 +105,10 @@ struct ResultPlan {
     size_t lo[kOutputs], hi[kOutputs], at[kOutputs];
     bool stage[kOutputs];
     size_t staged = 0;
+    // staged outputs that lie close together in the workspace come down as
+    // one transfer: [copy_lo, copy_hi) of the workspace to pinned + copy_at
+    int n_copies = 0;
+    size_t copy_lo[kOutputs], copy_hi[kOutputs], copy_at[kOutputs];
 };
 ResultPlan plan_results(const Layout &L, int n, const mhc_result *res, bool stage_all);
 // Enqueues the transfers on s: staged outputs into `pinned`, the others to res.

@@ -533,12 +533,15 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
         off = align256(off + bytes);
         return o;
     };
+    // the tables fill_values rewrites come first, the collision plan (which
+    // depends on the shapes only) last
     L.o_objs = put(L.objs.size() * sizeof(DObj));
     L.o_vals = put(L.vals.size() * sizeof(double));
     L.o_pairs = put(L.pairs.size() * sizeof(DPair));
+    L.o_polys = put(L.polys.size() * sizeof(DPoly));
+    L.value_bytes = off;
     L.o_work = put(L.work.size() * sizeof(WorkItem));
     L.o_bins = put(L.bins.size() * sizeof(int32_t));
-    L.o_polys = put(L.polys.size() * sizeof(DPoly));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
@@ -653,7 +656,7 @@ void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
     }
 }
 
-void pack_image(const Layout &L, char *dst)
+void pack_image(const Layout &L, char *dst, bool values_only)
 {
     // each table, then zeros up to the next one (the image is written once)
     auto cp = [&](size_t o, const void *src, size_t bytes, size_t next) {
@@ -662,10 +665,11 @@ void pack_image(const Layout &L, char *dst)
     };
     cp(L.o_objs, L.objs.data(), L.objs.size() * sizeof(DObj), L.o_vals);
     cp(L.o_vals, L.vals.data(), L.vals.size() * sizeof(double), L.o_pairs);
-    cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair), L.o_work);
+    cp(L.o_pairs, L.pairs.data(), L.pairs.size() * sizeof(DPair), L.o_polys);
+    cp(L.o_polys, L.polys.data(), L.polys.size() * sizeof(DPoly), L.value_bytes);
+    if (values_only) return;
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem), L.o_bins);
-    cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t), L.o_polys);
-    cp(L.o_polys, L.polys.data(), L.polys.size() * sizeof(DPoly), L.image_bytes);
+    cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t), L.image_bytes);
 }
 
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu)
@@ -970,7 +974,7 @@ std::vector<int32_t> mhc::shape_of(const mhc_scene *s)
 
 // Layout of `scene` for this context: the shape-dependent tables of the
 // previous call are reused when the shape (and the tile variant) repeats.
-static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool with_hits)
+static bool layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool with_hits)
 {
     const int v = ctx->variant_for(scene, 1);
     std::vector<int32_t> shape = shape_of(scene);
@@ -979,15 +983,16 @@ static void layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool wit
     shape.push_back(with_hits);
     if (!L.objs.empty() && shape == ctx->layout_shape) {
         fill_values(scene, 1, L);
-        return;
+        return true;
     }
     build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, with_hits);
     ctx->layout_shape = std::move(shape);
+    return false;
 }
 
 // Pinned staging for the scene image. The previous upload from it must have
 // left the host buffer before it is rewritten.
-static mhc_status stage_image(mhc_ctx *ctx, const Layout &L, char **host)
+static mhc_status stage_image(mhc_ctx *ctx, const Layout &L, char **host, bool values_only = false)
 {
     HIPC(hipEventSynchronize(ctx->staging_ev));
     if (ctx->staging_bytes < L.image_bytes) {
@@ -998,7 +1003,7 @@ static mhc_status stage_image(mhc_ctx *ctx, const Layout &L, char **host)
         HIPC(hipHostMalloc(reinterpret_cast<void **>(&ctx->staging), want, hipHostMallocDefault));
         ctx->staging_bytes = want;
     }
-    pack_image(L, ctx->staging);
+    pack_image(L, ctx->staging, values_only);
     *host = ctx->staging;
     return MHC_OK;
 }
@@ -1012,6 +1017,7 @@ mhc_status ensure_device(mhc_ctx *ctx, size_t bytes)
     if (ctx->dbuf_bytes >= bytes) return MHC_OK;
     HIPC(hipStreamSynchronize(ctx->stream));
     ctx->batch_graphs.clear();  // their launches point into the old workspace
+    ctx->resident_image.clear();
     if (ctx->dbuf) HIPC(hipFree(ctx->dbuf));
     ctx->dbuf = nullptr;
     ctx->dbuf_bytes = 0;
@@ -1044,25 +1050,27 @@ static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, 
 // call to call, its layout and every launch argument do not). A key's first
 // launch is direct: capturing costs more than it saves for a shape seen once.
 static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, bool keep_hits,
-                                          std::vector<int64_t> key, hipStream_t s)
+                                          std::vector<int64_t> key, hipStream_t s, bool values_only = false)
 {
     char *host = nullptr;
-    mhc_status st = stage_image(ctx, L, &host);
+    mhc_status st = stage_image(ctx, L, &host, values_only);
     if (st != MHC_OK) return st;
+    const size_t up = values_only ? L.value_bytes : L.image_bytes;
     key.push_back((int64_t)(uintptr_t)dbase);
     key.push_back((int64_t)(uintptr_t)host);
     key.push_back(keep_hits);
     key.push_back((int64_t)L.image_bytes);
+    key.push_back((int64_t)up);
     Launch X = make_launch(L, dbase, nullptr, keep_hits, ctx->n_cu);
     if (ctx->batch_graphs.repeated(key)) {
         hipGraphExec_t exec = nullptr;
         HIPC(ctx->batch_graphs.get(key, [&](hipStream_t cs) {
-            hipError_t e = hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, cs);
+            hipError_t e = hipMemcpyAsync(dbase, host, up, hipMemcpyHostToDevice, cs);
             return e == hipSuccess ? launch_all(X, cs) : e;
         }, &exec));
         HIPC(hipGraphLaunch(exec, s));
     } else {
-        HIPC(hipMemcpyAsync(dbase, host, L.image_bytes, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(dbase, host, up, hipMemcpyHostToDevice, s));
         HIPC(launch_all(X, s));
     }
     HIPC(hipEventRecord(ctx->staging_ev, s));
@@ -1228,14 +1236,21 @@ extern "C" mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_res
     if (!validate_scene(scene, ctx->err) || !validate_outputs(scene, res, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     Layout &L = ctx->layout;
-    layout_for(ctx, scene, L, res->first_hit != nullptr);
+    const bool reused = layout_for(ctx, scene, L, res->first_hit != nullptr);
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);
     std::vector<int64_t> key(ctx->layout_shape.begin(), ctx->layout_shape.end());
     key.push_back(-1);  // single scene
-    st = graph_upload_and_launch(ctx, L, dbase, res->first_hit != nullptr, key, ctx->stream);
+    // When the previous launch in this workspace was this shape's, its
+    // collision plan is still there and only the image's value part goes up.
+    std::vector<int64_t> resident = key;
+    resident.push_back((int64_t)(uintptr_t)dbase);
+    const bool values_only = reused && ctx->resident_image == resident;
+    ctx->resident_image.clear();
+    st = graph_upload_and_launch(ctx, L, dbase, res->first_hit != nullptr, key, ctx->stream, values_only);
     if (st != MHC_OK) return st;
+    ctx->resident_image = std::move(resident);
     return download_results(ctx, L, 1, dbase, res, ctx->stream);
 }
 
@@ -1513,6 +1528,7 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
 {
     Layout &L = ctx->layout;
     ctx->layout_shape.clear();
+    ctx->resident_image.clear();
     bool keep = false;
     for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
     const int v = ctx->variant_for(scenes, n);

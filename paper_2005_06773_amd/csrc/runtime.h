@@ -54,6 +54,7 @@ struct Layout {
     int k4t_y = 0;                // time-resolved reduction grid y (rows: slots + objects)
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_polys = 0, image_bytes = 0;
+    size_t value_bytes = 0;       // the image's leading part that fill_values rewrites (before the plan)
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
     size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
@@ -117,7 +118,8 @@ hipError_t enqueue_results(const ResultPlan &R, const Layout &L, int n, const ch
 // After the transfers: copies each scene's staged parts from `pinned` to res.
 void scatter_results(const ResultPlan &R, const Layout &L, int n, const char *pinned, const mhc_result *res);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
-void pack_image(const Layout &L, char *dst);
+// values_only: only the leading value_bytes (the collision plan is left out).
+void pack_image(const Layout &L, char *dst, bool values_only = false);
 std::vector<int32_t> shape_of(const mhc_scene *s);
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu);
 hipError_t launch_all(const Launch &X, hipStream_t s);
@@ -139,6 +141,9 @@ struct mhc_ctx {
     size_t res_pin_bytes = 0;
     mhc::Layout layout;           // reused by mhc_evaluate
     std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
+    // launch key (+ workspace address) of the single-scene image whose
+    // collision plan is in the workspace now; empty when other work wrote it
+    std::vector<int64_t> resident_image;
     mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
     int forced_variant = -1;                      // mhc_set_variant
     std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)

@@ -74,6 +74,7 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
     }
     if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
+    ctx->resident_image.clear();  // the timing launches overwrite the context workspace
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));

@@ -450,3 +450,34 @@ def test_size_limits(mhc, ctx):
     o = oracle.evaluate(s, threads=THREADS)
     parity.check(s, g, o, "32768 trajectories")
     assert (o.k64 >= 0).sum() > 1000 and (o.k64 < 0).sum() > 1000
+
+
+def test_repeated_shape_reuses_resident_plan(mhc, ctx):
+    """Calls on scenes of one shape upload only the value part of the scene
+    image while the shape's collision plan is still in the context's
+    workspace; a batch, an autotune run or a call of another shape in between
+    overwrites it. Every call must equal a fresh context's call on the same
+    scene, bit for bit."""
+    scenes = [sg.eleven_object_scene(s) for s in range(11, 17)]
+    other = sg.paper_scene(7, n_co=3)
+
+    def fresh(scene):
+        c = mhc.mhc_create(0)
+        try:
+            return mhc.mhc_evaluate(c, scene)
+        finally:
+            mhc.mhc_destroy(c)
+
+    steps = [("evaluate", 0), ("evaluate", 1), ("evaluate", 1), ("batch", None), ("evaluate", 2),
+             ("evaluate", 3), ("other", None), ("evaluate", 4), ("autotune", None), ("evaluate", 5),
+             ("evaluate", 0)]
+    for what, k in steps:
+        say(f"resident plan: {what} {k}")
+        if what == "batch":
+            mhc.mhc_evaluate_batch(ctx, sg.batch_scenes(2, 4), first_hit=False, q=False)
+        elif what == "other":
+            parity.same_results(mhc.mhc_evaluate(ctx, other), fresh(other), "another shape in between")
+        elif what == "autotune":
+            mhc.mhc_autotune(ctx, scenes[0], reps=2)
+        else:
+            parity.same_results(mhc.mhc_evaluate(ctx, scenes[k]), fresh(scenes[k]), f"11-object seed {11 + k}")

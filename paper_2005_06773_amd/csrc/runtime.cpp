@@ -1048,7 +1048,8 @@ static mhc_status upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, 
 // Upload + trajectory/collision/risk launches of a context-owned layout,
 // replayed as one graph per shape key (the scene image's values change from
 // call to call, its layout and every launch argument do not). A key's first
-// launch is direct: capturing costs more than it saves for a shape seen once.
+// launch is direct (GraphCache::repeated): capturing costs more than it saves
+// for a shape that does not come back soon.
 static mhc_status graph_upload_and_launch(mhc_ctx *ctx, const Layout &L, char *dbase, bool keep_hits,
                                           std::vector<int64_t> key, hipStream_t s, bool values_only = false)
 {
@@ -1297,14 +1298,19 @@ void GraphCache::clear()
 
 bool GraphCache::repeated(const std::vector<int64_t> &key)
 {
+    ++uses;
     if (graphs.count(key)) return true;
     for (auto it = seen.begin(); it != seen.end(); ++it)
-        if (*it == key) {
-            seen.erase(it);
-            return true;
+        if (it->first == key) {
+            if (uses - it->second <= (int64_t)kMaxGraphs) {
+                seen.erase(it);
+                return true;
+            }
+            it->second = uses;
+            return false;
         }
     if (seen.size() >= kMaxSeen) seen.pop_front();
-    seen.push_back(key);
+    seen.emplace_back(key, uses);
     return false;
 }
 

@@ -69,15 +69,19 @@ struct GraphCache {
     static constexpr size_t kMaxSeen = 64;
     std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<int64_t>> order;  // insertion order, for eviction
-    std::deque<std::vector<int64_t>> seen;     // keys launched once without a graph, newest last
+    // keys launched without a graph, with the use count at their last launch
+    std::deque<std::pair<std::vector<int64_t>, int64_t>> seen;
+    int64_t uses = 0;                          // calls of repeated()
     hipStream_t capture = nullptr;
     ~GraphCache();
     void clear();
     hipError_t get(const std::vector<int64_t> &key, const std::function<hipError_t(hipStream_t)> &enqueue,
                    hipGraphExec_t *out);
-    // Whether `key` has a graph or was launched before. A key's first launch
-    // goes without a graph (and is remembered), so shapes used once never pay
-    // for a capture; from its second launch on it is captured and replayed.
+    // Whether to launch `key` from a graph: it has one, or it comes back
+    // within kMaxGraphs launches of its previous (direct) launch, so that a
+    // graph captured now is likely still cached at its next use. Shapes used
+    // once, or cycling through more shapes than the cache holds, never pay
+    // for a capture.
     bool repeated(const std::vector<int64_t> &key);
 };
 

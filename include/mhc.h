@@ -23,6 +23,13 @@
  *     mhc_wait, mhc_server_stats) are thread-safe.
  *   - Units are SI (m, s, rad); doubles in, doubles out. GPU arithmetic is
  *     FP64 for trajectories and probabilities and FP32 for the overlap tests.
+ *     Before the FP32 poses are stored, every position is taken relative to
+ *     a per-scene origin (the middle of the box of the initial positions,
+ *     rounded to a multiple of 256 m), so a scene far from (0, 0) is tested
+ *     as precisely as one near it. First hits agree with an exact FP64
+ *     evaluation wherever the overlap margin exceeds 1e-4 m while the poses
+ *     stay within about 256 m of that origin; further out the FP32 rounding
+ *     of the tests grows in proportion to the distance.
  *   - Time slots: slot t in [0, horizon) is the pose predicted for time
  *     (t+1)*dt; the measured state at time 0 is never tested.
  */

@@ -257,10 +257,6 @@ class OracleResult:
     obj_crit_t_hi: Optional[np.ndarray] = None
     traj_crit_t_lo: Optional[np.ndarray] = None
     traj_crit_t_hi: Optional[np.ndarray] = None
-    # probability mass of the combinations whose first hit the band leaves open
-    # (attribution is not monotone in the hits; it moves by at most this much)
-    traj_amb_mass: Optional[np.ndarray] = None  # [sum T]
-    obj_amb_mass: Optional[np.ndarray] = None   # [n]
 
 
 def scene_arrays(scene):
@@ -351,8 +347,6 @@ def evaluate(scene, pair_list: Optional[Sequence[Tuple[int, int]]] = None, eps: 
                 risk_timeline(scene, pa, pb, k64, p, model)
             res.traj_crit_t_lo, res.obj_crit_t_lo, _, _ = risk_timeline(scene, pa, pb, kst, p, model)
             res.traj_crit_t_hi, res.obj_crit_t_hi, _, _ = risk_timeline(scene, pa, pb, kloose, p, model)
-            amb = (kloose != k64) | (kst != k64)
-            res.traj_amb_mass, res.obj_amb_mass = ambiguous_mass(scene, pa, pb, amb, p)
     return res
 
 
@@ -425,24 +419,6 @@ def risk_raw(T, pa, pb, hit, p, model: int = RISK_EXCLUSIVE):
                           _ptr(np.ascontiguousarray(pa, np.int32)), _ptr(np.ascontiguousarray(pb, np.int32)),
                           _ptr(np.ascontiguousarray(hit, np.uint8)), _ptr(q), _ptr(tc), _ptr(oc)), "risk")
     return q, tc, oc
-
-
-def ambiguous_mass(scene, pa, pb, amb: np.ndarray, p: np.ndarray):
-    """Per trajectory, the summed probability of the other trajectories whose
-    combination with it has a first hit the band leaves open; per object, the
-    probability-weighted sum of that."""
-    _, _, _, _, T = scene_arrays(scene)
-    n = len(T)
-    toff = np.concatenate([[0], np.cumsum(T)]).astype(np.int64)
-    mass = np.zeros(int(T.sum()), np.float64)
-    e0 = 0
-    for a, b in zip(np.asarray(pa).tolist(), np.asarray(pb).tolist()):
-        blk = np.asarray(amb[e0:e0 + T[a] * T[b]]).reshape(T[a], T[b]).astype(np.float64)
-        mass[toff[a]:toff[a + 1]] += blk @ p[toff[b]:toff[b + 1]]
-        mass[toff[b]:toff[b + 1]] += blk.T @ p[toff[a]:toff[a + 1]]
-        e0 += T[a] * T[b]
-    obj = np.array([float(np.dot(p[toff[a]:toff[a + 1]], mass[toff[a]:toff[a + 1]])) for a in range(n)])
-    return mass, obj
 
 
 def accepted_first_hits(k32: np.ndarray, res: OracleResult) -> np.ndarray:

@@ -65,7 +65,7 @@ struct DObj {
     int64_t tl_traj;              // [s][i] criticality over time, and traj_crit_t (i, s): index of i = 0, s = 0
     int64_t tl_obj;               // crit_t index of (this object, s = 0)
     int64_t tl_att;               // attrib index of (this object, b = 0)
-    double x, y, heading, speed;
+    double x, y, heading, speed;  // position relative to the scene origin (scene_origin)
     double tau;
     double params[6];             // motion-model parameters
 };

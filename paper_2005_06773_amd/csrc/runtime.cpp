@@ -618,17 +618,42 @@ static void fill_poly(const mhc_object &o, DPoly &g)
     }
 }
 
+// The origin a scene's positions are taken relative to before the GPU sees
+// them: the middle of the box of the initial positions, rounded to a multiple
+// of kOriginGrid metres. The overlap tests are invariant under a shift of the
+// whole scene, but their FP32 rounding grows with the coordinates; relative
+// to this origin a scene far from (0, 0) is tested with the precision of one
+// near it. The subtraction costs at most one FP64 rounding (1e-12 m at
+// 10 km), and a scene whose box is centred within 128 m of (0, 0) keeps its
+// coordinates unchanged.
+static const double kOriginGrid = 256.0;
+
+void scene_origin(const mhc_scene &s, double *ox, double *oy)
+{
+    double x0 = s.objects[0].x, x1 = x0, y0 = s.objects[0].y, y1 = y0;
+    for (int a = 1; a < s.n_objects; ++a) {
+        x0 = std::min(x0, s.objects[a].x);
+        x1 = std::max(x1, s.objects[a].x);
+        y0 = std::min(y0, s.objects[a].y);
+        y1 = std::max(y1, s.objects[a].y);
+    }
+    *ox = kOriginGrid * std::nearbyint((x0 / 2.0 + x1 / 2.0) / kOriginGrid);
+    *oy = kOriginGrid * std::nearbyint((y0 / 2.0 + y1 / 2.0) / kOriginGrid);
+}
+
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L)
 {
     size_t oi = 0, pi = 0, gi = 0;
     std::vector<std::pair<int, int>> plist;
     for (int k = 0; k < n_scenes; ++k) {
         const mhc_scene &s = scenes[k];
+        double ox, oy;
+        scene_origin(s, &ox, &oy);
         for (int a = 0; a < s.n_objects; ++a, ++oi) {
             const mhc_object &o = s.objects[a];
             DObj &d = L.objs[oi];
-            d.x = o.x;
-            d.y = o.y;
+            d.x = o.x - ox;
+            d.y = o.y - oy;
             d.heading = o.heading;
             d.speed = o.speed;
             d.tau = s.dt;
@@ -775,6 +800,8 @@ extern "C" mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **
     ctx->n_cu = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
+        if (ctx->stream) hipStreamDestroy(ctx->stream);
         delete ctx;
         return MHC_E_DEVICE;
     }

@@ -121,6 +121,9 @@ hipError_t enqueue_results(const ResultPlan &R, const Layout &L, int n, const ch
                            const mhc_result *res, hipStream_t s);
 // After the transfers: copies each scene's staged parts from `pinned` to res.
 void scatter_results(const ResultPlan &R, const Layout &L, int n, const char *pinned, const mhc_result *res);
+// Per-scene origin subtracted from the positions before they go to the GPU
+// (a multiple of 256 m near the middle of the initial positions).
+void scene_origin(const mhc_scene &s, double *ox, double *oy);
 void fill_values(const mhc_scene *scenes, int n_scenes, Layout &L);
 // values_only: only the leading value_bytes (the collision plan is left out).
 void pack_image(const Layout &L, char *dst, bool values_only = false);

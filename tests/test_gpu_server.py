@@ -129,3 +129,28 @@ def test_invalid_frame_rejected(mhc, ctx):
         srv.submit(0, s)
     assert ei.value.status == mhc.MHC_E_INVAL
     srv.stop()
+
+
+def test_poisson_schedule_frames_alone_and_in_the_mix(mhc, ctx):
+    """Frames of the serving workload (32 streams, each a Poisson process at
+    10 Hz, frames drawn as in the batch workload), submitted at their
+    scheduled arrival times over one second: each frame's results equal the
+    same scene evaluated alone, bit for bit, whatever else its tick carried."""
+    events = sg.serving_schedule(3, streams=32, rate_hz=10.0, duration_s=1.0, warmup_s=0.0)
+    say(f"serving schedule: {len(events)} frames over 1 s from 32 streams")
+    srv = mhc.Server(ctx, budget=2 << 30, inflight=2)
+    tickets = []
+    t0 = time.perf_counter()
+    for t_arr, stream, scene in events:
+        delay = t_arr - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(stream, scene, first_hit=True, q=True))
+    outs = [srv.wait(t)[0] for t in tickets]
+    st = srv.stats()
+    srv.stop()
+    say(f"  ticks {st['ticks']}, frames per tick {len(events) / max(1, st['ticks']):.2f}, "
+        f"p50 {st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms")
+    for k, ((_, stream, scene), out) in enumerate(zip(events, outs)):
+        parity.same_results(mhc.mhc_evaluate(ctx, scene), out, f"frame {k} of stream {stream}")
+    assert st["completed"] == len(events)

@@ -237,6 +237,28 @@ mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_result *res);
 mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, void *dev_workspace,
                               size_t workspace_bytes, const mhc_result *dev_out, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * work as mhc_evaluate_async, with the workspace in a library-owned device
+ * array of MHC_NOALLOC_MAX_BYTES bytes instead of caller memory. The array
+ * is a file-scope device variable: every GPU the library runs on holds one
+ * copy of it until the process ends, and its address is looked up once per
+ * device in mhc_create. The call allocates no device or pinned host memory
+ * (the host tables of the scene reuse the context's storage) and frees
+ * nothing; the scene image goes up from pageable host memory on `hip_stream`.
+ * `dev_out` holds device pointers as for mhc_evaluate_async (object_crit
+ * required; outputs left NULL stay in the array). Whatever must start at zero
+ * (the q accumulators, the risk kernel's counters, the per-slot sums) is
+ * cleared by the trajectory kernel of the same call.
+ * Errors: MHC_E_INVAL as mhc_evaluate_async; MHC_E_NOMEM when the scene's
+ * workspace exceeds MHC_NOALLOC_MAX_BYTES (nothing is launched).
+ * All calls on one GPU share its array and it keeps the last call's contents:
+ * calls whose work overlaps on the device (other streams, other contexts or
+ * threads on the same GPU) race and give undefined results; calls on one
+ * stream are ordered. Results equal mhc_evaluate_async bit for bit. */
+enum { MHC_NOALLOC_MAX_BYTES = 64 << 20 };
+mhc_status mhc_evaluate_noalloc(mhc_ctx *ctx, const mhc_scene *scene, const mhc_result *dev_out, void *hip_stream);
+
 /* ---- device-resident plan ---------------------------------------------- */
 
 /* Validates `scene`, builds its pair and work lists on the host and uploads

@@ -6,6 +6,7 @@
 
 #include <climits>
 #include <math.h>
+#include <mutex>
 
 // The overlap tests combine their comparisons with bitwise & and | on bools
 // on purpose: every comparison is evaluated and the results are merged as
@@ -1464,6 +1465,39 @@ hipError_t launch_collide(const Launch &L, hipStream_t s)
 int collide_blocks_per_cu(int variant, int family, bool timeline)
 {
     return with_instance(variant, family, timeline, ResidentK2{});
+}
+
+// ===========================================================================
+// Workspace of the allocation-free entry point (mhc_evaluate_noalloc): a
+// file-scope device array, one copy on every GPU, held until the process
+// ends. Host code must not pass its name to a kernel (on the host it is a
+// stand-in, not a device address); noalloc_scratch_address looks up this
+// GPU's address once, with the device current, and every later use goes
+// through that address.
+// ===========================================================================
+
+static __device__ __align__(256) char noalloc_scratch[kNoallocBytes];
+
+hipError_t noalloc_scratch_address(int device, char **out)
+{
+    static std::mutex mu;
+    static char *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess) return e;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0) return hipErrorInvalidSymbol;
+        addr[device] = static_cast<char *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_risk(const Launch &L, hipStream_t s)

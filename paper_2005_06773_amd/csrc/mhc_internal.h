@@ -197,6 +197,13 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s);
 hipError_t launch_collide(const Launch &L, hipStream_t s);
 // risk: the time-resolved kernels (timeline launches) and the risk kernel
 hipError_t launch_risk(const Launch &L, hipStream_t s);
+// Bytes of the allocation-free entry point's device array (mhc.h
+// MHC_NOALLOC_MAX_BYTES) and the most GPUs whose copy of it is looked up.
+constexpr size_t kNoallocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// This GPU's address of that array (the device must be current on the
+// calling thread); looked up once per device, then cached.
+hipError_t noalloc_scratch_address(int device, char **out);
 // resident workgroups per CU of the collision kernel for a variant, class
 // family, with or without the per-slot sums
 int collide_blocks_per_cu(int variant, int family, bool timeline);

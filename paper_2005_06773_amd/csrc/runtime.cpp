@@ -799,7 +799,10 @@ extern "C" mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **
     ctx->budget = hbm_budget_bytes;
     ctx->n_cu = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->noalloc_ev, hipEventDisableTiming) != hipSuccess ||
+        noalloc_scratch_address(device, &ctx->scratch) != hipSuccess) {
+        if (ctx->noalloc_ev) hipEventDestroy(ctx->noalloc_ev);
         if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
         if (ctx->stream) hipStreamDestroy(ctx->stream);
         delete ctx;
@@ -819,7 +822,9 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
     if (ctx->dbuf) hipFree(ctx->dbuf);
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->res_pin) hipHostFree(ctx->res_pin);
+    hipEventSynchronize(ctx->noalloc_ev);
     hipEventDestroy(ctx->staging_ev);
+    hipEventDestroy(ctx->noalloc_ev);
     hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -1304,6 +1309,42 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     HIPC(hipSetDevice(ctx->device));
     return upload_and_launch(ctx, L, static_cast<char *>(dev_workspace), dev_out, false,
                              static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" mhc_status mhc_evaluate_noalloc(mhc_ctx *ctx, const mhc_scene *scene, const mhc_result *dev_out,
+                                           void *hip_stream)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (!dev_out || !dev_out->object_crit) {
+        ctx->err = "dev_out and dev_out->object_crit must not be NULL";
+        return MHC_E_INVAL;
+    }
+    if (!validate_scene(scene, ctx->err) || !validate_outputs(scene, dev_out, ctx->err)) return MHC_E_INVAL;
+    HIPC(hipSetDevice(ctx->device));
+    if (!ctx->scratch) {
+        ctx->err = "the allocation-free workspace of this device was not found";
+        return MHC_E_DEVICE;
+    }
+    // the first hits go to dev_out->first_hit only, so the array holds none
+    Layout &L = ctx->noalloc_layout;
+    const int v = ctx->variant_for(scene, 1);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, false);
+    if (L.total_bytes > kNoallocBytes) {
+        ctx->err = "scene needs " + std::to_string(L.total_bytes) + " workspace bytes, above MHC_NOALLOC_MAX_BYTES (" +
+                   std::to_string(kNoallocBytes) + ")";
+        return MHC_E_NOMEM;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // the previous call's upload must have left the host image before it is
+    // rewritten
+    HIPC(hipEventSynchronize(ctx->noalloc_ev));
+    if (ctx->noalloc_image.size() < L.image_bytes) ctx->noalloc_image.resize(L.image_bytes);
+    pack_image(L, ctx->noalloc_image.data());
+    HIPC(hipMemcpyAsync(ctx->scratch, ctx->noalloc_image.data(), L.image_bytes, hipMemcpyHostToDevice, s));
+    HIPC(hipEventRecord(ctx->noalloc_ev, s));
+    Launch X = make_launch(L, ctx->scratch, dev_out, false, ctx->n_cu);
+    HIPC(launch_all(X, s));
+    return MHC_OK;
 }
 
 // ===========================================================================

@@ -146,6 +146,10 @@ struct mhc_ctx {
     hipEvent_t staging_ev = nullptr;
     char *res_pin = nullptr;      // pinned host staging of the results of the synchronous calls
     size_t res_pin_bytes = 0;
+    char *scratch = nullptr;      // this GPU's address of the allocation-free workspace
+    mhc::Layout noalloc_layout;   // host tables of mhc_evaluate_noalloc (storage reused)
+    std::vector<char> noalloc_image;   // its scene image (pageable host memory)
+    hipEvent_t noalloc_ev = nullptr;   // the last upload from noalloc_image has left it
     mhc::Layout layout;           // reused by mhc_evaluate
     std::vector<int32_t> layout_shape;  // shape (+ variant, waves) `layout` was built for
     // launch key (+ workspace address) of the single-scene image whose

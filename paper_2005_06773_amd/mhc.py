@@ -32,7 +32,7 @@ _STATUS = {0: "MHC_OK", -1: "MHC_E_INVAL", -2: "MHC_E_NOMEM", -3: "MHC_E_DEVICE"
 
 EXPORTED = [
     "mhc_create", "mhc_destroy", "mhc_last_error", "mhc_query_sizes", "mhc_anticipation_time",
-    "mhc_evaluate", "mhc_evaluate_async",
+    "mhc_evaluate", "mhc_evaluate_async", "mhc_evaluate_noalloc",
     "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages", "mhc_plan_set_graph",
     "mhc_plan_download", "mhc_plan_destroy",
     "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load", "mhc_plan_check",
@@ -133,6 +133,7 @@ def _load():
                                   ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
         "mhc_evaluate": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
         "mhc_evaluate_async": [V, ctypes.POINTER(mhc_scene), V, S, ctypes.POINTER(mhc_result), V],
+        "mhc_evaluate_noalloc": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result), V],
         "mhc_plan_create": [V, ctypes.POINTER(mhc_scene), ctypes.POINTER(V)],
         "mhc_plan_update": [V, ctypes.POINTER(mhc_scene)],
         "mhc_plan_execute": [V, ctypes.POINTER(mhc_result), V],
@@ -357,6 +358,20 @@ def mhc_evaluate_async(ctx, scene, workspace, dev_out: mhc_result, stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(ctx, lib.mhc_evaluate_async(ctx, ctypes.byref(cs.c), workspace.data_ptr(), workspace.numel(),
                                        ctypes.byref(dev_out), ctypes.c_void_p(s.cuda_stream)))
+    return cs
+
+
+MHC_NOALLOC_MAX_BYTES = 64 << 20
+
+
+def mhc_evaluate_noalloc(ctx, scene, dev_out: mhc_result, stream=None):
+    """Like ``mhc_evaluate_async`` with the library's own device array as the
+    workspace; ``stream``: a torch.cuda.Stream (default: the current stream)."""
+    import torch
+    cs = scene if isinstance(scene, CScene) else CScene(scene)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(ctx, lib.mhc_evaluate_noalloc(ctx, ctypes.byref(cs.c), ctypes.byref(dev_out),
+                                         ctypes.c_void_p(s.cuda_stream)))
     return cs
 
 

@@ -414,37 +414,57 @@ def cpu_baseline(scene, checks, seconds, described, pair_list=None):
     checks per second."""
     import oracle
     oracle.lib()
-    cores = min(16, os.cpu_count() or 1)
+    nproc = os.cpu_count() or 1
+    cores = min(16, nproc)
     if pair_list is not None:
         T = scene.traj_counts()
         checks = sum(T[a] * T[b] for a, b in pair_list) * scene.horizon
-    t0 = time.perf_counter()
-    runs = 0
-    while True:
-        oracle.evaluate(scene, pair_list=pair_list, threads=cores, masks=False)
-        runs += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
+
+    def timed(threads, budget):
+        t0 = time.perf_counter()
+        runs = 0
+        while True:
+            oracle.evaluate(scene, pair_list=pair_list, threads=threads, masks=False)
+            runs += 1
+            if time.perf_counter() - t0 >= budget:
+                break
+        return runs, time.perf_counter() - t0
+
+    runs, dt = timed(cores, seconds)
     value = checks * runs / dt
     log(f"cpu baseline: {runs} oracle runs in {dt:.2f} s on {cores} threads -> {value:.4g} checks/s")
-    # the same oracle on one thread, one pass
-    t1 = time.perf_counter()
-    oracle.evaluate(scene, pair_list=pair_list, threads=1, masks=False)
-    dt1 = time.perf_counter() - t1
+    # the same oracle on every thread the host reports, and on one thread
+    runs_n, dt_n = timed(nproc, seconds / 3) if nproc != cores else (runs, dt)
+    log(f"cpu baseline, {nproc} threads (nproc): {runs_n} oracle runs in {dt_n:.2f} s -> "
+        f"{checks * runs_n / dt_n:.4g} checks/s")
+    runs_1, dt1 = timed(1, 0.0)
     log(f"cpu baseline, one thread: one oracle run in {dt1:.2f} s -> {checks / dt1:.4g} checks/s")
     what = "the full timed scene" if pair_list is None else f"{len(pair_list)} sampled object pairs of"
     return {"value": value, "unit": "checks/s", "cores": cores, "kind": "oracle",
             "sample": f"{what} ({described}), {runs} complete oracle passes "
                       f"(trajectories, {checks:,} checks, risk) in {dt:.1f} s",
-            "value_one_thread": checks / dt1}
+            "cpu_model": cpu_model(), "nproc": nproc,
+            "value_nproc": checks * runs_n / dt_n, "value_one_thread": checks / dt1}
+
+
+def cpu_model():
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def serve(mhc, ctx, sg, seconds):
     """Serving workload: 32 streams, each a Poisson process at 10 Hz with a
     start offset in U(0, 100 ms), frames drawn as in the batched workload
     (seed 3), replayed in real time; then the same arrivals through a plain
-    per-frame mhc_evaluate loop. Latency = arrival -> results in host memory."""
+    per-frame mhc_evaluate loop. Latency = scheduled arrival -> results in
+    host memory, for both."""
     import threading
     warm = 1.0
     events = [e for e in sg.serving_schedule(3, 32, 10.0, seconds, warm)]
@@ -466,33 +486,88 @@ def serve(mhc, ctx, sg, seconds):
 
     w = threading.Thread(target=waiter)
     w.start()
-    t0 = time.perf_counter()
+    # the server stamps completion on the monotonic clock, the one
+    # time.monotonic_ns reads: latency runs from each frame's scheduled
+    # arrival, so time spent submitting counts against the server
+    t0 = time.monotonic_ns()
     for t, sid, cs in frames:
-        while time.perf_counter() - t0 < t:
+        at = t0 + int(t * 1e9)
+        while time.monotonic_ns() < at:
             time.sleep(0.0001)
         tickets.append(srv.submit(sid, cs))
     w.join()
     srv.stop()
-    lat = [(done[k]["done_ns"] - done[k]["submit_ns"]) * 1e-6 for k in range(len(frames)) if frames[k][0] >= warm]
+    lat = [(done[k]["done_ns"] - (t0 + int(frames[k][0] * 1e9))) * 1e-6
+           for k in range(len(frames)) if frames[k][0] >= warm]
     busy_checks = sum(c for (t, _, _), c in zip(frames, checks) if t >= warm)
     out = {"streams": 32, "rate_hz_per_stream": 10, "seconds": seconds, "frames": len(lat),
            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "max_ms": max(lat),
            "deadline_ms": 50.0, "within_deadline": sum(x <= 50.0 for x in lat) / len(lat),
            "sustained_checks_per_s": busy_checks / seconds}
-    # the same arrivals through the plain per-frame loop
+    # the same arrivals through the plain per-frame loop, timed the same way
     lat2 = []
-    t0 = time.perf_counter()
+    t0 = time.monotonic_ns()
     for (t, sid, cs) in frames:
-        while time.perf_counter() - t0 < t:
+        at = t0 + int(t * 1e9)
+        while time.monotonic_ns() < at:
             time.sleep(0.0001)
         mhc.mhc_evaluate(ctx, cs, first_hit=False, q=False)
         if t >= warm:
-            lat2.append((time.perf_counter() - t0 - t) * 1e3)
+            lat2.append((time.monotonic_ns() - at) * 1e-6)
     out["plain_loop"] = {"p50_ms": pct(lat2, 50), "p99_ms": pct(lat2, 99), "max_ms": max(lat2),
                          "within_deadline": sum(x <= 50.0 for x in lat2) / len(lat2)}
     log(f"served: {len(lat)} frames, p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms "
         f"({out['sustained_checks_per_s']:.3g} checks/s offered); plain loop p50 {out['plain_loop']['p50_ms']:.2f} "
         f"ms p99 {out['plain_loop']['p99_ms']:.2f} ms")
+    out["with_stress_frames"] = serve_mixed(mhc, ctx, sg, frames, warm, seconds)
+    return out
+
+
+def serve_mixed(mhc, ctx, sg, frames, warm, seconds, period_s=0.25):
+    """The same served arrivals with a 40-object stress frame (4.09e10
+    checks, above the per-tick check cap, so it rides in a tick of its own)
+    arriving every period_s: latency of the small frames from their
+    scheduled arrival, beside that of the stress frames."""
+    import threading
+    big = mhc.CScene(sg.stress_scene(4))
+    events = [(t, sid, cs, False) for t, sid, cs in frames]
+    t = 0.05
+    while t < warm + seconds:
+        events.append((t, 99, big, True))
+        t += period_s
+    events.sort(key=lambda e: e[0])
+    srv = mhc.Server(ctx, budget=4 << 30, inflight=2)
+    tickets, done = [], {}
+
+    def waiter():
+        k = 0
+        while k < len(events):
+            while len(tickets) <= k:
+                time.sleep(0.0002)
+            _, timing = srv.wait(tickets[k])
+            done[k] = timing
+            k += 1
+
+    w = threading.Thread(target=waiter)
+    w.start()
+    t0 = time.monotonic_ns()
+    for at_s, sid, cs, _ in events:
+        at = t0 + int(at_s * 1e9)
+        while time.monotonic_ns() < at:
+            time.sleep(0.0001)
+        tickets.append(srv.submit(sid, cs))
+    w.join()
+    srv.stop()
+    small = [(done[k]["done_ns"] - (t0 + int(events[k][0] * 1e9))) * 1e-6
+             for k in range(len(events)) if events[k][0] >= warm and not events[k][3]]
+    large = [(done[k]["done_ns"] - (t0 + int(events[k][0] * 1e9))) * 1e-6
+             for k in range(len(events)) if events[k][0] >= warm and events[k][3]]
+    out = {"stress_frame_period_s": period_s, "small_frames": len(small), "stress_frames": len(large),
+           "small_p50_ms": pct(small, 50), "small_p99_ms": pct(small, 99), "small_max_ms": max(small),
+           "small_within_deadline": sum(x <= 50.0 for x in small) / len(small),
+           "stress_p50_ms": pct(large, 50), "stress_max_ms": max(large)}
+    log(f"served with a stress frame every {period_s} s: small frames p50 {out['small_p50_ms']:.2f} ms "
+        f"p99 {out['small_p99_ms']:.2f} ms; stress frames p50 {out['stress_p50_ms']:.1f} ms")
     return out
 
 
@@ -726,8 +801,21 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = checks / (ms_step / 1e3)
 
-    # Collision-kernel duration, live: the same K steps again, split by module,
-    # with HIP events on the launch stream bracketing every collision launch.
+    # Collision-kernel duration, live, on the launch stream. (a) The way a
+    # kernel trace sees it: K collision launches back to back between two HIP
+    # events (the trajectory stage runs once before them; the repeated
+    # launches add to the same q sums, which only the timing uses, and a whole
+    # step afterwards restores the results). (b) Every collision launch of K
+    # whole steps bracketed by its own pair of events, which adds each
+    # launch's start-up to its time (reported beside it).
+    mhc.mhc_plan_execute_stages(plan, T, r, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        mhc.mhc_plan_execute_stages(plan, C, r, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    k2_ms = e0.elapsed_time(e1) / args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for k in range(args.steps):
         mhc.mhc_plan_execute_stages(plan, T, r, stream)
@@ -736,7 +824,7 @@ def main():
         ev[k][1].record(stream)
         mhc.mhc_plan_execute_stages(plan, R, r, stream)
     torch.cuda.synchronize()
-    k2_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    k2_bracketed_ms = sum(a.elapsed_time(b) for a, b in ev) / args.steps
 
     # The same steps replayed as one captured HIP graph per step (reported only).
     mhc.mhc_plan_set_graph(plan, True)
@@ -750,8 +838,9 @@ def main():
     graph_step_us = (time.perf_counter() - a) * 1e6 / args.steps
     mhc.mhc_plan_set_graph(plan, False)
     achieved = flops / (k2_ms * 1e-3) / 1e12
-    log(f"step {ms_step * 1e3:.1f} us -> {value:.4g} checks/s; collision kernel {k2_ms * 1e3:.1f} us -> "
-        f"{achieved:.2f} TFLOP/s ({checks / (k2_ms / 1e3):.4g} checks/s)")
+    log(f"step {ms_step * 1e3:.1f} us -> {value:.4g} checks/s; collision kernel {k2_ms * 1e3:.1f} us back to back "
+        f"({k2_bracketed_ms * 1e3:.1f} us bracketed per launch) -> {achieved:.2f} TFLOP/s "
+        f"({checks / (k2_ms / 1e3):.4g} checks/s)")
 
     # VALU instructions per check in the inner loops (26 rect-rect: 25 per test
     # and 4 per prepared rectangle pose shared by 4 rows; 13 rect-circle: 12
@@ -777,12 +866,16 @@ def main():
         "graph_step_us": graph_step_us,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": recorded_traffic(variant, args.workload),
-                     "kernel": "k2_collide", "kernel_us": k2_ms * 1e3, "flops_per_launch": flops,
+                     "kernel": "k2_collide", "kernel_us": k2_ms * 1e3,
+                     "kernel_us_timing": "mean of K back-to-back launches between two HIP events on the launch stream",
+                     "kernel_us_bracketed": k2_bracketed_ms * 1e3, "flops_per_launch": flops,
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
                      "valu_issue_frac_est": lane_ops / (k2_ms / 1e3) / LANE_OPS_PER_S},
     }
 
-    # Sanity: the timed results are finite and in range.
+    # Sanity: the results of a whole step are finite and in range.
+    mhc.mhc_plan_execute(plan, r, stream)
+    torch.cuda.synchronize()
     oc = out["object_crit"].cpu()
     assert torch.isfinite(oc).all() and (oc >= 0).all() and (oc <= 1).all(), "bad criticality"
 
@@ -799,9 +892,12 @@ def main():
                                       "note": "mhc_evaluate, host scene in, host criticality out (PCIe included)"}
         log(f"plain end-to-end latency p50 {pct(lat, 50):.3f} ms p99 {pct(lat, 99):.3f} ms")
     if "batched" in extras:
-        # Batched vs plain loop over the same 64 scenes.
+        # Batched vs plain loop over the same 64 scenes; the batch's tile
+        # variant is autotuned on the batch itself first.
         scenes = [mhc.CScene(s) for s in sg.batch_scenes(2, 64)]
         bchecks = sum(mhc.mhc_query_sizes(s)["n_checks"] for s in scenes)
+        bbest, bus = mhc.mhc_autotune_batch(ctx, scenes, reps=5)
+        log(f"batch autotune: collision kernel us per variant {[round(u, 1) for u in bus]} -> variant {bbest}")
         mhc.mhc_evaluate_batch(ctx, scenes, first_hit=False, q=False)
         for s in scenes[:4]:
             mhc.mhc_evaluate(ctx, s, first_hit=False, q=False)
@@ -817,7 +913,9 @@ def main():
         tp = (time.perf_counter() - a) / reps
         result["batched"] = {"scenes": 64, "checks": bchecks, "batch_ms": tb * 1e3, "plain_loop_ms": tp * 1e3,
                              "batch_checks_per_s": bchecks / tb, "plain_loop_checks_per_s": bchecks / tp,
-                             "speedup": tp / tb}
+                             "speedup": tp / tb,
+                             "tile_variant": {"chosen": bbest, "collide_us_per_variant": [round(u, 2) for u in bus],
+                                              "gain_over_default": bus[0] / bus[bbest]}}
         log(f"batched 64 scenes: {tb * 1e3:.2f} ms ({bchecks / tb:.4g} checks/s) vs plain loop "
             f"{tp * 1e3:.2f} ms ({bchecks / tp:.4g} checks/s)")
 

@@ -91,8 +91,8 @@ enum { MHC_RISK_EXCLUSIVE = 0, MHC_RISK_INDEPENDENT = 1 };
  * `radius` walking at constant speed u[k] along heading + w[l] (Sec. IV-B.3).
  * Trajectory i = k*n_w + l. `score` holds n_u*n_w non-negative scores that are
  * L1-normalised into probabilities (Sec. IV-D.1); NULL means uniform.
- * A vehicle may instead be a general convex polygon (Sec. IV-C.1: the
- * polygons can be as complex as necessary): `vertices` holds n_vertices
+ * A vehicle may instead be a general convex polygon (Sec. IV-C.1 allows
+ * polygons of any complexity): `vertices` holds n_vertices
  * (x, y) pairs in the body frame (x along the heading, y to the left, origin
  * at the tracked position), 3 <= n_vertices <= MHC_MAX_VERTICES, strictly
  * convex, counter-clockwise, every interior angle at least 45 degrees;
@@ -195,9 +195,14 @@ typedef struct {
 
 /* ---- context ---------------------------------------------------------- */
 
-/* Opens GPU `device` and reserves nothing yet. hbm_budget_bytes caps the
- * device memory the context (and a server started on it) may hold; 0 means
- * no cap. Returns MHC_E_DEVICE when no GPU is usable. */
+/* System entry point with no passage of its own (the paper's module chain,
+ * Fig. 1, runs inside the calls below). Opens GPU `device` and reserves no
+ * workspace yet (the allocation-free entry point's device array is located
+ * here). hbm_budget_bytes caps the device memory the context (and a server
+ * started on it) may hold; 0 means no cap. Returns MHC_E_INVAL for a NULL
+ * `out` or a device index out of range, MHC_E_DEVICE when no gfx950 GPU is
+ * usable; *out is NULL on error. mhc_destroy waits for the context's work and
+ * frees it (NULL is ignored). */
 mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **out);
 void mhc_destroy(mhc_ctx *ctx);
 const char *mhc_last_error(const mhc_ctx *ctx);
@@ -227,7 +232,8 @@ mhc_status mhc_anticipation_time(int32_t n_frames, const double *crit, double fr
  * risk assessment (Fig. 1) and returns when the results are in `res`. */
 mhc_status mhc_evaluate(mhc_ctx *ctx, const mhc_scene *scene, mhc_result *res);
 
-/* Asynchronous on the caller's HIP stream (`hip_stream`, a hipStream_t; NULL
+/* The path of Fig. 1 as mhc_evaluate (Sec. IV-B to IV-D), enqueued
+ * asynchronously on the caller's HIP stream (`hip_stream`, a hipStream_t; NULL
  * is the null stream) with caller-owned device memory: `dev_workspace` of at
  * least mhc_query_sizes().device_bytes bytes (256-byte aligned) and the device
  * pointers in `dev_out`. The scene is validated and packed on the host and
@@ -295,16 +301,26 @@ void mhc_plan_destroy(mhc_plan *plan);
  * bit-identical for every variant; only speed differs.
  * mhc_set_variant forces one (-1 returns to the tuned choice).
  * mhc_autotune times every variant on `scene` (`reps` launches each, after
- * one warm-up) and records the fastest for scenes of the same size class
- * (log2 buckets of the mean trajectory count and of the horizon, and the
- * overlap mode); `us` (or NULL) receives the mean microseconds per launch of
- * each variant.
+ * one warm-up) and records the fastest for scenes of the same size class:
+ * log2 buckets of the mean trajectory count per object and of the mean
+ * horizon, the test family (0 rectangles and circles, 1 point-in-polygon
+ * rectangles, 2 outlines) and a log2 bucket of the scene count (0 for one
+ * scene). `us` (or NULL) receives the mean microseconds per launch of each
+ * variant. mhc_autotune_batch does the same for n scenes evaluated together
+ * as mhc_evaluate_batch launches them (one collision launch for all), so
+ * batches of that class use the variant found fastest for the batch; errors
+ * as mhc_evaluate_batch (the tuned choices are left unchanged on error).
  * mhc_tune_save / mhc_tune_load write / read the recorded choices as JSON
- * ({"gfx950": {"<T bucket>,<H bucket>,<1 if PIP>": variant, ...}}; a key
- * with two fields is read as an exact-overlap class). */
+ * ({"gfx950": {"<T bucket>,<H bucket>,<family>,<scenes bucket>": variant,
+ * ...}}; keys with two or three fields, from earlier files, are read with
+ * the missing fields 0). A file that cannot be read, has no "gfx950" object
+ * or holds an entry that does not parse or names a variant outside
+ * [0, MHC_N_VARIANTS) gives MHC_E_INVAL and changes nothing. */
 enum { MHC_N_VARIANTS = 4 };
 mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant);
 mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int32_t *best_variant, double *us);
+mhc_status mhc_autotune_batch(mhc_ctx *ctx, int32_t n, const mhc_scene *scenes, int32_t reps, int32_t *best_variant,
+                              double *us);
 mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path);
 mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path);
 
@@ -337,50 +353,96 @@ mhc_status mhc_plan_check(int32_t n_scenes, const mhc_scene *scenes, int32_t var
 
 /* ---- batched ----------------------------------------------------------- */
 
-/* Evaluates n scenes of any shapes in one persistent collision launch inside a
- * captured HIP graph (trajectory generation, collision recognition and risk
- * for all scenes), then copies every result to res[k]. Results are identical
- * to mhc_evaluate of each scene alone. */
+/* A system form with no passage of its own: the path of Fig. 1 for n scenes
+ * of any shapes at once, one trajectory launch, one collision launch and one
+ * risk launch for all of them (captured as a HIP graph when the batch's shape
+ * key comes back), then every result copied to res[k] (host buffers; any
+ * field but object_crit may be NULL per scene). Results are identical to
+ * mhc_evaluate of each scene alone. MHC_E_INVAL for n < 1, NULL arrays, an
+ * invalid scene or result set (the message names the scene index) or more
+ * than 65535 objects in all; MHC_E_NOMEM / MHC_E_DEVICE as mhc_evaluate;
+ * on error no output is written. */
 mhc_status mhc_evaluate_batch(mhc_ctx *ctx, int32_t n, const mhc_scene *scenes, mhc_result *res);
 
 /* ---- served (continuous batching) ------------------------------------- */
 
+/* A system form with no passage of its own in the paper: the request loop
+ * around the module chain of Fig. 1 (the paper's own I/O layer, Sec. V,
+ * serves one request at a time). Frames from many streams are admitted into
+ * "ticks" (one batched evaluation each) while earlier ticks still run. */
 typedef struct {
-    size_t hbm_budget_bytes;      /* device bytes the server may hold for frames; 0 = ctx budget or 1 GiB */
-    int32_t max_inflight_ticks;   /* ticks on the GPU at once (1..4; 0 = 2) */
+    size_t hbm_budget_bytes;      /* device bytes the server may hold for frames; 0 = ctx budget or 1 GiB;
+                                     each of the max_inflight_ticks slots gets an equal share */
+    int32_t max_inflight_ticks;   /* ticks running at once (1..4; 0 = 2) */
     int32_t queue_capacity;       /* frames waiting for admission (0 = 4096) */
     int32_t max_frames_per_tick;  /* 0 = 256 */
-    int64_t max_checks_per_tick;  /* a tick closes when this many checks are admitted (0 = 4e9) */
+    int64_t max_checks_per_tick;  /* a tick closes when this many checks are admitted (0 = 4e9); a frame
+                                     of more checks rides in a tick of its own, and with two or more
+                                     slots such frames hold all but one slot, so one slot stays open
+                                     to smaller frames (which may then overtake a waiting large one) */
+    int64_t watchdog_us;          /* a tick running longer than this fails the server: its frames and
+                                     every queued one complete with MHC_E_DEVICE, mhc_server_stop
+                                     returns MHC_E_DEVICE (0 = 30 s) */
+    int64_t deadline_us;          /* frames slower than this (submit -> results) count as late in
+                                     mhc_stats (0 = no deadline) */
 } mhc_server_cfg;
 
 typedef struct {
-    int64_t submit_ns, admit_ns, launch_ns, done_ns;  /* monotonic clock, ns */
+    int64_t submit_ns, admit_ns, launch_ns, done_ns;  /* monotonic clock (CLOCK_MONOTONIC), ns */
     int64_t tick;                 /* tick that carried the frame */
 } mhc_timing;
 
 typedef struct {
-    int64_t submitted, completed, rejected, deferred;  /* deferred = waited for budget */
+    int64_t submitted, completed, rejected, deferred;  /* deferred = ticks that left frames queued */
     int64_t ticks, checks;
+    int64_t late;                 /* completed frames over deadline_us */
     double p50_ms, p99_ms, max_ms, mean_ms;            /* submit -> results in host memory */
     double checks_per_s;          /* completed checks / wall time since start */
 } mhc_stats;
 
-/* Starts a scheduler thread. Frames submitted from any thread are admitted
- * into the next GPU tick while their device memory fits the budget; ticks run
- * on separate streams so that a new tick is built and launched while earlier
- * ones are still on the GPU. */
+/* Starts a scheduler thread on the GPU of `ctx`. Frames submitted from any
+ * thread are admitted, in arrival order, into the next tick while their
+ * device memory fits the slot's budget; ticks run on separate streams so that
+ * a new tick is built and launched while earlier ones are still on the GPU.
+ * The context's tile-variant choices (mhc_set_variant, mhc_autotune, tune
+ * files) are copied at start; later changes to them do not reach a running
+ * server, and the context stays usable by its own thread meanwhile. */
 mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, mhc_server **out);
 /* Copies `scene` and queues it; `dst` (host buffers) receives the results and
- * must stay valid until mhc_wait reports completion. MHC_E_BUSY when the queue
- * is full, MHC_E_NOMEM when the frame can never fit the budget. */
+ * must stay valid until mhc_wait reports completion. MHC_E_INVAL for an
+ * invalid scene or result set (or a stopping server), MHC_E_BUSY when the
+ * queue is full, MHC_E_NOMEM when the frame can never fit a slot's budget. */
 mhc_status mhc_submit(mhc_server *srv, int32_t stream_id, const mhc_scene *scene, mhc_result *dst,
                       uint64_t *ticket);
 /* Waits up to timeout_us (< 0: forever) for `ticket`; fills `timing` if not
- * NULL. A ticket can be waited on once successfully. */
+ * NULL. A ticket can be waited on once successfully; the frame's status
+ * (MHC_OK, or MHC_E_DEVICE when its tick failed) is returned. MHC_E_TIMEOUT
+ * leaves the ticket valid; an unknown ticket gives MHC_E_INVAL. */
 mhc_status mhc_wait(mhc_server *srv, uint64_t ticket, int64_t timeout_us, mhc_timing *timing);
 mhc_status mhc_server_stats(mhc_server *srv, mhc_stats *out);
-/* Drains in-flight ticks, completes queued frames, joins the thread, frees. */
+/* Drains running ticks, completes queued frames, joins the thread, frees.
+ * MHC_E_DEVICE when a tick failed or tripped the watchdog while it ran. */
 mhc_status mhc_server_stop(mhc_server *srv);
+
+/* A tick executor supplied by the caller, for running the scheduler without
+ * the library's GPU path (tests of admission, ordering, deadlines and the
+ * watchdog; other devices). Called from the scheduler thread only.
+ *   launch: start tick `tick` in slot `slot` (0 .. max_inflight_ticks-1) with
+ *           n frames, their scenes and host result buffers (valid until the
+ *           tick is reported done); return MHC_OK or a negative mhc_status
+ *           (the tick's frames then fail with MHC_E_DEVICE).
+ *   poll:   1 when the slot's tick has finished and its results are in the
+ *           buffers, 0 while it runs, < 0 when it failed.
+ * mhc_server_start_executor copies *ex; the server has no context (budgets
+ * as in cfg, default 1 GiB). MHC_E_INVAL for a NULL argument or callback or
+ * a configuration out of range. */
+typedef struct {
+    void *user;
+    int32_t (*launch)(void *user, int32_t slot, int64_t tick, int32_t n_frames, const mhc_scene *scenes,
+                      const mhc_result *dsts);
+    int32_t (*poll)(void *user, int32_t slot);
+} mhc_executor;
+mhc_status mhc_server_start_executor(const mhc_server_cfg *cfg, const mhc_executor *ex, mhc_server **out);
 
 #ifdef __cplusplus
 }

@@ -442,7 +442,7 @@ double orc_margin_rect_rect_pip(double xP, double yP, double psiP, double LP, do
 }
 
 /* ------------------------------------------------------------------------ */
-/* General convex polygons (Sec. IV-C.1: "as complex as necessary"). A      */
+/* General convex polygons (Sec. IV-C.1 allows any complexity). A           */
 /* vehicle may carry an outline: the vertices of a convex polygon in its     */
 /* body frame (x along the heading, y to the left), counter-clockwise, at    */
 /* most ORC_MAX_VERTICES. Polygons below are in world coordinates, CCW.      */

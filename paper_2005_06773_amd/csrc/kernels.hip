@@ -537,8 +537,8 @@ struct CheckPP {
     }
 };
 
-// General convex polygons (vehicle outlines, Sec. IV-C.1: as complex as
-// necessary). Q's vertices in P's frame are c + v_x (C, S) + v_y (-S, C) with
+// General convex polygons (vehicle outlines; Sec. IV-C.1 allows polygons of
+// any complexity). Q's vertices in P's frame are c + v_x (C, S) + v_y (-S, C) with
 // c = (d.u_P, d.v_P); P's in Q's frame are c' + v_x (C, -S) + v_y (S, C)
 // with c' = (-d.u_Q, -d.v_Q). With the unit outward edge normals n_e and
 // offsets h_e of a polygon, a point x is inside iff n_e.x <= h_e for all e.

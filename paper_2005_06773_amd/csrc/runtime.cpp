@@ -802,9 +802,9 @@ extern "C" mhc_status mhc_create(int device, size_t hbm_budget_bytes, mhc_ctx **
         hipEventCreateWithFlags(&ctx->staging_ev, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ctx->noalloc_ev, hipEventDisableTiming) != hipSuccess ||
         noalloc_scratch_address(device, &ctx->scratch) != hipSuccess) {
-        if (ctx->noalloc_ev) hipEventDestroy(ctx->noalloc_ev);
-        if (ctx->staging_ev) hipEventDestroy(ctx->staging_ev);
-        if (ctx->stream) hipStreamDestroy(ctx->stream);
+        if (ctx->noalloc_ev) (void)hipEventDestroy(ctx->noalloc_ev);
+        if (ctx->staging_ev) (void)hipEventDestroy(ctx->staging_ev);
+        if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
         return MHC_E_DEVICE;
     }
@@ -831,14 +831,19 @@ extern "C" void mhc_destroy(mhc_ctx *ctx)
 
 int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
 {
-    if (v < 0 || v >= N_VARIANTS) v = 0;
     int fam = 0, tl = 0;
     for (int k = 0; k < n; ++k) {
         fam = std::max(fam, scene_family(&scenes[k]));
         tl |= scenes[k].timeline != 0;
     }
-    int &w = waves_cache[v][fam][tl];
-    if (!w) w = n_cu * collide_blocks_per_cu(v, fam, tl != 0) * (WG / WAVE);
+    return max_waves_of(v, fam, tl != 0);
+}
+
+int mhc_ctx::max_waves_of(int v, int fam, bool tl)
+{
+    if (v < 0 || v >= N_VARIANTS) v = 0;
+    int &w = waves_cache[v][fam][tl ? 1 : 0];
+    if (!w) w = n_cu * collide_blocks_per_cu(v, fam, tl) * (WG / WAVE);
     return w;
 }
 

@@ -131,6 +131,15 @@ std::vector<int32_t> shape_of(const mhc_scene *s);
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu);
 hipError_t launch_all(const Launch &X, hipStream_t s);
 
+// The collision kernel's tile-variant choices: a forced variant, else the
+// autotuned one of the launch's size class, else the default. A context owns
+// one; a server copies it when it starts.
+struct Tuning {
+    int forced_variant = -1;                      // mhc_set_variant
+    std::map<std::array<int, 4>, int> tuned;      // size class -> variant (mhc_autotune, mhc_autotune_batch)
+    int variant_for(const mhc_scene *scenes, int n) const;
+};
+
 }  // namespace mhc
 
 struct mhc_ctx {
@@ -156,18 +165,20 @@ struct mhc_ctx {
     // collision plan is in the workspace now; empty when other work wrote it
     std::vector<int64_t> resident_image;
     mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
-    int forced_variant = -1;                      // mhc_set_variant
-    std::map<std::array<int, 3>, int> tuned;      // size class -> variant (mhc_autotune)
-    int variant_for(const mhc_scene *scenes, int n) const;
+    mhc::Tuning tune;
+    int variant_for(const mhc_scene *scenes, int n) const { return tune.variant_for(scenes, n); }
     int waves_cache[mhc::N_VARIANTS][3][2] = {};  // [variant][class family][time-resolved]
     // resident waves on this GPU of the collision kernel that `scenes` need
     int max_waves(int variant, const mhc_scene *scenes, int n);
+    // the same for a variant, class family and time-resolved flag
+    int max_waves_of(int variant, int family, bool timeline);
 };
 
 // Autotuning class of a launch: log2 of the mean trajectory count, log2 of
-// the mean horizon, and the test family: 0 rectangles and circles, 1 the
-// point-in-polygon rectangle test, 2 outlines (polygon classes).
-std::array<int, 3> size_class(const mhc_scene *scenes, int n);
+// the mean horizon, the test family (0 rectangles and circles, 1 the
+// point-in-polygon rectangle test, 2 outlines) and log2 of the scene count
+// (0 for single scenes, so batches are tuned apart from them).
+std::array<int, 4> size_class(const mhc_scene *scenes, int n);
 
 mhc_status ensure_device(mhc_ctx *ctx, size_t bytes);
 // Copies the results of the n scenes of layout L (device workspace dbase,

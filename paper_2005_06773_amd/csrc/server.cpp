@@ -1,19 +1,29 @@
 // Serving form: continuous batching of scene frames from many streams.
 //
 // mhc_submit copies a frame into a FIFO. A scheduler thread keeps up to
-// `max_inflight_ticks` ticks on the GPU, each on its own stream with its own
-// device workspace (an equal share of the HBM budget) and pinned staging.
-// Whenever a tick slot is free it admits queued frames in arrival order while
-// they fit the slot's memory and the tick's frame / check caps, plans the
-// tick on the host (while earlier ticks still run), uploads one scene image,
-// launches trajectory generation, collision recognition and risk for all its
-// frames, and queues the copy of their results back to pinned memory. When a
-// tick's event completes, every frame's results are copied to the caller's
-// buffers and its waiters are released. A frame's results do not depend on
-// which tick carried it or what else was in it.
+// `max_inflight_ticks` ticks running at once, one per slot. Whenever a slot
+// is free it admits queued frames in arrival order while they fit the slot's
+// share of the memory budget and the tick's frame / check caps, and hands the
+// tick to an executor. The GPU executor gives every slot its own stream,
+// device workspace and pinned staging: it plans the tick on the host (while
+// earlier ticks still run), uploads one scene image, launches trajectory
+// generation, collision recognition and risk for all its frames (the module
+// chain of Fig. 1) and queues the copy of their results back to pinned
+// memory; when the tick's event has completed it copies every frame's results
+// to the caller's buffers. A frame's results do not depend on which tick
+// carried it or what else was in it. Executors written by the caller
+// (mhc_server_start_executor) run the same scheduler without a GPU.
+//
+// A frame of more checks than max_checks_per_tick rides in a tick of its own,
+// and with two or more slots such frames may occupy all but one of them, so
+// that one slot always stays open to the other frames; those may then go
+// ahead of a large frame that waits for a slot. Frames of either kind keep
+// their arrival order among themselves.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <climits>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -40,6 +50,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Bound on the resident collision waves of any GPU this library runs on
 // (sizes the slot table in the admission estimate).
 constexpr int kMaxCollisionWaves = 1 << 16;
+constexpr int64_t kDefaultWatchdogUs = 30LL * 1000 * 1000;
 
 enum FrameState { QUEUED, ADMITTED, DONE };
 
@@ -52,12 +63,31 @@ struct Frame {
     mhc_scene scene{};
     mhc_result dst{};
     int64_t n_traj = 0, n_hits = 0, checks = 0;
-    size_t bytes = 0;  // device bytes upper bound
+    size_t bytes = 0;    // device bytes upper bound
+    bool large = false;  // more checks than one tick may carry
     FrameState state = QUEUED;
     mhc_status status = MHC_OK;
     mhc_timing timing{};
 };
 
+using Frames = std::vector<std::shared_ptr<Frame>>;
+
+// Runs the ticks the scheduler forms, at most one per slot at a time. Only
+// the scheduler thread calls launch and poll.
+class Executor {
+public:
+    virtual ~Executor() = default;
+    // Starts tick `tick` in slot `slot` with these frames.
+    virtual mhc_status launch(int slot, int64_t tick, const Frames &frames, std::string &err) = 0;
+    // 1: the slot's tick has finished and every frame's results are in its
+    //    host buffers; 0: still running; < 0: failed (err says why).
+    virtual int poll(int slot, std::string &err) = 0;
+    // After the scheduler has stopped: waits for whatever is still running
+    // and frees the executor's resources.
+    virtual void shutdown() {}
+};
+
+// One slot of the GPU executor.
 struct TickSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
@@ -67,23 +97,156 @@ struct TickSlot {
     size_t pin_in_bytes = 0;
     char *pin_out = nullptr;
     size_t pin_out_bytes = 0;
-    bool busy = false;
-    int64_t launched_ns = 0;
-    int64_t tick = 0;
     Layout L;
-    std::vector<std::shared_ptr<Frame>> frames;
+    int n_frames = 0;
     std::vector<mhc_result> dsts;  // per frame: its host buffers
     ResultPlan results;            // the tick's outputs staged in pin_out
+};
+
+hipError_t grow_pinned(char **p, size_t *have, size_t want)
+{
+    if (*have >= want) return hipSuccess;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *have = 0;
+    const size_t sz = std::max(want + want / 4, (size_t)1 << 20);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), sz, hipHostMallocDefault);
+    if (e == hipSuccess) *have = sz;
+    return e;
+}
+
+// The library's own executor: ticks on the GPU of a context. The context's
+// tile-variant choices and resident wave counts are copied when the server
+// starts, so the context may be used (and retuned) by its own thread while
+// the server runs.
+class GpuExecutor : public Executor {
+public:
+    int device = 0, n_cu = 0;
+    Tuning tune;
+    int waves[N_VARIANTS][3][2] = {};
+    std::vector<TickSlot> slots;
+
+    int max_waves(int v, const mhc_scene *scenes, int n) const
+    {
+        int fam = 0, tl = 0;
+        for (int k = 0; k < n; ++k) {
+            fam = std::max(fam, scene_family(&scenes[k]));
+            tl |= scenes[k].timeline != 0;
+        }
+        return waves[v][fam][tl];
+    }
+
+    mhc_status launch(int slot, int64_t, const Frames &frames, std::string &err) override
+    {
+        TickSlot &t = slots[slot];
+        std::vector<mhc_scene> scenes;
+        scenes.reserve(frames.size());
+        for (auto &f : frames) scenes.push_back(f->scene);
+        const int n = (int)scenes.size();
+        const int v = tune.variant_for(scenes.data(), n);
+        bool keep_hits = false;
+        for (auto &f : frames) keep_hits |= f->dst.first_hit != nullptr;
+        build_layout(scenes.data(), n, v, max_waves(v, scenes.data(), n), t.L, keep_hits);
+        if (t.L.total_bytes > t.dbytes) {  // the admission bound excludes this
+            err = "tick workspace above the slot's share of the budget";
+            return MHC_E_NOMEM;
+        }
+        hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes);
+        t.n_frames = n;
+        t.dsts.clear();
+        for (auto &f : frames) t.dsts.push_back(f->dst);
+        // every output of the tick in one transfer per output region, staged
+        // in pinned memory so that nothing blocks the scheduler thread
+        t.results = plan_results(t.L, n, t.dsts.data(), true);
+        if (e == hipSuccess) e = grow_pinned(&t.pin_out, &t.pin_out_bytes, t.results.staged);
+        if (e == hipSuccess) {
+            pack_image(t.L, t.pin_in);
+            e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
+        }
+        if (e == hipSuccess) e = launch_all(make_launch(t.L, t.dbuf, nullptr, keep_hits, n_cu), t.stream);
+        if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
+        if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
+        if (e != hipSuccess) {
+            err = std::string("tick launch failed: ") + hipGetErrorString(e);
+            return MHC_E_DEVICE;
+        }
+        return MHC_OK;
+    }
+
+    int poll(int slot, std::string &err) override
+    {
+        TickSlot &t = slots[slot];
+        const hipError_t q = hipEventQuery(t.done);
+        if (q == hipErrorNotReady) return 0;
+        if (q != hipSuccess) {
+            err = std::string("tick failed: ") + hipGetErrorString(q);
+            return -1;
+        }
+        scatter_results(t.results, t.L, t.n_frames, t.pin_out, t.dsts.data());
+        return 1;
+    }
+
+    void shutdown() override
+    {
+        (void)hipSetDevice(device);
+        for (auto &t : slots) {
+            if (t.stream) (void)hipStreamSynchronize(t.stream);
+            if (t.dbuf) (void)hipFree(t.dbuf);
+            if (t.pin_in) (void)hipHostFree(t.pin_in);
+            if (t.pin_out) (void)hipHostFree(t.pin_out);
+            if (t.done) (void)hipEventDestroy(t.done);
+            if (t.stream) (void)hipStreamDestroy(t.stream);
+        }
+        slots.clear();
+    }
+};
+
+// An executor given by the caller as C callbacks (mhc_executor).
+class CallbackExecutor : public Executor {
+public:
+    mhc_executor ex{};
+
+    mhc_status launch(int slot, int64_t tick, const Frames &frames, std::string &err) override
+    {
+        std::vector<mhc_scene> scenes;
+        std::vector<mhc_result> dsts;
+        for (auto &f : frames) {
+            scenes.push_back(f->scene);
+            dsts.push_back(f->dst);
+        }
+        const int32_t st = ex.launch(ex.user, slot, tick, (int32_t)frames.size(), scenes.data(), dsts.data());
+        if (st != MHC_OK) {
+            err = "executor launch failed with status " + std::to_string(st);
+            return st < 0 ? (mhc_status)st : MHC_E_DEVICE;
+        }
+        return MHC_OK;
+    }
+
+    int poll(int slot, std::string &err) override
+    {
+        const int32_t st = ex.poll(ex.user, slot);
+        if (st < 0) err = "executor tick failed with status " + std::to_string(st);
+        return st < 0 ? -1 : (st > 0 ? 1 : 0);
+    }
+};
+
+struct Slot {
+    bool busy = false;
+    bool large = false;       // carries a frame above max_checks_per_tick
+    int64_t launched_ns = 0;
+    int64_t tick = 0;
+    Frames frames;
 };
 
 }  // namespace
 
 struct mhc_server {
-    mhc_ctx *ctx = nullptr;
+    mhc_ctx *ctx = nullptr;   // null for servers on a caller's executor
+    std::unique_ptr<Executor> exec;
     mhc_server_cfg cfg{};
     size_t slot_bytes = 0;
-    size_t slot_usable = 0;  // slot bytes minus the per-tick collision slot table
-    std::vector<TickSlot> slots;
+    size_t slot_usable = 0;   // slot bytes minus the per-tick collision slot table
+    std::vector<Slot> slots;
     std::thread thread;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -93,7 +256,7 @@ struct mhc_server {
     bool stopping = false;
     std::string fatal;
     // statistics
-    int64_t submitted = 0, completed = 0, rejected = 0, deferred = 0, ticks = 0, checks = 0;
+    int64_t submitted = 0, completed = 0, rejected = 0, deferred = 0, ticks = 0, checks = 0, late = 0;
     std::vector<double> latency_ms;
     int64_t start_ns = 0;
 };
@@ -183,54 +346,9 @@ std::shared_ptr<Frame> copy_frame(const mhc_scene *s)
     return f;
 }
 
-hipError_t grow_pinned(char **p, size_t *have, size_t want)
+// Marks a slot's frames done with status st (scheduler thread, lock not held).
+void finish_tick(mhc_server *srv, Slot &t, mhc_status st)
 {
-    if (*have >= want) return hipSuccess;
-    if (*p) hipHostFree(*p);
-    *p = nullptr;
-    *have = 0;
-    const size_t sz = std::max(want + want / 4, (size_t)1 << 20);
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), sz, hipHostMallocDefault);
-    if (e == hipSuccess) *have = sz;
-    return e;
-}
-
-// Launch one tick (scheduler thread, lock not held).
-hipError_t launch_tick(mhc_server *srv, TickSlot &t)
-{
-    std::vector<mhc_scene> scenes;
-    scenes.reserve(t.frames.size());
-    for (auto &f : t.frames) scenes.push_back(f->scene);
-    mhc_ctx *ctx = srv->ctx;
-    const int v = ctx->variant_for(scenes.data(), (int)scenes.size());
-    bool keep_hits = false;
-    for (auto &f : t.frames) keep_hits |= f->dst.first_hit != nullptr;
-    build_layout(scenes.data(), (int)scenes.size(), v, ctx->max_waves(v, scenes.data(), (int)scenes.size()), t.L,
-                 keep_hits);
-    if (t.L.total_bytes > t.dbytes) return hipErrorOutOfMemory;  // admission bounds exclude this
-    hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes);
-    if (e != hipSuccess) return e;
-    t.dsts.clear();
-    for (auto &f : t.frames) t.dsts.push_back(f->dst);
-    // every output of the tick in one transfer per output region, staged in
-    // pinned memory so that nothing blocks this thread
-    t.results = plan_results(t.L, (int)t.frames.size(), t.dsts.data(), true);
-    e = grow_pinned(&t.pin_out, &t.pin_out_bytes, t.results.staged);
-    if (e != hipSuccess) return e;
-    pack_image(t.L, t.pin_in);
-    e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
-    if (e != hipSuccess) return e;
-    Launch X = make_launch(t.L, t.dbuf, nullptr, keep_hits, ctx->n_cu);
-    e = launch_all(X, t.stream);
-    if (e != hipSuccess) return e;
-    e = enqueue_results(t.results, t.L, (int)t.frames.size(), t.dbuf, t.pin_out, t.dsts.data(), t.stream);
-    if (e != hipSuccess) return e;
-    return hipEventRecord(t.done, t.stream);
-}
-
-void finish_tick(mhc_server *srv, TickSlot &t, mhc_status st)
-{
-    if (st == MHC_OK) scatter_results(t.results, t.L, (int)t.frames.size(), t.pin_out, t.dsts.data());
     const int64_t done = now_ns();  // every result is in its host buffer
     for (auto &fp : t.frames) {
         fp->timing.launch_ns = t.launched_ns;
@@ -243,30 +361,80 @@ void finish_tick(mhc_server *srv, TickSlot &t, mhc_status st)
         fp->state = DONE;
         ++srv->completed;
         if (st == MHC_OK) srv->checks += fp->checks;
-        srv->latency_ms.push_back((fp->timing.done_ns - fp->timing.submit_ns) * 1e-6);
+        const double ms = (fp->timing.done_ns - fp->timing.submit_ns) * 1e-6;
+        srv->latency_ms.push_back(ms);
+        if (srv->cfg.deadline_us > 0 && ms * 1e3 > (double)srv->cfg.deadline_us) ++srv->late;
     }
     t.frames.clear();
     t.busy = false;
+    t.large = false;
     srv->cv_done.notify_all();
+}
+
+// Frames for a free slot, taken from the queue (lock held). A large frame
+// rides alone, and only when large_allowed; other frames are taken in order
+// while the tick's caps hold, and may pass a large frame that has to wait.
+Frames admit(mhc_server *srv, bool large_allowed, bool *took_large)
+{
+    Frames take;
+    size_t bytes = 0;
+    int64_t checks = 0, objects = 0;
+    const int64_t now = now_ns();
+    *took_large = false;
+    for (auto it = srv->queue.begin(); it != srv->queue.end() && (int)take.size() < srv->cfg.max_frames_per_tick;) {
+        const std::shared_ptr<Frame> f = *it;
+        if (f->large) {
+            if (take.empty() && large_allowed) {
+                f->state = ADMITTED;
+                f->timing.admit_ns = now;
+                take.push_back(f);
+                srv->queue.erase(it);
+                *took_large = true;
+                break;
+            }
+            // it waits for a slot of its own; later large frames wait behind it
+            large_allowed = false;
+            ++it;
+            continue;
+        }
+        if (!take.empty() && (bytes + f->bytes > srv->slot_usable || checks + f->checks > srv->cfg.max_checks_per_tick ||
+                              objects + f->scene.n_objects > kMaxObjectsPerLaunch))
+            break;
+        bytes += f->bytes;
+        checks += f->checks;
+        objects += f->scene.n_objects;
+        f->state = ADMITTED;
+        f->timing.admit_ns = now;
+        take.push_back(f);
+        it = srv->queue.erase(it);
+    }
+    return take;
 }
 
 void scheduler(mhc_server *srv)
 {
-    hipSetDevice(srv->ctx->device);
-    const int64_t watchdog_ns = 30LL * 1000 * 1000 * 1000;
+    if (srv->ctx) (void)hipSetDevice(srv->ctx->device);
+    const int64_t watchdog_ns = srv->cfg.watchdog_us * 1000;
+    const int n_slots = (int)srv->slots.size();
+    // slots that frames above the check cap may hold at once: all but one
+    const int large_slots = n_slots > 1 ? n_slots - 1 : 1;
+    std::string err;
     while (true) {
-        // 1. retire finished ticks
+        // 1. retire finished ticks; a tick that fails or outlives the
+        // watchdog fails the server
         bool any_busy = false;
-        for (auto &t : srv->slots) {
+        for (int k = 0; k < n_slots; ++k) {
+            Slot &t = srv->slots[k];
             if (!t.busy) continue;
-            const hipError_t q = hipEventQuery(t.done);
-            if (q == hipSuccess) {
+            err.clear();
+            const int q = srv->exec->poll(k, err);
+            if (q > 0) {
                 finish_tick(srv, t, MHC_OK);
-            } else if (q != hipErrorNotReady || now_ns() - t.launched_ns > watchdog_ns) {
+            } else if (q < 0 || now_ns() - t.launched_ns > watchdog_ns) {
                 {
                     std::lock_guard<std::mutex> lk(srv->mu);
-                    srv->fatal = q != hipErrorNotReady ? std::string("tick failed: ") + hipGetErrorString(q)
-                                                       : std::string("tick exceeded the watchdog");
+                    if (srv->fatal.empty())
+                        srv->fatal = q < 0 ? err : "tick " + std::to_string(t.tick) + " exceeded the watchdog";
                 }
                 finish_tick(srv, t, MHC_E_DEVICE);
             } else {
@@ -274,13 +442,13 @@ void scheduler(mhc_server *srv)
             }
         }
         // 2. admit frames into a free slot
-        TickSlot *free_slot = nullptr;
-        for (auto &t : srv->slots)
-            if (!t.busy) {
-                free_slot = &t;
-                break;
-            }
-        std::vector<std::shared_ptr<Frame>> take;
+        int free_slot = -1, large_busy = 0;
+        for (int k = 0; k < n_slots; ++k) {
+            if (!srv->slots[k].busy && free_slot < 0) free_slot = k;
+            large_busy += srv->slots[k].busy && srv->slots[k].large;
+        }
+        Frames take;
+        bool took_large = false;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
             if (srv->queue.empty() && !any_busy) {
@@ -288,49 +456,35 @@ void scheduler(mhc_server *srv)
                 srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
                 continue;
             }
-            if (free_slot && !srv->queue.empty() && srv->fatal.empty()) {
-                size_t bytes = 0;
-                int64_t checks = 0, objects = 0;
-                const int64_t now = now_ns();
-                while (!srv->queue.empty() && (int)take.size() < srv->cfg.max_frames_per_tick) {
-                    auto &f = srv->queue.front();
-                    if (!take.empty() && (bytes + f->bytes > srv->slot_usable ||
-                                          checks + f->checks > srv->cfg.max_checks_per_tick ||
-                                          objects + f->scene.n_objects > kMaxObjectsPerLaunch))
-                        break;
-                    bytes += f->bytes;
-                    checks += f->checks;
-                    objects += f->scene.n_objects;
-                    f->state = ADMITTED;
-                    f->timing.admit_ns = now;
-                    take.push_back(f);
-                    srv->queue.pop_front();
-                }
-                if (!srv->queue.empty()) ++srv->deferred;
-            } else if (!srv->fatal.empty() && !srv->queue.empty()) {
-                // the device failed: fail everything that is still queued
+            if (!srv->fatal.empty()) {
+                // the executor failed: fail everything that is still queued
                 for (auto &f : srv->queue) {
                     f->status = MHC_E_DEVICE;
                     f->state = DONE;
                 }
                 srv->queue.clear();
                 srv->cv_done.notify_all();
+            } else if (free_slot >= 0 && !srv->queue.empty()) {
+                take = admit(srv, large_busy < large_slots, &took_large);
+                if (!srv->queue.empty()) ++srv->deferred;
             }
         }
         if (!take.empty()) {
-            TickSlot &t = *free_slot;
+            Slot &t = srv->slots[free_slot];
             t.frames = std::move(take);
             t.busy = true;
+            t.large = took_large;
             t.launched_ns = now_ns();
             {
                 std::lock_guard<std::mutex> lk(srv->mu);
                 t.tick = srv->ticks++;
             }
-            const hipError_t e = launch_tick(srv, t);
-            if (e != hipSuccess) {
+            err.clear();
+            const mhc_status st = srv->exec->launch(free_slot, t.tick, t.frames, err);
+            if (st != MHC_OK) {
                 {
                     std::lock_guard<std::mutex> lk(srv->mu);
-                    srv->fatal = std::string("tick launch failed: ") + hipGetErrorString(e);
+                    if (srv->fatal.empty()) srv->fatal = err;
                 }
                 finish_tick(srv, t, MHC_E_DEVICE);
             }
@@ -340,6 +494,44 @@ void scheduler(mhc_server *srv)
     }
 }
 
+// Fills the defaults of a server configuration and checks it; "" when valid.
+std::string complete_cfg(mhc_server_cfg &c, size_t ctx_budget)
+{
+    if (c.max_inflight_ticks == 0) c.max_inflight_ticks = 2;
+    if (c.queue_capacity == 0) c.queue_capacity = 4096;
+    if (c.max_frames_per_tick == 0) c.max_frames_per_tick = 256;
+    if (c.max_checks_per_tick == 0) c.max_checks_per_tick = 4000000000LL;
+    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = ctx_budget ? ctx_budget : ((size_t)1 << 30);
+    if (c.watchdog_us == 0) c.watchdog_us = kDefaultWatchdogUs;
+    if (c.max_inflight_ticks < 1 || c.max_inflight_ticks > 4 || c.queue_capacity < 1 || c.max_frames_per_tick < 1 ||
+        c.max_checks_per_tick < 1 || c.watchdog_us < 1 || c.watchdog_us > INT64_MAX / 1000 || c.deadline_us < 0)
+        return "server config out of range (max_inflight_ticks 1..4, positive caps and watchdog, deadline >= 0)";
+    if (ctx_budget && c.hbm_budget_bytes > ctx_budget) return "server budget exceeds the context budget";
+    return "";
+}
+
+mhc_server *new_server(const mhc_server_cfg &c, std::string &err)
+{
+    auto *srv = new mhc_server();
+    srv->cfg = c;
+    srv->slot_bytes = (c.hbm_budget_bytes / c.max_inflight_ticks) & ~size_t(255);
+    const size_t table = align256(((size_t)kMaxCollisionWaves + 1) * 4);
+    if (srv->slot_bytes <= 2 * table) {
+        err = "server budget too small";
+        delete srv;
+        return nullptr;
+    }
+    srv->slot_usable = srv->slot_bytes - table;
+    srv->slots.resize(c.max_inflight_ticks);
+    return srv;
+}
+
+void run_server(mhc_server *srv)
+{
+    srv->start_ns = now_ns();
+    srv->thread = std::thread(scheduler, srv);
+}
+
 }  // namespace
 
 extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, mhc_server **out)
@@ -347,50 +539,53 @@ extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, 
     if (!ctx || !out) return MHC_E_INVAL;
     *out = nullptr;
     mhc_server_cfg c = cfg ? *cfg : mhc_server_cfg{};
-    if (c.max_inflight_ticks == 0) c.max_inflight_ticks = 2;
-    if (c.queue_capacity == 0) c.queue_capacity = 4096;
-    if (c.max_frames_per_tick == 0) c.max_frames_per_tick = 256;
-    if (c.max_checks_per_tick == 0) c.max_checks_per_tick = 4000000000LL;
-    if (c.hbm_budget_bytes == 0) c.hbm_budget_bytes = ctx->budget ? ctx->budget : ((size_t)1 << 30);
-    if (c.max_inflight_ticks < 1 || c.max_inflight_ticks > 4 || c.queue_capacity < 1 || c.max_frames_per_tick < 1 ||
-        c.max_checks_per_tick < 1) {
-        ctx->err = "server config out of range (max_inflight_ticks 1..4, positive caps)";
-        return MHC_E_INVAL;
-    }
-    if (ctx->budget && c.hbm_budget_bytes > ctx->budget) {
-        ctx->err = "server budget exceeds the context budget";
+    const std::string bad = complete_cfg(c, ctx->budget);
+    if (!bad.empty()) {
+        ctx->err = bad;
         return MHC_E_INVAL;
     }
     if (hipSetDevice(ctx->device) != hipSuccess) return MHC_E_DEVICE;
-    auto *srv = new mhc_server();
+    mhc_server *srv = new_server(c, ctx->err);
+    if (!srv) return MHC_E_INVAL;
     srv->ctx = ctx;
-    srv->cfg = c;
-    srv->slot_bytes = (c.hbm_budget_bytes / c.max_inflight_ticks) & ~size_t(255);
-    const size_t table = align256(((size_t)kMaxCollisionWaves + 1) * 4);
-    if (srv->slot_bytes <= 2 * table) {
-        ctx->err = "server budget too small";
-        delete srv;
-        return MHC_E_INVAL;
-    }
-    srv->slot_usable = srv->slot_bytes - table;
-    srv->slots.resize(c.max_inflight_ticks);
-    for (auto &t : srv->slots) {
+    auto ex = std::make_unique<GpuExecutor>();
+    ex->device = ctx->device;
+    ex->n_cu = ctx->n_cu;
+    ex->tune = ctx->tune;
+    for (int v = 0; v < N_VARIANTS; ++v)
+        for (int fam = 0; fam < 3; ++fam)
+            for (int tl = 0; tl < 2; ++tl) ex->waves[v][fam][tl] = ctx->max_waves_of(v, fam, tl != 0);
+    ex->slots.resize(c.max_inflight_ticks);
+    for (auto &t : ex->slots) {
         if (hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&t.done, hipEventDisableTiming) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&t.dbuf), srv->slot_bytes) != hipSuccess) {
             ctx->err = "server: cannot create streams or reserve the HBM budget";
-            for (auto &u : srv->slots) {
-                if (u.dbuf) hipFree(u.dbuf);
-                if (u.done) hipEventDestroy(u.done);
-                if (u.stream) hipStreamDestroy(u.stream);
-            }
+            ex->shutdown();
             delete srv;
             return MHC_E_NOMEM;
         }
         t.dbytes = srv->slot_bytes;
     }
-    srv->start_ns = now_ns();
-    srv->thread = std::thread(scheduler, srv);
+    srv->exec = std::move(ex);
+    run_server(srv);
+    *out = srv;
+    return MHC_OK;
+}
+
+extern "C" mhc_status mhc_server_start_executor(const mhc_server_cfg *cfg, const mhc_executor *ex, mhc_server **out)
+{
+    if (!out || !ex || !ex->launch || !ex->poll) return MHC_E_INVAL;
+    *out = nullptr;
+    mhc_server_cfg c = cfg ? *cfg : mhc_server_cfg{};
+    if (!complete_cfg(c, 0).empty()) return MHC_E_INVAL;
+    std::string err;
+    mhc_server *srv = new_server(c, err);
+    if (!srv) return MHC_E_INVAL;
+    auto cx = std::make_unique<CallbackExecutor>();
+    cx->ex = *ex;
+    srv->exec = std::move(cx);
+    run_server(srv);
     *out = srv;
     return MHC_OK;
 }
@@ -409,6 +604,7 @@ extern "C" mhc_status mhc_submit(mhc_server *srv, int32_t stream_id, const mhc_s
     auto f = copy_frame(scene);
     f->dst = *dst;
     frame_sizes(&f->scene, 0, dst->first_hit != nullptr, *f);
+    f->large = f->checks > srv->cfg.max_checks_per_tick;
     f->stream_id = stream_id;
     f->timing.submit_ns = now_ns();
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -460,6 +656,7 @@ extern "C" mhc_status mhc_server_stats(mhc_server *srv, mhc_stats *out)
         out->deferred = srv->deferred;
         out->ticks = srv->ticks;
         out->checks = srv->checks;
+        out->late = srv->late;
         lat = srv->latency_ms;
         const double secs = (now_ns() - srv->start_ns) * 1e-9;
         out->checks_per_s = secs > 0 ? srv->checks / secs : 0.0;
@@ -490,17 +687,9 @@ extern "C" mhc_status mhc_server_stop(mhc_server *srv)
         srv->cv_work.notify_all();
     }
     if (srv->thread.joinable()) srv->thread.join();
-    hipSetDevice(srv->ctx->device);
-    for (auto &t : srv->slots) {
-        if (t.stream) hipStreamSynchronize(t.stream);
-        if (t.dbuf) hipFree(t.dbuf);
-        if (t.pin_in) hipHostFree(t.pin_in);
-        if (t.pin_out) hipHostFree(t.pin_out);
-        if (t.done) hipEventDestroy(t.done);
-        if (t.stream) hipStreamDestroy(t.stream);
-    }
+    srv->exec->shutdown();
     const mhc_status st = srv->fatal.empty() ? MHC_OK : MHC_E_DEVICE;
-    if (st != MHC_OK) srv->ctx->err = srv->fatal;
+    if (st != MHC_OK && srv->ctx) srv->ctx->err = srv->fatal;
     delete srv;
     return st;
 }

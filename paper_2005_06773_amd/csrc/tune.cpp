@@ -1,5 +1,6 @@
 // Autotuning of the collision kernel's micro-tile shape: every compiled
-// variant is timed on a scene and the fastest is kept per size class.
+// variant is timed on a scene (or a batch of scenes in one launch) and the
+// fastest is kept per size class.
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -20,7 +21,7 @@ static int ilog2_floor(double x)
     return b;
 }
 
-std::array<int, 3> size_class(const mhc_scene *scenes, int n)
+std::array<int, 4> size_class(const mhc_scene *scenes, int n)
 {
     double traj = 0.0, objs = 0.0, hsum = 0.0;
     int family = 0;
@@ -34,10 +35,10 @@ std::array<int, 3> size_class(const mhc_scene *scenes, int n)
         objs += scenes[k].n_objects;
         hsum += scenes[k].horizon;
     }
-    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n)), family};
+    return {ilog2_floor(traj / std::max(1.0, objs)), ilog2_floor(hsum / std::max(1, n)), family, ilog2_floor(n)};
 }
 
-int mhc_ctx::variant_for(const mhc_scene *scenes, int n) const
+int Tuning::variant_for(const mhc_scene *scenes, int n) const
 {
     if (forced_variant >= 0) return forced_variant;
     auto it = tuned.find(size_class(scenes, n));
@@ -60,21 +61,19 @@ extern "C" mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant)
         ctx->err = "variant must be -1 or in [0, MHC_N_VARIANTS)";
         return MHC_E_INVAL;
     }
-    ctx->forced_variant = variant;
+    ctx->tune.forced_variant = variant;
     return MHC_OK;
 }
 
-extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int32_t *best_variant,
-                                   double *us)
+// Times the collision launch of every variant on the n scenes (one launch
+// for all of them, as mhc_evaluate_batch makes it) and records the fastest
+// for their size class.
+static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int32_t reps, int32_t *best_variant,
+                              double *us)
 {
-    if (!ctx) return MHC_E_INVAL;
-    if (reps < 1 || reps > 100000) {
-        ctx->err = "reps must be in [1, 100000]";
-        return MHC_E_INVAL;
-    }
-    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
     HIPC(hipSetDevice(ctx->device));
     ctx->resident_image.clear();  // the timing launches overwrite the context workspace
+    ctx->layout_shape.clear();
     hipEvent_t e0, e1;
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));
@@ -83,7 +82,7 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
     mhc_status st = MHC_OK;
     for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
         Layout L;
-        build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, false);
+        build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, false);
         st = ensure_device(ctx, L.total_bytes);
         if (st != MHC_OK) break;
         char *base = static_cast<char *>(ctx->dbuf);
@@ -114,12 +113,48 @@ extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t
             best_us = t;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != MHC_OK) return st;
-    ctx->tuned[size_class(scene, 1)] = best;
+    ctx->tune.tuned[size_class(scenes, n)] = best;
     if (best_variant) *best_variant = best;
     return MHC_OK;
+}
+
+extern "C" mhc_status mhc_autotune(mhc_ctx *ctx, const mhc_scene *scene, int32_t reps, int32_t *best_variant,
+                                   double *us)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (reps < 1 || reps > 100000) {
+        ctx->err = "reps must be in [1, 100000]";
+        return MHC_E_INVAL;
+    }
+    if (!validate_scene(scene, ctx->err)) return MHC_E_INVAL;
+    return tune_scenes(ctx, 1, scene, reps, best_variant, us);
+}
+
+extern "C" mhc_status mhc_autotune_batch(mhc_ctx *ctx, int32_t n, const mhc_scene *scenes, int32_t reps,
+                                         int32_t *best_variant, double *us)
+{
+    if (!ctx) return MHC_E_INVAL;
+    if (n < 1 || !scenes) {
+        ctx->err = "autotune batch needs n >= 1 scenes";
+        return MHC_E_INVAL;
+    }
+    if (reps < 1 || reps > 100000) {
+        ctx->err = "reps must be in [1, 100000]";
+        return MHC_E_INVAL;
+    }
+    int64_t total_objects = 0;
+    for (int k = 0; k < n; ++k) {
+        if (!validate_scene(&scenes[k], ctx->err, k)) return MHC_E_INVAL;
+        total_objects += scenes[k].n_objects;
+    }
+    if (total_objects > kMaxObjectsPerLaunch) {
+        ctx->err = "batch holds more than 65535 objects";
+        return MHC_E_INVAL;
+    }
+    return tune_scenes(ctx, n, scenes, reps, best_variant, us);
 }
 
 extern "C" mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path)
@@ -132,15 +167,18 @@ extern "C" mhc_status mhc_tune_save(mhc_ctx *ctx, const char *path)
     }
     f << "{\"gfx950\": {";
     bool firstk = true;
-    for (auto &kv : ctx->tuned) {
-        f << (firstk ? "" : ", ") << "\"" << kv.first[0] << "," << kv.first[1] << "," << kv.first[2]
-          << "\": " << kv.second;
+    for (auto &kv : ctx->tune.tuned) {
+        f << (firstk ? "" : ", ") << "\"" << kv.first[0] << "," << kv.first[1] << "," << kv.first[2] << ","
+          << kv.first[3] << "\": " << kv.second;
         firstk = false;
     }
     f << "}}\n";
     return f ? MHC_OK : MHC_E_INVAL;
 }
 
+// Reads the entries of the "gfx950" object: "T,H[,family[,scenes]]": variant.
+// Every entry is checked before any is applied, so a malformed file leaves
+// the context's choices as they were.
 extern "C" mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path)
 {
     if (!ctx || !path) return MHC_E_INVAL;
@@ -157,32 +195,39 @@ extern "C" mhc_status mhc_tune_load(mhc_ctx *ctx, const char *path)
         ctx->err = "tune file has no gfx950 entry";
         return MHC_E_INVAL;
     }
-    std::map<std::array<int, 3>, int> got;
-    size_t pos = s.find('{', arch);
-    const size_t end = s.find('}', pos);
-    if (pos == std::string::npos || end == std::string::npos) {
+    std::map<std::array<int, 4>, int> got;
+    const size_t open = s.find('{', arch);
+    const size_t end = open == std::string::npos ? std::string::npos : s.find('}', open);
+    if (open == std::string::npos || end == std::string::npos) {
         ctx->err = "malformed tune file";
         return MHC_E_INVAL;
     }
+    size_t pos = open;
     while (true) {
         const size_t q = s.find('"', pos + 1);
         if (q == std::string::npos || q > end) break;
-        // keys are "T bucket,H bucket,family" (family 0 rectangles and
-        // circles, 1 point-in-polygon rectangles, 2 outlines); a key without
-        // the third field is of family 0
-        int tb = 0, hb = 0, family = 0, v = 0;
-        if (std::sscanf(s.c_str() + q, "\"%d,%d,%d\": %d", &tb, &hb, &family, &v) != 4) {
-            family = 0;
-            if (std::sscanf(s.c_str() + q, "\"%d,%d\": %d", &tb, &hb, &v) != 3) v = -1;
+        // keys are "T bucket,H bucket,family,scene-count bucket" (family 0
+        // rectangles and circles, 1 point-in-polygon rectangles, 2 outlines);
+        // a key without the scene-count field is for single scenes, one
+        // without the family field also for family 0
+        int tb = 0, hb = 0, family = 0, nb = 0, v = -1, used = 0;
+        const char *c = s.c_str() + q;
+        if (std::sscanf(c, "\"%d,%d,%d,%d\": %d%n", &tb, &hb, &family, &nb, &v, &used) != 5) {
+            nb = 0;
+            if (std::sscanf(c, "\"%d,%d,%d\": %d%n", &tb, &hb, &family, &v, &used) != 4) {
+                family = 0;
+                if (std::sscanf(c, "\"%d,%d\": %d%n", &tb, &hb, &v, &used) != 3) v = -1;
+            }
         }
-        if (v < 0 || v >= N_VARIANTS || family < 0 || family > 2) {
+        if (v < 0 || v >= N_VARIANTS || family < 0 || family > 2 || tb < 0 || hb < 0 || nb < 0 || tb > 62 ||
+            hb > 62 || nb > 62) {
             ctx->err = "malformed tune file entry";
             return MHC_E_INVAL;
         }
-        got[{tb, hb, family}] = v;
-        pos = s.find('"', q + 1);
-        if (pos == std::string::npos) break;
+        got[{tb, hb, family, nb}] = v;
+        pos = q + (size_t)used - 1;
+        if (pos >= end) break;
     }
-    for (auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    for (auto &kv : got) ctx->tune.tuned[kv.first] = kv.second;
     return MHC_OK;
 }

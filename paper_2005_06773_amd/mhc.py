@@ -35,9 +35,10 @@ EXPORTED = [
     "mhc_evaluate", "mhc_evaluate_async", "mhc_evaluate_noalloc",
     "mhc_plan_create", "mhc_plan_update", "mhc_plan_execute", "mhc_plan_execute_stages", "mhc_plan_set_graph",
     "mhc_plan_download", "mhc_plan_destroy",
-    "mhc_set_variant", "mhc_autotune", "mhc_tune_save", "mhc_tune_load", "mhc_plan_check",
+    "mhc_set_variant", "mhc_autotune", "mhc_autotune_batch", "mhc_tune_save", "mhc_tune_load", "mhc_plan_check",
     "mhc_evaluate_batch",
-    "mhc_server_start", "mhc_submit", "mhc_wait", "mhc_server_stats", "mhc_server_stop",
+    "mhc_server_start", "mhc_server_start_executor", "mhc_submit", "mhc_wait", "mhc_server_stats",
+    "mhc_server_stop",
 ]
 
 
@@ -95,7 +96,8 @@ class mhc_result(ctypes.Structure):
 class mhc_server_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight_ticks", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("max_frames_per_tick", ctypes.c_int32),
-                ("max_checks_per_tick", ctypes.c_int64)]
+                ("max_checks_per_tick", ctypes.c_int64), ("watchdog_us", ctypes.c_int64),
+                ("deadline_us", ctypes.c_int64)]
 
 
 class mhc_timing(ctypes.Structure):
@@ -106,7 +108,18 @@ class mhc_timing(ctypes.Structure):
 class mhc_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("deferred", ctypes.c_int64), ("ticks", ctypes.c_int64), ("checks", ctypes.c_int64),
+                ("late", ctypes.c_int64),
                 ("p50_ms", _D), ("p99_ms", _D), ("max_ms", _D), ("mean_ms", _D), ("checks_per_s", _D)]
+
+
+#: mhc_executor callbacks: launch(user, slot, tick, n_frames, scenes, dsts), poll(user, slot)
+EXECUTOR_LAUNCH = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result))
+EXECUTOR_POLL = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32)
+
+
+class mhc_executor(ctypes.Structure):
+    _fields_ = [("user", ctypes.c_void_p), ("launch", EXECUTOR_LAUNCH), ("poll", EXECUTOR_POLL)]
 
 
 def _load():
@@ -144,12 +157,15 @@ def _load():
         "mhc_set_variant": [V, ctypes.c_int32],
         "mhc_autotune": [V, ctypes.POINTER(mhc_scene), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                          ctypes.POINTER(ctypes.c_double)],
+        "mhc_autotune_batch": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
         "mhc_tune_save": [V, ctypes.c_char_p],
         "mhc_tune_load": [V, ctypes.c_char_p],
         "mhc_plan_check": [ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.c_int32, ctypes.c_int32,
                            ctypes.POINTER(mhc_plan_info)],
         "mhc_evaluate_batch": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result)],
         "mhc_server_start": [V, ctypes.POINTER(mhc_server_cfg), ctypes.POINTER(V)],
+        "mhc_server_start_executor": [ctypes.POINTER(mhc_server_cfg), ctypes.POINTER(mhc_executor), ctypes.POINTER(V)],
         "mhc_submit": [V, ctypes.c_int32, ctypes.POINTER(mhc_scene), ctypes.POINTER(mhc_result),
                        ctypes.POINTER(ctypes.c_uint64)],
         "mhc_wait": [V, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(mhc_timing)],
@@ -451,6 +467,17 @@ def mhc_autotune(ctx, scene, reps: int = 20):
     return best.value, list(us)
 
 
+def mhc_autotune_batch(ctx, scenes: Sequence, reps: int = 10):
+    """Tunes the variant of batches like ``scenes`` (one collision launch for
+    all); returns (best variant, [microseconds per launch of each variant])."""
+    css = [s if isinstance(s, CScene) else CScene(s) for s in scenes]
+    arr = (mhc_scene * len(css))(*[c.c for c in css])
+    best = ctypes.c_int32()
+    us = (ctypes.c_double * MHC_N_VARIANTS)()
+    _check(ctx, lib.mhc_autotune_batch(ctx, len(css), arr, reps, ctypes.byref(best), us))
+    return best.value, list(us)
+
+
 def mhc_tune_save(ctx, path: str):
     _check(ctx, lib.mhc_tune_save(ctx, path.encode()))
 
@@ -462,12 +489,26 @@ def mhc_tune_load(ctx, path: str):
 # ---- server ---------------------------------------------------------------
 
 class Server:
+    """A server on the GPU of ``ctx`` (mhc_server_start), or, with ``ctx``
+    None and ``executor`` = (launch, poll) Python callables, on that executor
+    (mhc_server_start_executor): launch(slot, tick, n, scenes, dsts) -> status,
+    poll(slot) -> 1 done / 0 running / < 0 failed."""
+
     def __init__(self, ctx, budget: int = 0, inflight: int = 0, queue: int = 0, frames_per_tick: int = 0,
-                 checks_per_tick: int = 0):
+                 checks_per_tick: int = 0, watchdog_us: int = 0, deadline_us: int = 0, executor=None):
         self.ctx = ctx
-        cfg = mhc_server_cfg(budget, inflight, queue, frames_per_tick, checks_per_tick)
+        cfg = mhc_server_cfg(budget, inflight, queue, frames_per_tick, checks_per_tick, watchdog_us, deadline_us)
         self.h = ctypes.c_void_p()
-        _check(ctx, lib.mhc_server_start(ctx, ctypes.byref(cfg), ctypes.byref(self.h)))
+        if executor is None:
+            _check(ctx, lib.mhc_server_start(ctx, ctypes.byref(cfg), ctypes.byref(self.h)))
+        else:
+            launch, poll = executor
+            self._cb = (EXECUTOR_LAUNCH(lambda user, slot, tick, n, scenes, dsts: launch(slot, tick, n, scenes, dsts)),
+                        EXECUTOR_POLL(lambda user, slot: poll(slot)))
+            self._ex = mhc_executor(None, *self._cb)
+            st = lib.mhc_server_start_executor(ctypes.byref(cfg), ctypes.byref(self._ex), ctypes.byref(self.h))
+            if st != MHC_OK:
+                raise MhcError(st, "mhc_server_start_executor")
         self.pending = {}
 
     def submit(self, stream_id: int, scene, first_hit: bool = False, q: bool = False):
@@ -476,7 +517,7 @@ class Server:
         t = ctypes.c_uint64()
         st = lib.mhc_submit(self.h, stream_id, ctypes.byref(cs.c), ctypes.byref(r), ctypes.byref(t))
         if st != MHC_OK:
-            raise MhcError(st, mhc_last_error(self.ctx))
+            raise MhcError(st, mhc_last_error(self.ctx) if self.ctx else "mhc_submit")
         self.pending[t.value] = (out, r)
         return t.value
 
@@ -484,19 +525,25 @@ class Server:
         tm = mhc_timing()
         st = lib.mhc_wait(self.h, ticket, timeout_us, ctypes.byref(tm))
         if st != MHC_OK:
+            if st != MHC_E_TIMEOUT:
+                self.pending.pop(ticket, None)
             raise MhcError(st, "mhc_wait")
         out, _ = self.pending.pop(ticket)
         return out, {k: getattr(tm, k) for k, _ in mhc_timing._fields_}
 
     def stats(self) -> dict:
         s = mhc_stats()
-        _check(self.ctx, lib.mhc_server_stats(self.h, ctypes.byref(s)))
+        st = lib.mhc_server_stats(self.h, ctypes.byref(s))
+        if st != MHC_OK:
+            raise MhcError(st, "mhc_server_stats")
         return {k: getattr(s, k) for k, _ in mhc_stats._fields_}
 
     def stop(self):
         if self.h:
-            _check(self.ctx, lib.mhc_server_stop(self.h))
-            self.h = ctypes.c_void_p()
+            h, self.h = self.h, ctypes.c_void_p()
+            st = lib.mhc_server_stop(h)
+            if st != MHC_OK:
+                raise MhcError(st, mhc_last_error(self.ctx) if self.ctx else "mhc_server_stop")
 
 
 def mhc_server_start(ctx, **kw) -> Server:

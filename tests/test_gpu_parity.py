@@ -525,3 +525,4 @@ def test_repeated_shape_reuses_resident_plan(mhc, ctx):
             mhc.mhc_autotune(ctx, scenes[0], reps=2)
         else:
             parity.same_results(mhc.mhc_evaluate(ctx, scenes[k]), fresh(scenes[k]), f"11-object seed {11 + k}")
+

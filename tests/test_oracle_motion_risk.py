@@ -259,8 +259,8 @@ def test_single_collision_object_reduces_to_double_sum():
 
 
 def test_chronological_scaling_telescopes():
-    """Sec. IV-D.2: the first combination keeps its probability, the next is
-    scaled by the no-collision probability of the first, and so on. Summing
+    """Sec. IV-D.2: the earliest combination counts in full, each later one
+    is multiplied by the chance that none before it collided. Summing
     these in the chronological order of each object's earliest hit gives the
     oracle's 1 - prod(1 - q), in any order."""
     s = _colliding_scene(21, n=6)

@@ -1,5 +1,5 @@
-"""Pins of the oracle's general convex polygons (Sec. IV-C.1: the polygons
-"can be as complex as necessary").
+"""Pins of the oracle's general convex polygons (Sec. IV-C.1 allows object
+polygons of any complexity).
 
 The separating-axis margin is pinned by exact rational clipping (sign) and
 closed forms (value); the polygon-circle margin by exact rational

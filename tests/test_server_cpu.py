@@ -1,0 +1,206 @@
+"""The serving scheduler on the CPU, driven through the C ABI by a fake tick
+executor (mhc_server_start_executor): admission under the memory budget,
+arrival order, deadline accounting, the watchdog, failed ticks, and frames
+above the per-tick check cap keeping one slot open to smaller frames.
+
+The executor here writes a marker into each frame's object criticality (the
+tick number + 1) instead of evaluating anything, so the tests see which tick
+carried which frame and that results reach the caller's buffers."""
+import ctypes
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2005_06773_amd import scenegen as sg
+
+
+@pytest.fixture(scope="module")
+def mhc():
+    from paper_2005_06773_amd import mhc as m
+    return m
+
+
+class FakeExecutor:
+    """Ticks finish after `hold_s` seconds, or only once released when
+    `hold(tick)` says so; `fail` makes poll report a failure."""
+
+    def __init__(self, mhc, hold_s=0.0, hold=None, fail=False, launch_status=0):
+        self.mhc = mhc
+        self.hold_s = hold_s
+        self.hold = hold or (lambda tick, n_checks: False)
+        self.fail = fail
+        self.launch_status = launch_status
+        self.slots = {}
+        self.released = threading.Event()
+        self.ticks = []          # (tick, slot, n frames, large)
+        self.lock = threading.Lock()
+
+    def launch(self, slot, tick, n, scenes, dsts):
+        held = False
+        for k in range(n):
+            s = scenes[k]
+            nobj = s.n_objects
+            oc = ctypes.cast(dsts[k].object_crit, ctypes.POINTER(ctypes.c_double))
+            for a in range(nobj):
+                oc[a] = float(tick + 1)
+            T = [s.objects[a].n_u * s.objects[a].n_w for a in range(nobj)]
+            checks = sum(T[a] * T[b] for a in range(nobj) for b in range(a + 1, nobj)) * s.horizon
+            held |= self.hold(tick, checks)
+        with self.lock:
+            self.ticks.append((tick, slot, n, held))
+        self.slots[slot] = (time.monotonic(), held)
+        return self.launch_status
+
+    def poll(self, slot):
+        if self.fail:
+            return -1
+        t0, held = self.slots[slot]
+        if held and not self.released.is_set():
+            return 0
+        return 1 if time.monotonic() - t0 >= self.hold_s else 0
+
+    def callbacks(self):
+        return (self.launch, self.poll)
+
+
+def _server(mhc, ex, **kw):
+    return mhc.Server(None, executor=ex.callbacks(), **kw)
+
+
+def test_arrival_order_and_results(mhc):
+    ex = FakeExecutor(mhc, hold_s=0.002)
+    srv = _server(mhc, ex, inflight=1, frames_per_tick=3)
+    scenes = [sg.two_vehicle_scene(s) for s in range(10)]
+    tickets = [srv.submit(s % 3, sc) for s, sc in enumerate(scenes)]
+    got = [srv.wait(t, timeout_us=10_000_000) for t in tickets]
+    st = srv.stats()
+    srv.stop()
+    ticks = [timing["tick"] for _, timing in got]
+    assert ticks == sorted(ticks), f"frames left their arrival order: {ticks}"
+    assert all(n <= 3 for _, _, n, _ in ex.ticks) and st["ticks"] == len(ex.ticks) >= 4
+    for (out, timing) in got:
+        assert np.all(out["object_crit"] == timing["tick"] + 1)
+        assert timing["submit_ns"] <= timing["admit_ns"] <= timing["launch_ns"] <= timing["done_ns"]
+    assert st["completed"] == 10 and st["submitted"] == 10 and st["late"] == 0
+
+
+def _accepting_budget(mhc, scene):
+    """The smallest power-of-two budget (one slot) under which `scene` with its
+    first-hit output is accepted."""
+    for k in range(20, 34):
+        srv = _server(mhc, FakeExecutor(mhc), inflight=1, budget=1 << k)
+        try:
+            srv.submit(0, scene, first_hit=True)
+            return 1 << k
+        except mhc.MhcError as e:
+            assert e.status == mhc.MHC_E_NOMEM
+        finally:
+            srv.stop()
+    raise AssertionError("no budget accepted the frame")
+
+
+def test_budget_admission(mhc):
+    big = sg.eleven_object_scene(1)      # 5.6 MB of first hits per frame
+    b1 = _accepting_budget(mhc, big)
+    # half that budget refuses the frame outright
+    srv = _server(mhc, FakeExecutor(mhc), inflight=1, budget=b1 // 2)
+    with pytest.raises(mhc.MhcError) as ei:
+        srv.submit(0, big, first_hit=True)
+    assert ei.value.status == mhc.MHC_E_NOMEM
+    st = srv.stats()
+    srv.stop()
+    assert st["rejected"] == 1 and st["submitted"] == 0
+    # 1.5x holds one such frame per tick but not two: every tick carries one
+    ex = FakeExecutor(mhc, hold_s=0.02)      # all five are queued before the first tick ends
+    srv = _server(mhc, ex, inflight=1, budget=b1 + b1 // 2)
+    ts = [srv.submit(0, big, first_hit=True) for _ in range(5)]
+    for t in ts:
+        srv.wait(t, timeout_us=10_000_000)
+    st = srv.stats()
+    srv.stop()
+    assert [n for _, _, n, _ in ex.ticks] == [1] * 5 and st["deferred"] >= 1
+
+
+def test_deadline_accounting(mhc):
+    for deadline_us, want_late in ((10_000, 4), (10_000_000, 0)):
+        ex = FakeExecutor(mhc, hold_s=0.03)
+        srv = _server(mhc, ex, inflight=2, frames_per_tick=1, deadline_us=deadline_us)
+        ts = [srv.submit(0, sg.two_vehicle_scene(s)) for s in range(4)]
+        lat = []
+        for t in ts:
+            _, timing = srv.wait(t, timeout_us=10_000_000)
+            lat.append((timing["done_ns"] - timing["submit_ns"]) * 1e-6)
+        st = srv.stats()
+        srv.stop()
+        assert min(lat) >= 30.0 and st["late"] == want_late, (deadline_us, lat, st)
+        assert st["max_ms"] >= st["p99_ms"] >= st["p50_ms"] >= 30.0
+
+
+def test_watchdog_fails_a_tick_that_never_ends(mhc):
+    ex = FakeExecutor(mhc, hold=lambda tick, checks: True)     # never released
+    srv = _server(mhc, ex, inflight=1, frames_per_tick=1, watchdog_us=100_000)
+    t0 = time.monotonic()
+    ts = [srv.submit(0, sg.two_vehicle_scene(s)) for s in range(3)]
+    statuses = []
+    for t in ts:
+        with pytest.raises(mhc.MhcError) as ei:
+            srv.wait(t, timeout_us=10_000_000)
+        statuses.append(ei.value.status)
+    waited = time.monotonic() - t0
+    assert statuses == [mhc.MHC_E_DEVICE] * 3 and 0.1 <= waited < 5.0
+    assert len(ex.ticks) == 1          # nothing else was launched after the failure
+    with pytest.raises(mhc.MhcError) as ei:
+        srv.stop()
+    assert ei.value.status == mhc.MHC_E_DEVICE
+
+
+def test_failed_tick_and_failed_launch(mhc):
+    for kw in ({"fail": True}, {"launch_status": -3}):
+        ex = FakeExecutor(mhc, **kw)
+        srv = _server(mhc, ex, inflight=2, frames_per_tick=2)
+        ts = [srv.submit(0, sg.two_vehicle_scene(s)) for s in range(5)]
+        for t in ts:
+            with pytest.raises(mhc.MhcError) as ei:
+                srv.wait(t, timeout_us=10_000_000)
+            assert ei.value.status == mhc.MHC_E_DEVICE
+        with pytest.raises(mhc.MhcError):
+            srv.stop()
+
+
+def test_large_frames_leave_a_slot_to_small_ones(mhc):
+    """Frames above the per-tick check cap ride alone and hold at most all
+    but one slot: while two of them wait (one running, one queued), small
+    frames submitted after them still go through the other slot."""
+    cap = 100_000
+    ex = FakeExecutor(mhc, hold=lambda tick, checks: checks > cap)
+    srv = _server(mhc, ex, inflight=2, checks_per_tick=cap)
+    large = [srv.submit(0, sg.eleven_object_scene(s)) for s in range(2)]   # 83.5 M checks each
+    small = [srv.submit(1, sg.two_vehicle_scene(s)) for s in range(6)]     # 18,750 checks each
+    small_ticks = [srv.wait(t, timeout_us=10_000_000)[1]["tick"] for t in small]
+    with pytest.raises(mhc.MhcError) as ei:
+        srv.wait(large[0], timeout_us=50_000)      # still held
+    assert ei.value.status == mhc.MHC_E_TIMEOUT
+    ex.released.set()
+    large_ticks = [srv.wait(t, timeout_us=10_000_000)[1]["tick"] for t in large]
+    srv.stop()
+    assert large_ticks[0] == 0 and large_ticks[1] > max(small_ticks), (large_ticks, small_ticks)
+    held = [(tick, n) for tick, _, n, h in ex.ticks if h]
+    assert [n for _, n in held] == [1, 1]
+
+
+def test_invalid_configurations(mhc):
+    ex = FakeExecutor(mhc)
+    for kw in ({"inflight": 5}, {"watchdog_us": -1}, {"deadline_us": -5}, {"budget": 1 << 10}):
+        with pytest.raises(mhc.MhcError) as ei:
+            _server(mhc, ex, **kw)
+        assert ei.value.status == mhc.MHC_E_INVAL
+    srv = _server(mhc, ex)
+    bad = sg.two_vehicle_scene(0)
+    bad.horizon = 0
+    with pytest.raises(mhc.MhcError) as ei:
+        srv.submit(0, bad)
+    assert ei.value.status == mhc.MHC_E_INVAL
+    assert srv.stats()["rejected"] == 1
+    srv.stop()

@@ -377,9 +377,11 @@ typedef struct {
     int32_t queue_capacity;       /* frames waiting for admission (0 = 4096) */
     int32_t max_frames_per_tick;  /* 0 = 256 */
     int64_t max_checks_per_tick;  /* a tick closes when this many checks are admitted (0 = 4e9); a frame
-                                     of more checks rides in a tick of its own, and with two or more
-                                     slots such frames hold all but one slot, so one slot stays open
-                                     to smaller frames (which may then overtake a waiting large one) */
+                                     of more checks rides in a tick of its own, its collision work cut
+                                     into launches of at most about this many checks so that other
+                                     ticks reach the GPU in between; with two or more slots such frames
+                                     hold all but one slot, so one slot stays open to smaller frames
+                                     (which may then overtake a waiting large one) */
     int64_t watchdog_us;          /* a tick running longer than this fails the server: its frames and
                                      every queued one complete with MHC_E_DEVICE, mhc_server_stop
                                      returns MHC_E_DEVICE (0 = 30 s) */

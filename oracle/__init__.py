@@ -23,7 +23,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mhc_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB_PATH names another build of the same source (the sanitizer
+# build of the CPU tests).
+LIB = os.environ.get("ORACLE_LIB_PATH") or os.path.join(HERE, "liboracle.so")
 
 #: tolerance band (metres) within which an FP32 evaluation may decide an
 #: overlap either way; outside it first hits must agree bit for bit.

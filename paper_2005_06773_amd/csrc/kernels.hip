@@ -947,13 +947,17 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
 template <int FAM>
 constexpr int kCollideMinWaves = FAM == FAM_PLAIN ? 5 : FAM == FAM_PIP ? 4 : 1;
 
+// A launch may run one part of the plan (part of n_parts): every wave then
+// takes only its units [U part / n_parts, U (part + 1) / n_parts) of the U
+// units of its segments, so that n_parts launches cover each unit once.
 template <int V, int FAM, bool TL>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinWaves<FAM>))) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
                                                  const unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc,
-                                                 unsigned long long *__restrict__ hist, const DPoly *__restrict__ polys)
+                                                 unsigned long long *__restrict__ hist, const DPoly *__restrict__ polys,
+                                                 int part, int n_parts)
 {
     const int wave_in_block = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int blocks = (int)gridDim.x;
@@ -969,13 +973,24 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinW
     constexpr bool poly = FAM >= FAM_POLY;
     __shared__ DPoly lds_polys[poly ? 2 * (WG / WAVE) : 1];
     DPoly *lp = lds_polys + (poly ? 2 * wave_in_block : 0);
-    const int s1 = bins[slot + 1];
-    for (int k = bins[slot]; k < s1; ++k) {
+    const int s0 = bins[slot], s1 = bins[slot + 1];
+    int lo = 0, hi = INT_MAX;   // this launch's units of the wave
+    if (n_parts > 1) {
+        int units = 0;
+        for (int k = s0; k < s1; ++k) units += work[k].n_units;
+        lo = (int)((int64_t)units * part / n_parts);
+        hi = (int)((int64_t)units * (part + 1) / n_parts);
+    }
+    int base = 0;   // units of the wave's segments before segment k
+    for (int k = s0; k < s1 && base < hi; ++k) {
         const WorkItem w = work[k];
+        const int u0 = max(lo - base, 0), u1 = min(hi - base, w.n_units);
+        base += w.n_units;
+        if (u0 >= u1) continue;
         const DPair pr = pairs[w.pair];
         if (poly && pr.cls >= CLS_GG) stage_polygons(lp, polys, pr);
         const int per = WAVE >> pr.tshift;
-        for (int u = 0; u < w.n_units; ++u)
+        for (int u = u0; u < u1; ++u)
             collide_work<V, FAM, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, lp);
     }
 }
@@ -1398,9 +1413,14 @@ template <int V, int FAM, bool TL>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
-    hipLaunchKernelGGL((k2_collide<V, FAM, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins, L.n_bins,
-                       L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys);
-    return hipGetLastError();
+    const int parts = L.collide_parts > 1 ? L.collide_parts : 1;
+    for (int part = 0; part < parts; ++part) {
+        hipLaunchKernelGGL((k2_collide<V, FAM, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins,
+                           L.n_bins, L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys, part, parts);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int V, int FAM, bool TL>

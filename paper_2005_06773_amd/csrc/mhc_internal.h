@@ -189,6 +189,7 @@ struct Launch {
     double *ct_w;                 // criticality over time [s][i] per object
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
+    int collide_parts;            // the collision plan runs as this many launches (0 or 1: one)
     int variant;
     int family;                   // ClassFamily covering every pair of the launch
 };

@@ -18,7 +18,9 @@
 // and with two or more slots such frames may occupy all but one of them, so
 // that one slot always stays open to the other frames; those may then go
 // ahead of a large frame that waits for a slot. Frames of either kind keep
-// their arrival order among themselves.
+// their arrival order among themselves. On the GPU such a tick's collision
+// plan runs as several launches of at most about max_checks_per_tick checks
+// each, between which the other slots' kernels reach the GPU.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -46,6 +48,17 @@ int64_t now_ns()
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Deadline of a bounded condition-variable wait. Waits are timed on the
+// system clock: with it the standard library waits in
+// pthread_cond_timedwait, which thread sanitizers follow (the steady clock's
+// pthread_cond_clockwait is not followed by all of them, which then
+// misreport the mutex as still held). Only the bounded waits' length depends
+// on this clock; latencies are measured on the steady clock.
+std::chrono::system_clock::time_point wait_deadline(std::chrono::microseconds d)
+{
+    return std::chrono::system_clock::now() + d;
+}
 
 // Bound on the resident collision waves of any GPU this library runs on
 // (sizes the slot table in the admission estimate).
@@ -122,6 +135,7 @@ hipError_t grow_pinned(char **p, size_t *have, size_t want)
 class GpuExecutor : public Executor {
 public:
     int device = 0, n_cu = 0;
+    int64_t max_checks_per_tick = 0;
     Tuning tune;
     int waves[N_VARIANTS][3][2] = {};
     std::vector<TickSlot> slots;
@@ -163,7 +177,13 @@ public:
             pack_image(t.L, t.pin_in);
             e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
         }
-        if (e == hipSuccess) e = launch_all(make_launch(t.L, t.dbuf, nullptr, keep_hits, n_cu), t.stream);
+        Launch X = make_launch(t.L, t.dbuf, nullptr, keep_hits, n_cu);
+        // a tick above the check cap (one large frame) runs its collision
+        // plan as launches of at most about that many checks each, so that
+        // the other slots' ticks get the GPU in between
+        if (t.L.n_checks > max_checks_per_tick)
+            X.collide_parts = (int)std::min<int64_t>(64, (t.L.n_checks + max_checks_per_tick - 1) / max_checks_per_tick);
+        if (e == hipSuccess) e = launch_all(X, t.stream);
         if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
         if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
         if (e != hipSuccess) {
@@ -453,7 +473,7 @@ void scheduler(mhc_server *srv)
             std::unique_lock<std::mutex> lk(srv->mu);
             if (srv->queue.empty() && !any_busy) {
                 if (srv->stopping) return;
-                srv->cv_work.wait_for(lk, std::chrono::milliseconds(5));
+                srv->cv_work.wait_until(lk, wait_deadline(std::chrono::milliseconds(5)));
                 continue;
             }
             if (!srv->fatal.empty()) {
@@ -551,6 +571,7 @@ extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, 
     auto ex = std::make_unique<GpuExecutor>();
     ex->device = ctx->device;
     ex->n_cu = ctx->n_cu;
+    ex->max_checks_per_tick = c.max_checks_per_tick;
     ex->tune = ctx->tune;
     for (int v = 0; v < N_VARIANTS; ++v)
         for (int fam = 0; fam < 3; ++fam)
@@ -636,7 +657,7 @@ extern "C" mhc_status mhc_wait(mhc_server *srv, uint64_t ticket, int64_t timeout
     auto ready = [&] { return f->state == DONE; };
     if (timeout_us < 0) {
         srv->cv_done.wait(lk, ready);
-    } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+    } else if (!srv->cv_done.wait_until(lk, wait_deadline(std::chrono::microseconds(timeout_us)), ready)) {
         return MHC_E_TIMEOUT;
     }
     if (timing) *timing = f->timing;

@@ -15,7 +15,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmhc.so")
+# MHC_LIB_PATH names another build of the same library (the host-side
+# sanitizer builds of the CPU tests); there is never a fallback.
+LIB_PATH = os.environ.get("MHC_LIB_PATH") or os.path.join(HERE, "libmhc.so")
 
 MHC_OK = 0
 MHC_E_INVAL = -1
@@ -126,10 +128,11 @@ def _load():
     # One HIP runtime per process: torch ships its own copy of libamdhip64.so.7.
     # Loading torch first makes this library bind to that same copy, so device
     # pointers and streams created by torch are valid here.
-    try:
-        import torch  # noqa: F401
-    except ImportError:
-        pass
+    if not os.environ.get("MHC_LIB_PATH"):
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                           "(python -c 'import __graft_entry__ as g; g.build()')")

@@ -154,3 +154,25 @@ def test_poisson_schedule_frames_alone_and_in_the_mix(mhc, ctx):
     for k, ((_, stream, scene), out) in enumerate(zip(events, outs)):
         parity.same_results(mhc.mhc_evaluate(ctx, scene), out, f"frame {k} of stream {stream}")
     assert st["completed"] == len(events)
+
+
+def test_large_frames_run_in_parts(mhc, ctx):
+    """With a small per-tick check cap, 11-object frames (83.5 M checks) ride
+    alone and their collision plan runs as nine launches, while small frames
+    share the other slot: every frame equals the scene evaluated alone."""
+    big = [sg.eleven_object_scene(s) for s in (1, 2)]
+    small = [sg.two_vehicle_scene(s) for s in range(4)]
+    four = sg.eleven_object_scene(3)          # 2 vehicles, 2 pedestrians: 9.1 M checks
+    four.objects = four.objects[:2] + four.objects[6:8]
+    small.append(four)
+    say(f"large frames in parts: 2 x 83.5 M checks with cap 1e7, {len(small)} small frames")
+    srv = mhc.Server(ctx, budget=1 << 30, inflight=2, checks_per_tick=10_000_000)
+    tb = [srv.submit(0, s, first_hit=True, q=True) for s in big]
+    ts = [srv.submit(1, s, first_hit=True, q=True) for s in small]
+    outs_b = [srv.wait(t)[0] for t in tb]
+    outs_s = [srv.wait(t)[0] for t in ts]
+    srv.stop()
+    for k, (s, o) in enumerate(zip(big, outs_b)):
+        parity.same_results(mhc.mhc_evaluate(ctx, s), o, f"large frame {k}")
+    for k, (s, o) in enumerate(zip(small, outs_s)):
+        parity.same_results(mhc.mhc_evaluate(ctx, s), o, f"small frame {k}")

@@ -330,8 +330,9 @@ EXTRAS = ("latency", "batched", "served", "table_one", "timeline", "polygons", "
 
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
-WORKLOADS = ("eleven_object", "table_one_s2", "table_one_s2_pip", "table_one_s2_timeline", "eleven_object_octagons",
-             "eleven_object_timeline", "eleven_object_models", "stress")
+WORKLOADS = ("eleven_object", "two_vehicle", "table_one_s2", "table_one_s2_pip", "table_one_s2_timeline", "table_one_s2_5",
+             "table_one_s1", "table_one_s1_5", "eleven_object_octagons", "eleven_object_timeline",
+             "eleven_object_models", "stress")
 
 
 def make_workload(name, seed, sg):
@@ -356,6 +357,12 @@ def make_workload(name, seed, sg):
             cfg["motion_models"] = "one-track vehicles, accelerating pedestrians capped at 2.7 m/s"
             label += ", one-track / pedestrian acceleration models"
         return scene, label, cfg, f"{label} seed {seed}"
+    if name == "two_vehicle":
+        scene = sg.two_vehicle_scene(seed)
+        cfg = {"workload": "two_vehicle_scene", "objects": 2, "vehicles": 2, "pedestrians": 0,
+               "trajectories_per_object": 25, "horizon": 30, "dt": 0.1, "seed": seed, "pairs": "all",
+               "overlap": "exact"}
+        return scene, "two-vehicle scene", cfg, f"two-vehicle scene seed {seed}"
     if name == "stress":
         scene = sg.stress_scene(seed)
         cfg = {"workload": "stress_scene", "objects": 40, "vehicles": 24, "pedestrians": 16,
@@ -364,16 +371,19 @@ def make_workload(name, seed, sg):
         return scene, "40-object stress scene", cfg, f"40-object stress scene seed {seed}"
     pip = name.endswith("_pip")
     tl = name.endswith("_timeline")
-    scene = sg.paper_scene(seed, n_co=10, n_acc=6, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
+    s1 = name.startswith("table_one_s1")
+    n_acc = 5 if name.endswith("_5") else 6
+    n_co = 3 if s1 else 10
+    scene = sg.paper_scene(seed, n_co=n_co, n_acc=n_acc, overlap=sg.OVERLAP_PIP if pip else sg.OVERLAP_EXACT)
     scene.timeline = 1 if tl else 0
-    cfg = {"workload": "table_one_s2_scene", "objects": 11, "vehicles": 11, "pedestrians": 0,
-           "trajectories": {"ego": 2058, "co": 42}, "horizon": 100, "dt": 0.02, "seed": seed, "pairs": "ego",
-           "overlap": "pip" if pip else "exact"}
-    label = "Table I S2 scene" + (", point-in-polygon" if pip else "") + (", risk over time" if tl else "")
+    cfg = {"workload": f"table_one_{'s1' if s1 else 's2'}_scene", "objects": n_co + 1, "vehicles": n_co + 1,
+           "pedestrians": 0, "trajectories": {"ego": n_acc * 343, "co": n_acc * 7}, "horizon": 100, "dt": 0.02,
+           "seed": seed, "pairs": "ego", "overlap": "pip" if pip else "exact"}
+    label = (f"Table I {'S1' if s1 else 'S2'} scene" + (", 5 profiles" if n_acc == 5 else "")
+             + (", point-in-polygon" if pip else "") + (", risk over time" if tl else ""))
     if tl:
         cfg["risk_over_time"] = True
-    return scene, label, cfg, (f"Table I S2 scene seed {seed} ({'point-in-polygon' if pip else 'exact'} overlap"
-                               f"{', risk over time' if tl else ''})")
+    return scene, label, cfg, f"{label} seed {seed}"
 
 
 def recorded_traffic(variant, workload):
@@ -614,6 +624,70 @@ def stress_extra(mhc, ctx, sg, torch, steps=10):
     return out
 
 
+def sweep_arrivals(streams, seconds, warm, rate, n_pool):
+    """Poisson arrivals of `streams` streams at `rate` Hz over warm + seconds
+    (start offsets U(0, 100 ms)), with the stream of each arrival and the
+    pool frame it carries; the same draws for the served and the plain
+    sweep at a given load."""
+    import numpy as np
+    rng = np.random.default_rng(1000 + streams)
+    arr, sid = [], []
+    for s in range(streams):
+        t = float(rng.uniform(0.0, 0.1))
+        gaps = rng.exponential(1.0 / rate, int((warm + seconds) * rate * 3) + 20)
+        ts = t + np.concatenate([[0.0], np.cumsum(gaps)])
+        arr.append(ts[ts < warm + seconds])
+        sid.append(np.full(arr[-1].size, s))
+    order = np.argsort(np.concatenate(arr), kind="stable")
+    arrivals = np.concatenate(arr)[order]
+    stream_of = np.concatenate(sid)[order]
+    which = rng.integers(0, n_pool, arrivals.size)
+    return arrivals, stream_of, which
+
+
+def plain_sweep(mhc, ctx, sg, seconds, streams_list=(32, 128, 256, 384, 512, 640, 768, 1024)):
+    """The served load sweep's arrivals (same streams, draws and frame pool)
+    through the plain per-frame loop: each frame evaluated by mhc_evaluate
+    when the loop reaches it, latency from its scheduled arrival to its
+    results in host memory. Stops at the first load whose p99 passes 50 ms
+    and reports the largest sustained rate within the deadline, the
+    comparison point of the served sweep."""
+    scenes = sg.batch_scenes(3, 512)
+    pool = [mhc.CScene(s) for s in scenes]
+    pool_checks = [mhc.mhc_query_sizes(c)["n_checks"] for c in pool]
+    warm, rate, deadline = 0.5, 10.0, 50.0
+    points, best = [], None
+    for c in pool[:16]:
+        mhc.mhc_evaluate(ctx, c, first_hit=False, q=False)
+    for streams in streams_list:
+        arrivals, _, which = sweep_arrivals(streams, seconds, warm, rate, len(pool))
+        lat, chk = [], 0
+        t0 = time.monotonic_ns()
+        end = t0
+        for k in range(arrivals.size):
+            at = t0 + int(arrivals[k] * 1e9)
+            while time.monotonic_ns() < at:
+                time.sleep(0.00005)
+            mhc.mhc_evaluate(ctx, pool[which[k]], first_hit=False, q=False)
+            end = time.monotonic_ns()
+            if arrivals[k] >= warm:
+                lat.append((end - at) * 1e-6)
+                chk += pool_checks[which[k]]
+        span = (end - (t0 + int(warm * 1e9))) * 1e-9
+        pt = {"streams": streams, "frames": len(lat), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+              "max_ms": max(lat), "completed_checks_per_s": chk / span,
+              "within_deadline": sum(x <= deadline for x in lat) / len(lat)}
+        points.append(pt)
+        log(f"plain loop sweep: {streams} streams, {len(lat)} frames, p50 {pt['p50_ms']:.2f} ms p99 "
+            f"{pt['p99_ms']:.2f} ms, {pt['completed_checks_per_s']:.4g} checks/s")
+        if pt["p99_ms"] > deadline:
+            break
+        best = pt
+    return {"rate_hz_per_stream": rate, "seconds_per_point": seconds, "deadline_ms": deadline, "points": points,
+            "max_sustained_checks_per_s_within_deadline": None if best is None else best["completed_checks_per_s"],
+            "at_streams": None if best is None else best["streams"]}
+
+
 def serve_sweep(mhc, ctx, sg, seconds,
                 streams_list=(32, 256, 512, 768, 1024, 1280, 1536, 1792, 2048, 2304, 2560, 3072, 3584, 4096)):
     """Served load sweep: the serving workload with more and more 10 Hz
@@ -639,18 +713,7 @@ def serve_sweep(mhc, ctx, sg, seconds,
     warm, rate, deadline = 0.5, 10.0, 50.0
     points, best = [], None
     for streams in streams_list:
-        rng = np.random.default_rng(1000 + streams)
-        arr, sid = [], []
-        for s in range(streams):
-            t = float(rng.uniform(0.0, 0.1))
-            gaps = rng.exponential(1.0 / rate, int((warm + seconds) * rate * 3) + 20)
-            ts = t + np.concatenate([[0.0], np.cumsum(gaps)])
-            arr.append(ts[ts < warm + seconds])
-            sid.append(np.full(arr[-1].size, s))
-        order = np.argsort(np.concatenate(arr), kind="stable")
-        arrivals = np.concatenate(arr)[order]
-        stream_of = np.concatenate(sid)[order]
-        which = rng.integers(0, len(pool), arrivals.size)
+        arrivals, stream_of, which = sweep_arrivals(streams, seconds, warm, rate, len(pool))
         srv = mhc.Server(ctx, budget=4 << 30, inflight=2)
         n = arrivals.size
         tickets = [0] * n
@@ -750,7 +813,7 @@ def main():
         sys.exit(2)
     if args.seed is None:
         args.seed = {"eleven_object": 1, "eleven_object_octagons": 1, "eleven_object_timeline": 1,
-                     "eleven_object_models": 10, "stress": 4}.get(args.workload, 5)
+                     "eleven_object_models": 10, "stress": 4, "two_vehicle": 0}.get(args.workload, 5)
 
     import torch
     from paper_2005_06773_amd import mhc, scenegen as sg
@@ -923,6 +986,7 @@ def main():
         result["served"] = serve(mhc, ctx, sg, args.serve_seconds)
         if args.serve_sweep_seconds > 0:
             result["served_sweep"] = serve_sweep(mhc, ctx, sg, args.serve_sweep_seconds)
+            result["plain_loop_sweep"] = plain_sweep(mhc, ctx, sg, args.serve_sweep_seconds)
     for name, fn in (("table_one", table_one), ("timeline", timeline_extra), ("polygons", polygon_extra),
                      ("models", models_extra), ("stress", stress_extra)):
         if name in extras:

@@ -262,8 +262,13 @@ __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, c
 // Grid: y = object; x = 0 is the object's probability normalisation (the
 // longest block for large T, so it is dispatched first), x >= 1 are
 // trajectory blocks of K1_TPB trajectories, one wave each.
+// ONE_TRACK: whether the instance carries the one-track model's scan, whose
+// FP64 state needs far more registers (130 VGPRs against the kinematic
+// instance's); launches without one-track vehicles use the lighter instance,
+// which also fits beside a running collision kernel on a shared GPU.
 // For time-resolved scenes, trajectory block c also zeroes the c-th stretch
 // of K1_TPB * W * H entries of the object's per-slot q sums.
+template <bool ONE_TRACK>
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
@@ -290,9 +295,11 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
     if (i >= o.T) return;  // whole wave
     // this trajectory's row of the integer q accumulators starts from zero
     for (int k = lane; k < o.n_scene_obj; k += 64) qacc[o.q_row + (int64_t)i * o.n_scene_obj + k] = 0ull;
-    if (o.model == MODEL_ONE_TRACK) {
-        one_track_wave(o, vals, poses, i, lane);
-        return;
+    if constexpr (ONE_TRACK) {
+        if (o.model == MODEL_ONE_TRACK) {
+            one_track_wave(o, vals, poses, i, lane);
+            return;
+        }
     }
     const int k = i / o.n_w, l = i - (i / o.n_w) * o.n_w;
     const double tau = o.tau;
@@ -679,7 +686,13 @@ __device__ __forceinline__ float2 load_pose<float2>(__amdgpu_buffer_rsrc_t r, ui
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-template <int RI, int RJ, bool TL, class PA, class PB, class Check>
+// STAGE: the instance stages the poses of 8 x 8 item blocks in LDS (units of
+// 2-D blocks without a time split): per step, the wave loads each distinct
+// pose of its block once (lane k the k-th pose of either object), prepares it
+// once, and every lane then reads its tile's poses from LDS. The tests and
+// their results are those of the unstaged loop; only where the poses come
+// from differs. Each step's loads are issued before the previous step's tests.
+template <int RI, int RJ, bool TL, class PA, class PB, class Check, bool STAGE = false>
 __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const char *__restrict__ poses,
                                               int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
                                               unsigned long long *__restrict__ qacc,
@@ -711,9 +724,24 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
         // a column past the grid's edge is an idle lane
         f = col < n_jg ? (((bi << (6 - tshift)) >> bs) + (e >> bs)) * n_jg + col : INT_MAX;
     }
-    if (f >= n_ig * n_jg) return;  // every part of an item leaves together
-    const int ig = f / n_jg;
-    const int jg = f - ig * n_jg;
+    const bool stage = STAGE && bs == 3 && tshift == 0;
+    int ig, jg;
+    bool live = true;  // the lane's item lies in the grid (staged blocks keep every lane to the end)
+    int ig0 = 0, jg0 = 0;
+    if (stage) {
+        const int v = item0 >> 6;
+        const int nb = (n_jg + 7) >> 3;
+        const int bi = v / nb;
+        ig0 = bi << 3;              // the block's first item row and column
+        jg0 = (v - bi * nb) << 3;
+        ig = ig0 + (e >> 3);
+        jg = jg0 + (e & 7);
+        live = ig < n_ig && jg < n_jg;
+    } else {
+        if (f >= n_ig * n_jg) return;  // every part of an item leaves together
+        ig = f / n_jg;
+        jg = f - ig * n_jg;
+    }
     const int Ta = pr.Ta, Tb = pr.Tb;
     int ia[RI], jb[RJ];
 #pragma unroll
@@ -728,30 +756,77 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     const uint32_t strideA = (uint32_t)Ta * (uint32_t)sizeof(PA), strideB = (uint32_t)Tb * (uint32_t)sizeof(PB);
     // lane offsets: the trajectory and the first step of this lane's part
     const uint32_t t0 = (uint32_t)(part * chunk);
-    uint32_t oa[RI], ob[RJ];
-#pragma unroll
-    for (int r = 0; r < RI; ++r) oa[r] = (uint32_t)ia[r] * (uint32_t)sizeof(PA) + t0 * strideA;
-#pragma unroll
-    for (int s = 0; s < RJ; ++s) ob[s] = (uint32_t)jb[s] * (uint32_t)sizeof(PB) + t0 * strideB;
     int first[RI][RJ];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
 #pragma unroll
         for (int s = 0; s < RJ; ++s) first[r][s] = -1;
 
-    for (int t = chunk - 1; t >= 0; --t) {
-        const uint32_t sa = (uint32_t)t * strideA, sb = (uint32_t)t * strideB;
-        PA a[RI];
-        PB b[RJ];
+    if constexpr (STAGE) {
+        if (stage) {
+            // the block's 8 item rows give 8 * RI trajectories of a (entry
+            // r * 8 + row), its 8 columns 8 * RJ of b (entry s * 8 + column)
+            constexpr int NA = 8 * RI, NB = 8 * RJ;
+            __shared__ PA stage_a[WG / WAVE][NA];
+            __shared__ PB stage_b[WG / WAVE][NB];
+            const int w = (int)(threadIdx.x / WAVE);
+            const int ka = lane % NA, kb = lane % NB;
+            const uint32_t la = (uint32_t)min(ig0 + (ka & 7) + (ka >> 3) * n_ig, Ta - 1) * (uint32_t)sizeof(PA);
+            const uint32_t lb = (uint32_t)min(jg0 + (kb & 7) + (kb >> 3) * n_jg, Tb - 1) * (uint32_t)sizeof(PB);
+            const int row = e >> 3, col = e & 7;
+            PA ga = load_pose<PA>(A, la, (uint32_t)(chunk - 1) * strideA);
+            PB gb = load_pose<PB>(B, lb, (uint32_t)(chunk - 1) * strideB);
+            for (int t = chunk - 1; t >= 0; --t) {
+                if (lane < NA) stage_a[w][lane] = Prep<Check>::a(ga);
+                if (lane < NB) stage_b[w][lane] = Prep<Check>::b(gb);
+                // a wave's LDS operations complete in order; keep the
+                // compiler from moving the reads above the writes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (t > 0) {
+                    ga = load_pose<PA>(A, la, (uint32_t)(t - 1) * strideA);
+                    gb = load_pose<PB>(B, lb, (uint32_t)(t - 1) * strideB);
+                }
+                PA a[RI];
+                PB b[RJ];
 #pragma unroll
-        for (int r = 0; r < RI; ++r) a[r] = Prep<Check>::a(load_pose<PA>(A, oa[r], sa));
+                for (int r = 0; r < RI; ++r) a[r] = stage_a[w][r * 8 + row];
 #pragma unroll
-        for (int s = 0; s < RJ; ++s) b[s] = Prep<Check>::b(load_pose<PB>(B, ob[s], sb));
+                for (int s = 0; s < RJ; ++s) b[s] = stage_b[w][s * 8 + col];
 #pragma unroll
-        for (int r = 0; r < RI; ++r)
+                for (int r = 0; r < RI; ++r)
 #pragma unroll
-            for (int s = 0; s < RJ; ++s)
-                if (chk(a[r], b[s])) first[r][s] = t;
+                    for (int s = 0; s < RJ; ++s)
+                        if (chk(a[r], b[s])) first[r][s] = t;
+                // and the next step's writes below this step's reads
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (!live) return;
+        }
+    }
+    if (!stage) {
+        uint32_t oa[RI], ob[RJ];
+#pragma unroll
+        for (int r = 0; r < RI; ++r) oa[r] = (uint32_t)ia[r] * (uint32_t)sizeof(PA) + t0 * strideA;
+#pragma unroll
+        for (int s = 0; s < RJ; ++s) ob[s] = (uint32_t)jb[s] * (uint32_t)sizeof(PB) + t0 * strideB;
+        for (int t = chunk - 1; t >= 0; --t) {
+            const uint32_t sa = (uint32_t)t * strideA, sb = (uint32_t)t * strideB;
+            PA a[RI];
+            PB b[RJ];
+#pragma unroll
+            for (int r = 0; r < RI; ++r) a[r] = Prep<Check>::a(load_pose<PA>(A, oa[r], sa));
+#pragma unroll
+            for (int s = 0; s < RJ; ++s) b[s] = Prep<Check>::b(load_pose<PB>(B, ob[s], sb));
+#pragma unroll
+            for (int r = 0; r < RI; ++r)
+#pragma unroll
+                for (int s = 0; s < RJ; ++s)
+                    if (chk(a[r], b[s])) first[r][s] = t;
+        }
     }
     if (tshift) {
         // the earliest hit over the parts: parts hold consecutive step ranges,
@@ -856,7 +931,7 @@ __device__ __forceinline__ void stage_polygons(DPoly *slot, const DPoly *__restr
 // a launch uses the smallest family that covers its pairs.
 // TL: whether it can add to per-slot sums (time-resolved scenes); likewise
 // kept out of the instances that launches without such scenes use.
-template <int V, int FAM, bool TL>
+template <int V, int FAM, bool TL, bool STAGE = false>
 __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const char *__restrict__ poses,
                                              int16_t *__restrict__ hits, const unsigned long long *__restrict__ pfix,
                                              unsigned long long *__restrict__ qacc,
@@ -914,19 +989,19 @@ __device__ __forceinline__ void collide_work(const DPair &pr, int item0, const c
     }
     switch (pr.cls) {
     case CLS_VV:
-        collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, TL, float4, float4>(
+        collide_items<kTiles[V][CLS_VV].ri, kTiles[V][CLS_VV].rj, TL, float4, float4, CheckVV, STAGE>(
             pr, item0, poses, hits, pfix, qacc, hist, CheckVV{pr.la, pr.wa, pr.lb, pr.wb});
         break;
     case CLS_VP:
-        collide_items<kTiles[V][CLS_VP].ri, kTiles[V][CLS_VP].rj, TL, float4, float2>(
+        collide_items<kTiles[V][CLS_VP].ri, kTiles[V][CLS_VP].rj, TL, float4, float2, CheckVP, STAGE>(
             pr, item0, poses, hits, pfix, qacc, hist, CheckVP{pr.la, pr.wa, pr.rr});
         break;
     case CLS_PV:
-        collide_items<kTiles[V][CLS_PV].ri, kTiles[V][CLS_PV].rj, TL, float2, float4>(
+        collide_items<kTiles[V][CLS_PV].ri, kTiles[V][CLS_PV].rj, TL, float2, float4, CheckPV, STAGE>(
             pr, item0, poses, hits, pfix, qacc, hist, CheckPV{pr.lb, pr.wb, pr.rr});
         break;
     default:
-        collide_items<kTiles[V][CLS_PP].ri, kTiles[V][CLS_PP].rj, TL, float2, float2>(
+        collide_items<kTiles[V][CLS_PP].ri, kTiles[V][CLS_PP].rj, TL, float2, float2, CheckPP, STAGE>(
             pr, item0, poses, hits, pfix, qacc, hist, CheckPP{pr.rr});
         break;
     }
@@ -950,7 +1025,7 @@ constexpr int kCollideMinWaves = FAM == FAM_PLAIN ? 5 : FAM == FAM_PIP ? 4 : 1;
 // A launch may run one part of the plan (part of n_parts): every wave then
 // takes only its units [U part / n_parts, U (part + 1) / n_parts) of the U
 // units of its segments, so that n_parts launches cover each unit once.
-template <int V, int FAM, bool TL>
+template <int V, int FAM, bool TL, bool STAGE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinWaves<FAM>))) void k2_collide(const DPair *__restrict__ pairs, const WorkItem *__restrict__ work,
                                                  const int32_t *__restrict__ bins, int n_bins, int xcd_major,
                                                  const char *__restrict__ poses, int16_t *__restrict__ hits,
@@ -991,7 +1066,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinW
         if (poly && pr.cls >= CLS_GG) stage_polygons(lp, polys, pr);
         const int per = WAVE >> pr.tshift;
         for (int u = u0; u < u1; ++u)
-            collide_work<V, FAM, TL>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, lp);
+            collide_work<V, FAM, TL, STAGE>(pr, w.item0 + u * per, poses, hits, pfix, qacc, hist, lp);
     }
 }
 
@@ -1404,18 +1479,22 @@ __global__ __launch_bounds__(WG) void k4_timeline(const DObj *__restrict__ objs,
 hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k1_trajgen, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p, L.pfix, L.qacc,
-                       L.done, L.hist);
+    if (L.one_track)
+        hipLaunchKernelGGL(k1_trajgen<true>, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
+                           L.pfix, L.qacc, L.done, L.hist);
+    else
+        hipLaunchKernelGGL(k1_trajgen<false>, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
+                           L.pfix, L.qacc, L.done, L.hist);
     return hipGetLastError();
 }
 
-template <int V, int FAM, bool TL>
+template <int V, int FAM, bool TL, bool STAGE>
 static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
     const int parts = L.collide_parts > 1 ? L.collide_parts : 1;
     for (int part = 0; part < parts; ++part) {
-        hipLaunchKernelGGL((k2_collide<V, FAM, TL>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins,
+        hipLaunchKernelGGL((k2_collide<V, FAM, TL, STAGE>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins,
                            L.n_bins, L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys, part, parts);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -1423,40 +1502,43 @@ static hipError_t launch_k2(const Launch &L, hipStream_t s)
     return hipSuccess;
 }
 
-template <int V, int FAM, bool TL>
+template <int V, int FAM, bool TL, bool STAGE>
 static int k2_resident_blocks()
 {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, FAM, TL>, WG, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k2_collide<V, FAM, TL, STAGE>, WG, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     return per_cu;
 }
 
-// The kernel instance of (variant, class family, per-slot sums):
-// F::run<V, FAM, TL>() is called for the instance.
-template <int FAM, bool TL, class F>
+// The kernel instance of (variant, class family, per-slot sums, LDS-staged
+// blocks): F::run<V, FAM, TL, STAGE>() is called for the instance. Staged
+// instances exist for the plain family without per-slot sums only.
+template <int FAM, bool TL, bool STAGE, class F>
 static auto with_variant(int variant, const F &f)
 {
     switch (variant) {
-    case 0: return f.template run<0, FAM, TL>();
-    case 1: return f.template run<1, FAM, TL>();
-    case 2: return f.template run<2, FAM, TL>();
-    default: return f.template run<3, FAM, TL>();
+    case 0: return f.template run<0, FAM, TL, STAGE>();
+    case 1: return f.template run<1, FAM, TL, STAGE>();
+    case 2: return f.template run<2, FAM, TL, STAGE>();
+    default: return f.template run<3, FAM, TL, STAGE>();
     }
 }
 
 template <int FAM, class F>
 static auto with_timeline(int variant, bool tl, const F &f)
 {
-    return tl ? with_variant<FAM, true>(variant, f) : with_variant<FAM, false>(variant, f);
+    return tl ? with_variant<FAM, true, false>(variant, f) : with_variant<FAM, false, false>(variant, f);
 }
 
 template <class F>
-static auto with_instance(int variant, int family, bool tl, const F &f)
+static auto with_instance(int variant, int family, bool tl, bool stage, const F &f)
 {
     switch (family) {
-    case FAM_PLAIN: return with_timeline<FAM_PLAIN>(variant, tl, f);
+    case FAM_PLAIN:
+        if (stage && !tl) return with_variant<FAM_PLAIN, false, true>(variant, f);
+        return with_timeline<FAM_PLAIN>(variant, tl, f);
     case FAM_PIP: return with_timeline<FAM_PIP>(variant, tl, f);
     default: return with_timeline<FAM_POLY>(variant, tl, f);
     }
@@ -1465,13 +1547,13 @@ static auto with_instance(int variant, int family, bool tl, const F &f)
 struct LaunchK2 {
     const Launch &L;
     hipStream_t s;
-    template <int V, int FAM, bool TL>
-    hipError_t run() const { return launch_k2<V, FAM, TL>(L, s); }
+    template <int V, int FAM, bool TL, bool STAGE>
+    hipError_t run() const { return launch_k2<V, FAM, TL, STAGE>(L, s); }
 };
 
 struct ResidentK2 {
-    template <int V, int FAM, bool TL>
-    int run() const { return k2_resident_blocks<V, FAM, TL>(); }
+    template <int V, int FAM, bool TL, bool STAGE>
+    int run() const { return k2_resident_blocks<V, FAM, TL, STAGE>(); }
 };
 
 hipError_t launch_collide(const Launch &L, hipStream_t s)
@@ -1479,12 +1561,12 @@ hipError_t launch_collide(const Launch &L, hipStream_t s)
     if (L.n_work <= 0) return hipSuccess;
     if (L.variant < 0 || L.variant >= N_VARIANTS || L.family < FAM_PLAIN || L.family > FAM_POLY)
         return hipErrorInvalidValue;
-    return with_instance(L.variant, L.family, L.timeline != 0, LaunchK2{L, s});
+    return with_instance(L.variant, L.family, L.timeline != 0, L.stage != 0, LaunchK2{L, s});
 }
 
-int collide_blocks_per_cu(int variant, int family, bool timeline)
+int collide_blocks_per_cu(int variant, int family, bool timeline, bool stage)
 {
-    return with_instance(variant, family, timeline, ResidentK2{});
+    return with_instance(variant, family, timeline, stage, ResidentK2{});
 }
 
 // ===========================================================================

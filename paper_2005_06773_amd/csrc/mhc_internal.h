@@ -190,6 +190,8 @@ struct Launch {
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int collide_parts;            // the collision plan runs as this many launches (0 or 1: one)
+    int one_track;                // some object follows the one-track model (heavier trajectory kernel)
+    int stage;                    // collision instance that stages 8 x 8 item blocks in LDS
     int variant;
     int family;                   // ClassFamily covering every pair of the launch
 };
@@ -206,7 +208,7 @@ constexpr int kMaxDevices = 64;
 // calling thread); looked up once per device, then cached.
 hipError_t noalloc_scratch_address(int device, char **out);
 // resident workgroups per CU of the collision kernel for a variant, class
-// family, with or without the per-slot sums
-int collide_blocks_per_cu(int variant, int family, bool timeline);
+// family, with or without the per-slot sums, with or without LDS-staged blocks
+int collide_blocks_per_cu(int variant, int family, bool timeline, bool stage);
 
 }  // namespace mhc

@@ -268,7 +268,21 @@ static void reset_layout(Layout &L)
     L = std::move(fresh);
 }
 
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits)
+static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L,
+                              bool with_hits);
+
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits,
+                  int max_waves_staged)
+{
+    build_layout_once(scenes, n_scenes, variant, max_waves, L, with_hits);
+    const bool stage = L.family == FAM_PLAIN && !L.timeline && max_waves > 0 && L.staged_share >= 0.5;
+    if (stage && max_waves_staged > 0 && max_waves_staged != max_waves)
+        build_layout_once(scenes, n_scenes, variant, max_waves_staged, L, with_hits);
+    L.stage = stage;
+}
+
+static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L,
+                              bool with_hits)
 {
     reset_layout(L);
     L.variant = variant;
@@ -312,6 +326,7 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
             d.risk = s.risk;
             d.timeline = s.timeline;
             d.model = o.model;
+            L.one_track |= o.model == MHC_MODEL_ONE_TRACK;
             if (s.timeline) {
                 int W = 1;
                 while (W < n) W <<= 1;
@@ -437,11 +452,14 @@ void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_wa
 
     // Collision plan: every wave slot gets a list of segments of work units.
     int64_t n_units = 0;
-    double total_cost = 0.0;
+    double total_cost = 0.0, staged_cost = 0.0;
     for (const PairCost &pc : costs) {
         n_units += pc.n_units;
         total_cost += pc.c * pc.n_units;
+        const DPair &pr = L.pairs[pc.pidx];
+        if (pr.bshift == 3 && pr.tshift == 0) staged_cost += pc.c * pc.n_units;
     }
+    L.staged_share = total_cost > 0.0 ? staged_cost / total_cost : 0.0;
     const int n_bins = (int)std::max<int64_t>(1, std::min<int64_t>(n_units, max_waves > 0 ? max_waves : n_units));
     L.work.clear();
     L.bins.assign(n_bins + 1, 0);
@@ -718,6 +736,8 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.obj_crit = reinterpret_cast<double *>(base + L.o_oc);
     if (!keep_hits || !L.with_hits) X.hits = nullptr;
     X.timeline = L.timeline ? 1 : 0;
+    X.one_track = L.one_track ? 1 : 0;
+    X.stage = L.stage ? 1 : 0;
     if (L.timeline) {
         X.hist = reinterpret_cast<unsigned long long *>(base + L.o_hist);
         X.att_w = reinterpret_cast<double *>(base + L.o_attw);
@@ -839,11 +859,19 @@ int mhc_ctx::max_waves(int v, const mhc_scene *scenes, int n)
     return max_waves_of(v, fam, tl != 0);
 }
 
-int mhc_ctx::max_waves_of(int v, int fam, bool tl)
+int mhc_ctx::max_waves_staged(int v, const mhc_scene *scenes, int n)
+{
+    for (int k = 0; k < n; ++k)
+        if (scene_family(&scenes[k]) != FAM_PLAIN || scenes[k].timeline) return 0;
+    return max_waves_of(v, FAM_PLAIN, false, true);
+}
+
+int mhc_ctx::max_waves_of(int v, int fam, bool tl, bool stage)
 {
     if (v < 0 || v >= N_VARIANTS) v = 0;
-    int &w = waves_cache[v][fam][tl ? 1 : 0];
-    if (!w) w = n_cu * collide_blocks_per_cu(v, fam, tl) * (WG / WAVE);
+    stage = stage && fam == FAM_PLAIN && !tl;
+    int &w = waves_cache[v][fam][tl ? 1 : 0][stage ? 1 : 0];
+    if (!w) w = n_cu * collide_blocks_per_cu(v, fam, tl, stage) * (WG / WAVE);
     return w;
 }
 
@@ -1022,7 +1050,7 @@ static bool layout_for(mhc_ctx *ctx, const mhc_scene *scene, Layout &L, bool wit
         fill_values(scene, 1, L);
         return true;
     }
-    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, with_hits);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, with_hits, ctx->max_waves_staged(v, scene, 1));
     ctx->layout_shape = std::move(shape);
     return false;
 }
@@ -1306,7 +1334,8 @@ extern "C" mhc_status mhc_evaluate_async(mhc_ctx *ctx, const mhc_scene *scene, v
     }
     if (!validate_scene(scene, ctx->err) || !validate_outputs(scene, dev_out, ctx->err)) return MHC_E_INVAL;
     Layout L;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), L, true);
+    const int v = ctx->variant_for(scene, 1);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, true, ctx->max_waves_staged(v, scene, 1));
     if (workspace_bytes < L.total_bytes) {
         ctx->err = "workspace too small: need " + std::to_string(L.total_bytes) + " bytes";
         return MHC_E_INVAL;
@@ -1333,7 +1362,7 @@ extern "C" mhc_status mhc_evaluate_noalloc(mhc_ctx *ctx, const mhc_scene *scene,
     // the first hits go to dev_out->first_hit only, so the array holds none
     Layout &L = ctx->noalloc_layout;
     const int v = ctx->variant_for(scene, 1);
-    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, false);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), L, false, ctx->max_waves_staged(v, scene, 1));
     if (L.total_bytes > kNoallocBytes) {
         ctx->err = "scene needs " + std::to_string(L.total_bytes) + " workspace bytes, above MHC_NOALLOC_MAX_BYTES (" +
                    std::to_string(kNoallocBytes) + ")";
@@ -1449,8 +1478,8 @@ extern "C" mhc_status mhc_plan_create(mhc_ctx *ctx, const mhc_scene *scene, mhc_
     HIPC(hipSetDevice(ctx->device));
     mhc_plan *pl = new mhc_plan();
     pl->ctx = ctx;
-    build_layout(scene, 1, ctx->variant_for(scene, 1), ctx->max_waves(ctx->variant_for(scene, 1), scene, 1), pl->L,
-                 true);
+    const int v = ctx->variant_for(scene, 1);
+    build_layout(scene, 1, v, ctx->max_waves(v, scene, 1), pl->L, true, ctx->max_waves_staged(v, scene, 1));
     pl->shape = shape_of(scene);
     pl->flags = *scene;
     pl->flags.objects = nullptr;
@@ -1487,7 +1516,8 @@ extern "C" mhc_status mhc_plan_update(mhc_plan *pl, const mhc_scene *scene)
     }
     HIPC(hipSetDevice(ctx->device));
     Layout L;
-    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant, scene, 1), L, true);
+    build_layout(scene, 1, pl->L.variant, ctx->max_waves(pl->L.variant, scene, 1), L, true,
+                 ctx->max_waves_staged(pl->L.variant, scene, 1));
     std::vector<char> img(L.image_bytes);
     pack_image(L, img.data());
     HIPC(hipDeviceSynchronize());
@@ -1611,7 +1641,7 @@ mhc_status batch_run(mhc_ctx *ctx, int n, const mhc_scene *scenes, mhc_result *r
     bool keep = false;
     for (int k = 0; k < n; ++k) keep |= res[k].first_hit != nullptr;
     const int v = ctx->variant_for(scenes, n);
-    build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, keep);
+    build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, keep, ctx->max_waves_staged(v, scenes, n));
     mhc_status st = ensure_device(ctx, L.total_bytes);
     if (st != MHC_OK) return st;
     char *dbase = static_cast<char *>(ctx->dbuf);

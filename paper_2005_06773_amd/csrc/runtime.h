@@ -61,6 +61,9 @@ struct Layout {
     bool contiguous = false;      // collision plan of contiguous stretches
     int family = 0;               // ClassFamily covering every pair
     bool with_hits = true;        // the workspace holds the first-hit matrix
+    bool one_track = false;       // some object follows the one-track model
+    bool stage = false;           // the collision launch uses the LDS-staged instance
+    double staged_share = 0.0;    // share of the collision cost in 8 x 8 blocks without a time split
 };
 
 // Instantiated HIP graphs keyed by what their launch sequence depends on.
@@ -99,7 +102,12 @@ bool scene_has_outline(const mhc_scene *s);
 // The class family a scene needs (ClassFamily).
 int scene_family(const mhc_scene *s);
 // max_waves: resident waves of the collision kernel (0 = one per work unit).
-void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits);
+// When the plan's 8 x 8 item blocks without a time split carry at least half
+// its cost (plain class family, no risk over time), the launch uses the
+// collision instance that stages them in LDS, and the plan is made for that
+// instance's resident waves, max_waves_staged (0: the same as max_waves).
+void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits,
+                  int max_waves_staged = 0);
 
 // The host side of the results of the n scenes of a layout: per output, the
 // workspace range [lo, hi) of every requested part and, where staged, its
@@ -167,11 +175,13 @@ struct mhc_ctx {
     mhc::GraphCache batch_graphs;                 // mhc_evaluate_batch, keyed by batch shape
     mhc::Tuning tune;
     int variant_for(const mhc_scene *scenes, int n) const { return tune.variant_for(scenes, n); }
-    int waves_cache[mhc::N_VARIANTS][3][2] = {};  // [variant][class family][time-resolved]
+    int waves_cache[mhc::N_VARIANTS][3][2][2] = {};  // [variant][class family][time-resolved][staged]
     // resident waves on this GPU of the collision kernel that `scenes` need
+    // (of its LDS-staged instance: max_waves_staged, 0 where there is none)
     int max_waves(int variant, const mhc_scene *scenes, int n);
-    // the same for a variant, class family and time-resolved flag
-    int max_waves_of(int variant, int family, bool timeline);
+    int max_waves_staged(int variant, const mhc_scene *scenes, int n);
+    // the same for a variant, class family, time-resolved flag and staging
+    int max_waves_of(int variant, int family, bool timeline, bool stage = false);
 };
 
 // Autotuning class of a launch: log2 of the mean trajectory count, log2 of

@@ -20,7 +20,8 @@
 // ahead of a large frame that waits for a slot. Frames of either kind keep
 // their arrival order among themselves. On the GPU such a tick's collision
 // plan runs as several launches of at most about max_checks_per_tick checks
-// each, between which the other slots' kernels reach the GPU.
+// each, planned for 4/5 of the resident waves, so that the other slots'
+// kernels find room on every CU beside it and between its launches.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -138,6 +139,7 @@ public:
     int64_t max_checks_per_tick = 0;
     Tuning tune;
     int waves[N_VARIANTS][3][2] = {};
+    int waves_staged[N_VARIANTS] = {};   // of the LDS-staged instances (plain family, no per-slot sums)
     std::vector<TickSlot> slots;
 
     int max_waves(int v, const mhc_scene *scenes, int n) const
@@ -159,8 +161,24 @@ public:
         const int n = (int)scenes.size();
         const int v = tune.variant_for(scenes.data(), n);
         bool keep_hits = false;
-        for (auto &f : frames) keep_hits |= f->dst.first_hit != nullptr;
-        build_layout(scenes.data(), n, v, max_waves(v, scenes.data(), n), t.L, keep_hits);
+        int64_t checks = 0;
+        for (auto &f : frames) {
+            keep_hits |= f->dst.first_hit != nullptr;
+            checks += f->checks;
+        }
+        // a tick above the check cap (one large frame) plans its collision
+        // work for 4/5 of the resident waves, so that every CU keeps room
+        // for the other slots' kernels while it runs
+        const bool large = checks > max_checks_per_tick;
+        int waves_v = max_waves(v, scenes.data(), n);
+        bool plain = true;
+        for (int k = 0; k < n; ++k) plain &= scene_family(&scenes[k]) == FAM_PLAIN && !scenes[k].timeline;
+        int waves_s = plain ? waves_staged[v] : 0;
+        if (large) {
+            waves_v = std::max(1, waves_v / 5 * 4);
+            waves_s = waves_s / 5 * 4;
+        }
+        build_layout(scenes.data(), n, v, waves_v, t.L, keep_hits, waves_s);
         if (t.L.total_bytes > t.dbytes) {  // the admission bound excludes this
             err = "tick workspace above the slot's share of the budget";
             return MHC_E_NOMEM;
@@ -181,7 +199,7 @@ public:
         // a tick above the check cap (one large frame) runs its collision
         // plan as launches of at most about that many checks each, so that
         // the other slots' ticks get the GPU in between
-        if (t.L.n_checks > max_checks_per_tick)
+        if (large)
             X.collide_parts = (int)std::min<int64_t>(64, (t.L.n_checks + max_checks_per_tick - 1) / max_checks_per_tick);
         if (e == hipSuccess) e = launch_all(X, t.stream);
         if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
@@ -576,6 +594,7 @@ extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, 
     for (int v = 0; v < N_VARIANTS; ++v)
         for (int fam = 0; fam < 3; ++fam)
             for (int tl = 0; tl < 2; ++tl) ex->waves[v][fam][tl] = ctx->max_waves_of(v, fam, tl != 0);
+    for (int v = 0; v < N_VARIANTS; ++v) ex->waves_staged[v] = ctx->max_waves_of(v, FAM_PLAIN, false, true);
     ex->slots.resize(c.max_inflight_ticks);
     for (auto &t : ex->slots) {
         if (hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking) != hipSuccess ||

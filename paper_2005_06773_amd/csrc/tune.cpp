@@ -82,7 +82,7 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
     mhc_status st = MHC_OK;
     for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
         Layout L;
-        build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, false);
+        build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, false, ctx->max_waves_staged(v, scenes, n));
         st = ensure_device(ctx, L.total_bytes);
         if (st != MHC_OK) break;
         char *base = static_cast<char *>(ctx->dbuf);

@@ -128,7 +128,9 @@ def _load():
     # One HIP runtime per process: torch ships its own copy of libamdhip64.so.7.
     # Loading torch first makes this library bind to that same copy, so device
     # pointers and streams created by torch are valid here.
-    if not os.environ.get("MHC_LIB_PATH"):
+    # (MHC_NO_TORCH=1: a process that never touches a GPU, such as the CPU
+    # tests under a sanitizer, does without)
+    if os.environ.get("MHC_NO_TORCH") != "1":
         try:
             import torch  # noqa: F401
         except ImportError:

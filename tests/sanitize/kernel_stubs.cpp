@@ -10,7 +10,7 @@ namespace mhc {
 hipError_t launch_trajgen(const Launch &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_collide(const Launch &, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_risk(const Launch &, hipStream_t) { return hipErrorNoDevice; }
-int collide_blocks_per_cu(int, int, bool) { return 1; }
+int collide_blocks_per_cu(int, int, bool, bool) { return 1; }
 hipError_t noalloc_scratch_address(int, char **out)
 {
     *out = nullptr;

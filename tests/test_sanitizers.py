@@ -38,6 +38,7 @@ def _run(kind: str, env_extra: dict, tests, tmp_path):
     report = str(tmp_path / f"{kind}_report")
     env = dict(os.environ)
     env.update(env_extra)
+    env["MHC_NO_TORCH"] = "1"
     env["LD_PRELOAD"] = sb.runtime_library(kind)
     opts = f"halt_on_error=1:log_path={report}"
     if kind == "asan":

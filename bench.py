@@ -170,6 +170,43 @@ def timeline_extra(mhc, ctx, sg, torch, steps=50):
     return {"rows": rows, "approach": appr}
 
 
+def streams_extra(mhc, ctx, cs, checks, ref_out, steps, torch):
+    """Whole-path steps of the timed scene issued round-robin on S streams,
+    each with a plan (workspace) and outputs of its own, S = 1 .. 4: the
+    steps of one stream run in order, those of different streams overlap, so
+    one step's trajectory and risk stages and its collision kernel's tail
+    share the GPU with the others' collision kernels. Every stream's results
+    are checked bit for bit against the headline run's. Reported beside the
+    headline value, which issues one step at a time."""
+    import numpy as np
+    ref = {k: (None if v is None else v.cpu().numpy()) for k, v in ref_out.items()}
+    K = max(steps, 60)
+    rows = []
+    for S in (1, 2, 3, 4):
+        plans = [mhc.mhc_plan_create(ctx, cs) for _ in range(S)]
+        outs = [mhc.device_result(cs, first_hit=True, q=True) for _ in range(S)]
+        streams = [torch.cuda.current_stream()] if S == 1 else [torch.cuda.Stream() for _ in range(S)]
+        for k in range(4 * S):
+            mhc.mhc_plan_execute(plans[k % S], outs[k % S][1], streams[k % S])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(K):
+            mhc.mhc_plan_execute(plans[k % S], outs[k % S][1], streams[k % S])
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / K
+        for o, _ in outs:
+            for key in ("first_hit", "object_crit", "traj_crit", "traj_prob", "q"):
+                if ref.get(key) is not None:
+                    assert np.array_equal(o[key].cpu().numpy(), ref[key]), f"stream results differ: {key}"
+        for pl in plans:
+            pl.close()
+        rows.append({"streams": S, "us_per_step": us, "checks_per_s": checks / (us * 1e-6), "steps": K})
+        log(f"{S} stream(s), a plan each: {us:.1f} us per step -> {checks / (us * 1e-6):.4g} checks/s "
+            f"(results identical)")
+    return {"rows": rows, "note": "steps issued round-robin on S streams, one plan and output set per "
+                                  "stream; every step a whole pass; results bitwise equal to the headline's"}
+
+
 def polygon_flops(ka: int, kb: int, circle: bool) -> int:
     """Algorithmic FP32 work of one polygon test (FMA = 2, compare 1).
     Polygon-polygon (both modes): offset 2, relative rotation 6, both centres
@@ -326,7 +363,7 @@ def class_checks(scene):
 
 
 # Measurements after the timed workload, in this order (--extras).
-EXTRAS = ("latency", "batched", "served", "table_one", "timeline", "polygons", "models", "stress")
+EXTRAS = ("latency", "streams", "batched", "served", "table_one", "timeline", "polygons", "models", "stress")
 
 # Timed workloads: the 11-object scene is the headline; the Table I S2
 # configuration (Sec. VI-B) can be timed the same way in either overlap mode.
@@ -825,6 +862,14 @@ def main():
     cls, flops = class_checks(scene)
     assert sum(cls.values()) == checks
 
+    # Set-up that leaves the GPU idle (torch's first allocations and kernels)
+    # comes before the autotune, so that the warm-up steps follow the
+    # autotune's launches directly: after tens of milliseconds of idling the
+    # collision kernel takes ~15 ms of continuous launches to come back to
+    # its steady duration (38.5 -> 34.4 us on the 11-object scene).
+    out, r = mhc.device_result(cs, first_hit=True, q=True)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
     ctx = mhc.mhc_create(0)
     if args.variant >= 0:
         mhc.mhc_set_variant(ctx, args.variant)
@@ -834,10 +879,9 @@ def main():
         best, us = mhc.mhc_autotune(ctx, cs, reps=20)
         tune = {"chosen": best, "us_per_variant": [round(u, 2) for u in us]}
         variant = best
-        log(f"autotune: collision kernel us per variant {[round(u, 1) for u in us]} -> variant {best}")
     plan = mhc.mhc_plan_create(ctx, cs)
-    out, r = mhc.device_result(cs, first_hit=True, q=True)
-    stream = torch.cuda.current_stream()
+    if args.variant < 0:
+        log(f"autotune: collision kernel us per variant {[round(u, 1) for u in us]} -> variant {best}")
     T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
 
     if args.calibrate_copy:
@@ -954,6 +998,8 @@ def main():
         result["plain_latency_ms"] = {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat),
                                       "note": "mhc_evaluate, host scene in, host criticality out (PCIe included)"}
         log(f"plain end-to-end latency p50 {pct(lat, 50):.3f} ms p99 {pct(lat, 99):.3f} ms")
+    if "streams" in extras:
+        result["streams"] = streams_extra(mhc, ctx, cs, checks, out, args.steps, torch)
     if "batched" in extras:
         # Batched vs plain loop over the same 64 scenes; the batch's tile
         # variant is autotuned on the batch itself first.

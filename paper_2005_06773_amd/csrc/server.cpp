@@ -104,29 +104,43 @@ public:
 // One slot of the GPU executor.
 struct TickSlot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;          // the tick's results are in pinned memory
+    hipEvent_t kernels_done = nullptr;  // a large tick's kernels have ended
+    bool copies_pending = false;        // a large tick's result copies are not yet enqueued
     char *dbuf = nullptr;
     size_t dbytes = 0;
     char *pin_in = nullptr;
     size_t pin_in_bytes = 0;
     char *pin_out = nullptr;
     size_t pin_out_bytes = 0;
+    // staging buffers outgrown by a later tick, freed when the server stops:
+    // hipHostFree waits for every stream of the device, so freeing them here
+    // would hold the scheduler thread until the other slots' ticks end
+    std::vector<char *> retired;
     Layout L;
     int n_frames = 0;
     std::vector<mhc_result> dsts;  // per frame: its host buffers
     ResultPlan results;            // the tick's outputs staged in pin_out
 };
 
-hipError_t grow_pinned(char **p, size_t *have, size_t want)
+// Pinned staging per slot and direction from the start: a tick of small
+// frames (tens of scenes of the batched size mix) fits without growing it.
+constexpr size_t kInitialStaging = (size_t)4 << 20;
+
+// Grows a pinned staging buffer to hold `want` bytes, at least doubling it,
+// so that a slot's buffers are replaced a logarithmic number of times and
+// the retired ones total less than the live one.
+hipError_t grow_pinned(char **p, size_t *have, size_t want, std::vector<char *> &retired)
 {
     if (*have >= want) return hipSuccess;
-    if (*p) (void)hipHostFree(*p);
-    *p = nullptr;
-    *have = 0;
-    const size_t sz = std::max(want + want / 4, (size_t)1 << 20);
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(p), sz, hipHostMallocDefault);
-    if (e == hipSuccess) *have = sz;
-    return e;
+    const size_t sz = std::max({want, 2 * *have, (size_t)1 << 20});
+    char *fresh = nullptr;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&fresh), sz, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    if (*p) retired.push_back(*p);
+    *p = fresh;
+    *have = sz;
+    return hipSuccess;
 }
 
 // The library's own executor: ticks on the GPU of a context. The context's
@@ -183,14 +197,14 @@ public:
             err = "tick workspace above the slot's share of the budget";
             return MHC_E_NOMEM;
         }
-        hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes);
+        hipError_t e = grow_pinned(&t.pin_in, &t.pin_in_bytes, t.L.image_bytes, t.retired);
         t.n_frames = n;
         t.dsts.clear();
         for (auto &f : frames) t.dsts.push_back(f->dst);
         // every output of the tick in one transfer per output region, staged
         // in pinned memory so that nothing blocks the scheduler thread
         t.results = plan_results(t.L, n, t.dsts.data(), true);
-        if (e == hipSuccess) e = grow_pinned(&t.pin_out, &t.pin_out_bytes, t.results.staged);
+        if (e == hipSuccess) e = grow_pinned(&t.pin_out, &t.pin_out_bytes, t.results.staged, t.retired);
         if (e == hipSuccess) {
             pack_image(t.L, t.pin_in);
             e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
@@ -202,8 +216,17 @@ public:
         if (large)
             X.collide_parts = (int)std::min<int64_t>(64, (t.L.n_checks + max_checks_per_tick - 1) / max_checks_per_tick);
         if (e == hipSuccess) e = launch_all(X, t.stream);
-        if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
-        if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
+        // A large tick's result copies are enqueued only once its kernels
+        // have ended (poll): a copy enqueued now would wait for them at the
+        // head of a copy engine's queue, where the image and result copies of
+        // the other slots' ticks would wait behind it for the whole frame.
+        t.copies_pending = large;
+        if (large) {
+            if (e == hipSuccess) e = hipEventRecord(t.kernels_done, t.stream);
+        } else {
+            if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
+            if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
+        }
         if (e != hipSuccess) {
             err = std::string("tick launch failed: ") + hipGetErrorString(e);
             return MHC_E_DEVICE;
@@ -214,6 +237,19 @@ public:
     int poll(int slot, std::string &err) override
     {
         TickSlot &t = slots[slot];
+        if (t.copies_pending) {
+            const hipError_t k = hipEventQuery(t.kernels_done);
+            if (k == hipErrorNotReady) return 0;
+            hipError_t e = k;
+            if (e == hipSuccess)
+                e = enqueue_results(t.results, t.L, t.n_frames, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
+            if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
+            if (e != hipSuccess) {
+                err = std::string("tick failed: ") + hipGetErrorString(e);
+                return -1;
+            }
+            t.copies_pending = false;
+        }
         const hipError_t q = hipEventQuery(t.done);
         if (q == hipErrorNotReady) return 0;
         if (q != hipSuccess) {
@@ -232,7 +268,9 @@ public:
             if (t.dbuf) (void)hipFree(t.dbuf);
             if (t.pin_in) (void)hipHostFree(t.pin_in);
             if (t.pin_out) (void)hipHostFree(t.pin_out);
+            for (char *r : t.retired) (void)hipHostFree(r);
             if (t.done) (void)hipEventDestroy(t.done);
+            if (t.kernels_done) (void)hipEventDestroy(t.kernels_done);
             if (t.stream) (void)hipStreamDestroy(t.stream);
         }
         slots.clear();
@@ -599,7 +637,10 @@ extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, 
     for (auto &t : ex->slots) {
         if (hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&t.done, hipEventDisableTiming) != hipSuccess ||
-            hipMalloc(reinterpret_cast<void **>(&t.dbuf), srv->slot_bytes) != hipSuccess) {
+            hipEventCreateWithFlags(&t.kernels_done, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc(reinterpret_cast<void **>(&t.dbuf), srv->slot_bytes) != hipSuccess ||
+            grow_pinned(&t.pin_in, &t.pin_in_bytes, kInitialStaging, t.retired) != hipSuccess ||
+            grow_pinned(&t.pin_out, &t.pin_out_bytes, kInitialStaging, t.retired) != hipSuccess) {
             ctx->err = "server: cannot create streams or reserve the HBM budget";
             ex->shutdown();
             delete srv;

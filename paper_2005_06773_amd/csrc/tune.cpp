@@ -1,6 +1,8 @@
 // Autotuning of the collision kernel's micro-tile shape: every compiled
 // variant is timed on a scene (or a batch of scenes in one launch) and the
 // fastest is kept per size class.
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -67,55 +69,114 @@ extern "C" mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant)
 
 // Times the collision launch of every variant on the n scenes (one launch
 // for all of them, as mhc_evaluate_batch makes it) and records the fastest
-// for their size class.
+// for their size class. The variants are timed in interleaved rounds (each
+// round launches every variant once, back to back), each variant on an
+// image of its own, so that a change of clock or temperature during the
+// tuning weighs on every variant alike. Round 0 warms up; after `reps`
+// timed rounds the rounds go on while the fastest variant's median over the
+// last `reps` rounds is still falling (by more than 1 % from the `reps`
+// rounds before), for at most 0.5 s of tuning and 20 reps rounds: a GPU
+// that idled before the tuning runs its first milliseconds of launches at a
+// lower clock, and a variant's time is its median over the last reps
+// rounds. Where the variants' images do not fit in device memory together,
+// the rounds take one variant at a time in the context workspace.
 static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int32_t reps, int32_t *best_variant,
                               double *us)
 {
     HIPC(hipSetDevice(ctx->device));
     ctx->resident_image.clear();  // the timing launches overwrite the context workspace
     ctx->layout_shape.clear();
-    hipEvent_t e0, e1;
-    HIPC(hipEventCreate(&e0));
-    HIPC(hipEventCreate(&e1));
+    std::vector<Layout> Ls(N_VARIANTS);
+    std::vector<size_t> off(N_VARIANTS);
+    size_t total = 0;
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), Ls[v], false, ctx->max_waves_staged(v, scenes, n));
+        off[v] = total;
+        total += (Ls[v].total_bytes + 255) & ~(size_t)255;
+    }
+    char *own = nullptr;
+    const bool together = (!ctx->budget || total <= ctx->budget) &&
+                          hipMalloc(reinterpret_cast<void **>(&own), total) == hipSuccess;
+    if (!together) (void)hipGetLastError();  // a failed allocation leaves the one-at-a-time path
+    std::vector<std::vector<float>> ms(N_VARIANTS);
+    std::vector<hipEvent_t> ev(2 * N_VARIANTS, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    auto window_median = [&](int v, size_t end) {  // of rounds [end - reps, end) of variant v
+        std::vector<float> w(ms[v].begin() + (end - reps), ms[v].begin() + end);
+        std::sort(w.begin(), w.end());
+        const size_t k = w.size();
+        return k % 2 ? (double)w[k / 2] : 0.5 * ((double)w[k / 2 - 1] + (double)w[k / 2]);
+    };
+    auto run_rounds = [&](int v0, int v1, char *const *bases) {
+        std::vector<Launch> X;
+        for (int v = v0; v < v1; ++v) X.push_back(make_launch(Ls[v], bases[v], nullptr, false, ctx->n_cu));
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; e == hipSuccess; ++r) {
+            for (int v = v0; v < v1 && e == hipSuccess; ++v) {
+                const Launch &L = X[v - v0];
+                e = launch_trajgen(L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ev[2 * v], ctx->stream);
+                if (e == hipSuccess) e = launch_collide(L, ctx->stream);
+                if (e == hipSuccess) e = hipEventRecord(ev[2 * v + 1], ctx->stream);
+            }
+            if (e == hipSuccess) e = hipEventSynchronize(ev[2 * (v1 - 1) + 1]);
+            for (int v = v0; v < v1 && e == hipSuccess; ++v) {
+                float t = 0.f;
+                e = hipEventElapsedTime(&t, ev[2 * v], ev[2 * v + 1]);
+                if (r > 0) ms[v].push_back(t);  // round 0 warms up
+            }
+            if (e != hipSuccess || r < reps) continue;  // r timed rounds so far
+            const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (r >= 20 * reps || secs >= 0.5) break;
+            if (r < 2 * reps) continue;  // two windows to compare
+            int fast = v0;
+            for (int v = v0; v < v1; ++v)
+                if (window_median(v, ms[v].size()) < window_median(fast, ms[fast].size())) fast = v;
+            const size_t end = ms[fast].size();
+            if (window_median(fast, end) > 0.99 * window_median(fast, end - reps)) break;
+        }
+    };
+    mhc_status st = MHC_OK;
+    char *bases[N_VARIANTS] = {};
+    if (e == hipSuccess && together) {
+        for (int v = 0; v < N_VARIANTS && e == hipSuccess; ++v) {
+            std::vector<char> img(Ls[v].image_bytes);
+            pack_image(Ls[v], img.data());
+            bases[v] = own + off[v];
+            e = hipMemcpy(bases[v], img.data(), Ls[v].image_bytes, hipMemcpyHostToDevice);
+        }
+        run_rounds(0, N_VARIANTS, bases);
+    } else {
+        for (int v = 0; v < N_VARIANTS && e == hipSuccess && st == MHC_OK; ++v) {
+            st = ensure_device(ctx, Ls[v].total_bytes);
+            if (st != MHC_OK) break;
+            std::vector<char> img(Ls[v].image_bytes);
+            pack_image(Ls[v], img.data());
+            bases[v] = static_cast<char *>(ctx->dbuf);
+            e = hipMemcpy(bases[v], img.data(), Ls[v].image_bytes, hipMemcpyHostToDevice);
+            if (e == hipSuccess) run_rounds(v, v + 1, bases);
+        }
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (own) (void)hipFree(own);
+    if (st != MHC_OK) return st;
+    if (e != hipSuccess) {
+        ctx->err = std::string("autotune launch: ") + hipGetErrorString(e);
+        return MHC_E_DEVICE;
+    }
     int best = -1;
     double best_us = 0.0;
-    mhc_status st = MHC_OK;
-    for (int v = 0; v < N_VARIANTS && st == MHC_OK; ++v) {
-        Layout L;
-        build_layout(scenes, n, v, ctx->max_waves(v, scenes, n), L, false, ctx->max_waves_staged(v, scenes, n));
-        st = ensure_device(ctx, L.total_bytes);
-        if (st != MHC_OK) break;
-        char *base = static_cast<char *>(ctx->dbuf);
-        std::vector<char> img(L.image_bytes);
-        pack_image(L, img.data());
-        hipError_t e = hipMemcpy(base, img.data(), L.image_bytes, hipMemcpyHostToDevice);
-        Launch X = make_launch(L, base, nullptr, false, ctx->n_cu);
-        double total_ms = 0.0;
-        for (int r = 0; r <= reps && e == hipSuccess; ++r) {
-            e = launch_trajgen(X, ctx->stream);
-            if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
-            if (e == hipSuccess) e = launch_collide(X, ctx->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (r > 0) total_ms += ms;  // launch 0 warms up
-        }
-        if (e != hipSuccess) {
-            ctx->err = std::string("autotune launch: ") + hipGetErrorString(e);
-            st = MHC_E_DEVICE;
-            break;
-        }
-        const double t = total_ms * 1e3 / reps;
+    for (int v = 0; v < N_VARIANTS; ++v) {
+        const double t = 1e3 * window_median(v, ms[v].size());
         if (us) us[v] = t;
         if (best < 0 || t < best_us) {
             best = v;
             best_us = t;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != MHC_OK) return st;
     ctx->tune.tuned[size_class(scenes, n)] = best;
     if (best_variant) *best_variant = best;
     return MHC_OK;

@@ -281,6 +281,31 @@ def test_plan_and_async_match_evaluate(mhc, ctx):
     plan.close()
 
 
+def test_plans_on_concurrent_streams(mhc, ctx):
+    """Steps of three plans (different scenes, each with its own workspace and
+    outputs) issued round-robin on three streams overlap on the GPU; every
+    plan's results equal the scene evaluated alone, after each round."""
+    import torch
+    scenes = [sg.eleven_object_scene(1), sg.eleven_object_scene(2), sg.paper_scene(5, n_co=3)]
+    say("three plans on three streams, 4 rounds")
+    refs = [mhc.mhc_evaluate(ctx, s) for s in scenes]
+    plans = [mhc.mhc_plan_create(ctx, s) for s in scenes]
+    outs = [mhc.device_result(mhc.CScene(s)) for s in scenes]
+    streams = [torch.cuda.Stream() for _ in scenes]
+    try:
+        for rnd in range(4):
+            for _ in range(3):
+                for k in range(len(scenes)):
+                    mhc.mhc_plan_execute(plans[k], outs[k][1], streams[k])
+            torch.cuda.synchronize()
+            for k, (o, _) in enumerate(outs):
+                got = {key: (None if v is None else v.cpu().numpy()) for key, v in o.items()}
+                parity.same_results(refs[k], got, f"plan {k}, round {rnd}")
+    finally:
+        for pl in plans:
+            pl.close()
+
+
 @pytest.fixture(scope="module")
 def batch64(mhc, ctx):
     """The 64-scene batch workload evaluated in one batched call."""

@@ -70,7 +70,8 @@ extern "C" mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant)
 // Times the collision launch of every variant on the n scenes (one launch
 // for all of them, as mhc_evaluate_batch makes it) and records the fastest
 // for their size class. The variants are timed in interleaved rounds (each
-// round launches every variant once, back to back), each variant on an
+// round launches every variant in turn, kBackToBack collision launches
+// each), each variant on an
 // image of its own, so that a change of clock or temperature during the
 // tuning weighs on every variant alike. Round 0 warms up; after `reps`
 // timed rounds the rounds go on while the fastest variant's median over the
@@ -80,6 +81,11 @@ extern "C" mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant)
 // lower clock, and a variant's time is its median over the last reps
 // rounds. Where the variants' images do not fit in device memory together,
 // the rounds take one variant at a time in the context workspace.
+// Collision launches per variant and round, back to back between two events:
+// an event pair around a single launch adds the launch's start-up to it, and
+// more so, and unevenly between variants, under a kernel-tracing profiler.
+constexpr int kBackToBack = 2;
+
 static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int32_t reps, int32_t *best_variant,
                               double *us)
 {
@@ -118,14 +124,14 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
                 const Launch &L = X[v - v0];
                 e = launch_trajgen(L, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(ev[2 * v], ctx->stream);
-                if (e == hipSuccess) e = launch_collide(L, ctx->stream);
+                for (int b = 0; b < kBackToBack && e == hipSuccess; ++b) e = launch_collide(L, ctx->stream);
                 if (e == hipSuccess) e = hipEventRecord(ev[2 * v + 1], ctx->stream);
             }
             if (e == hipSuccess) e = hipEventSynchronize(ev[2 * (v1 - 1) + 1]);
             for (int v = v0; v < v1 && e == hipSuccess; ++v) {
                 float t = 0.f;
                 e = hipEventElapsedTime(&t, ev[2 * v], ev[2 * v + 1]);
-                if (r > 0) ms[v].push_back(t);  // round 0 warms up
+                if (r > 0) ms[v].push_back(t / kBackToBack);  // round 0 warms up
             }
             if (e != hipSuccess || r < reps) continue;  // r timed rounds so far
             const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

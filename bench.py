@@ -949,12 +949,11 @@ def main():
         f"({k2_bracketed_ms * 1e3:.1f} us bracketed per launch) -> {achieved:.2f} TFLOP/s "
         f"({checks / (k2_ms / 1e3):.4g} checks/s)")
 
-    # VALU instructions per check in the inner loops (26 rect-rect: 25 per test
-    # and 4 per prepared rectangle pose shared by 4 rows; 13 rect-circle: 12
-    # per test and 4 per rectangle pose shared by 4 circles; 6 circle-circle;
-    # 60 point-in-polygon; first-hit bookkeeping included) against the
-    # lane-op rate.
-    lane_ops = 26 * cls["VV"] + 13 * cls["VP"] + 6 * cls["PP"] + 60 * cls["VV_PIP"]
+    # VALU instructions per check in the inner loops (25 rect-rect, 12
+    # rect-circle, 6 circle-circle, 60 point-in-polygon; first-hit bookkeeping
+    # included; the rectangle's own frame comes from the trajectory kernel)
+    # against the lane-op rate.
+    lane_ops = 25 * cls["VV"] + 12 * cls["VP"] + 6 * cls["PP"] + 60 * cls["VV_PIP"]
     result = {
         "metric": f"pose-pair checks/sec ({label})",
         "value": value,

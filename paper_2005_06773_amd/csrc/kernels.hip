@@ -107,6 +107,24 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
     if (tid == 0) done[obj] = 0u;
 }
 
+// A vehicle pose (x, y, cos, sin) in its own frame: K = (x cos + y sin,
+// y cos - x sin) is its centre there, and (K_x, K_y, cos, sin) is what the
+// rectangle tests take for the rectangle they measure in its frame. The
+// trajectory kernel writes it beside the pose (the object's frame block), in
+// FP32 from the stored FP32 pose, so that no test prepares it again.
+__device__ __forceinline__ float4 rect_frame(const float4 P)
+{
+    return make_float4(fmaf(P.x, P.z, P.y * P.w), fmaf(P.y, P.z, -(P.x * P.w)), P.z, P.w);
+}
+
+// Stores vehicle pose n of trajectory i and its frame form.
+__device__ __forceinline__ void store_vehicle_pose(char *__restrict__ poses, const DObj &o, int n, int i, const float4 P)
+{
+    const size_t k = (size_t)n * o.T + i;
+    reinterpret_cast<float4 *>(poses + o.pose_off)[k] = P;
+    reinterpret_cast<float4 *>(poses + o.frame_off)[k] = rect_frame(P);
+}
+
 // Vehicle trajectory i on the linear one-track model (Sec. IV-B.1): side slip
 // beta and yaw rate r obey
 //   beta' = -(cf+cr)/(m v) beta + ((cr lr - cf lf)/(m v^2) - 1) r + cf/(m v) delta
@@ -163,7 +181,6 @@ __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, c
     // state at the chunk's first step
     double cx = o.x, cy = o.y, cpsi = o.heading, cbeta = 0.0, crate = 0.0, csp, ccp;
     sincos(cpsi, &csp, &ccp);
-    float4 *out = reinterpret_cast<float4 *>(poses + o.pose_off);
     for (int n0 = 0; n0 < o.H; n0 += 64) {
         const int n = n0 + lane;
         const bool active = n < o.H;
@@ -248,7 +265,7 @@ __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, c
         const double ay = sb * vdot + cb * v * (beta_dot + r);
         const double x1 = cx + scan_add(active ? cpb * v * tau + cp * ax * h2 - sp * ay * h2 : 0.0, lane);
         const double y1 = cy + scan_add(active ? spb * v * tau + sp * ax * h2 + cp * ay * h2 : 0.0, lane);
-        if (active) out[(size_t)n * o.T + i] = make_float4((float)x1, (float)y1, (float)cp1, (float)sp1);
+        if (active) store_vehicle_pose(poses, o, n, i, make_float4((float)x1, (float)y1, (float)cp1, (float)sp1));
         cx = __shfl(x1, 63, 64);
         cy = __shfl(y1, 63, 64);
         cpsi = __shfl(psi1, 63, 64);
@@ -369,8 +386,7 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
         const double x = cx + dx, y = cy + dy;
         if (active) {
             if (vehicle)
-                reinterpret_cast<float4 *>(poses + o.pose_off)[(size_t)n * o.T + i] =
-                    make_float4((float)x, (float)y, c_next, s_next);
+                store_vehicle_pose(poses, o, n, i, make_float4((float)x, (float)y, c_next, s_next));
             else
                 reinterpret_cast<float2 *>(poses + o.pose_off)[(size_t)n * o.T + i] = make_float2((float)x, (float)y);
         }
@@ -395,22 +411,16 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
 // against the other rectangle (the paper's test, both ways).
 // ===========================================================================
 
-// A rectangle's pose (x, y, cos, sin) prepared for tests in its frame: K =
-// (x cos + y sin, y cos - x sin) is its centre in its own frame.
-__device__ __forceinline__ float4 rect_frame(const float4 P)
-{
-    return make_float4(fmaf(P.x, P.z, P.y * P.w), fmaf(P.y, P.z, -(P.x * P.w)), P.z, P.w);
-}
 
 // Rectangle-rectangle (separating axes). With C = u_P.u_Q and S = v_P.u_Q
 // (so u_P = C u_Q - S v_Q, v_P = S u_Q + C v_Q) and d = c_Q - c_P, the
 // rectangles overlap iff
 //   |d.u_P| <= lP + lQ|C| + wQ|S|,   |d.v_P| <= wP + lQ|S| + wQ|C|,
 //   |d.u_Q| <= lQ + lP|C| + wP|S|,   |d.v_Q| <= wQ + lP|S| + wP|C|.
-// Q's pose is prepared once per step (rect_frame: K = c_Q in its own frame),
+// Q's pose comes in its own frame (its object's frame block: K = c_Q there),
 // so d.u_Q = K.x - (x_P cos_Q + y_P sin_Q) and d.v_Q = K.y - (y_P cos_Q - x_P
 // sin_Q) are two FMA chains each, and d.u_P, d.v_P follow from them by the
-// rotation (C, S): 25 VALU per test and 4 per prepared pose.
+// rotation (C, S): 25 VALU per test.
 struct CheckVV {
     float lP, wP, lQ, wQ;
     __device__ __forceinline__ bool operator()(const float4 P, const float4 Qk) const
@@ -437,8 +447,8 @@ struct CheckVV {
 // |x| <= lP and |y| <= wP. The corners of P in Q's frame follow with the roles
 // swapped; flipping both signs of a corner leaves |x| and |y| unchanged, so
 // they are (d.u_Q + al*lP*C + be*wP*S, d.v_Q - al*lP*S + be*wP*C).
-// Q's pose is prepared once per step (rect_frame) and the projections are
-// formed as in the separating-axes test.
+// Q's pose comes in its own frame and the projections are formed as in the
+// separating-axes test.
 struct CheckVVPip {
     float lP, wP, lQ, wQ;
     __device__ __forceinline__ bool operator()(const float4 P, const float4 Qk) const
@@ -472,12 +482,11 @@ struct CheckVVPip {
 // Rectangle-circle: the circle centre Q in P's frame is (lam, mu) =
 // ((Q - c_P) . u_P, (Q - c_P) . v_P), and the two overlap iff the distance
 // from Q to the rectangle, sqrt(max(|lam| - l, 0)^2 + max(|mu| - w, 0)^2), is
-// at most r. The rectangle's pose is prepared once per step (rect_frame): K =
-// (x_P cos + y_P sin, y_P cos - x_P sin) is c_P in its own frame, so
+// at most r. The rectangle's pose comes in its own frame (its object's frame
+// block): K = (x_P cos + y_P sin, y_P cos - x_P sin) is c_P there, so
 //   (lam, mu) = (x_Q cos + y_Q sin - K.x, y_Q cos - x_Q sin - K.y)
-// (two FMA chains each), and the circles paired with one rectangle pose skip
-// the difference Q - c_P: 12 VALU per test and 4 per prepared pose. Every
-// tile computes each test with the same operations, so results do not
+// (two FMA chains each) without the difference Q - c_P: 12 VALU per test.
+// Every tile computes each test with the same operations, so results do not
 // depend on the tile.
 __device__ __forceinline__ bool rect_circle(const float4 Pk, const float2 Q, float lP, float wP, float rr)
 {
@@ -488,50 +497,14 @@ __device__ __forceinline__ bool rect_circle(const float4 Pk, const float2 Q, flo
     return fmaf(ex, ex, ey * ey) <= rr;
 }
 
-struct CheckVP {  // a: the rectangle, prepared
+struct CheckVP {  // a: the rectangle, in its own frame
     float lP, wP, rr;
     __device__ __forceinline__ bool operator()(const float4 Pk, const float2 Q) const { return rect_circle(Pk, Q, lP, wP, rr); }
 };
 
-struct CheckPV {  // b: the rectangle, prepared
+struct CheckPV {  // b: the rectangle, in its own frame
     float lQ, wQ, rr;
     __device__ __forceinline__ bool operator()(const float2 P, const float4 Qk) const { return rect_circle(Qk, P, lQ, wQ, rr); }
-};
-
-// Per-pose preparation before the tests of a step, once per loaded pose and
-// shared by all tests of that pose: the identity, except for the second
-// rectangle of a rectangle-rectangle pair and the rectangle of a
-// rectangle-circle pair (rect_frame).
-template <class C>
-struct Prep {
-    template <class P>
-    __device__ __forceinline__ static P a(const P p) { return p; }
-    template <class P>
-    __device__ __forceinline__ static P b(const P p) { return p; }
-};
-
-template <>
-struct Prep<CheckVV> {
-    __device__ __forceinline__ static float4 a(const float4 p) { return p; }
-    __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
-};
-
-template <>
-struct Prep<CheckVVPip> {
-    __device__ __forceinline__ static float4 a(const float4 p) { return p; }
-    __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
-};
-
-template <>
-struct Prep<CheckVP> {
-    __device__ __forceinline__ static float4 a(const float4 p) { return rect_frame(p); }
-    __device__ __forceinline__ static float2 b(const float2 p) { return p; }
-};
-
-template <>
-struct Prep<CheckPV> {
-    __device__ __forceinline__ static float2 a(const float2 p) { return p; }
-    __device__ __forceinline__ static float4 b(const float4 p) { return rect_frame(p); }
 };
 
 struct CheckPP {
@@ -688,8 +661,8 @@ __device__ __forceinline__ float2 load_pose<float2>(__amdgpu_buffer_rsrc_t r, ui
 
 // STAGE: the instance stages the poses of 8 x 8 item blocks in LDS (units of
 // 2-D blocks without a time split): per step, the wave loads each distinct
-// pose of its block once (lane k the k-th pose of either object), prepares it
-// once, and every lane then reads its tile's poses from LDS. The tests and
+// pose of its block once (lane k the k-th pose of either object) into LDS,
+// and every lane then reads its tile's poses from there. The tests and
 // their results are those of the unstaged loop; only where the poses come
 // from differs. Each step's loads are issued before the previous step's tests.
 template <int RI, int RJ, bool TL, class PA, class PB, class Check, bool STAGE = false>
@@ -777,8 +750,8 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
             PA ga = load_pose<PA>(A, la, (uint32_t)(chunk - 1) * strideA);
             PB gb = load_pose<PB>(B, lb, (uint32_t)(chunk - 1) * strideB);
             for (int t = chunk - 1; t >= 0; --t) {
-                if (lane < NA) stage_a[w][lane] = Prep<Check>::a(ga);
-                if (lane < NB) stage_b[w][lane] = Prep<Check>::b(gb);
+                if (lane < NA) stage_a[w][lane] = ga;
+                if (lane < NB) stage_b[w][lane] = gb;
                 // a wave's LDS operations complete in order; keep the
                 // compiler from moving the reads above the writes
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -818,9 +791,9 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
             PA a[RI];
             PB b[RJ];
 #pragma unroll
-            for (int r = 0; r < RI; ++r) a[r] = Prep<Check>::a(load_pose<PA>(A, oa[r], sa));
+            for (int r = 0; r < RI; ++r) a[r] = load_pose<PA>(A, oa[r], sa);
 #pragma unroll
-            for (int s = 0; s < RJ; ++s) b[s] = Prep<Check>::b(load_pose<PB>(B, ob[s], sb));
+            for (int s = 0; s < RJ; ++s) b[s] = load_pose<PB>(B, ob[s], sb);
 #pragma unroll
             for (int r = 0; r < RI; ++r)
 #pragma unroll

@@ -57,6 +57,8 @@ struct DObj {
     int64_t traj_off;             // index of trajectory 0 in the p / traj_crit arrays
     int64_t q_row;                // q index of (this object, i = 0, b = 0)
     int64_t pose_off;             // byte offset of the pose block [H][T]
+    int64_t frame_off;            // vehicles: byte offset of the block [H][T] of the same poses in
+                                  // their own frame, (K_x, K_y, cos, sin) with K = c in that frame
     int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
     int64_t part_off;             // first partial sum of the risk kernel's chunks
     int64_t obj_out;              // index in the object_crit array
@@ -80,7 +82,8 @@ struct DPair {
     int32_t Ta, Tb;
     int32_t n_ig, n_jg;
     int64_t hit_off;              // first-hit entry of (i = 0, j = 0)
-    int64_t pose_a, pose_b;       // byte offsets of the two pose blocks
+    int64_t pose_a, pose_b;       // byte offsets of the two pose blocks (a rectangle whose tests take
+                                  // its pose in its own frame: the object's frame block)
     float la, wa, lb, wb;         // half length / half width of vehicles
     float rr;                     // squared test radius: r_Q^2 (rect-circle), (r_P + r_Q)^2 (circle-circle)
     int32_t qn;                   // q row stride: object count of the scene

@@ -48,7 +48,7 @@ int scene_family(const mhc_scene *s)
 
 // Relative VALU cost of one check per class, for longest-first ordering; the
 // polygon classes scale with the vertex counts (class_cost).
-static const double kClsCost[N_CLS] = {26.0, 13.0, 13.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
+static const double kClsCost[N_CLS] = {25.0, 12.0, 12.0, 6.4, 60.0, 0.0, 0.0, 0.0, 0.0};
 
 double class_cost(int cls, int k_a, int k_b)
 {
@@ -346,6 +346,11 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
             d.q_row = L.n_q + toff * n;
             d.pose_off = (int64_t)L.pose_bytes;
             L.pose_bytes += align256((size_t)s.horizon * d.T * (o.kind == MHC_VEHICLE ? 16 : 8));
+            d.frame_off = -1;
+            if (o.kind == MHC_VEHICLE) {
+                d.frame_off = (int64_t)L.pose_bytes;
+                L.pose_bytes += align256((size_t)s.horizon * d.T * 16);
+            }
             d.u_off = (int64_t)L.vals.size();
             d.w_off = d.u_off + o.n_u;
             d.score_off = d.w_off + o.n_w;
@@ -388,8 +393,12 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
             pr.n_ig = (pr.Ta + ts.ri - 1) / ts.ri;
             pr.n_jg = (pr.Tb + ts.rj - 1) / ts.rj;
             pr.hit_off = L.n_hits + hoff;
-            pr.pose_a = L.objs[obj_base + a].pose_off;
-            pr.pose_b = L.objs[obj_base + b].pose_off;
+            // the rectangle-rectangle tests take b's pose in b's frame, the
+            // rectangle-circle tests the rectangle's (frame blocks)
+            const bool frame_a = pr.cls == CLS_VP;
+            const bool frame_b = pr.cls == CLS_VV || pr.cls == CLS_VV_PIP || pr.cls == CLS_PV;
+            pr.pose_a = frame_a ? L.objs[obj_base + a].frame_off : L.objs[obj_base + a].pose_off;
+            pr.pose_b = frame_b ? L.objs[obj_base + b].frame_off : L.objs[obj_base + b].pose_off;
             pr.qn = n;
             pr.qa0 = L.objs[obj_base + a].q_row + b;
             pr.qb0 = L.objs[obj_base + b].q_row + a;
@@ -440,12 +449,9 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
         const int ka = pr.poly_a >= 0 ? pair_vertices[2 * pidx] : 0, kb = pr.poly_b >= 0 ? pair_vertices[2 * pidx + 1] : 0;
         // a wave executes every step of every test of a unit, whether or
         // not all of its lanes hold an item
-        // rectangle-rectangle and rectangle-circle tests: 25 and 12 VALU each
-        // plus 4 per prepared rectangle pose
-        const double per_test = pr.cls == CLS_VV   ? 25.0 + 4.0 / ts.ri
-                                : pr.cls == CLS_VP ? 12.0 + 4.0 / ts.rj
-                                : pr.cls == CLS_PV ? 12.0 + 4.0 / ts.ri
-                                                   : class_cost(pr.cls, ka, kb);
+        // (rectangle-rectangle and rectangle-circle tests: 25 and 12 VALU each,
+        // the rectangle's frame read ready from its frame block)
+        const double per_test = class_cost(pr.cls, ka, kb);
         const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * per_test + kUnitOverhead;
         costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)pair_units(pr, sh, pr.bshift)});
     }

@@ -551,3 +551,52 @@ def test_repeated_shape_reuses_resident_plan(mhc, ctx):
         else:
             parity.same_results(mhc.mhc_evaluate(ctx, scenes[k]), fresh(scenes[k]), f"11-object seed {11 + k}")
 
+
+
+def test_repeated_batch_shape_reuses_its_layout(mhc, ctx):
+    """Batches of one shape (same scenes' object kinds and grids, new
+    positions, speeds and controls) keep the batch layout and upload only the
+    image's value part; a single-scene call, a batch of another shape, a
+    change of the first-hit request or an autotune run in between rebuild it.
+    Every batch must equal a fresh context's batch, bit for bit, scene by
+    scene, for several rounds (the third repeat of a shape replays a captured
+    graph)."""
+    import copy
+    base = sg.batch_scenes(2, 12)
+
+    def moved(scenes, k):
+        out = copy.deepcopy(scenes)
+        rng = np.random.default_rng(100 + k)
+        for sc in out:
+            for o in sc.objects:
+                o.x += float(rng.uniform(-3, 3))
+                o.y += float(rng.uniform(-3, 3))
+                o.speed = max(0.0, o.speed + float(rng.uniform(-1, 1)))
+                o.u = o.u * float(rng.uniform(0.9, 1.1))
+        return out
+
+    def fresh(scenes, first_hit):
+        c = mhc.mhc_create(0)
+        try:
+            return mhc.mhc_evaluate_batch(c, scenes, first_hit=first_hit)
+        finally:
+            mhc.mhc_destroy(c)
+
+    steps = [("batch", 0, True), ("batch", 1, True), ("batch", 2, True), ("batch", 3, True),
+             ("single", None, True), ("batch", 4, True), ("batch", 5, False), ("batch", 6, False),
+             ("other", None, True), ("batch", 7, False), ("autotune", None, True), ("batch", 8, False),
+             ("batch", 9, True)]
+    for what, k, fh in steps:
+        say(f"repeated batch shape: {what} {k} first_hit={fh}")
+        if what == "single":
+            mhc.mhc_evaluate(ctx, sg.eleven_object_scene(3))
+        elif what == "other":
+            mhc.mhc_evaluate_batch(ctx, sg.batch_scenes(5, 6), first_hit=False)
+        elif what == "autotune":
+            mhc.mhc_autotune_batch(ctx, base, reps=1)
+        else:
+            scenes = moved(base, k)
+            got = mhc.mhc_evaluate_batch(ctx, scenes, first_hit=fh)
+            want = fresh(scenes, fh)
+            for i, (g, w) in enumerate(zip(got, want)):
+                parity.same_results(g, w, f"batch round {k}, scene {i}")

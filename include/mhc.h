@@ -300,18 +300,18 @@ void mhc_plan_destroy(mhc_plan *plan);
  * many trajectories of each object one GPU thread pairs up). Results are
  * bit-identical for every variant; only speed differs.
  * mhc_set_variant forces one (-1 returns to the tuned choice).
- * mhc_autotune times every variant on `scene` in interleaved rounds (the
+ * mhc_autotune times every variant on `scene` in interleaved passes (the
  * variants in turn, two collision launches back to back each, every variant
  * on an image of its own when all fit in device memory, else one variant at
- * a time): a warm-up round, `reps` timed rounds, and further rounds while
- * the fastest variant's median over the last `reps` rounds still falls by
+ * a time): a warm-up pass, `reps` timed passes, and further passes while
+ * the fastest variant's median over the last `reps` passes still falls by
  * more than 1 % (a GPU coming out of idle raises its clock over the first
- * milliseconds), up to 20 reps rounds or 0.5 s. It records the fastest for
+ * milliseconds), up to 20 reps passes or 0.5 s. It records the fastest for
  * scenes of the same size class: log2 buckets of the mean trajectory count
  * per object and of the mean horizon, the test family (0 rectangles and
  * circles, 1 point-in-polygon rectangles, 2 outlines) and a log2 bucket of
  * the scene count (0 for one scene). `us` (or NULL) receives each variant's
- * median microseconds per collision launch over the last `reps` rounds
+ * median microseconds per collision launch over the last `reps` passes
  * (host array of MHC_N_VARIANTS). reps in [1, 100000], else MHC_E_INVAL.
  * mhc_autotune_batch does the same for n scenes evaluated together
  * as mhc_evaluate_batch launches them (one collision launch for all), so

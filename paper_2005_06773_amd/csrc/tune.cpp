@@ -69,19 +69,19 @@ extern "C" mhc_status mhc_set_variant(mhc_ctx *ctx, int32_t variant)
 
 // Times the collision launch of every variant on the n scenes (one launch
 // for all of them, as mhc_evaluate_batch makes it) and records the fastest
-// for their size class. The variants are timed in interleaved rounds (each
-// round launches every variant in turn, kBackToBack collision launches
+// for their size class. The variants are timed in interleaved passes (each
+// pass launches every variant in turn, kBackToBack collision launches
 // each), each variant on an
 // image of its own, so that a change of clock or temperature during the
-// tuning weighs on every variant alike. Round 0 warms up; after `reps`
-// timed rounds the rounds go on while the fastest variant's median over the
-// last `reps` rounds is still falling (by more than 1 % from the `reps`
-// rounds before), for at most 0.5 s of tuning and 20 reps rounds: a GPU
+// tuning weighs on every variant alike. Pass 0 warms up; after `reps`
+// timed passes the passes go on while the fastest variant's median over the
+// last `reps` passes is still falling (by more than 1 % from the `reps`
+// passes before), for at most 0.5 s of tuning and 20 reps passes: a GPU
 // that idled before the tuning runs its first milliseconds of launches at a
 // lower clock, and a variant's time is its median over the last reps
-// rounds. Where the variants' images do not fit in device memory together,
-// the rounds take one variant at a time in the context workspace.
-// Collision launches per variant and round, back to back between two events:
+// passes. Where the variants' images do not fit in device memory together,
+// the passes take one variant at a time in the context workspace.
+// Collision launches per variant and pass, back to back between two events:
 // an event pair around a single launch adds the launch's start-up to it, and
 // more so, and unevenly between variants, under a kernel-tracing profiler.
 constexpr int kBackToBack = 2;
@@ -109,13 +109,13 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
     hipError_t e = hipSuccess;
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
-    auto window_median = [&](int v, size_t end) {  // of rounds [end - reps, end) of variant v
+    auto window_median = [&](int v, size_t end) {  // of passes [end - reps, end) of variant v
         std::vector<float> w(ms[v].begin() + (end - reps), ms[v].begin() + end);
         std::sort(w.begin(), w.end());
         const size_t k = w.size();
         return k % 2 ? (double)w[k / 2] : 0.5 * ((double)w[k / 2 - 1] + (double)w[k / 2]);
     };
-    auto run_rounds = [&](int v0, int v1, char *const *bases) {
+    auto run_passes = [&](int v0, int v1, char *const *bases) {
         std::vector<Launch> X;
         for (int v = v0; v < v1; ++v) X.push_back(make_launch(Ls[v], bases[v], nullptr, false, ctx->n_cu));
         const auto t0 = std::chrono::steady_clock::now();
@@ -131,9 +131,9 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
             for (int v = v0; v < v1 && e == hipSuccess; ++v) {
                 float t = 0.f;
                 e = hipEventElapsedTime(&t, ev[2 * v], ev[2 * v + 1]);
-                if (r > 0) ms[v].push_back(t / kBackToBack);  // round 0 warms up
+                if (r > 0) ms[v].push_back(t / kBackToBack);  // pass 0 warms up
             }
-            if (e != hipSuccess || r < reps) continue;  // r timed rounds so far
+            if (e != hipSuccess || r < reps) continue;  // r timed passes so far
             const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (r >= 20 * reps || secs >= 0.5) break;
             if (r < 2 * reps) continue;  // two windows to compare
@@ -153,7 +153,7 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
             bases[v] = own + off[v];
             e = hipMemcpy(bases[v], img.data(), Ls[v].image_bytes, hipMemcpyHostToDevice);
         }
-        run_rounds(0, N_VARIANTS, bases);
+        run_passes(0, N_VARIANTS, bases);
     } else {
         for (int v = 0; v < N_VARIANTS && e == hipSuccess && st == MHC_OK; ++v) {
             st = ensure_device(ctx, Ls[v].total_bytes);
@@ -162,7 +162,7 @@ static mhc_status tune_scenes(mhc_ctx *ctx, int n, const mhc_scene *scenes, int3
             pack_image(Ls[v], img.data());
             bases[v] = static_cast<char *>(ctx->dbuf);
             e = hipMemcpy(bases[v], img.data(), Ls[v].image_bytes, hipMemcpyHostToDevice);
-            if (e == hipSuccess) run_rounds(v, v + 1, bases);
+            if (e == hipSuccess) run_passes(v, v + 1, bases);
         }
     }
     for (auto &x : ev)

@@ -284,10 +284,10 @@ def test_plan_and_async_match_evaluate(mhc, ctx):
 def test_plans_on_concurrent_streams(mhc, ctx):
     """Steps of three plans (different scenes, each with its own workspace and
     outputs) issued round-robin on three streams overlap on the GPU; every
-    plan's results equal the scene evaluated alone, after each round."""
+    plan's results equal the scene evaluated alone, after each pass."""
     import torch
     scenes = [sg.eleven_object_scene(1), sg.eleven_object_scene(2), sg.paper_scene(5, n_co=3)]
-    say("three plans on three streams, 4 rounds")
+    say("three plans on three streams, 4 passes")
     refs = [mhc.mhc_evaluate(ctx, s) for s in scenes]
     plans = [mhc.mhc_plan_create(ctx, s) for s in scenes]
     outs = [mhc.device_result(mhc.CScene(s)) for s in scenes]
@@ -300,7 +300,7 @@ def test_plans_on_concurrent_streams(mhc, ctx):
             torch.cuda.synchronize()
             for k, (o, _) in enumerate(outs):
                 got = {key: (None if v is None else v.cpu().numpy()) for key, v in o.items()}
-                parity.same_results(refs[k], got, f"plan {k}, round {rnd}")
+                parity.same_results(refs[k], got, f"plan {k}, pass {rnd}")
     finally:
         for pl in plans:
             pl.close()
@@ -559,7 +559,7 @@ def test_repeated_batch_shape_reuses_its_layout(mhc, ctx):
     image's value part; a single-scene call, a batch of another shape, a
     change of the first-hit request or an autotune run in between rebuild it.
     Every batch must equal a fresh context's batch, bit for bit, scene by
-    scene, for several rounds (the third repeat of a shape replays a captured
+    scene, for several passes (the third repeat of a shape replays a captured
     graph)."""
     import copy
     base = sg.batch_scenes(2, 12)
@@ -599,4 +599,4 @@ def test_repeated_batch_shape_reuses_its_layout(mhc, ctx):
             got = mhc.mhc_evaluate_batch(ctx, scenes, first_hit=fh)
             want = fresh(scenes, fh)
             for i, (g, w) in enumerate(zip(got, want)):
-                parity.same_results(g, w, f"batch round {k}, scene {i}")
+                parity.same_results(g, w, f"batch pass {k}, scene {i}")

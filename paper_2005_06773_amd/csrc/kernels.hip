@@ -1466,7 +1466,10 @@ static hipError_t launch_k2(const Launch &L, hipStream_t s)
 {
     const int blocks = (L.n_bins + WG / WAVE - 1) / (WG / WAVE);
     const int parts = L.collide_parts > 1 ? L.collide_parts : 1;
-    for (int part = 0; part < parts; ++part) {
+    const int first = L.collide_only > 0 ? L.collide_only - 1 : 0;
+    const int last = L.collide_only > 0 ? L.collide_only : parts;
+    if (first >= parts) return hipErrorInvalidValue;
+    for (int part = first; part < last; ++part) {
         hipLaunchKernelGGL((k2_collide<V, FAM, TL, STAGE>), dim3(blocks), dim3(WG), 0, s, L.pairs, L.work, L.bins,
                            L.n_bins, L.xcd_major, L.poses, L.hits, L.pfix, L.qacc, L.hist, L.polys, part, parts);
         const hipError_t e = hipGetLastError();

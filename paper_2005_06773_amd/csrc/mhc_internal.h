@@ -193,6 +193,7 @@ struct Launch {
     double *crit_t, *traj_crit_t, *attrib, *traj_attrib;
     int xcd_major;                // plan of contiguous stretches: number the slots XCD-major
     int collide_parts;            // the collision plan runs as this many launches (0 or 1: one)
+    int collide_only;             // 0: launch every part; k > 0: launch only part k - 1
     int one_track;                // some object follows the one-track model (heavier trajectory kernel)
     int stage;                    // collision instance that stages 8 x 8 item blocks in LDS
     int variant;

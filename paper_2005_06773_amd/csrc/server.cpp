@@ -19,9 +19,11 @@
 // that one slot always stays open to the other frames; those may then go
 // ahead of a large frame that waits for a slot. Frames of either kind keep
 // their arrival order among themselves. On the GPU such a tick's collision
-// plan runs as several launches of at most about max_checks_per_tick checks
-// each, planned for 4/5 of the resident waves, so that the other slots'
-// kernels find room on every CU beside it and between its launches.
+// plan runs as several launches of at most about min(max_checks_per_tick,
+// 1e9) checks each, planned for 4/5 of the resident waves and enqueued one
+// ahead of the GPU as the earlier ones end, so that the other slots' kernels
+// find room on every CU beside it and between its launches, also where the
+// slots' streams share a hardware queue.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -35,6 +37,8 @@
 #include <thread>
 #include <unordered_map>
 #include <vector>
+
+#include <sys/prctl.h>
 
 #include "runtime.h"
 
@@ -101,12 +105,24 @@ public:
     virtual void shutdown() {}
 };
 
+// Checks per collision launch of a large tick, at most (about 0.4 ms of the
+// GPU): a tick of another slot that shares the large tick's hardware queue
+// waits for at most two such launches.
+constexpr int64_t kPartChecks = 1000000000;
+
 // One slot of the GPU executor.
 struct TickSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;          // the tick's results are in pinned memory
     hipEvent_t kernels_done = nullptr;  // a large tick's kernels have ended
     bool copies_pending = false;        // a large tick's result copies are not yet enqueued
+    // A large tick's collision parts are enqueued one ahead of the GPU (part
+    // k once part k - 2 has ended, part_ev[k % 2]), so that a tick of another
+    // slot whose stream shares this one's hardware queue waits for at most
+    // two parts, not for the whole frame.
+    hipEvent_t part_ev[2] = {nullptr, nullptr};
+    Launch X{};                         // the large tick's launch
+    int next_part = 0, parts = 0;
     char *dbuf = nullptr;
     size_t dbytes = 0;
     char *pin_in = nullptr;
@@ -166,6 +182,22 @@ public:
         return waves[v][fam][tl];
     }
 
+    // Enqueues the next collision part of a large tick; after the last, the
+    // risk stage and the event its result copies wait for.
+    static hipError_t enqueue_part(TickSlot &t)
+    {
+        Launch X = t.X;
+        X.collide_only = t.next_part + 1;
+        hipError_t e = launch_collide(X, t.stream);
+        if (e == hipSuccess) e = hipEventRecord(t.part_ev[t.next_part % 2], t.stream);
+        ++t.next_part;
+        if (e == hipSuccess && t.next_part == t.parts) {
+            e = launch_risk(X, t.stream);
+            if (e == hipSuccess) e = hipEventRecord(t.kernels_done, t.stream);
+        }
+        return e;
+    }
+
     mhc_status launch(int slot, int64_t, const Frames &frames, std::string &err) override
     {
         TickSlot &t = slots[slot];
@@ -210,20 +242,25 @@ public:
             e = hipMemcpyAsync(t.dbuf, t.pin_in, t.L.image_bytes, hipMemcpyHostToDevice, t.stream);
         }
         Launch X = make_launch(t.L, t.dbuf, nullptr, keep_hits, n_cu);
-        // a tick above the check cap (one large frame) runs its collision
-        // plan as launches of at most about that many checks each, so that
-        // the other slots' ticks get the GPU in between
-        if (large)
-            X.collide_parts = (int)std::min<int64_t>(64, (t.L.n_checks + max_checks_per_tick - 1) / max_checks_per_tick);
-        if (e == hipSuccess) e = launch_all(X, t.stream);
-        // A large tick's result copies are enqueued only once its kernels
-        // have ended (poll): a copy enqueued now would wait for them at the
-        // head of a copy engine's queue, where the image and result copies of
-        // the other slots' ticks would wait behind it for the whole frame.
+        // A tick above the check cap (one large frame) runs its collision
+        // plan as launches of at most about that many checks each, enqueued
+        // one ahead of the GPU as the earlier ones end (poll), so that the
+        // other slots' ticks get the GPU in between even where their streams
+        // share this one's hardware queue. Its result copies are enqueued
+        // only once its kernels have ended: a copy enqueued now would wait
+        // for them at the head of a copy engine's queue, where the image and
+        // result copies of the other slots' ticks would wait behind it.
         t.copies_pending = large;
         if (large) {
-            if (e == hipSuccess) e = hipEventRecord(t.kernels_done, t.stream);
+            const int64_t per_part = std::min<int64_t>(max_checks_per_tick, kPartChecks);
+            X.collide_parts = (int)std::max<int64_t>(2, std::min<int64_t>(64, (t.L.n_checks + per_part - 1) / per_part));
+            t.X = X;
+            t.parts = X.collide_parts;
+            t.next_part = 0;
+            if (e == hipSuccess) e = launch_trajgen(X, t.stream);
+            while (e == hipSuccess && t.next_part < 2) e = enqueue_part(t);
         } else {
+            if (e == hipSuccess) e = launch_all(X, t.stream);
             if (e == hipSuccess) e = enqueue_results(t.results, t.L, n, t.dbuf, t.pin_out, t.dsts.data(), t.stream);
             if (e == hipSuccess) e = hipEventRecord(t.done, t.stream);
         }
@@ -237,6 +274,15 @@ public:
     int poll(int slot, std::string &err) override
     {
         TickSlot &t = slots[slot];
+        while (t.copies_pending && t.next_part < t.parts) {
+            const hipError_t k = hipEventQuery(t.part_ev[t.next_part % 2]);  // part next_part - 2
+            if (k == hipErrorNotReady) return 0;
+            const hipError_t e = k == hipSuccess ? enqueue_part(t) : k;
+            if (e != hipSuccess) {
+                err = std::string("tick failed: ") + hipGetErrorString(e);
+                return -1;
+            }
+        }
         if (t.copies_pending) {
             const hipError_t k = hipEventQuery(t.kernels_done);
             if (k == hipErrorNotReady) return 0;
@@ -271,6 +317,8 @@ public:
             for (char *r : t.retired) (void)hipHostFree(r);
             if (t.done) (void)hipEventDestroy(t.done);
             if (t.kernels_done) (void)hipEventDestroy(t.kernels_done);
+            for (hipEvent_t &pe : t.part_ev)
+                if (pe) (void)hipEventDestroy(pe);
             if (t.stream) (void)hipStreamDestroy(t.stream);
         }
         slots.clear();
@@ -487,8 +535,15 @@ Frames admit(mhc_server *srv, bool large_allowed, bool *took_large)
     return take;
 }
 
+// Interval at which the scheduler polls running ticks.
+constexpr int kPollUs = 10;
+
 void scheduler(mhc_server *srv)
 {
+    // The thread polls running ticks every kPollUs; with Linux's default
+    // 50 us timer slack each of those sleeps would last about 70 us, which
+    // frames that finish in a fraction of a millisecond would wait out.
+    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
     if (srv->ctx) (void)hipSetDevice(srv->ctx->device);
     const int64_t watchdog_ns = srv->cfg.watchdog_us * 1000;
     const int n_slots = (int)srv->slots.size();
@@ -566,7 +621,7 @@ void scheduler(mhc_server *srv)
             }
             continue;
         }
-        if (any_busy) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (any_busy) std::this_thread::sleep_for(std::chrono::microseconds(kPollUs));
     }
 }
 
@@ -638,6 +693,8 @@ extern "C" mhc_status mhc_server_start(mhc_ctx *ctx, const mhc_server_cfg *cfg, 
         if (hipStreamCreateWithFlags(&t.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&t.done, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&t.kernels_done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&t.part_ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&t.part_ev[1], hipEventDisableTiming) != hipSuccess ||
             hipMalloc(reinterpret_cast<void **>(&t.dbuf), srv->slot_bytes) != hipSuccess ||
             grow_pinned(&t.pin_in, &t.pin_in_bytes, kInitialStaging, t.retired) != hipSuccess ||
             grow_pinned(&t.pin_out, &t.pin_out_bytes, kInitialStaging, t.retired) != hipSuccess) {

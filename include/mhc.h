@@ -353,7 +353,7 @@ typedef struct {
     int64_t repeated;       /* items tested more than once (0 when sound) */
     int64_t out_of_range;   /* threads deriving an index outside their pair (0 when sound) */
     int32_t contiguous;     /* 1: waves take contiguous stretches of the unit sequence */
-    int32_t pad;
+    int32_t time_split;     /* largest number of step ranges a unit is cut into (1, 2, 4 or 8) */
 } mhc_plan_info;
 mhc_status mhc_plan_check(int32_t n_scenes, const mhc_scene *scenes, int32_t variant, int32_t max_waves,
                           mhc_plan_info *info);

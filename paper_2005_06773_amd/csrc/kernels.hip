@@ -672,12 +672,14 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
                                               unsigned long long *__restrict__ hist, const Check chk)
 {
     const int n_ig = pr.n_ig, n_jg = pr.n_jg;
-    // time split: E = 64 >> tshift items per unit, part p of the steps per lane
+    // time split: E = 64 >> tshift items per unit; part p of the steps per
+    // lane, chunk = ceil(H / S) steps from min(p * chunk, H - chunk), so the
+    // last part ends at H (overlapping its neighbour when S does not divide H)
     const int lane = (int)(threadIdx.x & (WAVE - 1));
     const int tshift = pr.tshift;
     const int per = WAVE >> tshift;
     const int part = lane >> (6 - tshift);
-    const int chunk = pr.H >> tshift;
+    const int chunk = (pr.H + (1 << tshift) - 1) >> tshift;
     const int e = lane & (per - 1);
     // Item of this lane. Row-major units (bshift = 0) hold the items
     // item0 .. item0 + E-1; a block unit v is the block (v / nb, v % nb) of
@@ -728,7 +730,7 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     const __amdgpu_buffer_rsrc_t B = pose_rsrc(poses + pr.pose_b, (uint32_t)((size_t)pr.H * Tb * sizeof(PB)));
     const uint32_t strideA = (uint32_t)Ta * (uint32_t)sizeof(PA), strideB = (uint32_t)Tb * (uint32_t)sizeof(PB);
     // lane offsets: the trajectory and the first step of this lane's part
-    const uint32_t t0 = (uint32_t)(part * chunk);
+    const uint32_t t0 = (uint32_t)min(part * chunk, pr.H - chunk);
     int first[RI][RJ];
 #pragma unroll
     for (int r = 0; r < RI; ++r)
@@ -802,8 +804,8 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
         }
     }
     if (tshift) {
-        // the earliest hit over the parts: parts hold consecutive step ranges,
-        // so it is the smallest step found by any part (lanes l ^ E, l ^ 2E)
+        // the earliest hit over the parts: their step ranges cover [0, H), so
+        // it is the smallest step found by any part (lanes l ^ E, l ^ 2E, ...)
 #pragma unroll
         for (int r = 0; r < RI; ++r)
 #pragma unroll

@@ -87,7 +87,7 @@ struct DPair {
     float la, wa, lb, wb;         // half length / half width of vehicles
     float rr;                     // squared test radius: r_Q^2 (rect-circle), (r_P + r_Q)^2 (circle-circle)
     int32_t qn;                   // q row stride: object count of the scene
-    int32_t tshift;               // time split S = 2^tshift (S divides H): a unit's steps run in S parts
+    int32_t tshift;               // time split S = 2^tshift (S <= H): a unit's steps run in S parts
     int64_t qa0;                  // q index of (a, i = 0, b)
     int64_t qb0;                  // q index of (b, j = 0, a)
     int64_t pa_off, pb_off;       // trajectory index of (a, 0) and (b, 0)
@@ -103,8 +103,9 @@ struct DPair {
 // A run of collision work for one wave: n_units consecutive units of a pair.
 // A pair's items (ig, jg) form an n_ig x n_jg grid; with time split S a unit
 // holds E = 64 / S of them, and lane l takes item l % E of unit item0 / E + u
-// and the steps [p*H/S, (p+1)*H/S) of part p = l / E, so the S parts of an
-// item run side by side in one wave. With bshift = 0 the items of unit v are
+// and the c = ceil(H/S) steps from min(p*c, H - c) of part p = l / E, so the
+// S parts of an item run side by side in one wave and cover every step (the
+// last part overlaps its neighbour where S does not divide H). With bshift = 0 the items of unit v are
 // E*v .. E*v + E-1 in row-major order; otherwise unit v is the block
 // (v / nb, v % nb) of the grid cut into blocks of E / 2^bshift rows and
 // 2^bshift columns (nb blocks per block row), so that a wave reads few
@@ -120,7 +121,7 @@ struct WorkItem {
 
 constexpr int WG = 256;           // threads per workgroup, all kernels
 constexpr int WAVE = 64;          // wavefront size
-constexpr int MAX_TSHIFT = 2;     // time split of a collision unit: S <= 4
+constexpr int MAX_TSHIFT = 3;     // time split of a collision unit: S <= 8
 constexpr int N_XCD = 8;          // accelerator complex dies; workgroups are dealt to them in turn
 constexpr int K1_TPB = WG / 64;   // trajectories per trajectory workgroup (one wave each)
 // q sums are accumulated exactly as integers. EXCLUSIVE reading: p scaled by

@@ -71,7 +71,7 @@ static const double kUnitOverhead = 120.0;
 // stretches of the unit sequence instead of individually packed units.
 static const int kContiguousUnitsPerWave = 8;
 // Below this many work units per resident collision wave, units are split in
-// time (up to S = 4 parts side by side in a wave) to get more, shorter
+// time (up to S = 8 parts side by side in a wave) to get more, shorter
 // units. Around one unit per wave the split costs more than it balances
 // (measured on the 11-object scene: 40.5 us with S = 2 against 37.0 us).
 static const double kSplitBelowUnitsPerWave = 0.75;
@@ -106,6 +106,17 @@ static int unit_shape(const DPair &pr, int tshift)
         }
     }
     return best;
+}
+
+// Steps per part of a unit with time split 2^tshift: ceil(H / S).
+static int split_chunk(int H, int tshift) { return (H + (1 << tshift) - 1) >> tshift; }
+
+// A split fits a horizon when every part has a step and the parts' overlap
+// (S * ceil(H / S) - H steps tested twice) is at most an eighth of H.
+static bool split_fits(int H, int tshift)
+{
+    const int S = 1 << tshift;
+    return S <= H && 8 * (S * split_chunk(H, tshift) - H) <= H;
 }
 
 static bool finite(double v) { return std::isfinite(v); }
@@ -269,20 +280,21 @@ static void reset_layout(Layout &L)
 }
 
 static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L,
-                              bool with_hits);
+                              bool with_hits, int max_tshift);
 
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits,
-                  int max_waves_staged)
+                  int max_waves_staged, int max_tshift)
 {
-    build_layout_once(scenes, n_scenes, variant, max_waves, L, with_hits);
+    max_tshift = std::min(std::max(max_tshift, 0), MAX_TSHIFT);
+    build_layout_once(scenes, n_scenes, variant, max_waves, L, with_hits, max_tshift);
     const bool stage = L.family == FAM_PLAIN && !L.timeline && max_waves > 0 && L.staged_share >= 0.5;
     if (stage && max_waves_staged > 0 && max_waves_staged != max_waves)
-        build_layout_once(scenes, n_scenes, variant, max_waves_staged, L, with_hits);
+        build_layout_once(scenes, n_scenes, variant, max_waves_staged, L, with_hits, max_tshift);
     L.stage = stage;
 }
 
 static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L,
-                              bool with_hits)
+                              bool with_hits, int max_tshift)
 {
     reset_layout(L);
     L.variant = variant;
@@ -426,14 +438,15 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
         L.n_checks += ext.checks;
     }
     // Time split. With few units for the resident waves, a unit's steps are
-    // cut into S parts that run side by side in one wave (64/S items, H/S
-    // steps per lane): S times as many, S times shorter units, which the
-    // packing below can spread evenly and which fill the GPU. S is the
-    // smallest of 1, 2, 4 that gives enough units (4 for the size bound,
-    // max_waves = 0), lowered per pair until it divides the horizon.
-    int want = MAX_TSHIFT;
+    // cut into S parts that run side by side in one wave (64/S items,
+    // ceil(H/S) steps per lane): S times as many, S times shorter units, which
+    // the packing below can spread evenly and which fill the GPU. S is the
+    // smallest of 1, 2, 4, 8 that gives enough units (the largest allowed for
+    // the size bound, max_waves = 0), lowered per pair until it fits the
+    // horizon (split_fits).
+    int want = max_tshift;
     if (max_waves > 0) {
-        for (want = 0; want < MAX_TSHIFT; ++want) {
+        for (want = 0; want < max_tshift; ++want) {
             int64_t u = 0;
             for (const DPair &pr : L.pairs) u += pair_units(pr, want, 0);
             if ((double)u >= kSplitBelowUnitsPerWave * max_waves) break;
@@ -442,7 +455,7 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
     for (size_t pidx = 0; pidx < L.pairs.size(); ++pidx) {
         DPair &pr = L.pairs[pidx];
         int sh = want;
-        while (sh > 0 && (pr.H % (1 << sh)) != 0) --sh;
+        while (sh > 0 && !split_fits(pr.H, sh)) --sh;
         pr.tshift = sh;
         pr.bshift = unit_shape(pr, sh);
         const TileShape ts = kTiles[variant][pr.cls];
@@ -452,7 +465,7 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
         // (rectangle-rectangle and rectangle-circle tests: 25 and 12 VALU each,
         // the rectangle's frame read ready from its frame block)
         const double per_test = class_cost(pr.cls, ka, kb);
-        const double unit_cost = (double)ts.ri * ts.rj * (pr.H >> sh) * per_test + kUnitOverhead;
+        const double unit_cost = (double)ts.ri * ts.rj * split_chunk(pr.H, sh) * per_test + kUnitOverhead;
         costs.push_back(PairCost{unit_cost, (int32_t)pidx, (int32_t)pair_units(pr, sh, pr.bshift)});
     }
 
@@ -916,6 +929,7 @@ static void walk_plan(const Layout &L, mhc_plan_info &info)
     std::vector<uint8_t> seen((size_t)item_base.back(), 0);
     const int n_bins = (int)L.bins.size() - 1;
     int64_t bad = 0, units = 0;
+    int32_t time_split = 1;
     if (n_bins < 1 || L.bins[0] != 0 || L.bins[n_bins] != (int32_t)L.work.size()) ++bad;
     for (int b = 0; b < n_bins && !bad; ++b) {
         if (L.bins[b + 1] < L.bins[b]) {
@@ -930,10 +944,19 @@ static void walk_plan(const Layout &L, mhc_plan_info &info)
             }
             const DPair &pr = L.pairs[w.pair];
             const int per = WAVE >> pr.tshift;
-            const int chunk = pr.H >> pr.tshift;
+            const int chunk = split_chunk(pr.H, pr.tshift);
             const TileShape ts = kTiles[L.variant][pr.cls];
             const int ri = ts.ri, rj = ts.rj;
-            if (chunk << pr.tshift != pr.H || w.item0 % per != 0) ++bad;
+            if (pr.tshift < 0 || pr.tshift > MAX_TSHIFT || w.item0 % per != 0) ++bad;
+            // the parts' step ranges: inside [0, H), the first from 0, the
+            // last to H, each starting at or before the end of the one before
+            for (int part = 0, end = 0; part < (1 << pr.tshift); ++part) {
+                const int t0 = std::min(part * chunk, pr.H - chunk);
+                if (t0 < 0 || t0 > end || t0 + chunk > pr.H) ++bad;
+                end = t0 + chunk;
+                if (part == (1 << pr.tshift) - 1 && end != pr.H) ++bad;
+            }
+            time_split = std::max(time_split, 1 << pr.tshift);
             const int64_t n_units = pair_units(pr, pr.tshift, pr.bshift);
             for (int32_t u = 0; u < w.n_units; ++u) {
                 ++units;
@@ -961,8 +984,6 @@ static void walk_plan(const Layout &L, mhc_plan_info &info)
                         ++bad;
                         continue;
                     }
-                    // steps of this part: [part * chunk, part * chunk + chunk)
-                    if ((int64_t)(part + 1) * chunk > pr.H) ++bad;
                     for (int r = 0; r < ri; ++r)
                         for (int sidx = 0; sidx < rj; ++sidx) {
                             const int64_t i = ig + (int64_t)r * pr.n_ig, j = jg + (int64_t)sidx * pr.n_jg;
@@ -993,7 +1014,7 @@ static void walk_plan(const Layout &L, mhc_plan_info &info)
     info.repeated = repeated;
     info.out_of_range = bad;
     info.contiguous = L.contiguous ? 1 : 0;
-    info.pad = 0;
+    info.time_split = time_split;
 }
 
 extern "C" mhc_status mhc_plan_check(int32_t n_scenes, const mhc_scene *scenes, int32_t variant, int32_t max_waves,

@@ -106,8 +106,9 @@ int scene_family(const mhc_scene *s);
 // its cost (plain class family, no risk over time), the launch uses the
 // collision instance that stages them in LDS, and the plan is made for that
 // instance's resident waves, max_waves_staged (0: the same as max_waves).
+// max_tshift caps the time split of the plan's units (S <= 2^max_tshift).
 void build_layout(const mhc_scene *scenes, int n_scenes, int variant, int max_waves, Layout &L, bool with_hits,
-                  int max_waves_staged = 0);
+                  int max_waves_staged = 0, int max_tshift = MAX_TSHIFT);
 
 // The host side of the results of the n scenes of a layout: per output, the
 // workspace range [lo, hi) of every requested part and, where staged, its

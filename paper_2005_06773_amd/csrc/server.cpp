@@ -68,6 +68,9 @@ std::chrono::system_clock::time_point wait_deadline(std::chrono::microseconds d)
 // Bound on the resident collision waves of any GPU this library runs on
 // (sizes the slot table in the admission estimate).
 constexpr int kMaxCollisionWaves = 1 << 16;
+// Ticks split collision units in time into at most 4 parts: the admission
+// bound counts a collision segment per unit of 16 items.
+constexpr int kTickMaxTshift = 2;
 constexpr int64_t kDefaultWatchdogUs = 30LL * 1000 * 1000;
 
 enum FrameState { QUEUED, ADMITTED, DONE };
@@ -224,7 +227,7 @@ public:
             waves_v = std::max(1, waves_v / 5 * 4);
             waves_s = waves_s / 5 * 4;
         }
-        build_layout(scenes.data(), n, v, waves_v, t.L, keep_hits, waves_s);
+        build_layout(scenes.data(), n, v, waves_v, t.L, keep_hits, waves_s, kTickMaxTshift);
         if (t.L.total_bytes > t.dbytes) {  // the admission bound excludes this
             err = "tick workspace above the slot's share of the budget";
             return MHC_E_NOMEM;
@@ -396,7 +399,9 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     for (int a = 0; a < n; ++a) {
         const int64_t T = (int64_t)s->objects[a].n_u * s->objects[a].n_w;
         n_traj += T;
-        pose += align256((size_t)s->horizon * T * (s->objects[a].kind == MHC_VEHICLE ? 16 : 8));
+        // poses; a vehicle's frame block beside them
+        const bool vehicle = s->objects[a].kind == MHC_VEHICLE;
+        pose += align256((size_t)s->horizon * T * (vehicle ? 16 : 8)) * (vehicle ? 2 : 1);
         vals += s->objects[a].n_u + s->objects[a].n_w + (s->objects[a].score ? T : 0);
     }
     for (int a = 0; a < n; ++a)
@@ -406,8 +411,9 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
             const int64_t Tb = (int64_t)s->objects[b].n_u * s->objects[b].n_w;
             n_hits += Ta * Tb;
             // one collision segment per work unit, for the variant and the
-            // time split (up to 4 parts, 16 items a unit) that cut this pair
-            // into the most units
+            // time split (a tick's: up to 4 parts, 16 items a unit) that cut
+            // this pair into the most units (2-D blocks of items are taken
+            // where they add at most 1/32 to the units of the row-major cut)
             const bool poly = scene_has_outline(s);
             const int cls = pair_class(s->objects[a].kind, s->objects[b].kind, s->overlap,
                                        poly && s->objects[a].n_vertices > 0, poly && s->objects[b].n_vertices > 0);
@@ -415,8 +421,8 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
             for (int v = 0; v < N_VARIANTS; ++v) {
                 const int64_t items = (Ta + kTiles[v][cls].ri - 1) / kTiles[v][cls].ri *
                                       ((Tb + kTiles[v][cls].rj - 1) / kTiles[v][cls].rj);
-                const int64_t per = WAVE >> MAX_TSHIFT;
-                most = std::max(most, (items + per - 1) / per);
+                const int64_t per = WAVE >> kTickMaxTshift;
+                most = std::max(most, ((items + per - 1) / per * 33 + 31) / 32);
             }
             n_units += most;
             ++n_pairs;

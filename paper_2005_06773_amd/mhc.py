@@ -83,7 +83,7 @@ class mhc_sizes(ctypes.Structure):
 class mhc_plan_info(ctypes.Structure):
     _fields_ = [("n_units", ctypes.c_int64), ("n_waves", ctypes.c_int64), ("blocked_pairs", ctypes.c_int64),
                 ("uncovered", ctypes.c_int64), ("repeated", ctypes.c_int64), ("out_of_range", ctypes.c_int64),
-                ("contiguous", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("contiguous", ctypes.c_int32), ("time_split", ctypes.c_int32)]
 
 
 RESULT_FIELDS = ("object_crit", "traj_crit", "traj_prob", "q", "first_hit",
@@ -318,7 +318,7 @@ def mhc_plan_check(scenes, variant: int, max_waves: int = 0):
     arr = (mhc_scene * len(cs))(*[c.c for c in cs])
     info = mhc_plan_info()
     st = lib.mhc_plan_check(len(cs), arr, variant, max_waves, ctypes.byref(info))
-    return st, {k: getattr(info, k) for k, _ in mhc_plan_info._fields_ if k != "pad"}
+    return st, {k: getattr(info, k) for k, _ in mhc_plan_info._fields_}
 
 
 def mhc_query_sizes(scene) -> dict:

@@ -256,15 +256,24 @@ def test_collision_plan_covers_every_item_once(mhc, variant):
     scenes = [sg.eleven_object_scene(1), sg.paper_scene(5, n_co=3), sg.polygon_scene(2),
               _grid_scene(1, 4, 2, 32, 50),      # 32 x 32 grids: block units
               _grid_scene(2, 3, 3, 24, 36),      # 24 x 24: block units with time splits
-              _grid_scene(3, 2, 2, 13, 20)]      # ragged grids: row-major units
+              _grid_scene(3, 2, 2, 13, 20),      # ragged grids: row-major units
+              _grid_scene(4, 2, 1, 9, 37),       # a prime horizon: parts that overlap
+              _grid_scene(5, 2, 1, 7, 9),        # H = 9: S = 8 and 4 overlap too much, S = 2
+              _grid_scene(6, 2, 1, 7, 1)]        # H = 1: no split
     blocked = 0
-    for s in scenes:
+    splits = {}
+    for k, s in enumerate(scenes):
         for waves in (0, 256, 2048, 5120, 6144, 7168):
             st, info = mhc.mhc_plan_check(s, variant, waves)
             assert st == mhc.MHC_OK, (variant, waves, info)
             assert info["uncovered"] == info["repeated"] == info["out_of_range"] == 0
             blocked += info["blocked_pairs"]
+            splits[(k, waves)] = info["time_split"]
     assert blocked > 0
+    # the largest split where units are few; parts of ceil(H / S) steps where
+    # S does not divide H, as long as their overlap stays within H / 8
+    assert splits[(0, 256)] == 1 and splits[(6, 5120)] == 8
+    assert splits[(7, 5120)] == 2 and splits[(8, 5120)] == 1 and splits[(1, 0)] == 8
     batch = sg.batch_scenes(2, 12)
     for waves in (0, 512, 8192):
         st, info = mhc.mhc_plan_check(batch, variant, waves)

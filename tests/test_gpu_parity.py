@@ -468,6 +468,52 @@ def test_block_units_parity(mhc, ctx, name):
     assert (o.k64 >= 0).sum() > 100
 
 
+def _ragged_split_scenes():
+    """Scenes with few collision units whose horizons the chosen time split
+    does not divide, so the last part of every unit overlaps its neighbour:
+    Table I S1 (100 steps, split 8: parts of 13 steps), a prime horizon, and
+    all four classes on 30 steps (split 8: parts of 4)."""
+    rng = np.random.default_rng(505)
+    out = {"table_one_s1": sg.paper_scene(5, n_co=3), "table_one_s1_5_profiles_pip":
+           sg.paper_scene(6, n_co=3, n_acc=5, overlap=sg.OVERLAP_PIP)}
+    objs = [sg.draw_vehicle(rng, 10.0, 0.0, 12.0, 9, 9) for _ in range(2)]
+    objs += [sg.draw_pedestrian(rng, 10.0, 0.0, 2.0, 9, 9)]
+    out["prime_horizon_37"] = sg.Scene(objs, 37, 0.1)
+    objs = [sg.draw_vehicle(rng, 12.0, 0.0, 12.0, 7, 11) for _ in range(2)]
+    objs += [sg.draw_pedestrian(rng, 12.0, 0.0, 2.0, 5, 13) for _ in range(2)]
+    out["all_classes_H30"] = sg.Scene(objs, 30, 0.1)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_ragged_split_scenes().keys()))
+def test_ragged_time_split_parity(mhc, ctx, name):
+    """Time splits whose parts overlap (S does not divide H): against the
+    oracle, and every tile variant bit for bit; the host walk of each plan
+    first, which also shows that the split is ragged."""
+    s = _ragged_split_scenes()[name]
+    for v in range(mhc.MHC_N_VARIANTS):
+        for waves in (5120, 6144):
+            st, info = mhc.mhc_plan_check(s, v, waves)
+            assert st == mhc.MHC_OK, (name, v, waves, info)
+            if v == 0:      # the default variant, compared with the oracle below
+                assert info["time_split"] > 1 and s.horizon % info["time_split"] != 0, (name, waves, info)
+    say(f"ragged time split: {name}")
+    o = oracle.evaluate(s, threads=THREADS)
+    try:
+        ref = None
+        for v in range(mhc.MHC_N_VARIANTS):
+            mhc.mhc_set_variant(ctx, v)
+            g = mhc.mhc_evaluate(ctx, s)
+            if ref is None:
+                parity.check(s, g, o, f"{name} variant {v}")
+                ref = g
+            else:
+                parity.same_results(ref, g, f"{name} variant {v}")
+    finally:
+        mhc.mhc_set_variant(ctx, -1)
+    assert (o.k64 >= 0).sum() > 50
+
+
 def test_batch_with_different_outputs_per_scene(mhc, ctx):
     """A batch whose scenes ask for different outputs (first hits, q, the
     per-trajectory arrays, the risk over time, each for some scenes only):

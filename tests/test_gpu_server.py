@@ -98,8 +98,9 @@ def test_budget_admission(mhc, ctx):
     st = srv.stats()
     srv.stop()
     assert st["rejected"] == 1 and st["completed"] == 1
-    # a budget that holds one such frame per tick: frames wait for later ticks
-    srv = mhc.Server(ctx, budget=16 << 20, inflight=2)
+    # a budget that holds one such frame per tick (8.5 MB reserved for it, in
+    # slots of 9 MiB less the slot table): frames wait for later ticks
+    srv = mhc.Server(ctx, budget=18 << 20, inflight=2)
     ts = [srv.submit(0, big, first_hit=True) for _ in range(6)]
     outs = [srv.wait(t)[0] for t in ts]
     st = srv.stats()

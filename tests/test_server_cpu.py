@@ -86,24 +86,30 @@ def test_arrival_order_and_results(mhc):
     assert st["completed"] == 10 and st["submitted"] == 10 and st["late"] == 0
 
 
-def _accepting_budget(mhc, scene):
-    """The smallest power-of-two budget (one slot) under which `scene` with its
-    first-hit output is accepted."""
-    for k in range(20, 34):
-        srv = _server(mhc, FakeExecutor(mhc), inflight=1, budget=1 << k)
+def _admission_bytes(mhc, scene, first_hit):
+    """The bytes the scheduler reserves for `scene`: the exact budget at
+    which a one-slot server starts to accept it (bisection over multiples of
+    256 bytes), less the slot's collision slot table."""
+    table = ((65536 + 1) * 4 + 255) // 256 * 256
+    lo, hi = 1 << 20, 1 << 36            # refused at lo, accepted at hi
+    while hi - lo > 256:
+        mid = (lo + hi) // 2 // 256 * 256
+        srv = _server(mhc, FakeExecutor(mhc), inflight=1, budget=mid)
         try:
-            srv.submit(0, scene, first_hit=True)
-            return 1 << k
+            srv.submit(0, scene, first_hit=first_hit)
+            hi = mid
         except mhc.MhcError as e:
             assert e.status == mhc.MHC_E_NOMEM
+            lo = mid
         finally:
             srv.stop()
-    raise AssertionError("no budget accepted the frame")
+    return hi - table
 
 
 def test_budget_admission(mhc):
     big = sg.eleven_object_scene(1)      # 5.6 MB of first hits per frame
-    b1 = _accepting_budget(mhc, big)
+    table = ((65536 + 1) * 4 + 255) // 256 * 256
+    b1 = _admission_bytes(mhc, big, True) + table     # the smallest one-slot budget that takes it
     # half that budget refuses the frame outright
     srv = _server(mhc, FakeExecutor(mhc), inflight=1, budget=b1 // 2)
     with pytest.raises(mhc.MhcError) as ei:
@@ -121,6 +127,33 @@ def test_budget_admission(mhc):
     st = srv.stats()
     srv.stop()
     assert [n for _, _, n, _ in ex.ticks] == [1] * 5 and st["deferred"] >= 1
+
+
+def test_admission_bound_covers_the_workspace(mhc):
+    """What admission reserves for a frame covers every buffer of the
+    workspace its tick builds. mhc_query_sizes reports the largest layout
+    over the tile variants with one wave per collision unit (first hits
+    included); all of it but the collision plan (a segment of 16 bytes per
+    unit and a slot table of 4 bytes per wave, most units for the variant
+    with the most) is the same for every plan, and what admission reserves
+    must hold it plus the plan's segments. Vehicles' frame blocks, the risk
+    over time and polygon tables are part of it."""
+    rng = np.random.default_rng(12)
+    grid = [sg.draw_vehicle(rng, 30.0, 0.0, 15.0, 24, 24) for _ in range(3)]
+    grid += [sg.draw_pedestrian(rng, 30.0, 0.0, 2.0, 24, 24) for _ in range(3)]
+    timeline = sg.eleven_object_scene(3)
+    timeline.timeline = 1
+    scenes = {"eleven_object": sg.eleven_object_scene(1), "table_one_s1": sg.paper_scene(5, n_co=3),
+              "octagons": sg.polygon_scene(2), "block_units_24_grids": sg.Scene(grid, 36, 0.1),
+              "timeline": timeline, "two_vehicles": sg.two_vehicle_scene(4)}
+    a256 = lambda b: (b + 255) // 256 * 256
+    for name, s in scenes.items():
+        units = max(mhc.mhc_plan_check(s, v, 0)[1]["n_units"] for v in range(mhc.MHC_N_VARIANTS))
+        layout = mhc.mhc_query_sizes(mhc.CScene(s))["device_bytes"]
+        other = layout - a256(units * 16) - a256((units + 1) * 4)
+        reserved = _admission_bytes(mhc, s, True)
+        assert reserved >= other, (name, reserved, other, layout)
+        assert reserved < 2 * layout + (1 << 20), (name, reserved, layout)     # and not far above it
 
 
 def test_deadline_accounting(mhc):

@@ -140,13 +140,12 @@ struct TileShape {
 };
 constexpr int N_VARIANTS = 4;
 // variant -> shape per class {VV, VP, PV, PP, VV_PIP, GG, GG_PIP, GC, CG}.
-// The shapes keep the VALU cost of one work unit similar across classes (27,
-// 12-13, 6 and 59 VALU per rect-rect, rect-circle, circle-circle and
+// The shapes keep the VALU cost of one work unit similar across classes (25,
+// 12, 6 and 58 VALU per rect-rect, rect-circle, circle-circle and
 // point-in-polygon test; 100-500 for polygon pairs) and the loads per test
-// low. A rectangle-circle tile pairs each rectangle pose with 4 or 8 circles,
-// which share the rectangle's pose prepared once per step (12 VALU per test
-// plus 4 per rectangle pose). Variants 2 and 3 cut the work into more, smaller
-// units for scenes with few of them.
+// low: a rectangle-circle tile pairs each rectangle pose (read in its own
+// frame) with 4 or 8 circles. Variants 2 and 3 cut the work into more,
+// smaller units for scenes with few of them.
 // Polygon-polygon pairs always take one test per thread (their tests are
 // long, and the kernel has one code path per padded vertex-count pair).
 constexpr TileShape kTiles[N_VARIANTS][N_CLS] = {

@@ -280,8 +280,9 @@ def models_extra(mhc, ctx, sg, torch, steps=50):
     11-object scene with one-track vehicles and accelerating pedestrians
     (same grid sizes), and the Table I S2 scene with one-track vehicles:
     whole-path step and each module's time (HIP events on the launch
-    stream). The one-track trajectories are a sequential recursion per
-    trajectory (a thread each), the kinematic ones a scan over steps."""
+    stream). Both run a lane per step: the kinematic trajectories as prefix
+    sums of closed-form increments, the one-track ones as a scan of the
+    per-step affine maps of their lateral state."""
     stream = torch.cuda.current_stream()
     T, C, R = mhc.MHC_STAGE_TRAJ, mhc.MHC_STAGE_COLLIDE, mhc.MHC_STAGE_RISK
 

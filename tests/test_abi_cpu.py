@@ -282,6 +282,20 @@ def test_collision_plan_covers_every_item_once(mhc, variant):
     assert st == mhc.MHC_OK and info["contiguous"] == 1
 
 
+def test_collision_plan_of_random_scenes(mhc):
+    """The host walk of the collision plan over the random-scene sweep
+    (every scene option, horizons of 1 to 131 steps) for every variant and
+    two resident-wave counts."""
+    from tests.random_scenes import random_scene
+    for k in range(300):
+        s = random_scene(k)
+        for v in range(mhc.MHC_N_VARIANTS):
+            for waves in (512, 6144):
+                st, info = mhc.mhc_plan_check(s, v, waves)
+                assert st == mhc.MHC_OK, (k, v, waves, info)
+                assert info["uncovered"] == info["repeated"] == info["out_of_range"] == 0, (k, v, waves, info)
+
+
 def test_collision_plan_check_rejects_bad_arguments(mhc):
     s = sg.eleven_object_scene(0)
     assert mhc.mhc_plan_check(s, -1, 0)[0] == mhc.MHC_E_INVAL

@@ -1063,6 +1063,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinW
 // batched, so every result is identical for any tiling and any batch.
 // ===========================================================================
 
+constexpr int K3_LOADS = 16;
+
 __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
                                               const unsigned long long *__restrict__ qacc,
                                               const double *__restrict__ p, double *__restrict__ q,
@@ -1082,17 +1084,18 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
     if (i < o.T) {
         // The trajectory kernel zeroed all n accumulators of this trajectory,
         // so b == a and objects outside the pair set read as q = 0. Loads are
-        // issued eight at a time, ahead of the dependent product.
+        // issued sixteen at a time (scenes of up to 16 objects in one round),
+        // ahead of the dependent product.
         const unsigned long long *__restrict__ qa = qacc + o.q_row + (int64_t)i * n;
         double *__restrict__ qi = q ? q + o.q_row + (int64_t)i * n : nullptr;
         const double pi = p[o.traj_off + i];
         double no_collision = 1.0;
-        for (int b0 = 0; b0 < n; b0 += 8) {
-            unsigned long long v[8];
+        for (int b0 = 0; b0 < n; b0 += K3_LOADS) {
+            unsigned long long v[K3_LOADS];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = b0 + k < n ? qa[b0 + k] : 0ull;
+            for (int k = 0; k < K3_LOADS; ++k) v[k] = b0 + k < n ? qa[b0 + k] : 0ull;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < K3_LOADS; ++k) {
                 if (b0 + k < n) {
                     const double qv = q_of(o.risk, v[k]);
                     if (qi) qi[b0 + k] = qv;

@@ -59,7 +59,7 @@ __device__ __forceinline__ double q_of(int risk, unsigned long long v)
 // fixed tree: the order depends on T only.
 __device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals,
                                         double *__restrict__ p, unsigned long long *__restrict__ pfix,
-                                        unsigned int *__restrict__ done)
+                                        unsigned long long *__restrict__ done)
 {
     __shared__ double red[WG];
     const int tid = threadIdx.x;
@@ -104,7 +104,7 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
     }
     // the object's completion counter of the risk kernel starts from zero
     // (each trajectory's wave clears its row of the q accumulators)
-    if (tid == 0) done[obj] = 0u;
+    if (tid == 0) done[obj] = 0ull;
 }
 
 // A vehicle pose (x, y, cos, sin) in its own frame: K = (x cos + y sin,
@@ -289,7 +289,7 @@ template <bool ONE_TRACK>
 __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, const double *__restrict__ vals,
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
-                                                 unsigned long long *__restrict__ qacc, unsigned int *__restrict__ done,
+                                                 unsigned long long *__restrict__ qacc, unsigned long long *__restrict__ done,
                                                  unsigned long long *__restrict__ hist)
 {
     const int obj = (int)blockIdx.y;
@@ -1056,20 +1056,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinW
 // converts its sums (rounding once), clamps to 1, writes q and forms
 //   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b).
 // The workgroup adds p_{a,i} crit_{a,i} over its chunk in a fixed tree. An
-// object of one chunk writes C_a directly; otherwise each chunk stores its
-// partial sum and the chunk that finishes last (a per-object counter, zeroed
-// by the trajectory kernel and reset by that chunk) adds the partials in
-// chunk order. Nothing depends on how the collision work was tiled or
-// batched, so every result is identical for any tiling and any batch.
+// object of one chunk writes C_a directly; otherwise the chunks add their
+// sums in fixed point into a per-object word (zeroed by the trajectory
+// kernel) that also counts them, and the chunk that completes the count
+// writes C_a. Nothing depends on how the collision work was tiled or
+// batched, or on which chunk ends last, so every result is identical for any
+// tiling and any batch.
 // ===========================================================================
 
 constexpr int K3_LOADS = 16;
+constexpr unsigned long long kChunkOne = 1ull << 56;  // one finished chunk in the per-object word
+constexpr double kCritScale = 0x1p55, kCritInvScale = 0x1p-55;
 
 __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
                                               const unsigned long long *__restrict__ qacc,
                                               const double *__restrict__ p, double *__restrict__ q,
                                               double *__restrict__ traj_crit, double *__restrict__ obj_crit,
-                                              double *__restrict__ partial, unsigned int *__restrict__ done)
+                                              unsigned long long *__restrict__ done)
 {
     __shared__ double red[WG];
     const int obj = (int)blockIdx.y;
@@ -1118,15 +1121,17 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
         return;
     }
     if (tid != 0) return;
-    partial[o.part_off + c] = red[0];
-    __threadfence();  // the partial is visible device-wide before the count
-    if (atomicAdd(&done[obj], 1u) != (unsigned)(chunks - 1)) return;
-    __threadfence();  // every other chunk's partial is visible to this one
-    const volatile double *vp = partial + o.part_off;
-    double C = 0.0;
-    for (int k = 0; k < chunks; ++k) C += vp[k];
-    obj_crit[o.obj_out] = C;
-    done[obj] = 0u;  // the risk stage may run again on the same sums
+    // One atomic per chunk adds the chunk's sum in fixed point (units of
+    // 2^-55; an object's sum is at most 1, so it stays below 2^56) together
+    // with a count of one at bit 56 (at most 128 chunks). The chunk whose add
+    // completes the count has the whole sum in the value it gets back; the
+    // sum is exact in integers, so it does not depend on which chunk ends
+    // last, and nothing else is shared between the chunks.
+    const unsigned long long mine = kChunkOne + __double2ull_rn(red[0] * kCritScale);
+    const unsigned long long before = atomicAdd(&done[obj], mine);
+    if ((before >> 56) != (unsigned long long)(chunks - 1)) return;
+    obj_crit[o.obj_out] = (double)((before + mine) & (kChunkOne - 1)) * kCritInvScale;
+    done[obj] = 0ull;  // the risk stage may run again on the same sums
 }
 
 // ===========================================================================
@@ -1595,7 +1600,7 @@ hipError_t launch_risk(const Launch &L, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k3_crit, dim3(L.k3_x, L.n_obj), dim3(WG), 0, s, L.objs, L.qacc, L.p, L.q, L.traj_crit,
-                       L.obj_crit, L.k3_part, L.done);
+                       L.obj_crit, L.done);
     return hipGetLastError();
 }
 

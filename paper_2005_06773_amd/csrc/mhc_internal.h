@@ -60,7 +60,6 @@ struct DObj {
     int64_t frame_off;            // vehicles: byte offset of the block [H][T] of the same poses in
                                   // their own frame, (K_x, K_y, cos, sin) with K = c in that frame
     int64_t u_off, w_off, score_off;  // offsets (doubles) into the value array
-    int64_t part_off;             // first partial sum of the risk kernel's chunks
     int64_t obj_out;              // index in the object_crit array
     // time-resolved risk (timeline scenes only)
     int64_t hist_off;             // slot sums [s][i][b < tl_w]: index of (s = 0, i = 0, b = 0)
@@ -182,8 +181,8 @@ struct Launch {
     int n_obj, n_pairs, n_work, n_bins;
     int k1_x;                     // trajectory kernel grid x: blocks of the largest object + 1
     int k3_x;                     // risk kernel grid x: 256-trajectory chunks of the largest object
-    double *k3_part;              // risk kernel partial sums, one per chunk
-    unsigned int *done;           // per object: risk chunks finished
+    unsigned long long *done;     // per object: risk chunks finished (bits 56..63) and their
+                                  // criticality sum in units of 2^-55 (bits 0..55)
     // time-resolved risk (null / 0 when no scene of the launch asks for it)
     int timeline;
     int k3t_x, k4t_y;             // time-resolved kernel grids: a wave of lanes of the largest object per workgroup; rows

@@ -368,8 +368,6 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
             d.score_off = d.w_off + o.n_w;
             L.vals.resize(L.vals.size() + o.n_u + o.n_w + (o.score ? d.T : 0));
             d.obj_out = L.n_obj + a;
-            d.part_off = L.n_part;
-            L.n_part += (d.T + WG - 1) / WG;
             L.k3_x = std::max(L.k3_x, (d.T + WG - 1) / WG);
             L.objs.push_back(d);
             L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
@@ -583,8 +581,7 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
     L.o_qacc = put((size_t)L.n_q * sizeof(unsigned long long));
-    L.o_part = put((size_t)L.n_part * sizeof(double));
-    L.o_done = put((size_t)L.n_obj * sizeof(unsigned int));
+    L.o_done = put((size_t)L.n_obj * sizeof(unsigned long long));
     // the outputs most calls ask for are neighbours, so they come down together
     L.o_p = put((size_t)L.n_traj * sizeof(double));
     L.o_tc = put((size_t)L.n_traj * sizeof(double));
@@ -744,8 +741,7 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.poses = base + L.o_poses;
     X.pfix = reinterpret_cast<unsigned long long *>(base + L.o_pfix);
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
-    X.k3_part = reinterpret_cast<double *>(base + L.o_part);
-    X.done = reinterpret_cast<unsigned int *>(base + L.o_done);
+    X.done = reinterpret_cast<unsigned long long *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
     X.polys = reinterpret_cast<const DPoly *>(base + L.o_polys);
     X.p = reinterpret_cast<double *>(base + L.o_p);

@@ -47,7 +47,6 @@ struct Layout {
     int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
     int k1_x = 0;                 // trajectory kernel grid x
     int k3_x = 0;                 // risk kernel grid x (chunks of the largest object)
-    int64_t n_part = 0;           // risk kernel partial sums (chunks over all objects)
     bool timeline = false;        // some scene asks for the risk over time
     int64_t n_hist = 0, n_tl_traj = 0, n_tl_obj = 0, n_tl_att = 0;
     int64_t k3t_x = 0;            // time-resolved risk kernel grid x (one wave of lanes of the largest object per workgroup)
@@ -55,7 +54,7 @@ struct Layout {
     size_t pose_bytes = 0;
     size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_polys = 0, image_bytes = 0;
     size_t value_bytes = 0;       // the image's leading part that fill_values rewrites (before the plan)
-    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_part = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
+    size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
     size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;
     int variant = 0;
     bool contiguous = false;      // collision plan of contiguous stretches

@@ -433,7 +433,7 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     bytes += align256((scene_has_outline(s) ? n : 0) * sizeof(DPoly));
     bytes += align256((n_units + 1) * sizeof(WorkItem));
     bytes += pose + align256(n_traj * 8) * 3 + align256(n_q * 8) * 2;  // p*2^62, p, traj crit; q sums, q
-    bytes += align256((n_traj / WG + n) * 8) + align256(n * 4);         // risk partials and counters
+    bytes += align256(n * 8);                                            // risk kernel's per-object words
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);
     if (s->timeline) {
         // per-slot sums (W >= n lanes per trajectory), attribution scratch

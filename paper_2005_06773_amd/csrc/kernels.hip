@@ -290,25 +290,31 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
                                                  char *__restrict__ poses, double *__restrict__ p,
                                                  unsigned long long *__restrict__ pfix,
                                                  unsigned long long *__restrict__ qacc, unsigned long long *__restrict__ done,
-                                                 unsigned long long *__restrict__ hist)
+                                                 unsigned long long *__restrict__ hist, const int2 *__restrict__ rows)
 {
-    const int obj = (int)blockIdx.y;
+    // the row's object and the block of that object this workgroup is
+    int obj = (int)blockIdx.y, xb = (int)blockIdx.x;
+    if (rows) {
+        const int2 r = rows[blockIdx.y];
+        obj = r.x;
+        xb += r.y;
+    }
     const DObj o = objs[obj];
-    if (blockIdx.x == 0) {
+    if (xb == 0) {
         normalise_probabilities(o, obj, vals, p, pfix, done);
         return;
     }
     if (o.timeline) {
         const int64_t per = (int64_t)K1_TPB * o.tl_w * o.H;
         const int64_t total = (int64_t)o.T * o.tl_w * o.H;
-        const int64_t lo = ((int64_t)blockIdx.x - 1) * per;
+        const int64_t lo = ((int64_t)xb - 1) * per;
         const int64_t hi = min(total, lo + per);
         // 16-byte stores: hist_off, the stretch and the total are even
         ulonglong2 *h2 = reinterpret_cast<ulonglong2 *>(hist + o.hist_off);
         for (int64_t k = lo / 2 + (int64_t)threadIdx.x; k < hi / 2; k += WG) h2[k] = make_ulonglong2(0ull, 0ull);
     }
     const int lane = threadIdx.x & 63;
-    const int i = ((int)blockIdx.x - 1) * K1_TPB + (int)(threadIdx.x >> 6);
+    const int i = (xb - 1) * K1_TPB + (int)(threadIdx.x >> 6);
     if (i >= o.T) return;  // whole wave
     // this trajectory's row of the integer q accumulators starts from zero
     for (int k = lane; k < o.n_scene_obj; k += 64) qacc[o.q_row + (int64_t)i * o.n_scene_obj + k] = 0ull;
@@ -1463,11 +1469,11 @@ hipError_t launch_trajgen(const Launch &L, hipStream_t s)
 {
     if (L.n_obj <= 0) return hipSuccess;
     if (L.one_track)
-        hipLaunchKernelGGL(k1_trajgen<true>, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
-                           L.pfix, L.qacc, L.done, L.hist);
+        hipLaunchKernelGGL(k1_trajgen<true>, dim3(L.k1_x, L.k1_nrows), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
+                           L.pfix, L.qacc, L.done, L.hist, L.k1_rows);
     else
-        hipLaunchKernelGGL(k1_trajgen<false>, dim3(L.k1_x, L.n_obj), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
-                           L.pfix, L.qacc, L.done, L.hist);
+        hipLaunchKernelGGL(k1_trajgen<false>, dim3(L.k1_x, L.k1_nrows), dim3(WG), 0, s, L.objs, L.vals, L.poses, L.p,
+                           L.pfix, L.qacc, L.done, L.hist, L.k1_rows);
     return hipGetLastError();
 }
 

@@ -179,7 +179,9 @@ struct Launch {
     double *traj_crit;
     double *obj_crit;
     int n_obj, n_pairs, n_work, n_bins;
-    int k1_x;                     // trajectory kernel grid x: blocks of the largest object + 1
+    int k1_x;                     // trajectory kernel grid x: blocks of a row
+    int k1_nrows;                 // trajectory kernel grid y: rows (objects, or k1_rows entries)
+    const int2 *k1_rows;          // per row: object and its first block; null when row = object
     int k3_x;                     // risk kernel grid x: 256-trajectory chunks of the largest object
     unsigned long long *done;     // per object: risk chunks finished (bits 56..63) and their
                                   // criticality sum in units of 2^-55 (bits 0..55)

@@ -10,6 +10,7 @@
 #include <numeric>
 #include <cstdio>
 #include <cstdint>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -276,6 +277,7 @@ static void reset_layout(Layout &L)
     keep(fresh.bins, L.bins);
     keep(fresh.polys, L.polys);
     keep(fresh.sc, L.sc);
+    keep(fresh.k1_rows, L.k1_rows);
     L = std::move(fresh);
 }
 
@@ -370,7 +372,6 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
             d.obj_out = L.n_obj + a;
             L.k3_x = std::max(L.k3_x, (d.T + WG - 1) / WG);
             L.objs.push_back(d);
-            L.k1_x = std::max(L.k1_x, (d.T + K1_TPB - 1) / K1_TPB + 1);
             toff += d.T;
         }
         // polygons: with an outline anywhere in the scene, every vehicle of the
@@ -434,6 +435,40 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
         L.n_q += toff * n;
         L.n_obj += n;
         L.n_checks += ext.checks;
+    }
+    // Trajectory kernel grid. An object takes a normalisation block and a
+    // block per K1_TPB trajectories. With objects of one size the grid is
+    // (blocks, objects); otherwise rows of as many blocks as the smallest
+    // object has, each row a stretch of one object's blocks (the row table),
+    // so that no workgroup of a large object's extent is launched for a small
+    // one (empty workgroups cost dispatch time).
+    {
+        int bmin = INT_MAX, bmax = 0;
+        for (const DObj &d : L.objs) {
+            const int b = (d.T + K1_TPB - 1) / K1_TPB + 1;
+            bmin = std::min(bmin, b);
+            bmax = std::max(bmax, b);
+        }
+        L.k1_x = bmax;
+        L.k1_nrows = (int)L.objs.size();
+        if (bmin < bmax) {
+            int B = bmin;
+            auto rows_of = [&](int w) {
+                int64_t r = 0;
+                for (const DObj &d : L.objs) r += ((d.T + K1_TPB - 1) / K1_TPB + 1 + w - 1) / w;
+                return r;
+            };
+            while (rows_of(B) > 65535) B *= 2;  // the grid's y extent
+            for (int a = 0; a < (int)L.objs.size(); ++a) {
+                const int b = (L.objs[a].T + K1_TPB - 1) / K1_TPB + 1;
+                for (int s0 = 0; s0 < b; s0 += B) {
+                    L.k1_rows.push_back(a);
+                    L.k1_rows.push_back(s0);
+                }
+            }
+            L.k1_x = B;
+            L.k1_nrows = (int)(L.k1_rows.size() / 2);
+        }
     }
     // Time split. With few units for the resident waves, a unit's steps are
     // cut into S parts that run side by side in one wave (64/S items,
@@ -577,6 +612,7 @@ static void build_layout_once(const mhc_scene *scenes, int n_scenes, int variant
     L.value_bytes = off;
     L.o_work = put(L.work.size() * sizeof(WorkItem));
     L.o_bins = put(L.bins.size() * sizeof(int32_t));
+    L.o_k1rows = put(L.k1_rows.size() * sizeof(int32_t));
     L.image_bytes = off;
     L.o_poses = put(L.pose_bytes);
     L.o_pfix = put((size_t)L.n_traj * sizeof(unsigned long long));
@@ -728,7 +764,8 @@ void pack_image(const Layout &L, char *dst, bool values_only)
     cp(L.o_polys, L.polys.data(), L.polys.size() * sizeof(DPoly), L.value_bytes);
     if (values_only) return;
     cp(L.o_work, L.work.data(), L.work.size() * sizeof(WorkItem), L.o_bins);
-    cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t), L.image_bytes);
+    cp(L.o_bins, L.bins.data(), L.bins.size() * sizeof(int32_t), L.o_k1rows);
+    cp(L.o_k1rows, L.k1_rows.data(), L.k1_rows.size() * sizeof(int32_t), L.image_bytes);
 }
 
 Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool keep_hits, int n_cu)
@@ -743,6 +780,8 @@ Launch make_launch(const Layout &L, char *base, const mhc_result *dev_out, bool 
     X.qacc = reinterpret_cast<unsigned long long *>(base + L.o_qacc);
     X.done = reinterpret_cast<unsigned long long *>(base + L.o_done);
     X.bins = reinterpret_cast<const int32_t *>(base + L.o_bins);
+    X.k1_rows = L.k1_rows.empty() ? nullptr : reinterpret_cast<const int2 *>(base + L.o_k1rows);
+    X.k1_nrows = L.k1_nrows;
     X.polys = reinterpret_cast<const DPoly *>(base + L.o_polys);
     X.p = reinterpret_cast<double *>(base + L.o_p);
     X.hits = reinterpret_cast<int16_t *>(base + L.o_hits);
@@ -1000,6 +1039,30 @@ static void walk_plan(const Layout &L, mhc_plan_info &info)
     for (uint8_t c : seen) {
         uncovered += c == 0;
         repeated += c > 1;
+    }
+    // the trajectory kernel's grid: every block of every object (its
+    // normalisation block and one per K1_TPB trajectories) taken by exactly
+    // one workgroup, as the kernel maps (row, x) to (object, block)
+    {
+        const int n_obj = (int)L.objs.size();
+        std::vector<int64_t> first(n_obj + 1, 0);
+        for (int a = 0; a < n_obj; ++a) first[a + 1] = first[a] + (L.objs[a].T + K1_TPB - 1) / K1_TPB + 1;
+        std::vector<uint8_t> took((size_t)first[n_obj], 0);
+        const bool table = !L.k1_rows.empty();
+        if (table ? (int64_t)L.k1_rows.size() != 2LL * L.k1_nrows : L.k1_nrows != n_obj) ++bad;
+        for (int r = 0; r < L.k1_nrows && !bad; ++r) {
+            const int obj = table ? L.k1_rows[2 * r] : r, b0 = table ? L.k1_rows[2 * r + 1] : 0;
+            if (obj < 0 || obj >= n_obj || b0 < 0) {
+                ++bad;
+                break;
+            }
+            for (int x = 0; x < L.k1_x; ++x)
+                if (first[obj] + b0 + x < first[obj + 1]) {
+                    uint8_t &c = took[(size_t)(first[obj] + b0 + x)];
+                    if (c < 255) ++c;
+                }
+        }
+        for (uint8_t c : took) bad += c != 1;
     }
     int64_t blocked = 0;
     for (const DPair &pr : L.pairs) blocked += pr.bshift != 0;

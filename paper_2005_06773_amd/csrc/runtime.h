@@ -44,15 +44,17 @@ struct Layout {
     std::vector<int32_t> bins;       // [n_bins+1] range of each collision wave in `work`
     std::vector<DPoly> polys;        // polygons of the polygon pairs
     std::vector<SceneExt> sc;
+    std::vector<int32_t> k1_rows;    // trajectory kernel rows (object, first block) when objects differ in size
     int64_t n_traj = 0, n_hits = 0, n_q = 0, n_obj = 0, n_checks = 0;
-    int k1_x = 0;                 // trajectory kernel grid x
+    int k1_x = 0;                 // trajectory kernel grid x (blocks of a row)
+    int k1_nrows = 0;             // trajectory kernel grid y (rows)
     int k3_x = 0;                 // risk kernel grid x (chunks of the largest object)
     bool timeline = false;        // some scene asks for the risk over time
     int64_t n_hist = 0, n_tl_traj = 0, n_tl_obj = 0, n_tl_att = 0;
     int64_t k3t_x = 0;            // time-resolved risk kernel grid x (one wave of lanes of the largest object per workgroup)
     int k4t_y = 0;                // time-resolved reduction grid y (rows: slots + objects)
     size_t pose_bytes = 0;
-    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_polys = 0, image_bytes = 0;
+    size_t o_objs = 0, o_vals = 0, o_pairs = 0, o_work = 0, o_bins = 0, o_k1rows = 0, o_polys = 0, image_bytes = 0;
     size_t value_bytes = 0;       // the image's leading part that fill_values rewrites (before the plan)
     size_t o_poses = 0, o_pfix = 0, o_qacc = 0, o_done = 0, o_p = 0, o_hits = 0, o_q = 0, o_tc = 0, o_oc = 0;
     size_t o_hist = 0, o_attw = 0, o_ctw = 0, o_ct = 0, o_tct = 0, o_at = 0, o_tat = 0, total_bytes = 0;

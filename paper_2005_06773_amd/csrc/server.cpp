@@ -394,7 +394,7 @@ namespace {
 // workspace layout, with one collision segment per work unit).
 void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
 {
-    int64_t n_traj = 0, pose = 0, n_units = 0, n_hits = 0, vals = 0, n_pairs = 0;
+    int64_t n_traj = 0, pose = 0, n_units = 0, n_hits = 0, vals = 0, n_pairs = 0, k1_blocks = 0;
     const int n = s->n_objects;
     for (int a = 0; a < n; ++a) {
         const int64_t T = (int64_t)s->objects[a].n_u * s->objects[a].n_w;
@@ -403,6 +403,7 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
         const bool vehicle = s->objects[a].kind == MHC_VEHICLE;
         pose += align256((size_t)s->horizon * T * (vehicle ? 16 : 8)) * (vehicle ? 2 : 1);
         vals += s->objects[a].n_u + s->objects[a].n_w + (s->objects[a].score ? T : 0);
+        k1_blocks += (T + K1_TPB - 1) / K1_TPB + 1;
     }
     for (int a = 0; a < n; ++a)
         for (int b = a + 1; b < n; ++b) {
@@ -432,6 +433,7 @@ void frame_sizes(const mhc_scene *s, int max_waves, bool hits, Frame &f)
     bytes += align256(n * sizeof(DObj)) + align256(vals * 8) + align256(n_pairs * sizeof(DPair));
     bytes += align256((scene_has_outline(s) ? n : 0) * sizeof(DPoly));
     bytes += align256((n_units + 1) * sizeof(WorkItem));
+    bytes += align256(k1_blocks * 2 * sizeof(int32_t));  // trajectory kernel rows (at most one per block)
     bytes += pose + align256(n_traj * 8) * 3 + align256(n_q * 8) * 2;  // p*2^62, p, traj crit; q sums, q
     bytes += align256(n * 8);                                            // risk kernel's per-object words
     bytes += align256(hits ? n_hits * 2 : 0) + align256(n * 8);

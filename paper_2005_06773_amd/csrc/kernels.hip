@@ -149,17 +149,41 @@ __device__ __forceinline__ void store_vehicle_pose(char *__restrict__ poses, con
 // the heading and the position are prefix sums of the per-step increments.
 // Only the order of the additions differs from the serial recursion.
 
+// A double moved across lanes by the DPP control CTRL in the rows of
+// ROW_MASK; a lane without a source (or outside those rows) gets `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x, double old)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The steps of a wave-wide inclusive scan over 64 lanes without LDS: shifts
+// by 1, 2, 4 and 8 lanes within each row of 16 (row_shr), then lane 15 of
+// rows 0 and 2 into rows 1 and 3 (row_bcast:15), then lane 31 into rows 2 and
+// 3 (row_bcast:31). After step k every lane holds the combination of the
+// lanes below it up to the step's reach, so after the six it holds lanes
+// 0..l. DPP controls of the GFX9 family.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
 // Inclusive prefix sum over the 64 lanes of a wave (lane l gets the sum of
 // lanes 0..l).
 __device__ __forceinline__ double scan_add(double v, int lane)
 {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double t = __shfl_up(v, d, 64);
-        if (lane >= d) v += t;
-    }
+    (void)lane;
+    v += dpp_move<kDppRowShr1, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr2, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr4, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr8, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowBcast15, 0xA>(v, 0.0);
+    v += dpp_move<kDppRowBcast31, 0xC>(v, 0.0);
     return v;
 }
+
+// The value of the lane below (lane 0 gets `first`).
+__device__ __forceinline__ double lane_below(double x, double first) { return dpp_move<kDppWaveShr1, 0xF>(x, first); }
 
 __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, char *__restrict__ poses, int i,
                                int lane)
@@ -215,32 +239,34 @@ __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, c
                 b2 = v1 * delta / (L * g);
             }
         }
-        // lane n: the composition f_n o ... o f_{n0}; (A, b) o (P, q) = (AP, Aq + b)
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double p11 = __shfl_up(a11, d, 64), p12 = __shfl_up(a12, d, 64);
-            const double p21 = __shfl_up(a21, d, 64), p22 = __shfl_up(a22, d, 64);
-            const double q1 = __shfl_up(b1, d, 64), q2 = __shfl_up(b2, d, 64);
-            if (lane >= d) {
-                const double n11 = a11 * p11 + a12 * p21, n12 = a11 * p12 + a12 * p22;
-                const double n21 = a21 * p11 + a22 * p21, n22 = a21 * p12 + a22 * p22;
-                const double nb1 = a11 * q1 + a12 * q2 + b1, nb2 = a21 * q1 + a22 * q2 + b2;
-                a11 = n11;
-                a12 = n12;
-                a21 = n21;
-                a22 = n22;
-                b1 = nb1;
-                b2 = nb2;
-            }
-        }
+        // lane n: the composition f_n o ... o f_{n0}; (A, b) o (P, q) = (AP, Aq + b),
+        // in the steps of scan_add (a lane without a source composes with the
+        // identity, which leaves its map as it is)
+        auto compose = [&](double p11, double p12, double p21, double p22, double q1, double q2) {
+            const double n11 = a11 * p11 + a12 * p21, n12 = a11 * p12 + a12 * p22;
+            const double n21 = a21 * p11 + a22 * p21, n22 = a21 * p12 + a22 * p22;
+            const double nb1 = a11 * q1 + a12 * q2 + b1, nb2 = a21 * q1 + a22 * q2 + b2;
+            a11 = n11;
+            a12 = n12;
+            a21 = n21;
+            a22 = n22;
+            b1 = nb1;
+            b2 = nb2;
+        };
+#define MHC_COMPOSE_STEP(CTRL, ROWS)                                                                           \
+    compose(dpp_move<CTRL, ROWS>(a11, 1.0), dpp_move<CTRL, ROWS>(a12, 0.0), dpp_move<CTRL, ROWS>(a21, 0.0), \
+            dpp_move<CTRL, ROWS>(a22, 1.0), dpp_move<CTRL, ROWS>(b1, 0.0), dpp_move<CTRL, ROWS>(b2, 0.0))
+        MHC_COMPOSE_STEP(kDppRowShr1, 0xF);
+        MHC_COMPOSE_STEP(kDppRowShr2, 0xF);
+        MHC_COMPOSE_STEP(kDppRowShr4, 0xF);
+        MHC_COMPOSE_STEP(kDppRowShr8, 0xF);
+        MHC_COMPOSE_STEP(kDppRowBcast15, 0xA);
+        MHC_COMPOSE_STEP(kDppRowBcast31, 0xC);
+#undef MHC_COMPOSE_STEP
         // (beta, r) after step n, and before it (the previous lane's, or the carry)
         const double beta1 = a11 * cbeta + a12 * crate + b1;
         const double r1 = a21 * cbeta + a22 * crate + b2;
-        double beta = __shfl_up(beta1, 1, 64), r = __shfl_up(r1, 1, 64);
-        if (lane == 0) {
-            beta = cbeta;
-            r = crate;
-        }
+        const double beta = lane_below(beta1, cbeta), r = lane_below(r1, crate);
         double beta_dot, r_dot;
         if (stable) {
             beta_dot = -kb * iv * beta + (kc * iv * iv - 1.0) * r + kf * iv * delta;
@@ -253,11 +279,7 @@ __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, c
         const double psi1 = cpsi + scan_add(active ? r * tau + r_dot * h2 : 0.0, lane);
         double sp1, cp1;
         sincos(psi1, &sp1, &cp1);
-        double sp = __shfl_up(sp1, 1, 64), cp = __shfl_up(cp1, 1, 64);
-        if (lane == 0) {
-            sp = csp;
-            cp = ccp;
-        }
+        const double sp = lane_below(sp1, csp), cp = lane_below(cp1, ccp);
         double sb, cb;
         sincos(beta, &sb, &cb);
         const double spb = sp * cb + cp * sb, cpb = cp * cb - sp * sb;   // psi + beta
@@ -380,15 +402,8 @@ __global__ __launch_bounds__(WG) void k1_trajgen(const DObj *__restrict__ objs, 
                 dy = ped_s * u * tau;
             }
         }
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const double tx = __shfl_up(dx, d, 64);
-            const double ty = __shfl_up(dy, d, 64);
-            if (lane >= d) {
-                dx += tx;
-                dy += ty;
-            }
-        }
+        dx = scan_add(dx, lane);
+        dy = scan_add(dy, lane);
         const double x = cx + dx, y = cy + dy;
         if (active) {
             if (vehicle)

@@ -54,14 +54,65 @@ __device__ __forceinline__ double q_of(int risk, unsigned long long v)
     return -expm1(-(double)v * kLInvScale);
 }
 
+// A double moved across lanes by the DPP control CTRL in the rows of
+// ROW_MASK; a lane without a source (or outside those rows) gets `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x, double old)
+{
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// The steps of a wave-wide inclusive scan over 64 lanes without LDS: shifts
+// by 1, 2, 4 and 8 lanes within each row of 16 (row_shr), then lane 15 of
+// rows 0 and 2 into rows 1 and 3 (row_bcast:15), then lane 31 into rows 2 and
+// 3 (row_bcast:31). After step k every lane holds the combination of the
+// lanes below it up to the step's reach, so after the six it holds lanes
+// 0..l. DPP controls of the GFX9 family.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+// Inclusive prefix sum over the 64 lanes of a wave (lane l gets the sum of
+// lanes 0..l).
+__device__ __forceinline__ double scan_add(double v, int lane)
+{
+    (void)lane;
+    v += dpp_move<kDppRowShr1, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr2, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr4, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowShr8, 0xF>(v, 0.0);
+    v += dpp_move<kDppRowBcast15, 0xA>(v, 0.0);
+    v += dpp_move<kDppRowBcast31, 0xC>(v, 0.0);
+    return v;
+}
+
+// The value of the lane below (lane 0 gets `first`).
+__device__ __forceinline__ double lane_below(double x, double first) { return dpp_move<kDppWaveShr1, 0xF>(x, first); }
+
+// The sum of v over a workgroup of WG threads, in a fixed order: each wave's
+// sum by the DPP scan (its lane 63), then the waves' sums in wave order. Every
+// thread of the workgroup must call it; the result is valid in every thread.
+__device__ __forceinline__ double block_sum(double v, double *ws)
+{
+    const int lane = (int)(threadIdx.x & (WAVE - 1)), w = (int)(threadIdx.x / WAVE);
+    v = scan_add(v, lane);
+    if (lane == WAVE - 1) ws[w] = v;
+    __syncthreads();
+    double s = ws[0];
+#pragma unroll
+    for (int k = 1; k < WG / WAVE; ++k) s += ws[k];
+    return s;
+}
+
 // Thread tid adds the scores tid, tid + 256, ... in ascending order, eight
 // loads in flight at a time, then the workgroup adds the 256 partial sums in a
-// fixed tree: the order depends on T only.
+// fixed order (block_sum): the order depends on T only.
 __device__ void normalise_probabilities(const DObj &o, int obj, const double *__restrict__ vals,
                                         double *__restrict__ p, unsigned long long *__restrict__ pfix,
                                         unsigned long long *__restrict__ done)
 {
-    __shared__ double red[WG];
+    __shared__ double red[WG / WAVE];
     const int tid = threadIdx.x;
     const double *__restrict__ sc = vals + o.score_off;
     double part = 0.0;
@@ -78,13 +129,7 @@ __device__ void normalise_probabilities(const DObj &o, int obj, const double *__
                 if (base + k * WG + tid < o.T) part += v[k];
         }
     }
-    red[tid] = part;
-    __syncthreads();
-    for (int s = WG / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    const double total = red[0];
+    const double total = block_sum(part, red);
     for (int base = 0; base < o.T; base += 8 * WG) {
         double v[8];
 #pragma unroll
@@ -149,41 +194,6 @@ __device__ __forceinline__ void store_vehicle_pose(char *__restrict__ poses, con
 // the heading and the position are prefix sums of the per-step increments.
 // Only the order of the additions differs from the serial recursion.
 
-// A double moved across lanes by the DPP control CTRL in the rows of
-// ROW_MASK; a lane without a source (or outside those rows) gets `old`.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double x, double old)
-{
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(x), CTRL, ROW_MASK, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// The steps of a wave-wide inclusive scan over 64 lanes without LDS: shifts
-// by 1, 2, 4 and 8 lanes within each row of 16 (row_shr), then lane 15 of
-// rows 0 and 2 into rows 1 and 3 (row_bcast:15), then lane 31 into rows 2 and
-// 3 (row_bcast:31). After step k every lane holds the combination of the
-// lanes below it up to the step's reach, so after the six it holds lanes
-// 0..l. DPP controls of the GFX9 family.
-constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
-
-// Inclusive prefix sum over the 64 lanes of a wave (lane l gets the sum of
-// lanes 0..l).
-__device__ __forceinline__ double scan_add(double v, int lane)
-{
-    (void)lane;
-    v += dpp_move<kDppRowShr1, 0xF>(v, 0.0);
-    v += dpp_move<kDppRowShr2, 0xF>(v, 0.0);
-    v += dpp_move<kDppRowShr4, 0xF>(v, 0.0);
-    v += dpp_move<kDppRowShr8, 0xF>(v, 0.0);
-    v += dpp_move<kDppRowBcast15, 0xA>(v, 0.0);
-    v += dpp_move<kDppRowBcast31, 0xC>(v, 0.0);
-    return v;
-}
-
-// The value of the lane below (lane 0 gets `first`).
-__device__ __forceinline__ double lane_below(double x, double first) { return dpp_move<kDppWaveShr1, 0xF>(x, first); }
 
 __device__ void one_track_wave(const DObj &o, const double *__restrict__ vals, char *__restrict__ poses, int i,
                                int lane)
@@ -1076,7 +1086,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(kCollideMinW
 // trajectories; thread tid of chunk c takes trajectory i = 256 c + tid,
 // converts its sums (rounding once), clamps to 1, writes q and forms
 //   crit_{a,i} = 1 - prod_{b != a} (1 - q_{a,i;b})     (ascending b).
-// The workgroup adds p_{a,i} crit_{a,i} over its chunk in a fixed tree. An
+// The workgroup adds p_{a,i} crit_{a,i} over its chunk in a fixed order. An
 // object of one chunk writes C_a directly; otherwise the chunks add their
 // sums in fixed point into a per-object word (zeroed by the trajectory
 // kernel) that also counts them, and the chunk that completes the count
@@ -1095,7 +1105,7 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
                                               double *__restrict__ traj_crit, double *__restrict__ obj_crit,
                                               unsigned long long *__restrict__ done)
 {
-    __shared__ double red[WG];
+    __shared__ double red[WG / WAVE];
     const int obj = (int)blockIdx.y;
     const DObj o = objs[obj];
     const int chunks = (o.T + WG - 1) / WG;
@@ -1131,14 +1141,9 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
         traj_crit[o.traj_off + i] = crit;
         acc = pi * crit;
     }
-    red[tid] = acc;
-    __syncthreads();
-    for (int st = WG / 2; st > 0; st >>= 1) {
-        if (tid < st) red[tid] += red[tid + st];
-        __syncthreads();
-    }
+    const double chunk_sum = block_sum(acc, red);
     if (chunks == 1) {
-        if (tid == 0) obj_crit[o.obj_out] = red[0];
+        if (tid == 0) obj_crit[o.obj_out] = chunk_sum;
         return;
     }
     if (tid != 0) return;
@@ -1148,7 +1153,7 @@ __global__ __launch_bounds__(WG) void k3_crit(const DObj *__restrict__ objs,
     // completes the count has the whole sum in the value it gets back; the
     // sum is exact in integers, so it does not depend on which chunk ends
     // last, and nothing else is shared between the chunks.
-    const unsigned long long mine = kChunkOne + __double2ull_rn(red[0] * kCritScale);
+    const unsigned long long mine = kChunkOne + __double2ull_rn(chunk_sum * kCritScale);
     const unsigned long long before = atomicAdd(&done[obj], mine);
     if ((before >> 56) != (unsigned long long)(chunks - 1)) return;
     obj_crit[o.obj_out] = (double)((before + mine) & (kChunkOne - 1)) * kCritInvScale;
@@ -1434,13 +1439,13 @@ __device__ __forceinline__ double wave_sum(double v)
 // K4t: grid x = object, y = row: rows 0..H-1 are the slots (C_a(s)), rows
 // H..H+n-1 the collision objects (A_{a,b}). Thread t adds p_{a,i} times the
 // trajectory value over i = t, t + 256, ... in ascending order (loads four
-// ahead), and the workgroup adds the 256 partial sums in a fixed tree: every
-// sum has a fixed order.
+// ahead), and the workgroup adds the 256 partial sums in a fixed order
+// (block_sum): every sum has a fixed order.
 __global__ __launch_bounds__(WG) void k4_timeline(const DObj *__restrict__ objs, const double *__restrict__ p,
                                                   const double *__restrict__ ct_w, const double *__restrict__ att_w,
                                                   double *__restrict__ crit_t, double *__restrict__ attrib)
 {
-    __shared__ double red[WG];
+    __shared__ double red[WG / WAVE];
     const DObj o = objs[blockIdx.x];
     if (!o.timeline) return;
     const int row = (int)blockIdx.y;
@@ -1463,17 +1468,12 @@ __global__ __launch_bounds__(WG) void k4_timeline(const DObj *__restrict__ objs,
         for (int k = 0; k < 4; ++k)
             if (base + k * WG + tid < T) acc += w[k] * x[k];
     }
-    red[tid] = acc;
-    __syncthreads();
-    for (int st = WG / 2; st > 0; st >>= 1) {
-        if (tid < st) red[tid] += red[tid + st];
-        __syncthreads();
-    }
+    const double total = block_sum(acc, red);
     if (tid != 0) return;
     if (row < H)
-        crit_t[o.tl_obj + row] = red[0];
+        crit_t[o.tl_obj + row] = total;
     else
-        attrib[o.tl_att + (row - H)] = red[0];
+        attrib[o.tl_att + (row - H)] = total;
 }
 
 // ===========================================================================

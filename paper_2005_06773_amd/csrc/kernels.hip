@@ -690,6 +690,21 @@ __device__ __forceinline__ float2 load_pose<float2>(__amdgpu_buffer_rsrc_t r, ui
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
+// The minimum of v over the lanes l ^ E, l ^ 2E, ... (E = 64 >> tshift, the
+// lanes of one item's parts), moved without LDS: lane l ^ 8 by a rotation of
+// its row of 16 by 8 (DPP row_ror), l ^ 16 and l ^ 32 by the gfx950 lane-half
+// swaps, whose two results hold each lane's own value and its partner's.
+__device__ __forceinline__ int min_over_parts(int v, int tshift)
+{
+    if (tshift >= 3) v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false));
+    if (tshift >= 2) {
+        const auto h = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        v = min((int)h[0], (int)h[1]);
+    }
+    const auto w = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return min((int)w[0], (int)w[1]);
+}
+
 // STAGE: the instance stages the poses of 8 x 8 item blocks in LDS (units of
 // 2-D blocks without a time split): per step, the wave loads each distinct
 // pose of its block once (lane k the k-th pose of either object) into LDS,
@@ -836,14 +851,15 @@ __device__ __forceinline__ void collide_items(const DPair &pr, int item0, const 
     }
     if (tshift) {
         // the earliest hit over the parts: their step ranges cover [0, H), so
-        // it is the smallest step found by any part (lanes l ^ E, l ^ 2E, ...)
+        // it is the smallest step found by any part (lanes l ^ E, l ^ 2E, ...;
+        // the parts of an item are active together)
 #pragma unroll
         for (int r = 0; r < RI; ++r)
 #pragma unroll
             for (int s = 0; s < RJ; ++s) {
-                int v = first[r][s] >= 0 ? first[r][s] + (int)t0 : INT_MAX;
-                for (int off = per; off < WAVE; off <<= 1) v = min(v, __shfl_xor(v, off));
-                first[r][s] = v == INT_MAX ? -1 : v;
+                const int v = first[r][s] >= 0 ? first[r][s] + (int)t0 : INT_MAX;
+                const int m = min_over_parts(v, tshift);
+                first[r][s] = m == INT_MAX ? -1 : m;
             }
         if (part != 0) return;
     }

@@ -426,9 +426,10 @@ def make_workload(name, seed, sg):
 
 def recorded_traffic(variant, workload):
     """HBM bytes per collision launch from the committed counter runs
-    (profiles/k2_collide_eleven_object_traffic.txt), each counter scaled by
-    what it reads for a plain copy kernel of known size; None when the kernel
-    sources or the tile variant differ from those the counters were taken on."""
+    (profiles/k2_collide_eleven_object_traffic.txt, one FETCH_SIZE and one
+    WRITE_SIZE figure per tile variant), each counter scaled by what it reads
+    for a plain copy kernel of known size; None when the kernel sources differ
+    from those the counters were taken on or the variant has no record."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k2_collide_eleven_object_traffic.txt")
     if workload != "eleven_object" or not os.path.exists(path):
@@ -441,11 +442,12 @@ def recorded_traffic(variant, workload):
     h = hashlib.sha256()
     for f in ("paper_2005_06773_amd/csrc/kernels.hip", "paper_2005_06773_amd/csrc/mhc_internal.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("kernel_source_sha256") != h.hexdigest() or int(rec.get("variant", -1)) != variant:
+    fkey, wkey = f"fetch_kib_per_dispatch[{variant}]", f"write_kib_per_dispatch[{variant}]"
+    if rec.get("kernel_source_sha256") != h.hexdigest() or fkey not in rec or wkey not in rec:
         return None
     copy_kib = float(rec["copy_mib"]) * 1024.0
-    fetch = float(rec["fetch_kib_per_dispatch"]) * copy_kib / float(rec["copy_fetch_kib"])
-    write = float(rec["write_kib_per_dispatch"]) * copy_kib / float(rec["copy_write_kib"])
+    fetch = float(rec[fkey]) * copy_kib / float(rec["copy_fetch_kib"])
+    write = float(rec[wkey]) * copy_kib / float(rec["copy_write_kib"])
     return (fetch + write) * 1024.0
 
 

@@ -314,3 +314,20 @@ def test_bench_command_line_guards():
         r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], capture_output=True,
                            text=True, timeout=120)
         assert r.returncode != 0 and msg in r.stderr, (argv, r.returncode, r.stderr[-300:])
+
+
+def test_recorded_traffic_covers_every_tile_variant():
+    """The committed FETCH_SIZE/WRITE_SIZE record matches the current kernel
+    sources and has a figure for every tile variant the autotuner can pick, so
+    the bench line's traffic is never dropped because of the variant chosen;
+    each figure lies between the collision kernel's algorithmic bytes (poses in,
+    first hits out, 6.49 MB on the 11-object scene) and a few times that."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    for v in range(4):
+        t = bench.recorded_traffic(v, "eleven_object")
+        assert t is not None, v
+        assert 6.49e6 < t < 4 * 6.49e6, (v, t)
+    assert bench.recorded_traffic(4, "eleven_object") is None
+    assert bench.recorded_traffic(0, "stress") is None
